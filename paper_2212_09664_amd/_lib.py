@@ -1,0 +1,226 @@
+"""ctypes binding of include/altgdmin.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+MASK_LINES, MASK_INDEX = 0, 1
+FP32, MIXED = 0, 1
+TIMED_KERNELS = {"fwd_transform": 1, "gram_rhs": 2, "solve": 3, "fold": 4, "adj_transform": 5,
+                 "qr_gram": 6, "qr_small": 7, "apply_qr": 8}
+
+_STATUS = {0: "ok", 1: "invalid argument", 2: "call out of order", 3: "HIP runtime error",
+           4: "Gram matrix not positive definite", 5: "non-finite value", 6: "unsupported configuration"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nc", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("r", ctypes.c_int32), ("m_max", ctypes.c_int32),
+                ("mask_kind", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("trunc_c", ctypes.c_double), ("eta_c", ctypes.c_double),
+                ("eta_cap_c", ctypes.c_double), ("eps_exit", ctypes.c_double),
+                ("t_max", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int32), ("exited", ctypes.c_int32), ("f", ctypes.c_double),
+                ("sd", ctypes.c_double), ("grad_norm", ctypes.c_double), ("eta", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
+
+
+class AltGDminError(RuntimeError):
+    def __init__(self, status: int, where: str, frame: Optional[int] = None):
+        self.status = status
+        self.frame = frame
+        msg = f"{where}: {_STATUS.get(status, 'unknown')} (status {status})"
+        if frame is not None and frame >= 0:
+            msg += f", frame {frame}"
+        super().__init__(msg)
+
+
+_LIB = None
+
+
+def lib_path() -> str:
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaltgdmin.so")
+
+
+def load_library():
+    """Load libaltgdmin.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2212_09664_amd.build")
+    L = ctypes.CDLL(path)
+    vp, i32, pi32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_double
+    sig = {
+        "altgdmin_create": ([ctypes.POINTER(Params), ctypes.POINTER(vp)], i32),
+        "altgdmin_workspace_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "altgdmin_set_problem": ([vp, vp, vp, vp, vp, vp, vp], i32),
+        "altgdmin_init": ([vp, vp], i32),
+        "altgdmin_init_from": ([vp, vp, vp], i32),
+        "altgdmin_iterate": ([vp, i32, vp, vp, vp, pi32], i32),
+        "altgdmin_get_eta": ([vp, ctypes.POINTER(dbl)], i32),
+        "altgdmin_set_eta": ([vp, dbl], i32),
+        "altgdmin_cost": ([vp, vp, vp], i32),
+        "altgdmin_gradient": ([vp, vp, vp, vp], i32),
+        "altgdmin_apply_A": ([vp, vp, vp], i32),
+        "altgdmin_apply_AH": ([vp, vp, vp], i32),
+        "altgdmin_get_stats": ([vp, ctypes.POINTER(Stats)], i32),
+        "altgdmin_last_error": ([vp, pi32], i32),
+        "altgdmin_set_timing": ([vp, i32], i32),
+        "altgdmin_kernel_time": ([vp, ctypes.POINTER(ctypes.c_char_p), pi32, ctypes.POINTER(dbl)], i32),
+        "altgdmin_status_string": ([i32], ctypes.c_char_p),
+        "altgdmin_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _LIB = L
+    return L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class AltGDmin:
+    """One reconstruction context (one problem shape, one bound problem)."""
+
+    def __init__(self, nx, ny, nc, q, r, m_max, mask_kind=MASK_LINES, precision=FP32, trunc_c=36.0,
+                 eta_c=0.14, eta_cap_c=0.0, eps_exit=0.0, t_max=70):
+        self._L = load_library()
+        self.p = Params(nx, ny, nc, q, r, m_max, mask_kind, precision, trunc_c, eta_c, eta_cap_c,
+                        eps_exit, t_max)
+        self.n = nx * ny
+        h = ctypes.c_void_p()
+        self._check(self._L.altgdmin_create(ctypes.byref(self.p), ctypes.byref(h)), "create")
+        self._h = h
+        nb = ctypes.c_size_t()
+        self._check(self._L.altgdmin_workspace_bytes(self._h, ctypes.byref(nb)), "workspace_bytes")
+        self.workspace_bytes = nb.value
+        self._keep = []
+        self.ws = None
+        self.device = None
+
+    def _check(self, st, where):
+        if st != 0:
+            frame = None
+            if st == 4 and getattr(self, "_h", None):
+                f = ctypes.c_int32(-1)
+                self._L.altgdmin_last_error(self._h, ctypes.byref(f))
+                frame = f.value
+            raise AltGDminError(st, where, frame)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and self._L is not None:
+            self._L.altgdmin_destroy(h)
+            self._h = None
+
+    # --- binding -------------------------------------------------------------
+    def set_problem(self, coils, mask, m_k, y=None, workspace=None, stream=None):
+        dev = coils.device
+        if dev.type != "cuda":
+            raise ValueError("inputs must be on the GPU")
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        base = workspace.data_ptr()
+        off = (-base) % 256
+        ws = workspace[off: off + self.workspace_bytes]
+        coils = coils.contiguous()
+        mask = mask.to(torch.int32).contiguous()
+        m_k = m_k.to(torch.int32).contiguous()
+        y = None if y is None else y.contiguous()
+        self._keep = [coils, mask, m_k, y, workspace]
+        self.ws = ws
+        self.device = dev
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.stream = s
+        self._check(self._L.altgdmin_set_problem(self._h, _ptr(coils), _ptr(mask), _ptr(m_k), _ptr(y),
+                                                 ctypes.c_void_p(ws.data_ptr()),
+                                                 ctypes.c_void_p(s.cuda_stream)), "set_problem")
+
+    def _new(self, *shape, dtype=torch.complex64):
+        return torch.empty(*shape, dtype=dtype, device=self.device)
+
+    # --- algorithm -----------------------------------------------------------
+    def init(self, U=None):
+        U = self._new(self.p.r, self.n) if U is None else U
+        self._check(self._L.altgdmin_init(self._h, _ptr(U)), "init")
+        return U
+
+    def init_from(self, U0, U=None):
+        U = U0 if U is None else U
+        self._check(self._L.altgdmin_init_from(self._h, _ptr(U0), _ptr(U)), "init_from")
+        return U
+
+    def iterate(self, n_iter, U, B=None, U_prev=None, sync=False):
+        B = self._new(self.p.q, self.p.r) if B is None else B
+        done = ctypes.c_int32(0)
+        self._check(self._L.altgdmin_iterate(self._h, int(n_iter), _ptr(U), _ptr(B), _ptr(U_prev),
+                                             ctypes.byref(done) if sync else None), "iterate")
+        return (B, done.value) if sync else B
+
+    def get_eta(self):
+        v = ctypes.c_double()
+        self._check(self._L.altgdmin_get_eta(self._h, ctypes.byref(v)), "get_eta")
+        return v.value
+
+    def set_eta(self, eta):
+        self._check(self._L.altgdmin_set_eta(self._h, float(eta)), "set_eta")
+
+    def cost(self, U):
+        f = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._check(self._L.altgdmin_cost(self._h, _ptr(U), _ptr(f)), "cost")
+        return f
+
+    def gradient(self, U):
+        """(B, G) at U: B (q, r) the LS coefficients, G (r, n) the gradient."""
+        B = self._new(self.p.q, self.p.r)
+        G = self._new(self.p.r, self.n)
+        self._check(self._L.altgdmin_gradient(self._h, _ptr(U), _ptr(B), _ptr(G)), "gradient")
+        return B, G
+
+    def apply_A(self, X, Y=None):
+        Y = self._new(self.p.q, self.p.nc, self.p.m_max) if Y is None else Y
+        self._check(self._L.altgdmin_apply_A(self._h, _ptr(X.contiguous()), _ptr(Y)), "apply_A")
+        return Y
+
+    def apply_AH(self, Y, X=None):
+        X = self._new(self.p.q, self.n) if X is None else X
+        self._check(self._L.altgdmin_apply_AH(self._h, _ptr(Y.contiguous()), _ptr(X)), "apply_AH")
+        return X
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self._L.altgdmin_get_stats(self._h, ctypes.byref(s)), "get_stats")
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def last_error(self):
+        f = ctypes.c_int32(-1)
+        st = self._L.altgdmin_last_error(self._h, ctypes.byref(f))
+        return st, f.value
+
+    def set_timing(self, kernel: str):
+        self._check(self._L.altgdmin_set_timing(self._h, TIMED_KERNELS.get(kernel, 0)), "set_timing")
+
+    def kernel_time(self):
+        name = ctypes.c_char_p()
+        cnt = ctypes.c_int32()
+        ms = ctypes.c_double()
+        self._check(self._L.altgdmin_kernel_time(self._h, ctypes.byref(name), ctypes.byref(cnt),
+                                                 ctypes.byref(ms)), "kernel_time")
+        return name.value.decode(), cnt.value, ms.value

@@ -1,0 +1,866 @@
+// Host side of the C ABI declared in include/altgdmin.h: argument checks,
+// workspace carving and the launch sequences of setup, spectral
+// initialisation, the altGDmin iteration (Algorithm 2) and the operators.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/altgdmin.h"
+#include "kernels_core.hpp"
+
+using namespace ag;
+
+namespace {
+
+enum TimedKernel {
+  TK_NONE = 0,
+  TK_FWD = 1,
+  TK_GRAM = 2,
+  TK_SOLVE = 3,
+  TK_FOLD = 4,
+  TK_ADJ = 5,
+  TK_QRGRAM = 6,
+  TK_QRSMALL = 7,
+  TK_APPLY = 8,
+  TK_COUNT = 9
+};
+const char* kTimedNames[TK_COUNT] = {"none",  "fwd_transform", "gram_rhs", "solve",     "fold",
+                                     "adj_transform", "qr_gram", "qr_small", "apply_qr"};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct altgdmin_ctx {
+  altgdmin_params p;
+  int n, lines, fp64;
+  int width;     // mask row width: lines per frame (LINES) or m_max (INDEX)
+  int lmax;      // LINES: m_max / nx
+  int per;       // samples per mask entry (nx for LINES, 1 for INDEX)
+  int n_loc, nw;
+  int ua;        // rows per (c, j) plane of W / K
+  int nchunks;   // INDEX gram chunks per frame
+  int qr_nblk;
+  long qr_rows;
+  int kc;        // INDEX: frames per chunk of the operator passes
+  int gram_xc, gram_pc;
+  size_t bytes;
+  // bound problem
+  const float2* coils = nullptr;
+  const int32_t* mask = nullptr;
+  const int32_t* m_k = nullptr;
+  const float2* y = nullptr;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int bound = 0, initialized = 0;
+  // workspace carve
+  size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
+      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_end;
+  size_t T_bytes;
+  // timing
+  int timed = TK_NONE;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+
+  template <typename T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  DevState* st() const { return at<DevState>(o_st); }
+};
+
+namespace {
+
+#define HIPCHK(x)                            \
+  do {                                       \
+    hipError_t _e = (x);                     \
+    if (_e != hipSuccess) return ALTGDMIN_EHIP; \
+  } while (0)
+
+void carve(altgdmin_ctx* c) {
+  const altgdmin_params& p = c->p;
+  const int r = p.r, q = p.q, nc = p.nc;
+  const long n = c->n;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = align256(off + b);
+    return o;
+  };
+  c->o_st = take(sizeof(DevState));
+  c->o_twx = take(sizeof(float2) * p.nx);
+  c->o_twy = take(sizeof(float2) * p.ny);
+  c->o_bitmap = take(sizeof(uint32_t) * (size_t)c->n_loc * c->nw);
+  c->o_locptr = take(sizeof(int32_t) * (size_t)(c->n_loc + 1));
+  c->o_loc2unit = take(sizeof(int32_t) * (size_t)c->n_loc);
+  c->o_unitloc = take(sizeof(int32_t) * (size_t)c->n_loc);
+  c->o_pairs = take(sizeof(int2) * (size_t)q * c->width);
+  c->o_pairof = take(sizeof(int32_t) * (size_t)q * c->width);
+  const size_t ysz = sizeof(float2) * (size_t)q * nc * p.m_max;
+  c->o_yh = take(c->lines ? ysz : 0);
+  c->o_ysq = take(sizeof(double) * q);
+  c->o_cost = take(sizeof(double) * q);
+  const size_t wsz = sizeof(float2) * (size_t)nc * r * c->ua * p.nx;
+  c->o_W = take(wsz);
+  c->o_K = take(wsz);
+  const int nP = r * (r + 1) / 2;
+  if (c->lines) {
+    c->o_P = take(sizeof(double2) * (size_t)p.ny * r * r);
+    c->o_hp = take(sizeof(double2) * (size_t)q * c->width * r);
+  } else {
+    c->o_P = take(sizeof(double2) * (size_t)q * c->nchunks * (nP + r));
+    c->o_hp = take(0);
+  }
+  c->o_B = take(sizeof(float2) * (size_t)q * r);
+  c->o_G = take(sizeof(float2) * (size_t)n * r);
+  const int m_iter = 2 * r;
+  const size_t qo = (size_t)std::max(m_iter * (m_iter + 1) / 2, q * (q + 1) / 2);
+  c->o_qpart = take(sizeof(double2) * qo * c->qr_nblk);
+  c->o_rinv = take(sizeof(float2) * r * r);
+  c->o_Vs = take(sizeof(float2) * (size_t)q * r);
+  c->o_V = take(sizeof(double2) * (size_t)q * q);
+  // temp: X0 plus the truncated hybrid data (LINES) or a chunk of coil images (INDEX)
+  size_t tb = sizeof(float2) * (size_t)n * q;
+  if (c->lines)
+    tb += ysz;
+  else
+    tb += sizeof(float2) * (size_t)c->kc * nc * n;
+  c->T_bytes = tb;
+  c->o_T = take(tb);
+  c->o_end = off;
+  c->bytes = off;
+}
+
+altgdmin_status check_params(const altgdmin_params* p) {
+  if (!p) return ALTGDMIN_EINVAL;
+  if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < 8 || p->ny < 8 || p->nx > 512 || p->ny > 512)
+    return ALTGDMIN_EINVAL;
+  if (p->nc < 1 || p->nc > 64 || p->q < 1 || p->q > 128 || p->r < 1 || p->r > 16 || p->r > p->q)
+    return ALTGDMIN_EINVAL;
+  if (p->mask_kind != ALTGDMIN_MASK_LINES && p->mask_kind != ALTGDMIN_MASK_INDEX) return ALTGDMIN_EINVAL;
+  if (p->precision != ALTGDMIN_FP32 && p->precision != ALTGDMIN_MIXED) return ALTGDMIN_EINVAL;
+  if (p->m_max < 1 || p->m_max > p->nx * p->ny) return ALTGDMIN_EINVAL;
+  if (p->mask_kind == ALTGDMIN_MASK_LINES && (p->m_max % p->nx) != 0) return ALTGDMIN_EINVAL;
+  if (!(p->eta_c > 0) || !isfinite(p->eta_c) || !isfinite(p->trunc_c) || !(p->eta_cap_c >= 0) ||
+      !isfinite(p->eps_exit))
+    return ALTGDMIN_EINVAL;
+  if (p->t_max < 1) return ALTGDMIN_EINVAL;
+  return ALTGDMIN_OK;
+}
+
+// ---- timing of one kernel class ------------------------------------------
+void tmark(altgdmin_ctx* c, int which) {
+  if (c->timed != which) return;
+  if (c->ev_used + 1 >= c->ev.size()) {
+    for (int i = 0; i < 256; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      c->ev.push_back(e);
+    }
+  }
+  (void)hipEventRecord(c->ev[c->ev_used++], c->stream);
+}
+
+// ---- launch sequences -------------------------------------------------------
+hipError_t fwd_transform(altgdmin_ctx* c, const float2* U, int check_halt) {
+  const altgdmin_params& p = c->p;
+  ColFwdArgs f{};
+  f.src = U;
+  f.src_img_stride = c->n;
+  f.coils = c->coils;
+  f.n = c->n;
+  f.nx = p.nx;
+  f.tw = c->at<float2>(c->o_twy);
+  f.dst = c->at<float2>(c->o_W);
+  f.dst_c_stride = (long)p.r * c->ua * p.nx;
+  f.dst_img_stride = (long)c->ua * p.nx;
+  f.scale = (float)(1.0 / sqrt((double)p.ny));
+  f.check_halt = check_halt;
+  f.st = c->st();
+  if (c->lines) {
+    f.rows = c->at<int32_t>(c->o_unitloc);
+    f.n_rows_ptr = &c->st()->n_units;
+  }
+  hipError_t e = launch_cols(p.ny, &f, nullptr, p.nx, p.r, p.nc, c->stream);
+  if (e != hipSuccess || c->lines) return e;
+  RowArgs ra{};
+  ra.src = ra.dst = c->at<float2>(c->o_W);
+  ra.tw = c->at<float2>(c->o_twx);
+  ra.nrows = (long)p.nc * p.r * p.ny;
+  ra.scale = (float)(1.0 / sqrt((double)p.nx));
+  ra.check_halt = check_halt;
+  ra.st = c->st();
+  return launch_rows(p.nx, ra, false, c->stream);
+}
+
+hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
+  const altgdmin_params& p = c->p;
+  hipError_t e;
+  if (c->lines) {
+    GramLinesArgs g{};
+    g.W = c->at<float2>(c->o_W);
+    g.yh = c->at<float2>(c->o_yh);
+    g.pairs = c->at<int2>(c->o_pairs);
+    g.loc_ptr = c->at<int32_t>(c->o_locptr);
+    g.unit_loc = c->at<int32_t>(c->o_unitloc);
+    g.nc = p.nc;
+    g.r = p.r;
+    g.nx = p.nx;
+    g.lmax = c->lmax;
+    g.ua = c->ua;
+    g.xc = c->gram_xc;
+    g.pc = c->gram_pc;
+    g.P = c->at<double2>(c->o_P);
+    g.hp = c->at<double2>(c->o_hp);
+    g.st = c->st();
+    g.check_halt = check_halt;
+    tmark(c, TK_GRAM);
+    e = launch_gram_lines(g, p.ny, c->fp64, c->stream);
+    tmark(c, TK_GRAM);
+  } else {
+    GramIndexArgs g{};
+    g.W = c->at<float2>(c->o_W);
+    g.y = c->y;
+    g.mask = c->mask;
+    g.m_k = c->m_k;
+    g.nc = p.nc;
+    g.r = p.r;
+    g.n = c->n;
+    g.m_max = p.m_max;
+    g.part = c->at<double2>(c->o_P);
+    g.st = c->st();
+    g.check_halt = check_halt;
+    tmark(c, TK_GRAM);
+    e = launch_gram_index(g, c->nchunks, p.q, c->fp64, c->stream);
+    tmark(c, TK_GRAM);
+  }
+  if (e != hipSuccess) return e;
+  SolveArgs s{};
+  s.P = c->at<double2>(c->o_P);
+  s.hp = c->at<double2>(c->o_hp);
+  s.mask = c->mask;
+  s.m_k = c->m_k;
+  s.loc2unit = c->at<int32_t>(c->o_loc2unit);
+  s.pair_of = c->at<int32_t>(c->o_pairof);
+  s.width = c->width;
+  s.nx = p.nx;
+  s.r = p.r;
+  s.kind = c->lines ? 0 : 1;
+  s.nchunks = c->nchunks;
+  s.ysq_k = c->at<double>(c->o_ysq);
+  s.B = c->at<float2>(c->o_B);
+  s.cost_k = c->at<double>(c->o_cost);
+  s.st = c->st();
+  s.check_halt = check_halt;
+  tmark(c, TK_SOLVE);
+  e = launch_solve(s, p.q, c->fp64, c->stream);
+  tmark(c, TK_SOLVE);
+  return e;
+}
+
+hipError_t cholqr(altgdmin_ctx* c, float2* U) {
+  const altgdmin_params& p = c->p;
+  GramColsArgs g{};
+  g.A = U;
+  g.m1 = p.r;
+  g.m2 = 0;
+  g.n = c->n;
+  g.rows_per_block = c->qr_rows;
+  g.part = c->at<double2>(c->o_qpart);
+  g.st = c->st();
+  hipError_t e = launch_gram_cols(g, c->qr_nblk, true, c->stream);
+  if (e != hipSuccess) return e;
+  QrSmallArgs qa{};
+  qa.part = c->at<double2>(c->o_qpart);
+  qa.nblk = c->qr_nblk;
+  qa.r = p.r;
+  qa.mode = 1;
+  qa.n = c->n;
+  qa.q = p.q;
+  qa.rinv = c->at<float2>(c->o_rinv);
+  qa.st = c->st();
+  e = launch_qr_small(qa, c->stream);
+  if (e != hipSuccess) return e;
+  ApplyArgs aa{};
+  aa.U = U;
+  aa.rinv = c->at<float2>(c->o_rinv);
+  aa.n = c->n;
+  aa.r = p.r;
+  aa.mode = 1;
+  aa.st = c->st();
+  return launch_apply(aa, c->stream);
+}
+
+// b_k for every frame and the gradient at U (into the workspace's B and G)
+hipError_t gradient_pieces(altgdmin_ctx* c, const float2* U, int check_halt) {
+  const altgdmin_params& p = c->p;
+  hipError_t e;
+  tmark(c, TK_FWD);
+  e = fwd_transform(c, U, check_halt);
+  tmark(c, TK_FWD);
+  if (e != hipSuccess) return e;
+  e = gram_solve(c, check_halt);
+  if (e != hipSuccess) return e;
+  // fold the residual over frames
+  FoldArgs fa{};
+  fa.W = c->at<float2>(c->o_W);
+  fa.yh = c->at<float2>(c->o_yh);
+  fa.y = c->y;
+  fa.B = c->at<float2>(c->o_B);
+  fa.pairs = c->at<int2>(c->o_pairs);
+  fa.loc_ptr = c->at<int32_t>(c->o_locptr);
+  fa.unit_loc = c->at<int32_t>(c->o_unitloc);
+  fa.nc = p.nc;
+  fa.r = p.r;
+  fa.nx = p.nx;
+  fa.lmax = c->lmax;
+  fa.ua = c->ua;
+  fa.cg = c->lines ? std::max(1, std::min(p.nc, 4096 / p.nx / 4)) : 1;
+  fa.n = c->n;
+  fa.m_max = p.m_max;
+  fa.K = c->at<float2>(c->o_K);
+  fa.st = c->st();
+  fa.check_halt = check_halt;
+  tmark(c, TK_FOLD);
+  if (c->lines)
+    e = launch_fold(fa, true, p.ny, (p.nc + fa.cg - 1) / fa.cg, c->stream);
+  else
+    e = launch_fold(fa, false, (int)((c->n + AG_NT - 1) / AG_NT), p.nc, c->stream);
+  tmark(c, TK_FOLD);
+  if (e != hipSuccess) return e;
+  // inverse transform + coil combine -> gradient
+  tmark(c, TK_ADJ);
+  if (!c->lines) {
+    RowArgs ra{};
+    ra.src = ra.dst = c->at<float2>(c->o_K);
+    ra.tw = c->at<float2>(c->o_twx);
+    ra.nrows = (long)p.nc * p.r * p.ny;
+    ra.scale = (float)(1.0 / sqrt((double)p.nx));
+    ra.check_halt = check_halt;
+    ra.st = c->st();
+    e = launch_rows(p.nx, ra, true, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  ColAdjArgs d{};
+  d.src = c->at<float2>(c->o_K);
+  d.src_c_stride = (long)p.r * c->ua * p.nx;
+  d.src_img_stride = (long)c->ua * p.nx;
+  if (c->lines) {
+    d.rows = c->at<int32_t>(c->o_unitloc);
+    d.n_rows_ptr = &c->st()->n_units;
+  }
+  d.coils = c->coils;
+  d.n = c->n;
+  d.nx = p.nx;
+  d.nc = p.nc;
+  d.tw = c->at<float2>(c->o_twy);
+  d.dst = c->at<float2>(c->o_G);
+  d.dst_img_stride = c->n;
+  d.scale = (float)(1.0 / sqrt((double)p.ny));
+  d.check_halt = check_halt;
+  d.st = c->st();
+  e = launch_cols(p.ny, nullptr, &d, p.nx, p.r, p.nc, c->stream);
+  tmark(c, TK_ADJ);
+  return e;
+}
+
+hipError_t one_iteration(altgdmin_ctx* c, float2* U, float2* U_prev) {
+  const altgdmin_params& p = c->p;
+  hipError_t e = gradient_pieces(c, U, 1);
+  if (e != hipSuccess) return e;
+  // Gram of [U grad], then the small QR work, then the update
+  GramColsArgs g{};
+  g.A = U;
+  g.B = c->at<float2>(c->o_G);
+  g.m1 = p.r;
+  g.m2 = p.r;
+  g.n = c->n;
+  g.rows_per_block = c->qr_rows;
+  g.part = c->at<double2>(c->o_qpart);
+  g.st = c->st();
+  g.check_halt = 1;
+  tmark(c, TK_QRGRAM);
+  e = launch_gram_cols(g, c->qr_nblk, c->fp64, c->stream);
+  tmark(c, TK_QRGRAM);
+  if (e != hipSuccess) return e;
+  QrSmallArgs qa{};
+  qa.part = c->at<double2>(c->o_qpart);
+  qa.nblk = c->qr_nblk;
+  qa.r = p.r;
+  qa.mode = 0;
+  qa.n = c->n;
+  qa.q = p.q;
+  qa.eta_c = p.eta_c;
+  qa.eta_cap_c = p.eta_cap_c;
+  qa.eps_exit = p.eps_exit;
+  qa.guard = 1e-6;  // FP32 gradient: below this it is rounding noise
+  qa.B = c->at<float2>(c->o_B);
+  qa.cost_k = c->at<double>(c->o_cost);
+  qa.rinv = c->at<float2>(c->o_rinv);
+  qa.st = c->st();
+  qa.check_halt = 1;
+  tmark(c, TK_QRSMALL);
+  e = launch_qr_small(qa, c->stream);
+  tmark(c, TK_QRSMALL);
+  if (e != hipSuccess) return e;
+  ApplyArgs aa{};
+  aa.U = U;
+  aa.G = c->at<float2>(c->o_G);
+  aa.rinv = c->at<float2>(c->o_rinv);
+  aa.U_prev = U_prev;
+  aa.n = c->n;
+  aa.r = p.r;
+  aa.mode = 0;
+  aa.st = c->st();
+  tmark(c, TK_APPLY);
+  e = launch_apply(aa, c->stream);
+  tmark(c, TK_APPLY);
+  return e;
+}
+
+// X = A^H(Y) scaled per column (back-projection when trunc/scale are set)
+hipError_t adjoint_op(altgdmin_ctx* c, const float2* Y, float2* X, int trunc, int scale_mk) {
+  const altgdmin_params& p = c->p;
+  hipError_t e;
+  float2* T = c->at<float2>(c->o_T) + (size_t)c->n * p.q;  // after the X0 slot
+  if (c->lines) {
+    RowArgs ra{};
+    ra.src = Y;
+    ra.dst = T;
+    ra.tw = c->at<float2>(c->o_twx);
+    ra.nrows = (long)p.q * p.nc * c->lmax;
+    ra.m_k = c->m_k;
+    ra.nc = p.nc;
+    ra.lmax = c->lmax;
+    ra.scale = (float)(1.0 / sqrt((double)p.nx));
+    ra.trunc = trunc;
+    ra.st = c->st();
+    e = launch_rows(p.nx, ra, true, c->stream);
+    if (e != hipSuccess) return e;
+    ColAdjArgs d{};
+    d.src = T;
+    d.src_c_stride = (long)c->lmax * p.nx;
+    d.src_img_stride = (long)p.nc * c->lmax * p.nx;
+    d.rows = c->mask;
+    d.rows_img_stride = c->width;
+    d.m_k_rows = c->m_k;
+    d.coils = c->coils;
+    d.n = c->n;
+    d.nx = p.nx;
+    d.nc = p.nc;
+    d.tw = c->at<float2>(c->o_twy);
+    d.dst = X;
+    d.dst_img_stride = c->n;
+    d.m_k_scale = scale_mk ? c->m_k : nullptr;
+    d.scale = (float)(1.0 / sqrt((double)p.ny));
+    d.st = c->st();
+    return launch_cols(p.ny, nullptr, &d, p.nx, p.q, p.nc, c->stream);
+  }
+  for (int k0 = 0; k0 < p.q; k0 += c->kc) {
+    const int kc = std::min(c->kc, p.q - k0);
+    const long nimg = (long)kc * p.nc * c->n;
+    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, c->stream, T, nimg);
+    hipLaunchKernelGGL(k_scatter, dim3((p.m_max + 255) / 256, kc, p.nc), dim3(256), 0, c->stream, Y, c->mask,
+                       c->m_k, p.m_max, p.nc, k0, T, (long)c->n, (long)p.nc * c->n, c->st(), trunc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    RowArgs ra{};
+    ra.src = ra.dst = T;
+    ra.tw = c->at<float2>(c->o_twx);
+    ra.nrows = (long)kc * p.nc * p.ny;
+    ra.scale = (float)(1.0 / sqrt((double)p.nx));
+    ra.st = c->st();
+    e = launch_rows(p.nx, ra, true, c->stream);
+    if (e != hipSuccess) return e;
+    ColAdjArgs d{};
+    d.src = T;
+    d.src_c_stride = c->n;
+    d.src_img_stride = (long)p.nc * c->n;
+    d.coils = c->coils;
+    d.n = c->n;
+    d.nx = p.nx;
+    d.nc = p.nc;
+    d.tw = c->at<float2>(c->o_twy);
+    d.dst = X + (size_t)k0 * c->n;
+    d.dst_img_stride = c->n;
+    d.m_k_scale = scale_mk ? c->m_k + k0 : nullptr;
+    d.scale = (float)(1.0 / sqrt((double)p.ny));
+    d.st = c->st();
+    e = launch_cols(p.ny, nullptr, &d, p.nx, kc, p.nc, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+altgdmin_status map_hip(hipError_t e) { return e == hipSuccess ? ALTGDMIN_OK : ALTGDMIN_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+const char* altgdmin_status_string(altgdmin_status s) {
+  switch (s) {
+    case ALTGDMIN_OK: return "ok";
+    case ALTGDMIN_EINVAL: return "invalid argument";
+    case ALTGDMIN_ESTATE: return "call out of order";
+    case ALTGDMIN_EHIP: return "HIP runtime error";
+    case ALTGDMIN_ENOTPD: return "Gram matrix not positive definite";
+    case ALTGDMIN_ENONFINITE: return "non-finite value";
+    case ALTGDMIN_EUNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** out) {
+  if (!out) return ALTGDMIN_EINVAL;
+  *out = nullptr;
+  altgdmin_status s = check_params(params);
+  if (s != ALTGDMIN_OK) return s;
+  altgdmin_ctx* c = new (std::nothrow) altgdmin_ctx();
+  if (!c) return ALTGDMIN_EINVAL;
+  c->p = *params;
+  const altgdmin_params& p = c->p;
+  c->n = p.nx * p.ny;
+  c->lines = (p.mask_kind == ALTGDMIN_MASK_LINES);
+  c->fp64 = (p.precision == ALTGDMIN_MIXED);
+  c->lmax = c->lines ? p.m_max / p.nx : 0;
+  c->width = c->lines ? c->lmax : p.m_max;
+  c->per = c->lines ? p.nx : 1;
+  c->n_loc = c->lines ? p.ny : c->n;
+  c->nw = (p.q + 31) / 32;
+  c->ua = p.ny;
+  c->nchunks = (p.m_max + AG_NT - 1) / AG_NT;
+  c->qr_nblk = std::max(1, std::min(256, c->n / 64));
+  c->qr_rows = ((long)c->n + c->qr_nblk - 1) / c->qr_nblk;
+  c->qr_rows = (c->qr_rows + 63) / 64 * 64;
+  c->qr_nblk = (int)((c->n + c->qr_rows - 1) / c->qr_rows);
+  c->kc = std::min(p.q, 16);
+  // gram_lines staging: x-chunk and pair-chunk within 64 KB of LDS and the
+  // per-thread output budget
+  c->gram_xc = std::min(p.nx, 256);
+  const int nP = p.r * (p.r + 1) / 2;
+  int pc = (GRAM_OPT * AG_NT - nP) / p.r;
+  pc = std::min(pc, (8192 - c->gram_xc * p.r) / c->gram_xc);
+  c->gram_pc = std::max(1, std::min(pc, 32));
+  if (p.q > 64) {  // spectral initialisation holds the q x q Gram in one workgroup
+    delete c;
+    return ALTGDMIN_EUNSUPPORTED;
+  }
+  carve(c);
+  *out = c;
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_workspace_bytes(const altgdmin_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return ALTGDMIN_EINVAL;
+  *bytes = c->bytes;
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const int32_t* d_mask,
+                                     const int32_t* d_m_k, const void* d_y, void* d_ws, void* stream) {
+  if (!c || !d_coils || !d_mask || !d_m_k || !d_ws) return ALTGDMIN_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0) return ALTGDMIN_EINVAL;
+  const altgdmin_params& p = c->p;
+  c->coils = static_cast<const float2*>(d_coils);
+  c->mask = d_mask;
+  c->m_k = d_m_k;
+  c->y = static_cast<const float2*>(d_y);
+  c->ws = static_cast<char*>(d_ws);
+  c->stream = static_cast<hipStream_t>(stream);
+  c->bound = 0;
+  c->initialized = 0;
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, c->st(), 1);
+  hipLaunchKernelGGL(k_twiddle, dim3((p.nx + 255) / 256), dim3(256), 0, s, c->at<float2>(c->o_twx), p.nx);
+  hipLaunchKernelGGL(k_twiddle, dim3((p.ny + 255) / 256), dim3(256), 0, s, c->at<float2>(c->o_twy), p.ny);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemsetAsync(c->at<uint32_t>(c->o_bitmap), 0, sizeof(uint32_t) * (size_t)c->n_loc * c->nw, s));
+  hipLaunchKernelGGL(k_inv_bitmap, dim3((c->width + 255) / 256, p.q), dim3(256), 0, s, c->mask, c->m_k,
+                     c->width, c->per, c->n_loc, c->at<uint32_t>(c->o_bitmap), c->nw, c->st());
+  hipLaunchKernelGGL(k_inv_scan, dim3(1), dim3(1024), 0, s, c->at<uint32_t>(c->o_bitmap), c->nw, c->n_loc,
+                     c->at<int32_t>(c->o_locptr), c->at<int32_t>(c->o_loc2unit), c->at<int32_t>(c->o_unitloc),
+                     c->st());
+  hipLaunchKernelGGL(k_inv_fill, dim3((c->width + 255) / 256, p.q), dim3(256), 0, s, c->mask, c->m_k,
+                     c->width, c->per, c->at<uint32_t>(c->o_bitmap), c->nw, c->at<int32_t>(c->o_locptr),
+                     c->at<int2>(c->o_pairs), c->at<int32_t>(c->o_pairof), c->st());
+  HIPCHK(hipGetLastError());
+  if (c->y) {
+    hipLaunchKernelGGL(k_ysq, dim3(p.q), dim3(AG_NT), 0, s, c->y, c->m_k, p.nc, p.m_max, c->at<double>(c->o_ysq));
+    hipLaunchKernelGGL(k_init_stats, dim3(1), dim3(1), 0, s, c->at<double>(c->o_ysq), c->m_k, p.q, p.trunc_c,
+                       c->st());
+    HIPCHK(hipGetLastError());
+    if (c->lines) {
+      RowArgs ra{};
+      ra.src = c->y;
+      ra.dst = c->at<float2>(c->o_yh);
+      ra.tw = c->at<float2>(c->o_twx);
+      ra.nrows = (long)p.q * p.nc * c->lmax;
+      ra.m_k = c->m_k;
+      ra.nc = p.nc;
+      ra.lmax = c->lmax;
+      ra.scale = (float)(1.0 / sqrt((double)p.nx));
+      ra.st = c->st();
+      HIPCHK(launch_rows(p.nx, ra, true, s));
+    }
+  }
+  c->bound = 1;
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_init(altgdmin_ctx* c, void* d_U) {
+  if (!c || !d_U) return ALTGDMIN_EINVAL;
+  if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
+  const altgdmin_params& p = c->p;
+  hipStream_t s = c->stream;
+  float2* U = static_cast<float2*>(d_U);
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, c->st(), 0);
+  float2* X0 = c->at<float2>(c->o_T);
+  HIPCHK(adjoint_op(c, c->y, X0, p.trunc_c > 0 ? 1 : 0, 1));
+  GramColsArgs g{};
+  g.A = X0;
+  g.m1 = p.q;
+  g.m2 = 0;
+  g.n = c->n;
+  g.rows_per_block = c->qr_rows;
+  g.part = c->at<double2>(c->o_qpart);
+  g.st = c->st();
+  HIPCHK(launch_gram_cols(g, c->qr_nblk, true, s));
+  InitEigArgs ie{};
+  ie.part = c->at<double2>(c->o_qpart);
+  ie.nblk = c->qr_nblk;
+  ie.q = p.q;
+  ie.r = p.r;
+  ie.V = c->at<double2>(c->o_V);
+  ie.Vs = c->at<float2>(c->o_Vs);
+  ie.st = c->st();
+  HIPCHK(launch_init_eig(ie, s));
+  hipLaunchKernelGGL(k_x_times_v, dim3((c->n + AG_NT - 1) / AG_NT), dim3(AG_NT), 0, s, X0,
+                     c->at<float2>(c->o_Vs), c->n, p.q, p.r, U, c->st());
+  HIPCHK(hipGetLastError());
+  HIPCHK(cholqr(c, U));
+  HIPCHK(cholqr(c, U));
+  c->initialized = 1;
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_init_from(altgdmin_ctx* c, const void* d_U0, void* d_U) {
+  if (!c || !d_U0 || !d_U) return ALTGDMIN_EINVAL;
+  if (!c->bound) return ALTGDMIN_ESTATE;
+  const altgdmin_params& p = c->p;
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, c->st(), 0);
+  if (d_U0 != d_U)
+    hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, static_cast<const float2*>(d_U0),
+                       static_cast<float2*>(d_U), (long)c->n * p.r);
+  HIPCHK(hipGetLastError());
+  HIPCHK(cholqr(c, static_cast<float2*>(d_U)));
+  HIPCHK(cholqr(c, static_cast<float2*>(d_U)));
+  c->initialized = 1;
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_iterate(altgdmin_ctx* c, int32_t n_iter, void* d_U, void* d_B, void* d_U_prev,
+                                 int32_t* h_iters_done) {
+  if (!c || !d_U) return ALTGDMIN_EINVAL;
+  if (!c->bound || !c->y || !c->initialized) return ALTGDMIN_ESTATE;
+  const altgdmin_params& p = c->p;
+  if (n_iter <= 0) n_iter = p.t_max;
+  int32_t t0 = 0;
+  if (h_iters_done) HIPCHK(hipMemcpy(&t0, &c->st()->t, sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int t = 0; t < n_iter; ++t)
+    HIPCHK(one_iteration(c, static_cast<float2*>(d_U), static_cast<float2*>(d_U_prev)));
+  if (d_B) {
+    hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, c->stream, c->at<float2>(c->o_B),
+                       static_cast<float2*>(d_B), (long)p.q * p.r);
+    HIPCHK(hipGetLastError());
+  }
+  if (h_iters_done) {
+    int32_t t1 = 0;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(&t1, &c->st()->t, sizeof(int32_t), hipMemcpyDeviceToHost));
+    *h_iters_done = t1 - t0;
+    int32_t err = 0;
+    HIPCHK(hipMemcpy(&err, &c->st()->err, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (err) return (altgdmin_status)err;
+  }
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_get_eta(altgdmin_ctx* c, double* eta) {
+  if (!c || !eta) return ALTGDMIN_EINVAL;
+  if (!c->bound) return ALTGDMIN_ESTATE;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(eta, &c->st()->eta, sizeof(double), hipMemcpyDeviceToHost));
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_set_eta(altgdmin_ctx* c, double eta) {
+  if (!c || !isfinite(eta)) return ALTGDMIN_EINVAL;
+  if (!c->bound) return ALTGDMIN_ESTATE;
+  hipLaunchKernelGGL(k_state_set_eta, dim3(1), dim3(1), 0, c->stream, c->st(), eta > 0 ? eta : -1.0);
+  return map_hip(hipGetLastError());
+}
+
+altgdmin_status altgdmin_cost(altgdmin_ctx* c, const void* d_U, double* d_f) {
+  if (!c || !d_U || !d_f) return ALTGDMIN_EINVAL;
+  if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
+  HIPCHK(fwd_transform(c, static_cast<const float2*>(d_U), 0));
+  HIPCHK(gram_solve(c, 0));
+  hipLaunchKernelGGL(k_cost_total, dim3(1), dim3(1), 0, c->stream, c->at<double>(c->o_cost), c->p.q, d_f,
+                     c->st());
+  return map_hip(hipGetLastError());
+}
+
+altgdmin_status altgdmin_gradient(altgdmin_ctx* c, const void* d_U, void* d_B, void* d_G) {
+  if (!c || !d_U) return ALTGDMIN_EINVAL;
+  if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
+  const altgdmin_params& p = c->p;
+  HIPCHK(gradient_pieces(c, static_cast<const float2*>(d_U), 0));
+  if (d_B)
+    hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, c->stream, c->at<float2>(c->o_B),
+                       static_cast<float2*>(d_B), (long)p.q * p.r);
+  if (d_G)
+    hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, c->stream, c->at<float2>(c->o_G),
+                       static_cast<float2*>(d_G), (long)c->n * p.r);
+  return map_hip(hipGetLastError());
+}
+
+altgdmin_status altgdmin_apply_A(altgdmin_ctx* c, const void* d_X, void* d_Y) {
+  if (!c || !d_X || !d_Y) return ALTGDMIN_EINVAL;
+  if (!c->bound) return ALTGDMIN_ESTATE;
+  const altgdmin_params& p = c->p;
+  const float2* X = static_cast<const float2*>(d_X);
+  float2* Y = static_cast<float2*>(d_Y);
+  hipStream_t s = c->stream;
+  if (c->lines) {
+    ColFwdArgs f{};
+    f.src = X;
+    f.src_img_stride = c->n;
+    f.coils = c->coils;
+    f.n = c->n;
+    f.nx = p.nx;
+    f.tw = c->at<float2>(c->o_twy);
+    f.dst = Y;
+    f.dst_c_stride = p.m_max;
+    f.dst_img_stride = (long)p.nc * p.m_max;
+    f.rows = c->mask;
+    f.rows_img_stride = c->width;
+    f.m_k = c->m_k;
+    f.zero_pad_rows = c->lmax;
+    f.scale = (float)(1.0 / sqrt((double)p.ny));
+    f.st = c->st();
+    HIPCHK(launch_cols(p.ny, &f, nullptr, p.nx, p.q, p.nc, s));
+    RowArgs ra{};
+    ra.src = ra.dst = Y;
+    ra.tw = c->at<float2>(c->o_twx);
+    ra.nrows = (long)p.q * p.nc * c->lmax;
+    ra.m_k = c->m_k;
+    ra.nc = p.nc;
+    ra.lmax = c->lmax;
+    ra.scale = (float)(1.0 / sqrt((double)p.nx));
+    ra.st = c->st();
+    HIPCHK(launch_rows(p.nx, ra, false, s));
+    return ALTGDMIN_OK;
+  }
+  float2* T = c->at<float2>(c->o_T) + (size_t)c->n * p.q;
+  for (int k0 = 0; k0 < p.q; k0 += c->kc) {
+    const int kc = std::min(c->kc, p.q - k0);
+    ColFwdArgs f{};
+    f.src = X + (size_t)k0 * c->n;
+    f.src_img_stride = c->n;
+    f.coils = c->coils;
+    f.n = c->n;
+    f.nx = p.nx;
+    f.tw = c->at<float2>(c->o_twy);
+    f.dst = T;
+    f.dst_c_stride = c->n;
+    f.dst_img_stride = (long)p.nc * c->n;
+    f.scale = (float)(1.0 / sqrt((double)p.ny));
+    f.st = c->st();
+    HIPCHK(launch_cols(p.ny, &f, nullptr, p.nx, kc, p.nc, s));
+    RowArgs ra{};
+    ra.src = ra.dst = T;
+    ra.tw = c->at<float2>(c->o_twx);
+    ra.nrows = (long)kc * p.nc * p.ny;
+    ra.scale = (float)(1.0 / sqrt((double)p.nx));
+    ra.st = c->st();
+    HIPCHK(launch_rows(p.nx, ra, false, s));
+    hipLaunchKernelGGL(k_gather, dim3((p.m_max + 255) / 256, kc, p.nc), dim3(256), 0, s, T, (long)c->n,
+                       (long)p.nc * c->n, c->mask, c->m_k, p.m_max, p.nc, k0, Y, c->st());
+    HIPCHK(hipGetLastError());
+  }
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_apply_AH(altgdmin_ctx* c, const void* d_Y, void* d_X) {
+  if (!c || !d_X || !d_Y) return ALTGDMIN_EINVAL;
+  if (!c->bound) return ALTGDMIN_ESTATE;
+  return map_hip(adjoint_op(c, static_cast<const float2*>(d_Y), static_cast<float2*>(d_X), 0, 0));
+}
+
+altgdmin_status altgdmin_get_stats(altgdmin_ctx* c, altgdmin_stats* out) {
+  if (!c || !out) return ALTGDMIN_EINVAL;
+  if (!c->bound) return ALTGDMIN_ESTATE;
+  DevState h;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(&h, c->st(), sizeof(DevState), hipMemcpyDeviceToHost));
+  out->t = h.t;
+  out->exited = h.exited;
+  out->f = h.f;
+  out->sd = h.sd;
+  out->grad_norm = h.grad_norm;
+  out->eta = h.eta;
+  out->gamma = h.gamma;
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_last_error(altgdmin_ctx* c, int32_t* frame) {
+  if (!c) return ALTGDMIN_EINVAL;
+  if (!c->bound) return ALTGDMIN_ESTATE;
+  int32_t v[2];
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(v, c->st(), sizeof(v), hipMemcpyDeviceToHost));
+  if (frame) *frame = v[0] ? v[1] : -1;
+  if (v[0]) {
+    const int32_t z[2] = {0, -1};
+    HIPCHK(hipMemcpy(c->st(), z, sizeof(z), hipMemcpyHostToDevice));
+  }
+  return (altgdmin_status)v[0];
+}
+
+altgdmin_status altgdmin_set_timing(altgdmin_ctx* c, int32_t which) {
+  if (!c || which < 0 || which >= TK_COUNT) return ALTGDMIN_EINVAL;
+  c->timed = which;
+  c->ev_used = 0;
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_kernel_time(altgdmin_ctx* c, const char** name, int32_t* launches, double* total_ms) {
+  if (!c) return ALTGDMIN_EINVAL;
+  if (name) *name = kTimedNames[c->timed];
+  double tot = 0.0;
+  int32_t cnt = 0;
+  if (c->ev_used >= 2) {
+    HIPCHK(hipEventSynchronize(c->ev[c->ev_used - 1]));
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+      tot += ms;
+      ++cnt;
+    }
+  }
+  c->ev_used = 0;
+  if (launches) *launches = cnt;
+  if (total_ms) *total_ms = tot;
+  return ALTGDMIN_OK;
+}
+
+void altgdmin_destroy(altgdmin_ctx* c) {
+  if (!c) return;
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

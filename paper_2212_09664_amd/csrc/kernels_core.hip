@@ -1,0 +1,1061 @@
+// altGDmin kernels other than the transforms: the inverse sampling map,
+// per-frame Gram / right-hand side (the LS step of Algorithm 2), the batched
+// r x r Cholesky solves, the gradient fold, the Gram of the QR step, the
+// small dense r x r / q x q work (Cholesky, triangular inverse, Jacobi
+// eigensolver) and the spectral-initialisation helpers.
+#include "kernels_core.hpp"
+
+namespace ag {
+
+__device__ __forceinline__ void set_error(DevState* st, int code, int frame) {
+  if (atomicCAS(&st->err, 0, code) == 0) st->err_frame = frame;
+  st->halt = 1;
+}
+
+// ===========================================================================
+// setup: inverse sampling map
+// A "location" is a phase-encode line ky (LINES) or a flat k-space index
+// (INDEX).  For every location the list of (frame k, position e) samples
+// that hit it is stored contiguously, in increasing k (deterministic).
+// ===========================================================================
+__global__ void k_inv_bitmap(const int32_t* mask, const int32_t* m_k, int width, int per, int n_loc,
+                             uint32_t* bitmap, int nw, DevState* st) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y;
+  const int mk = m_k[k];
+  if (mk < 0 || mk > width * per || (mk % per) != 0) {
+    if (e == 0) set_error(st, 1 /*EINVAL: bad m_k*/, k);
+    return;
+  }
+  if (e >= mk / per) return;
+  const int loc = mask[(long)k * width + e];
+  if (loc < 0 || loc >= n_loc) {
+    set_error(st, 1 /*EINVAL*/, k);
+    return;
+  }
+  const uint32_t bit = 1u << (k & 31);
+  const uint32_t old = atomicOr(&bitmap[(long)loc * nw + (k >> 5)], bit);
+  if (old & bit) set_error(st, 1 /*EINVAL: repeated location in a frame*/, k);
+}
+
+__global__ __launch_bounds__(1024) void k_inv_scan(const uint32_t* bitmap, int nw, int n_loc,
+                                                   int32_t* loc_ptr, int32_t* loc2unit,
+                                                   int32_t* unit_loc, DevState* st) {
+  __shared__ int s_cnt[1024], s_un[1024];
+  const int tid = threadIdx.x;
+  const int chunk = (n_loc + 1023) / 1024;
+  const int a = tid * chunk, b = min(n_loc, a + chunk);
+  int cnt = 0, un = 0;
+  for (int l = a; l < b; ++l) {
+    int c = 0;
+    for (int w = 0; w < nw; ++w) c += __popc(bitmap[(long)l * nw + w]);
+    cnt += c;
+    un += (c > 0);
+  }
+  s_cnt[tid] = cnt;
+  s_un[tid] = un;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
+    int vc = (tid >= off) ? s_cnt[tid - off] : 0;
+    int vu = (tid >= off) ? s_un[tid - off] : 0;
+    __syncthreads();
+    s_cnt[tid] += vc;
+    s_un[tid] += vu;
+    __syncthreads();
+  }
+  int pc = s_cnt[tid] - cnt, pu = s_un[tid] - un;
+  for (int l = a; l < b; ++l) {
+    int c = 0;
+    for (int w = 0; w < nw; ++w) c += __popc(bitmap[(long)l * nw + w]);
+    loc_ptr[l] = pc;
+    if (c > 0) {
+      loc2unit[l] = pu;
+      unit_loc[pu] = l;
+      ++pu;
+    } else {
+      loc2unit[l] = -1;
+    }
+    pc += c;
+  }
+  if (tid == 1023) {
+    loc_ptr[n_loc] = s_cnt[1023];
+    st->n_units = s_un[1023];
+  }
+}
+
+__global__ void k_inv_fill(const int32_t* mask, const int32_t* m_k, int width, int per,
+                           const uint32_t* bitmap, int nw, const int32_t* loc_ptr, int2* pairs,
+                           int32_t* pair_of, const DevState* st) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y;
+  if (st->err) return;
+  if (e >= m_k[k] / per) return;
+  const int loc = mask[(long)k * width + e];
+  const uint32_t* bm = bitmap + (long)loc * nw;
+  int rank = 0;
+  for (int w = 0; w < (k >> 5); ++w) rank += __popc(bm[w]);
+  rank += __popc(bm[k >> 5] & ((1u << (k & 31)) - 1u));
+  const int pos = loc_ptr[loc] + rank;
+  pairs[pos] = make_int2(k, e);
+  pair_of[(long)k * width + e] = pos;
+}
+
+// ||y_k||^2 in FP64, one workgroup per frame
+__global__ __launch_bounds__(AG_NT) void k_ysq(const float2* y, const int32_t* m_k, int nc, int m_max,
+                                               double* ysq_k) {
+  __shared__ double red[AG_NT];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int mk = m_k[k];
+  double s = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    const float2* yk = y + ((long)k * nc + c) * m_max;
+    for (int i = tid; i < mk; i += AG_NT) {
+      float2 v = yk[i];
+      s += (double)v.x * v.x + (double)v.y * v.y;
+    }
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int off = AG_NT / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) ysq_k[k] = red[0];
+}
+
+// gamma = trunc_c * sum |y|^2 / (m q), m = max_k m_k; mbar = sum_k m_k / q
+__global__ void k_init_stats(const double* ysq_k, const int32_t* m_k, int q, double trunc_c, DevState* st) {
+  if (threadIdx.x != 0) return;
+  double ys = 0.0, msum = 0.0;
+  int mmax = 0;
+  for (int k = 0; k < q; ++k) {
+    ys += ysq_k[k];
+    msum += m_k[k];
+    mmax = max(mmax, m_k[k]);
+  }
+  st->ysq = ys;
+  st->mbar = msum / q;
+  st->gamma = trunc_c > 0 ? trunc_c * ys / ((double)mmax * q) : INFINITY;
+}
+
+__global__ void k_state_reset(DevState* st, int full) {
+  if (threadIdx.x != 0) return;
+  if (full) {
+    st->err = 0;
+    st->err_frame = -1;
+    st->n_units = 0;
+  }
+  st->halt = 0;
+  st->step_ok = 0;
+  st->t = 0;
+  st->exited = 0;
+  st->converged = 0;
+  st->eta = -1.0;
+  st->f = 0.0;
+  st->sd = 0.0;
+  st->grad_norm = 0.0;
+}
+
+__global__ void k_state_set_eta(DevState* st, double eta) {
+  if (threadIdx.x == 0) st->eta = eta;
+}
+
+// ===========================================================================
+// per-frame Gram and right-hand side, 1D Cartesian (hybrid ky, x form)
+// For each sampled line (unit u, phase-encode ky):
+//   P_u  = sum_{c,x} W_c(u,x,:)^H W_c(u,x,:)                  (r x r)
+//   hp_p = sum_{c,x} conj(W_c(u,x,:)) y'_{k,c}(l,x)            per sample (k,l) of ky
+// so that G_k = sum_{l} P_{u(k,l)} and h_k = sum_l hp_{(k,l)}.
+// Rows of W_c(u,:,:) and the samples' y' rows are staged in LDS; every
+// thread owns a few outputs and forms their dot products over x.
+// ===========================================================================
+__device__ __forceinline__ void tri_index(int o, int r, int& i, int& j) {
+  i = 0;
+  int rem = o;
+  while (rem >= r - i) {
+    rem -= r - i;
+    ++i;
+  }
+  j = i + rem;
+}
+
+template <typename ACC>
+struct Acc2;
+template <>
+struct Acc2<float> {
+  using T = float2;
+  __device__ static T zero() { return make_float2(0.f, 0.f); }
+  __device__ static T fma_cj(T acc, float2 a, float2 b) {  // acc + conj(a) b
+    acc.x += a.x * b.x + a.y * b.y;
+    acc.y += a.x * b.y - a.y * b.x;
+    return acc;
+  }
+  __device__ static double2 to_d(T v) { return f2d(v); }
+};
+template <>
+struct Acc2<double> {
+  using T = double2;
+  __device__ static T zero() { return make_double2(0.0, 0.0); }
+  __device__ static T fma_cj(T acc, float2 a, float2 b) {
+    const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+    acc.x += ax * bx + ay * by;
+    acc.y += ax * by - ay * bx;
+    return acc;
+  }
+  __device__ static double2 to_d(T v) { return v; }
+};
+
+template <typename ACC>
+__global__ __launch_bounds__(AG_NT) void k_gram_lines(GramLinesArgs a) {
+  using A2 = Acc2<ACC>;
+  extern __shared__ float2 sm[];
+  const int u = blockIdx.x, tid = threadIdx.x;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (u >= a.st->n_units) return;
+  const int r = a.r, nx = a.nx, XC = a.xc, PC = a.pc;
+  float2* Ws = sm;            // [XC][r]
+  float2* Ys = sm + XC * r;   // [PC][XC]
+  const int ky = a.unit_loc[u];
+  const int p0 = a.loc_ptr[ky], np = a.loc_ptr[ky + 1] - p0;
+  const int nP = r * (r + 1) / 2;
+  for (int pc = 0; pc == 0 || pc < np; pc += PC) {
+    const int npc = min(PC, np - pc);
+    const int nPo = (pc == 0) ? nP : 0;
+    const int nout = nPo + npc * r;
+    typename A2::T acc[GRAM_OPT];
+#pragma unroll
+    for (int t = 0; t < GRAM_OPT; ++t) acc[t] = A2::zero();
+    for (int c = 0; c < a.nc; ++c) {
+      for (int x0 = 0; x0 < nx; x0 += XC) {
+        for (int g = tid; g < XC * r; g += AG_NT) {
+          const int j = g / XC, x = g % XC;
+          Ws[x * r + j] = a.W[(((long)c * r + j) * a.ua + u) * nx + x0 + x];
+        }
+        for (int g = tid; g < npc * XC; g += AG_NT) {
+          const int p = g / XC, x = g % XC;
+          const int2 kl = a.pairs[p0 + pc + p];
+          Ys[p * XC + x] = a.yh[(((long)kl.x * a.nc + c) * a.lmax + kl.y) * nx + x0 + x];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < GRAM_OPT; ++t) {
+          const int o = tid + t * AG_NT;
+          if (o < nout) {
+            if (o < nPo) {
+              int i, j;
+              tri_index(o, r, i, j);
+              for (int x = 0; x < XC; ++x) acc[t] = A2::fma_cj(acc[t], Ws[x * r + i], Ws[x * r + j]);
+            } else {
+              const int oo = o - nPo, p = oo / r, j = oo % r;
+              for (int x = 0; x < XC; ++x) acc[t] = A2::fma_cj(acc[t], Ws[x * r + j], Ys[p * XC + x]);
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < GRAM_OPT; ++t) {
+      const int o = tid + t * AG_NT;
+      if (o < nout) {
+        double2 v = A2::to_d(acc[t]);
+        if (o < nPo) {
+          int i, j;
+          tri_index(o, r, i, j);
+          a.P[((long)u * r + i) * r + j] = v;
+          a.P[((long)u * r + j) * r + i] = dconj(v);
+        } else {
+          const int oo = o - nPo, p = oo / r, j = oo % r;
+          a.hp[(long)(p0 + pc + p) * r + j] = v;
+        }
+      }
+    }
+  }
+}
+
+// ===========================================================================
+// per-frame Gram and right-hand side, general masks: directly per frame,
+// over chunks of the frame's samples (partials per chunk).
+// ===========================================================================
+template <typename ACC>
+__global__ __launch_bounds__(AG_NT) void k_gram_index(GramIndexArgs a) {
+  using A2 = Acc2<ACC>;
+  __shared__ float2 Ws[AG_NT * 16];
+  __shared__ float2 ys[AG_NT];
+  const int k = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  const int r = a.r;
+  const int nP = r * (r + 1) / 2, nout = nP + r;
+  const int mk = a.m_k[k];
+  const int i0 = ch * AG_NT;
+  typename A2::T acc[GRAM_OPT];
+#pragma unroll
+  for (int t = 0; t < GRAM_OPT; ++t) acc[t] = A2::zero();
+  const int i = i0 + tid;
+  const int loc = (i < mk) ? a.mask[(long)k * a.m_max + i] : -1;
+  for (int c = 0; c < a.nc; ++c) {
+    for (int j = 0; j < r; ++j)
+      Ws[tid * r + j] = (loc >= 0) ? a.W[((long)c * r + j) * a.n + loc] : make_float2(0.f, 0.f);
+    ys[tid] = (loc >= 0) ? a.y[((long)k * a.nc + c) * a.m_max + i] : make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < GRAM_OPT; ++t) {
+      const int o = tid + t * AG_NT;
+      if (o < nout) {
+        if (o < nP) {
+          int ii, jj;
+          tri_index(o, r, ii, jj);
+          for (int x = 0; x < AG_NT; ++x) acc[t] = A2::fma_cj(acc[t], Ws[x * r + ii], Ws[x * r + jj]);
+        } else {
+          const int jj = o - nP;
+          for (int x = 0; x < AG_NT; ++x) acc[t] = A2::fma_cj(acc[t], Ws[x * r + jj], ys[x]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < GRAM_OPT; ++t) {
+    const int o = tid + t * AG_NT;
+    if (o < nout) a.part[((long)k * gridDim.x + ch) * nout + o] = A2::to_d(acc[t]);
+  }
+}
+
+// ===========================================================================
+// batched LS solve: b_k = G_k^{-1} h_k by Cholesky, one wavefront per frame;
+// also cost_k = ||y_k||^2 - Re(h_k^H b_k).
+// ===========================================================================
+template <typename T>
+struct Cx;
+template <>
+struct Cx<float> {
+  using T2 = float2;
+  __device__ static T2 from(double2 v) { return d2f(v); }
+  __device__ static T2 mul(T2 a, T2 b) { return cmul(a, b); }
+  __device__ static T2 cjm(T2 a, T2 b) { return cjmul(a, b); }
+  __device__ static T2 sub(T2 a, T2 b) { return csub(a, b); }
+  __device__ static T2 scale(T2 a, float s) { return cscale(a, s); }
+  __device__ static T2 zero() { return make_float2(0.f, 0.f); }
+  static constexpr double tiny = 1e-6;
+};
+template <>
+struct Cx<double> {
+  using T2 = double2;
+  __device__ static T2 from(double2 v) { return v; }
+  __device__ static T2 mul(T2 a, T2 b) { return dmul(a, b); }
+  __device__ static T2 cjm(T2 a, T2 b) { return djmul(a, b); }
+  __device__ static T2 sub(T2 a, T2 b) { return dsub(a, b); }
+  __device__ static T2 scale(T2 a, double s) { return make_double2(a.x * s, a.y * s); }
+  __device__ static T2 zero() { return make_double2(0.0, 0.0); }
+  static constexpr double tiny = 1e-13;
+};
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
+  using C = Cx<T>;
+  using T2 = typename C::T2;
+  __shared__ T2 G[16 * 16];
+  __shared__ T2 h[16];
+  __shared__ T2 z[16];
+  __shared__ int bad;
+  const int k = blockIdx.x, tid = threadIdx.x, r = a.r;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (tid == 0) bad = 0;
+  if (a.kind == 0) {  // LINES: sum the per-line Grams and per-sample rhs
+    const int L = a.m_k[k] / a.nx;
+    const int32_t* mk = a.mask + (long)k * a.width;
+    const int32_t* po = a.pair_of + (long)k * a.width;
+    for (int e = tid; e < r * r; e += 64) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int l = 0; l < L; ++l) s = dadd(s, a.P[(long)a.loc2unit[mk[l]] * r * r + e]);
+      G[(e / r) * 16 + (e % r)] = C::from(s);
+    }
+    for (int j = tid; j < r; j += 64) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int l = 0; l < L; ++l) s = dadd(s, a.hp[(long)po[l] * r + j]);
+      h[j] = C::from(s);
+    }
+  } else {  // INDEX: sum the chunk partials
+    const int nP = r * (r + 1) / 2, nout = nP + r;
+    for (int o = tid; o < nout; o += 64) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int ch = 0; ch < a.nchunks; ++ch) s = dadd(s, a.P[((long)k * a.nchunks + ch) * nout + o]);
+      if (o < nP) {
+        int i, j;
+        tri_index(o, r, i, j);
+        G[i * 16 + j] = C::from(s);
+        G[j * 16 + i] = C::from(dconj(s));
+      } else {
+        h[o - nP] = C::from(s);
+      }
+    }
+  }
+  __syncthreads();
+  // right-looking Cholesky G = L L^H (lower part of G overwritten by L)
+  double dmax = 0.0;
+  for (int i = 0; i < r; ++i) dmax = fmax(dmax, (double)G[i * 16 + i].x);
+  for (int j = 0; j < r; ++j) {
+    const double d = (double)G[j * 16 + j].x;
+    if (!(d > C::tiny * dmax) || !isfinite(d)) {
+      if (tid == 0) bad = 1;
+    }
+    __syncthreads();
+    if (bad) break;
+    const T ljj = (T)sqrt(d);
+    if (tid == 0) G[j * 16 + j] = T2{ljj, (T)0};
+    for (int i = j + 1 + tid; i < r; i += 64) G[i * 16 + j] = C::scale(G[i * 16 + j], (T)1 / ljj);
+    __syncthreads();
+    const int m = r - j - 1;
+    for (int e = tid; e < m * m; e += 64) {
+      const int i = j + 1 + e / m, c2 = j + 1 + e % m;
+      if (c2 <= i) {
+        // G[i][c2] -= L[i][j] conj(L[c2][j])
+        T2 lij = G[i * 16 + j], lcj = G[c2 * 16 + j];
+        T2 prod = C::mul(lij, T2{lcj.x, -lcj.y});
+        G[i * 16 + c2] = C::sub(G[i * 16 + c2], prod);
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) set_error(a.st, 4 /*ENOTPD*/, k);
+    return;
+  }
+  if (tid == 0) {
+    for (int i = 0; i < r; ++i) {  // L z = h
+      T2 s = h[i];
+      for (int m = 0; m < i; ++m) s = C::sub(s, C::mul(G[i * 16 + m], z[m]));
+      z[i] = C::scale(s, (T)1 / G[i * 16 + i].x);
+    }
+    for (int i = r - 1; i >= 0; --i) {  // L^H b = z
+      T2 s = z[i];
+      for (int m = i + 1; m < r; ++m) s = C::sub(s, C::cjm(G[m * 16 + i], z[m]));
+      z[i] = C::scale(s, (T)1 / G[i * 16 + i].x);
+    }
+    double hb = 0.0;
+    bool fin = true;
+    for (int j = 0; j < r; ++j) {
+      // Re(conj(h_j) b_j)
+      hb += (double)h[j].x * (double)z[j].x + (double)h[j].y * (double)z[j].y;
+      fin = fin && isfinite((double)z[j].x) && isfinite((double)z[j].y);
+      a.B[(long)k * r + j] = make_float2((float)z[j].x, (float)z[j].y);
+    }
+    a.cost_k[k] = a.ysq_k[k] - hb;
+    if (!fin) set_error(a.st, 5 /*ENONFINITE*/, k);
+  }
+}
+
+// ===========================================================================
+// gradient fold, 1D Cartesian: per sampled line u (ky) and coil c
+//   K_c(u,x,:) = W_c(u,x,:) S_u - sum_{(k,l) on ky} y'_{k,c}(l,x) conj(b_k),
+//   S_u = sum_{(k,l) on ky} b_k b_k^H.
+// ===========================================================================
+template <int RT>
+__global__ __launch_bounds__(AG_NT) void k_fold_lines(FoldArgs a) {
+  __shared__ float2 S[RT * RT];
+  __shared__ float2 bc[128 * RT];
+  __shared__ int2 kl[128];
+  const int u = blockIdx.x, tid = threadIdx.x;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (u >= a.st->n_units) return;
+  const int r = a.r, nx = a.nx;
+  const int ky = a.unit_loc[u];
+  const int p0 = a.loc_ptr[ky], np = a.loc_ptr[ky + 1] - p0;
+  for (int e = tid; e < np; e += AG_NT) kl[e] = a.pairs[p0 + e];
+  __syncthreads();
+  for (int e = tid; e < np * r; e += AG_NT) {
+    const int p = e / r, j = e % r;
+    float2 b = a.B[(long)kl[p].x * r + j];
+    bc[p * RT + j] = make_float2(b.x, -b.y);
+  }
+  for (int e = tid; e < r * r; e += AG_NT) {
+    const int i = e / r, j = e % r;
+    float2 s = make_float2(0.f, 0.f);
+    for (int p = 0; p < np; ++p) {
+      const float2* b = a.B + (long)kl[p].x * r;
+      s = cadd(s, cmulj(b[i], b[j]));
+    }
+    S[i * RT + j] = s;
+  }
+  __syncthreads();
+  const int c0 = blockIdx.y * a.cg;
+  const int c1 = min(a.nc, c0 + a.cg);
+  for (int g = tid; g < (c1 - c0) * nx; g += AG_NT) {
+    const int c = c0 + g / nx, x = g % nx;
+    float2 w[RT], kk[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) w[i] = (i < r) ? a.W[(((long)c * r + i) * a.ua + u) * nx + x] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+      float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+        if (i < r) s = cadd(s, cmul(w[i], S[i * RT + j]));
+      kk[j] = s;
+    }
+    for (int p = 0; p < np; ++p) {
+      const float2 yv = a.yh[(((long)kl[p].x * a.nc + c) * a.lmax + kl[p].y) * nx + x];
+#pragma unroll
+      for (int j = 0; j < RT; ++j) kk[j] = csub(kk[j], cmul(yv, bc[p * RT + j]));
+    }
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+      if (j < r) a.K[(((long)c * r + j) * a.ua + u) * nx + x] = kk[j];
+  }
+}
+
+// gradient fold, general masks: per location and coil,
+//   K_c(loc,:) = sum_{(k,e) at loc} (W_c(loc,:) b_k - y_{k,c}(e)) conj(b_k)
+template <int RT>
+__global__ __launch_bounds__(AG_NT) void k_fold_index(FoldArgs a) {
+  const int loc = blockIdx.x * AG_NT + threadIdx.x, c = blockIdx.y;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (loc >= a.n) return;
+  const int r = a.r;
+  float2 w[RT], kk[RT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i) {
+    w[i] = (i < r) ? a.W[((long)c * r + i) * a.n + loc] : make_float2(0.f, 0.f);
+    kk[i] = make_float2(0.f, 0.f);
+  }
+  const int p0 = a.loc_ptr[loc], p1 = a.loc_ptr[loc + 1];
+  for (int p = p0; p < p1; ++p) {
+    const int2 ke = a.pairs[p];
+    const float2* b = a.B + (long)ke.x * r;
+    float2 bb[RT];
+    float2 res = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      bb[i] = (i < r) ? b[i] : make_float2(0.f, 0.f);
+      res = cadd(res, cmul(w[i], bb[i]));
+    }
+    res = csub(res, a.y[((long)ke.x * a.nc + c) * a.m_max + ke.y]);
+#pragma unroll
+    for (int j = 0; j < RT; ++j) kk[j] = cadd(kk[j], cmulj(res, bb[j]));
+  }
+#pragma unroll
+  for (int j = 0; j < RT; ++j)
+    if (j < r) a.K[((long)c * r + j) * a.n + loc] = kk[j];
+}
+
+// ===========================================================================
+// Gram of column blocks: C = [A B]^H [A B] over n rows (column-major n x m1
+// and n x m2), upper triangle, partial sums per workgroup in FP64.
+// ===========================================================================
+template <typename ACC>
+__global__ __launch_bounds__(AG_NT) void k_gram_cols(GramColsArgs a) {
+  using A2 = Acc2<ACC>;
+  __shared__ float2 Xs[64 * 64];
+  const int tid = threadIdx.x, blk = blockIdx.x;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  const int m = a.m1 + a.m2;
+  const int nout = m * (m + 1) / 2;
+  typename A2::T acc[GCOLS_OPT];
+#pragma unroll
+  for (int t = 0; t < GCOLS_OPT; ++t) acc[t] = A2::zero();
+  const long pa = (long)blk * a.rows_per_block;
+  const long pb = min((long)a.n, pa + a.rows_per_block);
+  for (long p0 = pa; p0 < pb; p0 += 64) {
+    const int np = (int)min((long)64, pb - p0);
+    for (int g = tid; g < 64 * m; g += AG_NT) {
+      const int j = g / 64, pp = g % 64;
+      float2 v = make_float2(0.f, 0.f);
+      if (pp < np) v = (j < a.m1) ? a.A[(long)j * a.n + p0 + pp] : a.B[(long)(j - a.m1) * a.n + p0 + pp];
+      Xs[pp * m + j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < GCOLS_OPT; ++t) {
+      const int o = tid + t * AG_NT;
+      if (o < nout) {
+        int i, j;
+        tri_index(o, m, i, j);
+        for (int pp = 0; pp < np; ++pp) acc[t] = A2::fma_cj(acc[t], Xs[pp * m + i], Xs[pp * m + j]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < GCOLS_OPT; ++t) {
+    const int o = tid + t * AG_NT;
+    if (o < nout) a.part[(long)blk * nout + o] = A2::to_d(acc[t]);
+  }
+}
+
+// ===========================================================================
+// small dense FP64 routines for one workgroup (matrices in LDS, leading
+// dimension ld).
+// ===========================================================================
+__device__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  double s = red[0];
+  __syncthreads();
+  return s;
+}
+
+// Cyclic Jacobi eigen-decomposition of the Hermitian n x n matrix A (LDS,
+// overwritten: eigenvalues end on the diagonal).  Disjoint pairs are rotated
+// together (round-robin ordering); each 2 x 2 rotation removes the phase of
+// A_pq and then applies the real symmetric Jacobi rotation.  V (global
+// memory, row-major n x n, row i owned by thread i) accumulates the
+// eigenvectors as columns when non-null.
+__device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch* js, int max_sweeps) {
+  const int tid = threadIdx.x, NT = blockDim.x;
+  if (V && tid < n)
+    for (int j = 0; j < n; ++j) V[(long)tid * n + j] = make_double2(tid == j ? 1.0 : 0.0, 0.0);
+  const int Q = n + (n & 1);
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < n * n; e += NT) {
+      const int i = e / n, j = e % n;
+      const double2 v = A[i * ld + j];
+      const double m2 = v.x * v.x + v.y * v.y;
+      tot += m2;
+      if (i != j) off += m2;
+    }
+    off = block_sum(off, js->red);
+    tot = block_sum(tot, js->red);
+    if (!(off > 1e-30 * tot)) break;
+    for (int s = 0; s < Q - 1; ++s) {
+      for (int i = tid; i < Q / 2; i += NT) {
+        int p, q;
+        if (i == 0) {
+          p = Q - 1;
+          q = s;
+        } else {
+          p = (s + i) % (Q - 1);
+          q = (s - i + Q - 1) % (Q - 1);
+        }
+        if (p > q) {
+          int t = p;
+          p = q;
+          q = t;
+        }
+        js->p[i] = p;
+        js->q[i] = q;
+        double c = 1.0, sn = 0.0;
+        double2 e = make_double2(1.0, 0.0);
+        if (q < n) {
+          const double2 apq = A[p * ld + q];
+          const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+          const double app = A[p * ld + p].x, aqq = A[q * ld + q].x;
+          if (mag > 1e-300 && mag > 1e-18 * (fabs(app) + fabs(aqq))) {
+            e = make_double2(apq.x / mag, -apq.y / mag);  // exp(-i phi)
+            const double tau = (aqq - app) / (2.0 * mag);
+            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+          }
+        }
+        js->c[i] = c;
+        js->s[i] = sn;
+        js->e[i] = e;
+      }
+      __syncthreads();
+      // A <- A G  (columns p, q)
+      for (int it = tid; it < n * (Q / 2); it += NT) {
+        const int i = it / n, k = it % n;
+        const int p = js->p[i], q = js->q[i];
+        if (q >= n || js->s[i] == 0.0) continue;
+        const double c = js->c[i], sn = js->s[i];
+        const double2 e = js->e[i];
+        const double2 x = A[k * ld + p], y = dmul(A[k * ld + q], e);
+        A[k * ld + p] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+        A[k * ld + q] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+      }
+      __syncthreads();
+      // A <- G^H A  (rows p, q)
+      for (int it = tid; it < n * (Q / 2); it += NT) {
+        const int i = it / n, k = it % n;
+        const int p = js->p[i], q = js->q[i];
+        if (q >= n || js->s[i] == 0.0) continue;
+        const double c = js->c[i], sn = js->s[i];
+        const double2 e = dconj(js->e[i]);
+        const double2 x = A[p * ld + k], y = dmul(A[q * ld + k], e);
+        A[p * ld + k] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+        A[q * ld + k] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+      }
+      if (V && tid < n) {
+        for (int i = 0; i < Q / 2; ++i) {
+          const int p = js->p[i], q = js->q[i];
+          if (q >= n || js->s[i] == 0.0) continue;
+          const double c = js->c[i], sn = js->s[i];
+          const double2 e = js->e[i];
+          const double2 x = V[(long)tid * n + p], y = dmul(V[(long)tid * n + q], e);
+          V[(long)tid * n + p] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+          V[(long)tid * n + q] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Cholesky of the Hermitian r x r matrix M (LDS, ld 16) in FP64, lower L in
+// place; then R = L^H and Rinv = R^{-1} (upper triangular) into Ri.  Run by
+// one thread.  Returns false if M is not positive definite.
+__device__ bool chol_rinv(double2* M, int r, double2* Ri) {
+  double dmax = 0.0;
+  for (int i = 0; i < r; ++i) dmax = fmax(dmax, M[i * 16 + i].x);
+  for (int j = 0; j < r; ++j) {
+    double d = M[j * 16 + j].x;
+    for (int m = 0; m < j; ++m) d -= M[j * 16 + m].x * M[j * 16 + m].x + M[j * 16 + m].y * M[j * 16 + m].y;
+    if (!(d > 1e-14 * dmax) || !isfinite(d)) return false;
+    const double ljj = sqrt(d);
+    M[j * 16 + j] = make_double2(ljj, 0.0);
+    for (int i = j + 1; i < r; ++i) {
+      double2 s = M[i * 16 + j];
+      for (int m = 0; m < j; ++m) s = dsub(s, dmul(M[i * 16 + m], dconj(M[j * 16 + m])));
+      M[i * 16 + j] = make_double2(s.x / ljj, s.y / ljj);
+    }
+  }
+  // R = L^H upper; Rinv upper with R Rinv = I, column by column
+  for (int j = 0; j < r; ++j) {
+    for (int i = j + 1; i < r; ++i) Ri[i * 16 + j] = make_double2(0.0, 0.0);
+    Ri[j * 16 + j] = make_double2(1.0 / M[j * 16 + j].x, 0.0);
+    for (int i = j - 1; i >= 0; --i) {
+      // sum_{m=i+1..j} R[i][m] Rinv[m][j], R[i][m] = conj(L[m][i])
+      double2 s = make_double2(0.0, 0.0);
+      for (int m = i + 1; m <= j; ++m) s = dadd(s, dmul(dconj(M[m * 16 + i]), Ri[m * 16 + j]));
+      Ri[i * 16 + j] = make_double2(-s.x / M[i * 16 + i].x, -s.y / M[i * 16 + i].x);
+    }
+  }
+  return true;
+}
+
+// ===========================================================================
+// the QR step's small work (one workgroup): reduce the Gram partials of
+// [U grad]; at the first iteration set eta = eta_c / sigma_max(grad) (with
+// the stationarity guard and the optional cap); Gram of Uhat = U - eta grad
+// from the blocks; R = chol(.)^H, R^{-1}; SD(U, U+) from r x r data.
+// mode 1: plain CholeskyQR of U (no gradient).
+// ===========================================================================
+__global__ __launch_bounds__(AG_NT) void k_qr_small(QrSmallArgs a) {
+  __shared__ double2 UU[256], UG[256], GG[256], Gh[256], Ri[256], Tm[256];
+  __shared__ JacobiScratch js;
+  __shared__ int s_ok;
+  const int tid = threadIdx.x, r = a.r;
+  DevState* st = a.st;
+  if (st->err || (a.mode == 0 && a.check_halt && st->halt)) {
+    if (tid == 0 && a.mode == 0) st->step_ok = 0;
+    return;
+  }
+  const int m = a.mode == 0 ? 2 * r : r;
+  const int nout = m * (m + 1) / 2;
+  for (int o = tid; o < nout; o += AG_NT) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int b = 0; b < a.nblk; ++b) s = dadd(s, a.part[(long)b * nout + o]);
+    int i, j;
+    tri_index(o, m, i, j);
+    // entry (i, j), i <= j, of [U G]^H [U G]
+    if (j < r) {
+      UU[i * 16 + j] = s;
+      UU[j * 16 + i] = dconj(s);
+    } else if (i < r) {
+      UG[i * 16 + (j - r)] = s;  // (U^H G)[i][j-r]
+    } else {
+      GG[(i - r) * 16 + (j - r)] = s;
+      GG[(j - r) * 16 + (i - r)] = dconj(s);
+    }
+  }
+  __syncthreads();
+  if (a.mode == 1) {
+    if (tid == 0) {
+      for (int e = 0; e < 256; ++e) Gh[e] = UU[e];
+      s_ok = chol_rinv(Gh, r, Ri);
+      if (!s_ok) set_error(st, 4, -1);
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) a.rinv[i * r + j] = d2f(Ri[i * 16 + j]);
+    }
+    return;
+  }
+  // first iteration: step size from the spectral norm of grad
+  if (st->eta <= 0.0) {
+    for (int e = tid; e < 256; e += AG_NT) Tm[e] = GG[e];
+    __syncthreads();
+    jacobi_eig(Tm, r, 16, nullptr, &js, 40);
+    __syncthreads();
+    if (tid == 0) {
+      double lam = 0.0;
+      for (int i = 0; i < r; ++i) lam = fmax(lam, Tm[i * 16 + i].x);
+      const double smax = sqrt(lam);
+      st->grad_norm = smax;
+      if (!(smax > a.guard * st->ysq)) {
+        st->converged = 1;
+        st->halt = 1;
+        st->step_ok = 0;
+        s_ok = 0;
+      } else {
+        st->eta = a.eta_c / smax;
+        s_ok = 1;
+      }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    if (a.eta_cap_c > 0.0) {  // cap: eta <= c n / (mbar ||B_0||_2^2)
+      for (int e = tid; e < r * r; e += AG_NT) {
+        const int i = e / r, j = e % r;
+        double2 s = make_double2(0.0, 0.0);
+        for (int k = 0; k < a.q; ++k) s = dadd(s, dmul(f2d(a.B[(long)k * r + i]), dconj(f2d(a.B[(long)k * r + j]))));
+        Tm[i * 16 + j] = s;
+      }
+      __syncthreads();
+      jacobi_eig(Tm, r, 16, nullptr, &js, 40);
+      __syncthreads();
+      if (tid == 0) {
+        double lam = 0.0;
+        for (int i = 0; i < r; ++i) lam = fmax(lam, Tm[i * 16 + i].x);
+        const double cap = a.eta_cap_c * (double)a.n / (st->mbar * lam);
+        if (cap < st->eta) st->eta = cap;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    const double eta = st->eta;
+    // Gram of Uhat = U - eta G
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) {
+        const double2 ug = UG[i * 16 + j], gu = dconj(UG[j * 16 + i]);
+        const double2 v = UU[i * 16 + j];
+        const double2 g = GG[i * 16 + j];
+        Gh[i * 16 + j] = make_double2(v.x - eta * (ug.x + gu.x) + eta * eta * g.x,
+                                      v.y - eta * (ug.y + gu.y) + eta * eta * g.y);
+      }
+    s_ok = chol_rinv(Gh, r, Ri);
+    if (!s_ok) {
+      set_error(st, 4, -1);
+      st->step_ok = 0;
+    } else {
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) a.rinv[i * r + j] = d2f(Ri[i * 16 + j]);
+      // U^H U+ = (U^H U - eta U^H G) Rinv; SD^2 = r - ||U^H U+||_F^2
+      double fro = 0.0;
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) {
+          double2 s = make_double2(0.0, 0.0);
+          for (int mm = 0; mm <= j; ++mm) {
+            const double2 lhs = make_double2(UU[i * 16 + mm].x - eta * UG[i * 16 + mm].x,
+                                             UU[i * 16 + mm].y - eta * UG[i * 16 + mm].y);
+            s = dadd(s, dmul(lhs, Ri[mm * 16 + j]));
+          }
+          fro += s.x * s.x + s.y * s.y;
+        }
+      const double sd2 = fmax(0.0, (double)r - fro);
+      double tr = 0.0;
+      for (int i = 0; i < r; ++i) tr += GG[i * 16 + i].x;
+      double f = 0.0;
+      for (int k = 0; k < a.q; ++k) f += a.cost_k[k];
+      st->sd = sqrt(sd2);
+      st->grad_norm = sqrt(tr);
+      st->f = f;
+      st->t += 1;
+      st->step_ok = 1;
+      if (a.eps_exit > 0.0 && sqrt(sd2 / r) < a.eps_exit) {
+        st->exited = 1;
+        st->halt = 1;
+      }
+    }
+  }
+}
+
+// U <- (U - eta grad) Rinv per pixel (mode 0, when the step is applied), or
+// U <- U Rinv (mode 1).  Optionally keeps U before the update.
+template <int RT>
+__global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
+  __shared__ float2 Ri[RT * RT];
+  const int tid = threadIdx.x;
+  const long p = (long)blockIdx.x * AG_NT + tid;
+  if (a.mode == 0 && !a.st->step_ok) return;
+  if (a.st->err) return;
+  const int r = a.r;
+  for (int e = tid; e < r * r; e += AG_NT) Ri[(e / r) * RT + (e % r)] = a.rinv[e];
+  __syncthreads();
+  if (p >= a.n) return;
+  const float eta = (a.mode == 0) ? (float)a.st->eta : 0.f;
+  float2 uh[RT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i) {
+    if (i < r) {
+      float2 u = a.U[(long)i * a.n + p];
+      if (a.U_prev) a.U_prev[(long)i * a.n + p] = u;
+      if (a.mode == 0) {
+        const float2 g = a.G[(long)i * a.n + p];
+        u = make_float2(u.x - eta * g.x, u.y - eta * g.y);
+      }
+      uh[i] = u;
+    } else {
+      uh[i] = make_float2(0.f, 0.f);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RT; ++j) {
+    if (j < r) {
+      float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i <= j; ++i) s = cadd(s, cmul(uh[i], Ri[i * RT + j]));
+      a.U[(long)j * a.n + p] = s;
+    }
+  }
+}
+
+// ===========================================================================
+// spectral initialisation: eigen-decomposition of X_0^H X_0 (q x q) and the
+// scaled top-r eigenvectors V_r Sigma_r^{-1}, so that X_0 V_r Sigma_r^{-1}
+// are the top-r left singular vectors of X_0.
+// ===========================================================================
+__global__ __launch_bounds__(AG_NT) void k_init_eig(InitEigArgs a) {
+  extern __shared__ double2 A[];  // q x q
+  __shared__ JacobiScratch js;
+  __shared__ int idx[16];
+  __shared__ double lam_s[16];
+  const int tid = threadIdx.x, q = a.q, r = a.r;
+  const int nout = q * (q + 1) / 2;
+  for (int o = tid; o < nout; o += AG_NT) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int b = 0; b < a.nblk; ++b) s = dadd(s, a.part[(long)b * nout + o]);
+    int i, j;
+    tri_index(o, q, i, j);
+    A[i * q + j] = s;
+    A[j * q + i] = dconj(s);
+  }
+  __syncthreads();
+  if (tid < q) A[tid * q + tid].y = 0.0;
+  __syncthreads();
+  jacobi_eig(A, q, q, a.V, &js, 60);
+  __syncthreads();
+  if (tid == 0) {
+    // top-r eigenvalues, descending
+    for (int j = 0; j < r; ++j) {
+      int best = -1;
+      double bv = -INFINITY;
+      for (int i = 0; i < q; ++i) {
+        bool used = false;
+        for (int m = 0; m < j; ++m) used = used || (idx[m] == i);
+        if (!used && A[i * q + i].x > bv) {
+          bv = A[i * q + i].x;
+          best = i;
+        }
+      }
+      idx[j] = best;
+      lam_s[j] = bv;
+    }
+    if (!(lam_s[r - 1] > 1e-14 * lam_s[0]) || !(lam_s[0] > 0.0)) set_error(a.st, 4, -1);
+  }
+  __syncthreads();
+  if (a.st->err) return;
+  for (int e = tid; e < q * r; e += AG_NT) {
+    const int k = e / r, j = e % r;
+    const double2 v = a.V[(long)k * q + idx[j]];
+    const double sc = 1.0 / sqrt(lam_s[j]);
+    a.Vs[k * r + j] = make_float2((float)(v.x * sc), (float)(v.y * sc));
+  }
+}
+
+// U0[:, j] = sum_k X0[:, k] Vs[k][j]
+__global__ __launch_bounds__(AG_NT) void k_x_times_v(const float2* X, const float2* Vs, int n, int q, int r,
+                                                     float2* U, const DevState* st) {
+  __shared__ float2 V[128 * 16];
+  const int tid = threadIdx.x;
+  if (st->err) return;
+  for (int e = tid; e < q * r; e += AG_NT) V[e] = Vs[e];
+  __syncthreads();
+  const long p = (long)blockIdx.x * AG_NT + tid;
+  if (p >= n) return;
+  float2 acc[16];
+  for (int j = 0; j < 16; ++j) acc[j] = make_float2(0.f, 0.f);
+  for (int k = 0; k < q; ++k) {
+    const float2 x = X[(long)k * n + p];
+    for (int j = 0; j < r; ++j) acc[j] = cadd(acc[j], cmul(x, V[k * r + j]));
+  }
+  for (int j = 0; j < r; ++j) U[(long)j * n + p] = acc[j];
+}
+
+__global__ void k_copy(const float2* src, float2* dst, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long stride = (long)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ void k_cost_total(const double* cost_k, int q, double* out, DevState* st) {
+  if (threadIdx.x != 0) return;
+  double f = 0.0;
+  for (int k = 0; k < q; ++k) f += cost_k[k];
+  st->cost_out = f;
+  if (out) *out = f;
+}
+
+// ---------------------------------------------------------------------------
+// launchers (explicit instantiations behind plain functions)
+// ---------------------------------------------------------------------------
+hipError_t launch_gram_lines(const GramLinesArgs& a, int ny, bool fp64, hipStream_t s) {
+  const size_t lds = (size_t)(a.xc * a.r + a.pc * a.xc) * sizeof(float2);
+  if (fp64)
+    hipLaunchKernelGGL(k_gram_lines<double>, dim3(ny), dim3(AG_NT), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_gram_lines<float>, dim3(ny), dim3(AG_NT), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp64, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_gram_index<double>, dim3(nchunks, q), dim3(AG_NT), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_gram_index<float>, dim3(nchunks, q), dim3(AG_NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_solve<double>, dim3(q), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_solve<float>, dim3(q), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s) {
+  const dim3 g(grid_x, grid_y);
+  if (lines) {
+    if (a.r <= 4) hipLaunchKernelGGL(k_fold_lines<4>, g, dim3(AG_NT), 0, s, a);
+    else if (a.r <= 8) hipLaunchKernelGGL(k_fold_lines<8>, g, dim3(AG_NT), 0, s, a);
+    else hipLaunchKernelGGL(k_fold_lines<16>, g, dim3(AG_NT), 0, s, a);
+  } else {
+    if (a.r <= 4) hipLaunchKernelGGL(k_fold_index<4>, g, dim3(AG_NT), 0, s, a);
+    else if (a.r <= 8) hipLaunchKernelGGL(k_fold_index<8>, g, dim3(AG_NT), 0, s, a);
+    else hipLaunchKernelGGL(k_fold_index<16>, g, dim3(AG_NT), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_cols(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_gram_cols<double>, dim3(nblk), dim3(AG_NT), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_gram_cols<float>, dim3(nblk), dim3(AG_NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const ApplyArgs& a, hipStream_t s) {
+  const dim3 g((unsigned)((a.n + AG_NT - 1) / AG_NT));
+  if (a.r <= 4) hipLaunchKernelGGL(k_apply<4>, g, dim3(AG_NT), 0, s, a);
+  else if (a.r <= 8) hipLaunchKernelGGL(k_apply<8>, g, dim3(AG_NT), 0, s, a);
+  else hipLaunchKernelGGL(k_apply<16>, g, dim3(AG_NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_qr_small, dim3(1), dim3(AG_NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)a.q * a.q * sizeof(double2);
+  hipLaunchKernelGGL(k_init_eig, dim3(1), dim3(AG_NT), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace ag

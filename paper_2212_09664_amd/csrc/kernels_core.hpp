@@ -1,0 +1,138 @@
+// Argument blocks and launchers of the non-transform kernels.
+#pragma once
+
+#include "kernels.hpp"
+
+#define GRAM_OPT 2    // outputs per thread in the per-line Gram kernels
+#define GCOLS_OPT 9   // outputs per thread in the column-Gram kernel (m <= 64)
+
+namespace ag {
+
+struct JacobiScratch {
+  int p[64], q[64];
+  double c[64], s[64];
+  double2 e[64];
+  double red[AG_NT];
+};
+
+struct GramLinesArgs {
+  const float2* W;       // [c][j][u][x], ua rows per (c, j)
+  const float2* yh;      // hybrid data [k][c][l][x]
+  const int2* pairs;
+  const int32_t* loc_ptr;
+  const int32_t* unit_loc;
+  int nc, r, nx, lmax, ua;
+  int xc, pc;            // x-chunk and pair-chunk staged in LDS
+  double2* P;            // [u][r][r]
+  double2* hp;           // [pair][r]
+  DevState* st;
+  int check_halt;
+};
+
+struct GramIndexArgs {
+  const float2* W;       // [c][j][n]
+  const float2* y;       // [k][c][m_max]
+  const int32_t* mask;
+  const int32_t* m_k;
+  int nc, r, n, m_max;
+  double2* part;         // [k][chunk][r(r+1)/2 + r]
+  DevState* st;
+  int check_halt;
+};
+
+struct SolveArgs {
+  const double2* P;      // LINES: per-line Grams; INDEX: chunk partials
+  const double2* hp;
+  const int32_t* mask;
+  const int32_t* m_k;
+  const int32_t* loc2unit;
+  const int32_t* pair_of;
+  int width, nx, r, kind, nchunks;
+  const double* ysq_k;
+  float2* B;             // r x q
+  double* cost_k;
+  DevState* st;
+  int check_halt;
+};
+
+struct FoldArgs {
+  const float2* W;
+  const float2* yh;      // LINES: hybrid data
+  const float2* y;       // INDEX: measurements
+  const float2* B;
+  const int2* pairs;
+  const int32_t* loc_ptr;
+  const int32_t* unit_loc;
+  int nc, r, nx, lmax, ua, cg, n, m_max;
+  float2* K;
+  DevState* st;
+  int check_halt;
+};
+
+struct GramColsArgs {
+  const float2* A;
+  const float2* B;
+  int m1, m2;
+  long n;
+  long rows_per_block;
+  double2* part;
+  DevState* st;
+  int check_halt;
+};
+
+struct QrSmallArgs {
+  const double2* part;
+  int nblk, r, mode, n, q;
+  double eta_c, eta_cap_c, eps_exit;
+  double guard;          // stationary start: ||grad_0||_2 <= guard * sum_k ||y_k||^2
+  const float2* B;
+  const double* cost_k;
+  float2* rinv;
+  DevState* st;
+  int check_halt;
+};
+
+struct ApplyArgs {
+  float2* U;
+  const float2* G;
+  const float2* rinv;
+  float2* U_prev;
+  long n;
+  int r, mode;
+  DevState* st;
+};
+
+struct InitEigArgs {
+  const double2* part;
+  int nblk, q, r;
+  double2* V;            // q x q scratch (global)
+  float2* Vs;            // q x r out: V_r Sigma_r^{-1}
+  DevState* st;
+};
+
+__global__ void k_inv_bitmap(const int32_t* mask, const int32_t* m_k, int width, int per, int n_loc,
+                             uint32_t* bitmap, int nw, DevState* st);
+__global__ void k_inv_scan(const uint32_t* bitmap, int nw, int n_loc, int32_t* loc_ptr, int32_t* loc2unit,
+                           int32_t* unit_loc, DevState* st);
+__global__ void k_inv_fill(const int32_t* mask, const int32_t* m_k, int width, int per, const uint32_t* bitmap,
+                           int nw, const int32_t* loc_ptr, int2* pairs, int32_t* pair_of, const DevState* st);
+__global__ void k_ysq(const float2* y, const int32_t* m_k, int nc, int m_max, double* ysq_k);
+__global__ void k_init_stats(const double* ysq_k, const int32_t* m_k, int q, double trunc_c, DevState* st);
+__global__ void k_state_reset(DevState* st, int full);
+__global__ void k_state_set_eta(DevState* st, double eta);
+__global__ void k_x_times_v(const float2* X, const float2* Vs, int n, int q, int r, float2* U,
+                            const DevState* st);
+__global__ void k_copy(const float2* src, float2* dst, long n);
+__global__ void k_cost_total(const double* cost_k, int q, double* out, DevState* st);
+__global__ void k_init_eig(InitEigArgs a);
+
+hipError_t launch_gram_lines(const GramLinesArgs& a, int ny, bool fp64, hipStream_t s);
+hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp64, hipStream_t s);
+hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s);
+hipError_t launch_fold(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
+hipError_t launch_gram_cols(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);
+hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
+hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s);
+hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s);
+
+}  // namespace ag

@@ -1,0 +1,285 @@
+// Transform kernels: batched 1D DFTs along x (contiguous rows) and along y
+// (image columns), with the coil weighting, the sampling selection and the
+// conjugate-coil combine fused into their loads and stores.
+//
+// The 2D DFT of the measurement model (Sec. II-A) is separable, F = F_y F_x.
+// For 1D Cartesian masks every sampled line is complete along kx, so the
+// kx half moves to a one-time pass over the data and each iteration needs
+// only the y half, restricted on output to the sampled lines.  For general
+// masks both halves run.
+#include "kernels.hpp"
+
+namespace ag {
+
+// ---------------------------------------------------------------------------
+// twiddle table: tw[t] = exp(-2 pi i t / N), from a double-precision sincospi
+// ---------------------------------------------------------------------------
+__global__ void k_twiddle(float2* tw, int N) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) {
+    double s, c;
+    sincospi(2.0 * (double)t / (double)N, &s, &c);
+    tw[t] = make_float2((float)c, (float)(-s));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// rows: FFT along x of TR rows of length N per workgroup.
+// Row rho of the batch lives at src + rho*N.  With m_k != null the rows are
+// the padded measurement lines rho = (k*nc + c)*lmax + l, valid when
+// l < m_k[k]/N; invalid rows are written as zeros.  trunc: zero every input
+// sample with |v|^2 > gamma (state) before the transform.
+// ---------------------------------------------------------------------------
+template <int N, int TR, bool INV>
+__global__ __launch_bounds__(AG_NT) void k_rows(RowArgs a) {
+  __shared__ float2 s[N * TR];
+  const int tid = threadIdx.x;
+  const long rho0 = (long)blockIdx.x * TR;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  const double gamma = a.trunc ? a.st->gamma : 0.0;
+  for (int g = tid; g < N * TR; g += AG_NT) {
+    const int t = g / N, e = g % N;
+    const long rho = rho0 + t;
+    float2 v = make_float2(0.f, 0.f);
+    if (rho < a.nrows && row_valid(a, rho, N)) {
+      v = a.src[rho * N + e];
+      if (a.trunc) {
+        double m2 = (double)v.x * v.x + (double)v.y * v.y;
+        if (m2 > gamma) v = make_float2(0.f, 0.f);
+      }
+    }
+    s[e * TR + t] = v;
+  }
+  __syncthreads();
+  fft_lds<N, TR, AG_NT, INV>(s, a.tw);
+  for (int g = tid; g < N * TR; g += AG_NT) {
+    const int t = g / N, e = g % N;
+    const long rho = rho0 + t;
+    if (rho < a.nrows) {
+      float2 v = row_valid(a, rho, N) ? cscale(s[e * TR + t], a.scale) : make_float2(0.f, 0.f);
+      a.dst[rho * N + e] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward column transform: dst rows = F_y (s_c o src_img) restricted to a
+// row list.  Grid (nx/TX, n_img, nc).
+// ---------------------------------------------------------------------------
+template <int N, int TX>
+__global__ __launch_bounds__(AG_NT) void k_cols_fwd(ColFwdArgs a) {
+  __shared__ float2 s[N * TX];
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * TX, img = blockIdx.y, c = blockIdx.z;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  const float2* src = a.src + (long)img * a.src_img_stride;
+  const float2* coil = a.coils + (long)c * a.n;
+  for (int g = tid; g < N * TX; g += AG_NT) {
+    const int y = g / TX, col = g % TX;
+    const long p = (long)y * a.nx + x0 + col;
+    s[g] = cmul(coil[p], src[p]);
+  }
+  __syncthreads();
+  fft_lds<N, TX, AG_NT, false>(s, a.tw);
+  int n_rows;
+  const int32_t* rows = nullptr;
+  if (a.m_k) {
+    n_rows = a.m_k[img] / a.nx;
+    rows = a.rows + (long)img * a.rows_img_stride;
+  } else if (a.n_rows_ptr) {
+    n_rows = *a.n_rows_ptr;
+    rows = a.rows;
+  } else {
+    n_rows = N;
+  }
+  float2* dst = a.dst + (long)c * a.dst_c_stride + (long)img * a.dst_img_stride;
+  for (int g = tid; g < n_rows * TX; g += AG_NT) {
+    const int u = g / TX, col = g % TX;
+    const int ky = rows ? rows[u] : u;
+    dst[(long)u * a.nx + x0 + col] = cscale(s[ky * TX + col], a.scale);
+  }
+  if (a.zero_pad_rows > 0) {  // padding lines of a measurement layout
+    for (int g = tid; g < (a.zero_pad_rows - n_rows) * TX; g += AG_NT) {
+      const int u = n_rows + g / TX, col = g % TX;
+      dst[(long)u * a.nx + x0 + col] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint column transform with the coil combine:
+//   dst_img = scale_img * sum_c conj(s_c) o F_y^H (rows of src_{c,img}
+//             scattered onto their ky, zeros elsewhere).
+// Grid (nx/TX, n_img).
+// ---------------------------------------------------------------------------
+template <int N, int TX>
+__global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
+  __shared__ float2 s[N * TX];
+  constexpr int IT = (N * TX + AG_NT - 1) / AG_NT;
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * TX, img = blockIdx.y;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  int n_rows;
+  const int32_t* rows = nullptr;
+  if (a.m_k_rows) {
+    n_rows = a.m_k_rows[img] / a.nx;
+    rows = a.rows + (long)img * a.rows_img_stride;
+  } else if (a.n_rows_ptr) {
+    n_rows = *a.n_rows_ptr;
+    rows = a.rows;
+  } else {
+    n_rows = N;
+  }
+  const bool full = (rows == nullptr);
+  float2 acc[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) acc[it] = make_float2(0.f, 0.f);
+  for (int c = 0; c < a.nc; ++c) {
+    const float2* src = a.src + (long)c * a.src_c_stride + (long)img * a.src_img_stride;
+    if (!full) {
+      for (int g = tid; g < N * TX; g += AG_NT) s[g] = make_float2(0.f, 0.f);
+      __syncthreads();
+    }
+    for (int g = tid; g < n_rows * TX; g += AG_NT) {
+      const int u = g / TX, col = g % TX;
+      const int ky = full ? u : rows[u];
+      s[ky * TX + col] = src[(long)u * a.nx + x0 + col];
+    }
+    __syncthreads();
+    fft_lds<N, TX, AG_NT, true>(s, a.tw);
+    const float2* coil = a.coils + (long)c * a.n;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int g = tid + it * AG_NT;
+      if (g < N * TX) {
+        const int y = g / TX, col = g % TX;
+        acc[it] = cadd(acc[it], cjmul(coil[(long)y * a.nx + x0 + col], s[g]));
+      }
+    }
+    __syncthreads();
+  }
+  float sc = a.scale;
+  if (a.m_k_scale) sc *= (float)(1.0 / sqrt((double)a.m_k_scale[img] * a.st->mbar));
+  float2* dst = a.dst + (long)img * a.dst_img_stride;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int g = tid + it * AG_NT;
+    if (g >= N * TX) break;
+    const int y = g / TX, col = g % TX;
+    const long p = (long)y * a.nx + x0 + col;
+    float2 v = cscale(acc[it], sc);
+    if (a.accumulate) v = cadd(dst[p], v);
+    dst[p] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// general masks: gather the frame's samples from full k-space images, and
+// the adjoint scatter (with optional truncation).
+// ---------------------------------------------------------------------------
+__global__ void k_gather(const float2* img, long img_stride_c, long img_stride_k, const int32_t* mask,
+                         const int32_t* m_k, int m_max, int nc, int k0, float2* y, const DevState* st) {
+  if (st->err) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int kk = blockIdx.y, c = blockIdx.z, k = k0 + kk;
+  if (i >= m_max) return;
+  float2 v = make_float2(0.f, 0.f);
+  if (i < m_k[k]) v = img[c * img_stride_c + kk * img_stride_k + mask[(long)k * m_max + i]];
+  y[((long)k * nc + c) * m_max + i] = v;
+}
+
+__global__ void k_scatter(const float2* y, const int32_t* mask, const int32_t* m_k, int m_max, int nc,
+                          int k0, float2* img, long img_stride_c, long img_stride_k, const DevState* st,
+                          int trunc) {
+  if (st->err) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int kk = blockIdx.y, c = blockIdx.z, k = k0 + kk;
+  if (i >= m_k[k]) return;
+  float2 v = y[((long)k * nc + c) * m_max + i];
+  if (trunc) {
+    double m2 = (double)v.x * v.x + (double)v.y * v.y;
+    if (m2 > st->gamma) v = make_float2(0.f, 0.f);
+  }
+  img[c * img_stride_c + kk * img_stride_k + mask[(long)k * m_max + i]] = v;
+}
+
+__global__ void k_zero(float2* p, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long stride = (long)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = make_float2(0.f, 0.f);
+}
+
+// ---------------------------------------------------------------------------
+// host-side dispatch over the transform length
+// ---------------------------------------------------------------------------
+template <int N>
+static hipError_t launch_rows_n(const RowArgs& a, bool inv, hipStream_t st) {
+  constexpr int TR = ColTile<N>::TX;
+  dim3 grid((unsigned)((a.nrows + TR - 1) / TR));
+  if (inv)
+    hipLaunchKernelGGL((k_rows<N, TR, true>), grid, dim3(AG_NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_rows<N, TR, false>), grid, dim3(AG_NT), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows(int N, const RowArgs& a, bool inv, hipStream_t st) {
+  if (a.nrows <= 0) return hipSuccess;
+  switch (N) {
+    case 8: return launch_rows_n<8>(a, inv, st);
+    case 16: return launch_rows_n<16>(a, inv, st);
+    case 32: return launch_rows_n<32>(a, inv, st);
+    case 64: return launch_rows_n<64>(a, inv, st);
+    case 128: return launch_rows_n<128>(a, inv, st);
+    case 256: return launch_rows_n<256>(a, inv, st);
+    case 512: return launch_rows_n<512>(a, inv, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+int col_tile(int N, int nx) {
+  int tx = (N >= 512) ? 8 : (N >= 256 ? 16 : 32);
+  return tx < nx ? tx : nx;
+}
+
+template <int N, int TX>
+static hipError_t launch_cols_tx(const ColFwdArgs* f, const ColAdjArgs* d, int n_img, int nc, hipStream_t st) {
+  if (f) {
+    dim3 grid((unsigned)(f->nx / TX), (unsigned)n_img, (unsigned)nc);
+    hipLaunchKernelGGL((k_cols_fwd<N, TX>), grid, dim3(AG_NT), 0, st, *f);
+  } else {
+    dim3 grid((unsigned)(d->nx / TX), (unsigned)n_img);
+    hipLaunchKernelGGL((k_cols_adj<N, TX>), grid, dim3(AG_NT), 0, st, *d);
+  }
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_cols_n(const ColFwdArgs* f, const ColAdjArgs* d, int nx, int n_img, int nc, hipStream_t st) {
+  const int tx = col_tile(N, nx);
+  if constexpr (N <= 128) {
+    if (tx == 32) return launch_cols_tx<N, 32>(f, d, n_img, nc, st);
+  }
+  if constexpr (N <= 256) {
+    if (tx == 16) return launch_cols_tx<N, 16>(f, d, n_img, nc, st);
+  }
+  if (tx == 8) return launch_cols_tx<N, 8>(f, d, n_img, nc, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cols(int N, const ColFwdArgs* f, const ColAdjArgs* d, int nx, int n_img, int nc,
+                       hipStream_t st) {
+  if (n_img <= 0) return hipSuccess;
+  switch (N) {
+    case 8: return launch_cols_n<8>(f, d, nx, n_img, nc, st);
+    case 16: return launch_cols_n<16>(f, d, nx, n_img, nc, st);
+    case 32: return launch_cols_n<32>(f, d, nx, n_img, nc, st);
+    case 64: return launch_cols_n<64>(f, d, nx, n_img, nc, st);
+    case 128: return launch_cols_n<128>(f, d, nx, n_img, nc, st);
+    case 256: return launch_cols_n<256>(f, d, nx, n_img, nc, st);
+    case 512: return launch_cols_n<512>(f, d, nx, n_img, nc, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ag

@@ -1,0 +1,62 @@
+"""The C ABI: the built library loads and exports every function that
+include/altgdmin.h declares; the Python binding names them all.  No GPU
+calls are made (host-only entry points only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "altgdmin.h")
+LIB = os.path.join(ROOT, "paper_2212_09664_amd", "libaltgdmin.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(altgdmin_[a-z_A-Z0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("altgdmin_init", "altgdmin_iterate", "altgdmin_apply_A", "altgdmin_apply_AH",
+                 "altgdmin_create", "altgdmin_set_problem", "altgdmin_destroy"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_covers_every_declared_symbol():
+    from paper_2212_09664_amd import _lib
+    src = open(_lib.__file__).read()
+    missing = [n for n in declared() if f'"{n}"' not in src]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_only_argument_checks():
+    """altgdmin_create validates shapes on the host without touching a GPU."""
+    from paper_2212_09664_amd import _lib
+    L = _lib.load_library()
+    P = _lib.Params
+    h = ctypes.c_void_p()
+    ok = P(64, 64, 4, 16, 4, 1024, 0, 0, 36.0, 0.14, 0.0, 0.0, 70)
+    assert L.altgdmin_create(ctypes.byref(ok), ctypes.byref(h)) == 0
+    nb = ctypes.c_size_t()
+    assert L.altgdmin_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
+    L.altgdmin_destroy(h)
+    for bad in (P(48, 64, 4, 16, 4, 1024, 0, 0, 36.0, 0.14, 0.0, 0.0, 70),   # nx not 2^k
+                P(64, 64, 4, 16, 17, 1024, 0, 0, 36.0, 0.14, 0.0, 0.0, 70),  # r > 16
+                P(64, 64, 4, 3, 4, 1024, 0, 0, 36.0, 0.14, 0.0, 0.0, 70),    # r > q
+                P(64, 64, 4, 16, 4, 1000, 0, 0, 36.0, 0.14, 0.0, 0.0, 70),   # m_max % nx
+                P(64, 64, 4, 16, 4, 1024, 2, 0, 36.0, 0.14, 0.0, 0.0, 70),   # mask kind
+                P(64, 64, 4, 16, 4, 1024, 0, 0, 36.0, 0.0, 0.0, 0.0, 70)):   # eta_c
+        assert L.altgdmin_create(ctypes.byref(bad), ctypes.byref(h)) == 1
+    assert L.altgdmin_status_string(4) == b"Gram matrix not positive definite"

@@ -1,0 +1,181 @@
+"""GPU (HIP, through the C ABI) versus the FP64 oracle on identical inputs.
+
+Tolerances: operators (A, A^H, W-derived G_k/h_k through b_k, the gradient)
+at 1e-5 relative (the gradient normalised by the size of the terms it is a
+difference of: ||sum_k A_k^H A_k U b_k b_k^H||_F); end to end, |NMSE_gpu -
+NMSE_oracle| <= 1e-4 after the fixed iteration count.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import altgdmin as AG
+from oracle import metrics as M
+from oracle import operators as O
+
+from gpu_cases import GPU_OK, Case, from_gpu_B, from_gpu_U, log, proj_dist, rel, to_gpu_U
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not GPU_OK, reason="needs a GPU")]
+
+if GPU_OK:
+    import torch
+
+OP_CASES = [
+    # (nx, ny, nc, q, r, kind, lines/m, variable m_k)
+    (64, 64, 4, 6, 3, "lines", 16, True),
+    (32, 16, 3, 5, 2, "lines", 5, True),
+    (16, 64, 2, 4, 2, "lines", 9, False),
+    (128, 128, 3, 3, 2, "lines", 20, True),
+    (256, 256, 2, 2, 2, "lines", 33, True),
+    (32, 32, 3, 6, 3, "index", 300, True),
+    (16, 64, 2, 5, 2, "index", 250, True),
+    (128, 128, 2, 4, 4, "index", 2000, True),
+]
+
+
+def _case(cfg, seed=0, snr=30.0):
+    nx, ny, nc, q, r, kind, lm, var = cfg
+    p = datagen.make_small(nx, ny, nc, q, r, seed=seed, kind=kind, n_lines=lm, m=lm, lowrank=False,
+                           snr_db=snr, coils="random", variable_m=var)
+    return Case(p)
+
+
+@pytest.mark.parametrize("cfg", OP_CASES, ids=[f"{c[0]}x{c[1]}_{c[5]}" for c in OP_CASES])
+def test_apply_A_and_AH_match_oracle(cfg):
+    log(f"apply_A/AH {cfg}")
+    cs = _case(cfg)
+    ctx = cs.gpu_ctx()
+    rng = np.random.default_rng(5)
+    X = datagen.crandn(rng, cs.prob.n, cs.prob.q).astype(np.complex64).astype(np.complex128)
+    Xg = torch.from_numpy(np.ascontiguousarray(X.T.astype(np.complex64))).cuda()
+    Yg = ctx.apply_A(Xg)
+    Yref = cs.op.apply_A(X)
+    Ygn = Yg.cpu().numpy().astype(np.complex128)
+    assert rel(Ygn, Yref) < 1e-5
+    # padding is written as zero
+    for k in range(cs.prob.q):
+        assert np.all(Ygn[k, :, cs.m_k[k]:] == 0)
+    Xa = ctx.apply_AH(torch.from_numpy(cs.y32).cuda())
+    Xref = cs.op.apply_AH(cs.y)
+    assert rel(Xa.cpu().numpy().T.astype(np.complex128), Xref) < 1e-5
+    # adjoint identity on the GPU's own operators
+    Yr = datagen.crandn(rng, *cs.y.shape)
+    Yr = np.where(np.arange(cs.y.shape[2])[None, None, :] < cs.m_k[:, None, None], Yr, 0).astype(np.complex64)
+    AHY = ctx.apply_AH(torch.from_numpy(Yr).cuda()).cpu().numpy().T.astype(np.complex128)
+    lhs = np.vdot(Ygn, Yr.astype(np.complex128))
+    rhs = np.vdot(X, AHY)
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("cfg", OP_CASES, ids=[f"{c[0]}x{c[1]}_{c[5]}" for c in OP_CASES])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "mixed"])
+def test_ls_step_and_gradient_match_oracle(cfg, precision):
+    log(f"gradient {cfg} precision={precision}")
+    cs = _case(cfg, seed=1)
+    ctx = cs.gpu_ctx(precision=precision)
+    rng = np.random.default_rng(9)
+    U, _ = np.linalg.qr(datagen.crandn(rng, cs.prob.n, cs.prob.r))
+    U = U.astype(np.complex64).astype(np.complex128)
+    Bg, Gg = ctx.gradient(to_gpu_U(U))
+    B = from_gpu_B(Bg)
+    G = from_gpu_U(Gg)
+    Bref = AG.ls_step(cs.op, U, cs.y)
+    Gref = AG.gradient(cs.op, U, Bref, cs.y)
+    conds = []
+    FU = cs.op.transform_basis(U)
+    for k in range(cs.prob.q):
+        Mk = cs.op.AU(k, U, FU)
+        conds.append(np.linalg.cond(Mk.conj().T @ Mk))
+    tol_b = 1e-5 * max(1.0, max(conds) / 10.0)
+    assert rel(B, Bref) < tol_b, (rel(B, Bref), max(conds))
+    # grad = T1 - T2 with T1 = sum_k A_k^H A_k U b_k b_k^H, T2 = sum_k A_k^H y_k b_k^H:
+    # normalise by the larger of the two terms
+    t1 = np.linalg.norm(AG.gradient(cs.op, U, Bref, np.zeros_like(cs.y)))
+    t2 = np.linalg.norm(AG.gradient(cs.op, np.zeros_like(U), Bref, cs.y))
+    scale = max(t1, t2)
+    err = np.linalg.norm(G - Gref) / scale
+    log(f"  b rel {rel(B, Bref):.2e} (tol {tol_b:.1e}), grad rel/scale {err:.2e}, plain {rel(G, Gref):.2e}")
+    assert err < 1e-5
+
+
+def test_spectral_init_matches_oracle():
+    log("init gauss64")
+    cs = Case(datagen.make("gauss64", 0))
+    ctx = cs.gpu_ctx()
+    U0 = from_gpu_U(ctx.init())
+    st = ctx.stats()
+    Ytr, gamma, _ = AG.truncation(cs.op, cs.y, 36.0)
+    X0 = AG.backprojection(cs.op, Ytr)
+    s = np.linalg.svd(X0, compute_uv=False)
+    Uref = AG.spectral_init(X0, cs.prob.r)
+    assert st["gamma"] == pytest.approx(gamma, rel=1e-12)
+    assert np.allclose(U0.conj().T @ U0, np.eye(cs.prob.r), atol=2e-6)
+    gap = (s[cs.prob.r - 1] - s[cs.prob.r]) / s[0]
+    d = proj_dist(U0, Uref)
+    log(f"  projector distance {d:.2e}, relative gap {gap:.2e}")
+    assert d < 1e-5 / gap
+
+
+@pytest.mark.parametrize("cfg", [(32, 32, 3, 8, 3, "lines", 10, True), (32, 32, 3, 8, 3, "index", 400, True),
+                                 (64, 32, 4, 12, 4, "lines", 12, False)],
+                         ids=["lines32", "index32", "lines64x32"])
+def test_spectral_init_small_shapes(cfg):
+    log(f"init {cfg}")
+    nx, ny, nc, q, r, kind, lm, var = cfg
+    p = datagen.make_small(nx, ny, nc, q, r, seed=3, kind=kind, n_lines=lm, m=lm, lowrank=True,
+                           snr_db=40.0, variable_m=var)
+    cs = Case(p)
+    ctx = cs.gpu_ctx()
+    U0 = from_gpu_U(ctx.init())
+    Ytr, gamma, _ = AG.truncation(cs.op, cs.y, 36.0)
+    X0 = AG.backprojection(cs.op, Ytr)
+    s = np.linalg.svd(X0, compute_uv=False)
+    Uref = AG.spectral_init(X0, r)
+    gap = (s[r - 1] - s[r]) / s[0]
+    assert proj_dist(U0, Uref) < 1e-5 / gap
+
+
+def _end_to_end(cs, T, trunc_c=36.0, precision=0):
+    ctx = cs.gpu_ctx(precision=precision, trunc_c=trunc_c)
+    U = ctx.init()
+    Uprev = torch.empty_like(U)
+    B, done = ctx.iterate(T, U, U_prev=Uprev, sync=True)
+    assert done == T
+    Xg = from_gpu_U(Uprev) @ from_gpu_B(B)
+    ref = AG.run(cs.op, cs.y, AG.Params(r=cs.prob.r, trunc_c=trunc_c), t_fixed=T, record=False)
+    return ctx, Xg, ref
+
+
+def test_end_to_end_gauss64_20_iterations():
+    """The exact-low-rank 64x64 workload (4 coils, 16 frames, rank 4,
+    noise-free), 20 iterations."""
+    log("end-to-end gauss64")
+    cs = Case(datagen.make("gauss64", 0))
+    ctx, Xg, ref = _end_to_end(cs, 20)
+    n_gpu = M.nmse(Xg, cs.prob.zstar)
+    n_ref = M.nmse(ref.X, cs.prob.zstar)
+    log(f"  NMSE gpu {n_gpu:.6e} oracle {n_ref:.6e}; X rel {rel(Xg, ref.X):.2e}")
+    assert abs(n_gpu - n_ref) <= 1e-4
+    assert rel(Xg, ref.X) < 1e-3
+    eta = ctx.get_eta()
+    assert eta == pytest.approx(ref.eta, rel=1e-4)
+
+
+@pytest.mark.parametrize("kind", ["lines", "index"])
+def test_end_to_end_small_ragged(kind):
+    log(f"end-to-end small {kind}")
+    p = datagen.make_small(32, 16, 3, 10, 2, seed=4, kind=kind, n_lines=6, m=170, lowrank=True,
+                           snr_db=35.0, variable_m=True)
+    cs = Case(p)
+    ctx, Xg, ref = _end_to_end(cs, 15)
+    assert abs(M.nmse(Xg, p.zstar) - M.nmse(ref.X, p.zstar)) <= 1e-4
+    assert rel(Xg, ref.X) < 1e-3
+
+
+def test_mixed_precision_end_to_end_gauss64():
+    log("end-to-end gauss64 mixed")
+    cs = Case(datagen.make("gauss64", 0))
+    ctx, Xg, ref = _end_to_end(cs, 20, precision=1)
+    assert abs(M.nmse(Xg, cs.prob.zstar) - M.nmse(ref.X, cs.prob.zstar)) <= 1e-4
