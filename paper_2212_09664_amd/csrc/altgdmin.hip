@@ -46,7 +46,9 @@ struct altgdmin_ctx {
   int qr_nblk;
   long qr_rows;
   int kc;        // INDEX: frames per chunk of the operator passes
-  int gram_xc, gram_pc;
+  int gram_cg, gram_ngroups, gram_chunk;
+  int adj_parts, adj_cgs;  // coil groups of the adjoint transform (partial gradients)
+  int txx;                 // image columns per workgroup in the basis transforms
   size_t bytes;
   // bound problem
   const float2* coils = nullptr;
@@ -58,7 +60,7 @@ struct altgdmin_ctx {
   int bound = 0, initialized = 0;
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
-      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_end;
+      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_Ui, o_unitof, o_end;
   size_t T_bytes;
   // timing
   int timed = TK_NONE;
@@ -97,6 +99,8 @@ void carve(altgdmin_ctx* c) {
   c->o_unitloc = take(sizeof(int32_t) * (size_t)c->n_loc);
   c->o_pairs = take(sizeof(int2) * (size_t)q * c->width);
   c->o_pairof = take(sizeof(int32_t) * (size_t)q * c->width);
+  c->o_unitof = take(sizeof(int32_t) * (size_t)q * c->width);
+  c->o_Ui = take(sizeof(float2) * (size_t)n * r);
   const size_t ysz = sizeof(float2) * (size_t)q * nc * p.m_max;
   c->o_yh = take(c->lines ? ysz : 0);
   c->o_ysq = take(sizeof(double) * q);
@@ -106,14 +110,14 @@ void carve(altgdmin_ctx* c) {
   c->o_K = take(wsz);
   const int nP = r * (r + 1) / 2;
   if (c->lines) {
-    c->o_P = take(sizeof(double2) * (size_t)p.ny * r * r);
-    c->o_hp = take(sizeof(double2) * (size_t)q * c->width * r);
+    c->o_P = take(sizeof(double2) * (size_t)c->gram_ngroups * p.ny * r * r);
+    c->o_hp = take(sizeof(double2) * (size_t)c->gram_ngroups * q * c->width * r);
   } else {
-    c->o_P = take(sizeof(double2) * (size_t)q * c->nchunks * (nP + r));
+    c->o_P = take(sizeof(double2) * (size_t)q * c->nchunks * (r * r + r));
     c->o_hp = take(0);
   }
   c->o_B = take(sizeof(float2) * (size_t)q * r);
-  c->o_G = take(sizeof(float2) * (size_t)n * r);
+  c->o_G = take(sizeof(float2) * (size_t)c->adj_parts * n * r);
   const int m_iter = 2 * r;
   const size_t qo = (size_t)std::max(m_iter * (m_iter + 1) / 2, q * (q + 1) / 2);
   c->o_qpart = take(sizeof(double2) * qo * c->qr_nblk);
@@ -163,35 +167,50 @@ void tmark(altgdmin_ctx* c, int which) {
 }
 
 // ---- launch sequences -------------------------------------------------------
-hipError_t fwd_transform(altgdmin_ctx* c, const float2* U, int check_halt) {
+BasisArgs basis_args(altgdmin_ctx* c, int check_halt) {
   const altgdmin_params& p = c->p;
-  ColFwdArgs f{};
-  f.src = U;
-  f.src_img_stride = c->n;
-  f.coils = c->coils;
-  f.n = c->n;
-  f.nx = p.nx;
-  f.tw = c->at<float2>(c->o_twy);
-  f.dst = c->at<float2>(c->o_W);
-  f.dst_c_stride = (long)p.r * c->ua * p.nx;
-  f.dst_img_stride = (long)c->ua * p.nx;
-  f.scale = (float)(1.0 / sqrt((double)p.ny));
-  f.check_halt = check_halt;
-  f.st = c->st();
+  BasisArgs b{};
+  b.U = c->at<float2>(c->o_Ui);
+  b.W = c->at<float2>(c->o_W);
+  b.K = c->at<float2>(c->o_K);
+  b.G = c->at<float2>(c->o_G);
+  b.coils = c->coils;
+  b.n = c->n;
+  b.nx = p.nx;
+  b.r = p.r;
+  b.nc = p.nc;
+  b.ua = c->ua;
+  b.txx = c->txx;
+  b.cgs = c->adj_cgs;
+  b.part_stride = (long)c->n * p.r;
   if (c->lines) {
-    f.rows = c->at<int32_t>(c->o_unitloc);
-    f.n_rows_ptr = &c->st()->n_units;
+    b.rows = c->at<int32_t>(c->o_unitloc);
+    b.n_rows_ptr = &c->st()->n_units;
   }
-  hipError_t e = launch_cols(p.ny, &f, nullptr, p.nx, p.r, p.nc, c->stream);
+  b.tw = c->at<float2>(c->o_twy);
+  b.tw_x = c->at<float2>(c->o_twx);
+  b.scale = (float)(1.0 / sqrt((double)p.ny));
+  b.scale_x = (float)(1.0 / sqrt((double)p.nx));
+  b.st = c->st();
+  b.check_halt = check_halt;
+  return b;
+}
+
+// the pixel-major working copy of a column-major basis
+hipError_t to_pixmajor(altgdmin_ctx* c, const float2* U) {
+  hipLaunchKernelGGL(k_to_pixmajor, dim3(512), dim3(256), 0, c->stream, U, c->p.r, (long)c->n,
+                     c->at<float2>(c->o_Ui));
+  return hipGetLastError();
+}
+
+// W_{c,j} = F(s_c o u_j) on the sampled rows (y half only for LINES), from
+// the pixel-major working copy of U
+hipError_t fwd_transform(altgdmin_ctx* c, int check_halt) {
+  const altgdmin_params& p = c->p;
+  const BasisArgs b = basis_args(c, check_halt);
+  hipError_t e = launch_basis(0, p.ny, b, p.nx / c->txx, c->adj_parts, c->stream);
   if (e != hipSuccess || c->lines) return e;
-  RowArgs ra{};
-  ra.src = ra.dst = c->at<float2>(c->o_W);
-  ra.tw = c->at<float2>(c->o_twx);
-  ra.nrows = (long)p.nc * p.r * p.ny;
-  ra.scale = (float)(1.0 / sqrt((double)p.nx));
-  ra.check_halt = check_halt;
-  ra.st = c->st();
-  return launch_rows(p.nx, ra, false, c->stream);
+  return launch_basis(2, p.nx, b, p.nc * p.ny, 1, c->stream);
 }
 
 hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
@@ -200,7 +219,7 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
   if (c->lines) {
     GramLinesArgs g{};
     g.W = c->at<float2>(c->o_W);
-    g.yh = c->at<float2>(c->o_yh);
+    g.yu = c->at<float2>(c->o_yh);
     g.pairs = c->at<int2>(c->o_pairs);
     g.loc_ptr = c->at<int32_t>(c->o_locptr);
     g.unit_loc = c->at<int32_t>(c->o_unitloc);
@@ -209,14 +228,15 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
     g.nx = p.nx;
     g.lmax = c->lmax;
     g.ua = c->ua;
-    g.xc = c->gram_xc;
-    g.pc = c->gram_pc;
+    g.cg = c->gram_cg;
+    g.nx_shift = __builtin_ctz((unsigned)p.nx);
+    g.npairs = (long)p.q * c->width;
     g.P = c->at<double2>(c->o_P);
     g.hp = c->at<double2>(c->o_hp);
     g.st = c->st();
     g.check_halt = check_halt;
     tmark(c, TK_GRAM);
-    e = launch_gram_lines(g, p.ny, c->fp64, c->stream);
+    e = launch_gram_lines(g, p.ny, c->gram_ngroups, p.q, c->fp64, c->stream);
     tmark(c, TK_GRAM);
   } else {
     GramIndexArgs g{};
@@ -228,6 +248,7 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
     g.r = p.r;
     g.n = c->n;
     g.m_max = p.m_max;
+    g.chunk = c->gram_chunk;
     g.part = c->at<double2>(c->o_P);
     g.st = c->st();
     g.check_halt = check_halt;
@@ -243,11 +264,15 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
   s.m_k = c->m_k;
   s.loc2unit = c->at<int32_t>(c->o_loc2unit);
   s.pair_of = c->at<int32_t>(c->o_pairof);
+  s.unit_of = c->at<int32_t>(c->o_unitof);
   s.width = c->width;
   s.nx = p.nx;
   s.r = p.r;
   s.kind = c->lines ? 0 : 1;
   s.nchunks = c->nchunks;
+  s.ngroups = c->gram_ngroups;
+  s.ua = c->ua;
+  s.npairs = (long)p.q * c->width;
   s.ysq_k = c->at<double>(c->o_ysq);
   s.B = c->at<float2>(c->o_B);
   s.cost_k = c->at<double>(c->o_cost);
@@ -261,15 +286,18 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
 
 hipError_t cholqr(altgdmin_ctx* c, float2* U) {
   const altgdmin_params& p = c->p;
+  hipError_t e0 = to_pixmajor(c, U);
+  if (e0 != hipSuccess) return e0;
   GramColsArgs g{};
-  g.A = U;
+  g.A = c->at<float2>(c->o_Ui);
   g.m1 = p.r;
   g.m2 = 0;
   g.n = c->n;
   g.rows_per_block = c->qr_rows;
+  g.nparts = 1;
   g.part = c->at<double2>(c->o_qpart);
   g.st = c->st();
-  hipError_t e = launch_gram_cols(g, c->qr_nblk, true, c->stream);
+  hipError_t e = launch_qr_gram(g, c->qr_nblk, true, c->stream);
   if (e != hipSuccess) return e;
   QrSmallArgs qa{};
   qa.part = c->at<double2>(c->o_qpart);
@@ -284,6 +312,7 @@ hipError_t cholqr(altgdmin_ctx* c, float2* U) {
   if (e != hipSuccess) return e;
   ApplyArgs aa{};
   aa.U = U;
+  aa.Ui = c->at<float2>(c->o_Ui);
   aa.rinv = c->at<float2>(c->o_rinv);
   aa.n = c->n;
   aa.r = p.r;
@@ -293,11 +322,11 @@ hipError_t cholqr(altgdmin_ctx* c, float2* U) {
 }
 
 // b_k for every frame and the gradient at U (into the workspace's B and G)
-hipError_t gradient_pieces(altgdmin_ctx* c, const float2* U, int check_halt) {
+hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   const altgdmin_params& p = c->p;
   hipError_t e;
   tmark(c, TK_FWD);
-  e = fwd_transform(c, U, check_halt);
+  e = fwd_transform(c, check_halt);
   tmark(c, TK_FWD);
   if (e != hipSuccess) return e;
   e = gram_solve(c, check_halt);
@@ -305,7 +334,7 @@ hipError_t gradient_pieces(altgdmin_ctx* c, const float2* U, int check_halt) {
   // fold the residual over frames
   FoldArgs fa{};
   fa.W = c->at<float2>(c->o_W);
-  fa.yh = c->at<float2>(c->o_yh);
+  fa.yu = c->at<float2>(c->o_yh);
   fa.y = c->y;
   fa.B = c->at<float2>(c->o_B);
   fa.pairs = c->at<int2>(c->o_pairs);
@@ -316,7 +345,7 @@ hipError_t gradient_pieces(altgdmin_ctx* c, const float2* U, int check_halt) {
   fa.nx = p.nx;
   fa.lmax = c->lmax;
   fa.ua = c->ua;
-  fa.cg = c->lines ? std::max(1, std::min(p.nc, 4096 / p.nx / 4)) : 1;
+  fa.cg = 1;
   fa.n = c->n;
   fa.m_max = p.m_max;
   fa.K = c->at<float2>(c->o_K);
@@ -324,64 +353,43 @@ hipError_t gradient_pieces(altgdmin_ctx* c, const float2* U, int check_halt) {
   fa.check_halt = check_halt;
   tmark(c, TK_FOLD);
   if (c->lines)
-    e = launch_fold(fa, true, p.ny, (p.nc + fa.cg - 1) / fa.cg, c->stream);
+    e = launch_fold2(fa, true, p.ny, p.nc, c->stream);
   else
-    e = launch_fold(fa, false, (int)((c->n + AG_NT - 1) / AG_NT), p.nc, c->stream);
+    e = launch_fold2(fa, false, (int)((c->n + AG_NT - 1) / AG_NT), p.nc, c->stream);
   tmark(c, TK_FOLD);
   if (e != hipSuccess) return e;
-  // inverse transform + coil combine -> gradient
+  // inverse transform + coil combine -> partial gradients per coil group
+  const BasisArgs b = basis_args(c, check_halt);
   tmark(c, TK_ADJ);
   if (!c->lines) {
-    RowArgs ra{};
-    ra.src = ra.dst = c->at<float2>(c->o_K);
-    ra.tw = c->at<float2>(c->o_twx);
-    ra.nrows = (long)p.nc * p.r * p.ny;
-    ra.scale = (float)(1.0 / sqrt((double)p.nx));
-    ra.check_halt = check_halt;
-    ra.st = c->st();
-    e = launch_rows(p.nx, ra, true, c->stream);
+    e = launch_basis(3, p.nx, b, p.nc * p.ny, 1, c->stream);
     if (e != hipSuccess) return e;
   }
-  ColAdjArgs d{};
-  d.src = c->at<float2>(c->o_K);
-  d.src_c_stride = (long)p.r * c->ua * p.nx;
-  d.src_img_stride = (long)c->ua * p.nx;
-  if (c->lines) {
-    d.rows = c->at<int32_t>(c->o_unitloc);
-    d.n_rows_ptr = &c->st()->n_units;
-  }
-  d.coils = c->coils;
-  d.n = c->n;
-  d.nx = p.nx;
-  d.nc = p.nc;
-  d.tw = c->at<float2>(c->o_twy);
-  d.dst = c->at<float2>(c->o_G);
-  d.dst_img_stride = c->n;
-  d.scale = (float)(1.0 / sqrt((double)p.ny));
-  d.check_halt = check_halt;
-  d.st = c->st();
-  e = launch_cols(p.ny, nullptr, &d, p.nx, p.r, p.nc, c->stream);
+  e = launch_basis(1, p.ny, b, p.nx / c->txx, c->adj_parts, c->stream);
   tmark(c, TK_ADJ);
   return e;
 }
 
 hipError_t one_iteration(altgdmin_ctx* c, float2* U, float2* U_prev) {
   const altgdmin_params& p = c->p;
-  hipError_t e = gradient_pieces(c, U, 1);
+  hipError_t e = gradient_pieces(c, 1);
   if (e != hipSuccess) return e;
   // Gram of [U grad], then the small QR work, then the update
   GramColsArgs g{};
-  g.A = U;
+  g.A = c->at<float2>(c->o_Ui);
   g.B = c->at<float2>(c->o_G);
   g.m1 = p.r;
   g.m2 = p.r;
   g.n = c->n;
   g.rows_per_block = c->qr_rows;
+  g.nparts = c->adj_parts;
+  g.part_stride = (long)c->n * p.r;
+  g.write_sum = 1;
   g.part = c->at<double2>(c->o_qpart);
   g.st = c->st();
   g.check_halt = 1;
   tmark(c, TK_QRGRAM);
-  e = launch_gram_cols(g, c->qr_nblk, c->fp64, c->stream);
+  e = launch_qr_gram(g, c->qr_nblk, c->fp64, c->stream);
   tmark(c, TK_QRGRAM);
   if (e != hipSuccess) return e;
   QrSmallArgs qa{};
@@ -406,6 +414,7 @@ hipError_t one_iteration(altgdmin_ctx* c, float2* U, float2* U_prev) {
   if (e != hipSuccess) return e;
   ApplyArgs aa{};
   aa.U = U;
+  aa.Ui = c->at<float2>(c->o_Ui);
   aa.G = c->at<float2>(c->o_G);
   aa.rinv = c->at<float2>(c->o_rinv);
   aa.U_prev = U_prev;
@@ -530,19 +539,22 @@ altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** ou
   c->n_loc = c->lines ? p.ny : c->n;
   c->nw = (p.q + 31) / 32;
   c->ua = p.ny;
-  c->nchunks = (p.m_max + AG_NT - 1) / AG_NT;
-  c->qr_nblk = std::max(1, std::min(256, c->n / 64));
+  c->gram_chunk = std::max(64, 2048 / p.nc);
+  c->nchunks = (p.m_max + c->gram_chunk - 1) / c->gram_chunk;
+  c->gram_cg = std::max(1, std::min(p.nc, 1024 / p.nx));
+  c->gram_ngroups = (p.nc + c->gram_cg - 1) / c->gram_cg;
+  c->txx = basis_txx(p.ny, p.nx, p.r);
+  {
+    const int tiles = p.nx / c->txx;
+    int parts = std::max(1, std::min(p.nc, (512 + tiles - 1) / tiles));
+    c->adj_cgs = (p.nc + parts - 1) / parts;
+    c->adj_parts = (p.nc + c->adj_cgs - 1) / c->adj_cgs;
+  }
+  c->qr_nblk = std::max(1, std::min(256, c->n / 256));
   c->qr_rows = ((long)c->n + c->qr_nblk - 1) / c->qr_nblk;
   c->qr_rows = (c->qr_rows + 63) / 64 * 64;
   c->qr_nblk = (int)((c->n + c->qr_rows - 1) / c->qr_rows);
   c->kc = std::min(p.q, 16);
-  // gram_lines staging: x-chunk and pair-chunk within 64 KB of LDS and the
-  // per-thread output budget
-  c->gram_xc = std::min(p.nx, 256);
-  const int nP = p.r * (p.r + 1) / 2;
-  int pc = (GRAM_OPT * AG_NT - nP) / p.r;
-  pc = std::min(pc, (8192 - c->gram_xc * p.r) / c->gram_xc);
-  c->gram_pc = std::max(1, std::min(pc, 32));
   if (p.q > 64) {  // spectral initialisation holds the q x q Gram in one workgroup
     delete c;
     return ALTGDMIN_EUNSUPPORTED;
@@ -584,7 +596,8 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
                      c->st());
   hipLaunchKernelGGL(k_inv_fill, dim3((c->width + 255) / 256, p.q), dim3(256), 0, s, c->mask, c->m_k,
                      c->width, c->per, c->at<uint32_t>(c->o_bitmap), c->nw, c->at<int32_t>(c->o_locptr),
-                     c->at<int2>(c->o_pairs), c->at<int32_t>(c->o_pairof), c->st());
+                     c->at<int32_t>(c->o_loc2unit), c->at<int2>(c->o_pairs), c->at<int32_t>(c->o_pairof),
+                     c->at<int32_t>(c->o_unitof), c->st());
   HIPCHK(hipGetLastError());
   if (c->y) {
     hipLaunchKernelGGL(k_ysq, dim3(p.q), dim3(AG_NT), 0, s, c->y, c->m_k, p.nc, p.m_max, c->at<double>(c->o_ysq));
@@ -594,7 +607,7 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
     if (c->lines) {
       RowArgs ra{};
       ra.src = c->y;
-      ra.dst = c->at<float2>(c->o_yh);
+      ra.dst = c->at<float2>(c->o_T);  // frame-major hybrid data, temporary
       ra.tw = c->at<float2>(c->o_twx);
       ra.nrows = (long)p.q * p.nc * c->lmax;
       ra.m_k = c->m_k;
@@ -603,6 +616,12 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
       ra.scale = (float)(1.0 / sqrt((double)p.nx));
       ra.st = c->st();
       HIPCHK(launch_rows(p.nx, ra, true, s));
+      // per-line layout: the largest pair count is q per line
+      hipLaunchKernelGGL(k_build_yu, dim3(p.q * c->width, p.nc), dim3(256), 0, s, c->at<float2>(c->o_T),
+                         c->at<int2>(c->o_pairs), c->mask, c->at<int32_t>(c->o_locptr), c->n_loc, c->width,
+                         p.nc, p.nx,
+                         c->lmax, c->at<float2>(c->o_yh), c->st());
+      HIPCHK(hipGetLastError());
     }
   }
   c->bound = 1;
@@ -669,6 +688,7 @@ altgdmin_status altgdmin_iterate(altgdmin_ctx* c, int32_t n_iter, void* d_U, voi
   if (n_iter <= 0) n_iter = p.t_max;
   int32_t t0 = 0;
   if (h_iters_done) HIPCHK(hipMemcpy(&t0, &c->st()->t, sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
   for (int t = 0; t < n_iter; ++t)
     HIPCHK(one_iteration(c, static_cast<float2*>(d_U), static_cast<float2*>(d_U_prev)));
   if (d_B) {
@@ -706,7 +726,8 @@ altgdmin_status altgdmin_set_eta(altgdmin_ctx* c, double eta) {
 altgdmin_status altgdmin_cost(altgdmin_ctx* c, const void* d_U, double* d_f) {
   if (!c || !d_U || !d_f) return ALTGDMIN_EINVAL;
   if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
-  HIPCHK(fwd_transform(c, static_cast<const float2*>(d_U), 0));
+  HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
+  HIPCHK(fwd_transform(c, 0));
   HIPCHK(gram_solve(c, 0));
   hipLaunchKernelGGL(k_cost_total, dim3(1), dim3(1), 0, c->stream, c->at<double>(c->o_cost), c->p.q, d_f,
                      c->st());
@@ -717,13 +738,17 @@ altgdmin_status altgdmin_gradient(altgdmin_ctx* c, const void* d_U, void* d_B, v
   if (!c || !d_U) return ALTGDMIN_EINVAL;
   if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
   const altgdmin_params& p = c->p;
-  HIPCHK(gradient_pieces(c, static_cast<const float2*>(d_U), 0));
+  HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
+  HIPCHK(gradient_pieces(c, 0));
+  if (c->adj_parts > 1)
+    hipLaunchKernelGGL(k_sum_parts, dim3(1024), dim3(256), 0, c->stream, c->at<float2>(c->o_G),
+                       (long)c->n * p.r, c->adj_parts, c->at<float2>(c->o_G), (long)c->n * p.r);
   if (d_B)
     hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, c->stream, c->at<float2>(c->o_B),
                        static_cast<float2*>(d_B), (long)p.q * p.r);
   if (d_G)
-    hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, c->stream, c->at<float2>(c->o_G),
-                       static_cast<float2*>(d_G), (long)c->n * p.r);
+    hipLaunchKernelGGL(k_to_colmajor, dim3(1024), dim3(256), 0, c->stream, c->at<float2>(c->o_G), p.r,
+                       (long)c->n, static_cast<float2*>(d_G));
   return map_hip(hipGetLastError());
 }
 

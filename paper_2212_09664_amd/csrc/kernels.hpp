@@ -59,6 +59,8 @@ struct ColAdjArgs {
   const float2* tw;
   float2* dst;
   long dst_img_stride;
+  int cgs;                    // coils per workgroup (0: all); group g writes dst + g*dst_part_stride
+  long dst_part_stride;
   const int32_t* m_k_scale;   // non-null: scale by 1/sqrt(m_k[img] * mbar)
   float scale;
   int accumulate;
@@ -70,6 +72,7 @@ hipError_t launch_rows(int N, const RowArgs& a, bool inv, hipStream_t st);
 hipError_t launch_cols(int N, const ColFwdArgs* f, const ColAdjArgs* d, int nx, int n_img, int nc,
                        hipStream_t st);
 int col_tile(int N, int nx);
+int col_tile_adj(int N, int nx);
 
 __global__ void k_twiddle(float2* tw, int N);
 __global__ void k_gather(const float2* img, long img_stride_c, long img_stride_k, const int32_t* mask,

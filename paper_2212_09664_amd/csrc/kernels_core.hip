@@ -7,10 +7,6 @@
 
 namespace ag {
 
-__device__ __forceinline__ void set_error(DevState* st, int code, int frame) {
-  if (atomicCAS(&st->err, 0, code) == 0) st->err_frame = frame;
-  st->halt = 1;
-}
 
 // ===========================================================================
 // setup: inverse sampling map
@@ -83,8 +79,8 @@ __global__ __launch_bounds__(1024) void k_inv_scan(const uint32_t* bitmap, int n
 }
 
 __global__ void k_inv_fill(const int32_t* mask, const int32_t* m_k, int width, int per,
-                           const uint32_t* bitmap, int nw, const int32_t* loc_ptr, int2* pairs,
-                           int32_t* pair_of, const DevState* st) {
+                           const uint32_t* bitmap, int nw, const int32_t* loc_ptr, const int32_t* loc2unit,
+                           int2* pairs, int32_t* pair_of, int32_t* unit_of, const DevState* st) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y;
   if (st->err) return;
   if (e >= m_k[k] / per) return;
@@ -96,6 +92,7 @@ __global__ void k_inv_fill(const int32_t* mask, const int32_t* m_k, int width, i
   const int pos = loc_ptr[loc] + rank;
   pairs[pos] = make_int2(k, e);
   pair_of[(long)k * width + e] = pos;
+  unit_of[(long)k * width + e] = loc2unit[loc];
 }
 
 // ||y_k||^2 in FP64, one workgroup per frame
@@ -167,15 +164,6 @@ __global__ void k_state_set_eta(DevState* st, double eta) {
 // Rows of W_c(u,:,:) and the samples' y' rows are staged in LDS; every
 // thread owns a few outputs and forms their dot products over x.
 // ===========================================================================
-__device__ __forceinline__ void tri_index(int o, int r, int& i, int& j) {
-  i = 0;
-  int rem = o;
-  while (rem >= r - i) {
-    rem -= r - i;
-    ++i;
-  }
-  j = i + rem;
-}
 
 template <typename ACC>
 struct Acc2;
@@ -203,246 +191,6 @@ struct Acc2<double> {
   __device__ static double2 to_d(T v) { return v; }
 };
 
-template <typename ACC>
-__global__ __launch_bounds__(AG_NT) void k_gram_lines(GramLinesArgs a) {
-  using A2 = Acc2<ACC>;
-  extern __shared__ float2 sm[];
-  const int u = blockIdx.x, tid = threadIdx.x;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
-  if (u >= a.st->n_units) return;
-  const int r = a.r, nx = a.nx, XC = a.xc, PC = a.pc;
-  float2* Ws = sm;            // [XC][r]
-  float2* Ys = sm + XC * r;   // [PC][XC]
-  const int ky = a.unit_loc[u];
-  const int p0 = a.loc_ptr[ky], np = a.loc_ptr[ky + 1] - p0;
-  const int nP = r * (r + 1) / 2;
-  for (int pc = 0; pc == 0 || pc < np; pc += PC) {
-    const int npc = min(PC, np - pc);
-    const int nPo = (pc == 0) ? nP : 0;
-    const int nout = nPo + npc * r;
-    typename A2::T acc[GRAM_OPT];
-#pragma unroll
-    for (int t = 0; t < GRAM_OPT; ++t) acc[t] = A2::zero();
-    for (int c = 0; c < a.nc; ++c) {
-      for (int x0 = 0; x0 < nx; x0 += XC) {
-        for (int g = tid; g < XC * r; g += AG_NT) {
-          const int j = g / XC, x = g % XC;
-          Ws[x * r + j] = a.W[(((long)c * r + j) * a.ua + u) * nx + x0 + x];
-        }
-        for (int g = tid; g < npc * XC; g += AG_NT) {
-          const int p = g / XC, x = g % XC;
-          const int2 kl = a.pairs[p0 + pc + p];
-          Ys[p * XC + x] = a.yh[(((long)kl.x * a.nc + c) * a.lmax + kl.y) * nx + x0 + x];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int t = 0; t < GRAM_OPT; ++t) {
-          const int o = tid + t * AG_NT;
-          if (o < nout) {
-            if (o < nPo) {
-              int i, j;
-              tri_index(o, r, i, j);
-              for (int x = 0; x < XC; ++x) acc[t] = A2::fma_cj(acc[t], Ws[x * r + i], Ws[x * r + j]);
-            } else {
-              const int oo = o - nPo, p = oo / r, j = oo % r;
-              for (int x = 0; x < XC; ++x) acc[t] = A2::fma_cj(acc[t], Ws[x * r + j], Ys[p * XC + x]);
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < GRAM_OPT; ++t) {
-      const int o = tid + t * AG_NT;
-      if (o < nout) {
-        double2 v = A2::to_d(acc[t]);
-        if (o < nPo) {
-          int i, j;
-          tri_index(o, r, i, j);
-          a.P[((long)u * r + i) * r + j] = v;
-          a.P[((long)u * r + j) * r + i] = dconj(v);
-        } else {
-          const int oo = o - nPo, p = oo / r, j = oo % r;
-          a.hp[(long)(p0 + pc + p) * r + j] = v;
-        }
-      }
-    }
-  }
-}
-
-// ===========================================================================
-// per-frame Gram and right-hand side, general masks: directly per frame,
-// over chunks of the frame's samples (partials per chunk).
-// ===========================================================================
-template <typename ACC>
-__global__ __launch_bounds__(AG_NT) void k_gram_index(GramIndexArgs a) {
-  using A2 = Acc2<ACC>;
-  __shared__ float2 Ws[AG_NT * 16];
-  __shared__ float2 ys[AG_NT];
-  const int k = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
-  const int r = a.r;
-  const int nP = r * (r + 1) / 2, nout = nP + r;
-  const int mk = a.m_k[k];
-  const int i0 = ch * AG_NT;
-  typename A2::T acc[GRAM_OPT];
-#pragma unroll
-  for (int t = 0; t < GRAM_OPT; ++t) acc[t] = A2::zero();
-  const int i = i0 + tid;
-  const int loc = (i < mk) ? a.mask[(long)k * a.m_max + i] : -1;
-  for (int c = 0; c < a.nc; ++c) {
-    for (int j = 0; j < r; ++j)
-      Ws[tid * r + j] = (loc >= 0) ? a.W[((long)c * r + j) * a.n + loc] : make_float2(0.f, 0.f);
-    ys[tid] = (loc >= 0) ? a.y[((long)k * a.nc + c) * a.m_max + i] : make_float2(0.f, 0.f);
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < GRAM_OPT; ++t) {
-      const int o = tid + t * AG_NT;
-      if (o < nout) {
-        if (o < nP) {
-          int ii, jj;
-          tri_index(o, r, ii, jj);
-          for (int x = 0; x < AG_NT; ++x) acc[t] = A2::fma_cj(acc[t], Ws[x * r + ii], Ws[x * r + jj]);
-        } else {
-          const int jj = o - nP;
-          for (int x = 0; x < AG_NT; ++x) acc[t] = A2::fma_cj(acc[t], Ws[x * r + jj], ys[x]);
-        }
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int t = 0; t < GRAM_OPT; ++t) {
-    const int o = tid + t * AG_NT;
-    if (o < nout) a.part[((long)k * gridDim.x + ch) * nout + o] = A2::to_d(acc[t]);
-  }
-}
-
-// ===========================================================================
-// batched LS solve: b_k = G_k^{-1} h_k by Cholesky, one wavefront per frame;
-// also cost_k = ||y_k||^2 - Re(h_k^H b_k).
-// ===========================================================================
-template <typename T>
-struct Cx;
-template <>
-struct Cx<float> {
-  using T2 = float2;
-  __device__ static T2 from(double2 v) { return d2f(v); }
-  __device__ static T2 mul(T2 a, T2 b) { return cmul(a, b); }
-  __device__ static T2 cjm(T2 a, T2 b) { return cjmul(a, b); }
-  __device__ static T2 sub(T2 a, T2 b) { return csub(a, b); }
-  __device__ static T2 scale(T2 a, float s) { return cscale(a, s); }
-  __device__ static T2 zero() { return make_float2(0.f, 0.f); }
-  static constexpr double tiny = 1e-6;
-};
-template <>
-struct Cx<double> {
-  using T2 = double2;
-  __device__ static T2 from(double2 v) { return v; }
-  __device__ static T2 mul(T2 a, T2 b) { return dmul(a, b); }
-  __device__ static T2 cjm(T2 a, T2 b) { return djmul(a, b); }
-  __device__ static T2 sub(T2 a, T2 b) { return dsub(a, b); }
-  __device__ static T2 scale(T2 a, double s) { return make_double2(a.x * s, a.y * s); }
-  __device__ static T2 zero() { return make_double2(0.0, 0.0); }
-  static constexpr double tiny = 1e-13;
-};
-
-template <typename T>
-__global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
-  using C = Cx<T>;
-  using T2 = typename C::T2;
-  __shared__ T2 G[16 * 16];
-  __shared__ T2 h[16];
-  __shared__ T2 z[16];
-  __shared__ int bad;
-  const int k = blockIdx.x, tid = threadIdx.x, r = a.r;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
-  if (tid == 0) bad = 0;
-  if (a.kind == 0) {  // LINES: sum the per-line Grams and per-sample rhs
-    const int L = a.m_k[k] / a.nx;
-    const int32_t* mk = a.mask + (long)k * a.width;
-    const int32_t* po = a.pair_of + (long)k * a.width;
-    for (int e = tid; e < r * r; e += 64) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int l = 0; l < L; ++l) s = dadd(s, a.P[(long)a.loc2unit[mk[l]] * r * r + e]);
-      G[(e / r) * 16 + (e % r)] = C::from(s);
-    }
-    for (int j = tid; j < r; j += 64) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int l = 0; l < L; ++l) s = dadd(s, a.hp[(long)po[l] * r + j]);
-      h[j] = C::from(s);
-    }
-  } else {  // INDEX: sum the chunk partials
-    const int nP = r * (r + 1) / 2, nout = nP + r;
-    for (int o = tid; o < nout; o += 64) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int ch = 0; ch < a.nchunks; ++ch) s = dadd(s, a.P[((long)k * a.nchunks + ch) * nout + o]);
-      if (o < nP) {
-        int i, j;
-        tri_index(o, r, i, j);
-        G[i * 16 + j] = C::from(s);
-        G[j * 16 + i] = C::from(dconj(s));
-      } else {
-        h[o - nP] = C::from(s);
-      }
-    }
-  }
-  __syncthreads();
-  // right-looking Cholesky G = L L^H (lower part of G overwritten by L)
-  double dmax = 0.0;
-  for (int i = 0; i < r; ++i) dmax = fmax(dmax, (double)G[i * 16 + i].x);
-  for (int j = 0; j < r; ++j) {
-    const double d = (double)G[j * 16 + j].x;
-    if (!(d > C::tiny * dmax) || !isfinite(d)) {
-      if (tid == 0) bad = 1;
-    }
-    __syncthreads();
-    if (bad) break;
-    const T ljj = (T)sqrt(d);
-    if (tid == 0) G[j * 16 + j] = T2{ljj, (T)0};
-    for (int i = j + 1 + tid; i < r; i += 64) G[i * 16 + j] = C::scale(G[i * 16 + j], (T)1 / ljj);
-    __syncthreads();
-    const int m = r - j - 1;
-    for (int e = tid; e < m * m; e += 64) {
-      const int i = j + 1 + e / m, c2 = j + 1 + e % m;
-      if (c2 <= i) {
-        // G[i][c2] -= L[i][j] conj(L[c2][j])
-        T2 lij = G[i * 16 + j], lcj = G[c2 * 16 + j];
-        T2 prod = C::mul(lij, T2{lcj.x, -lcj.y});
-        G[i * 16 + c2] = C::sub(G[i * 16 + c2], prod);
-      }
-    }
-    __syncthreads();
-  }
-  if (bad) {
-    if (tid == 0) set_error(a.st, 4 /*ENOTPD*/, k);
-    return;
-  }
-  if (tid == 0) {
-    for (int i = 0; i < r; ++i) {  // L z = h
-      T2 s = h[i];
-      for (int m = 0; m < i; ++m) s = C::sub(s, C::mul(G[i * 16 + m], z[m]));
-      z[i] = C::scale(s, (T)1 / G[i * 16 + i].x);
-    }
-    for (int i = r - 1; i >= 0; --i) {  // L^H b = z
-      T2 s = z[i];
-      for (int m = i + 1; m < r; ++m) s = C::sub(s, C::cjm(G[m * 16 + i], z[m]));
-      z[i] = C::scale(s, (T)1 / G[i * 16 + i].x);
-    }
-    double hb = 0.0;
-    bool fin = true;
-    for (int j = 0; j < r; ++j) {
-      // Re(conj(h_j) b_j)
-      hb += (double)h[j].x * (double)z[j].x + (double)h[j].y * (double)z[j].y;
-      fin = fin && isfinite((double)z[j].x) && isfinite((double)z[j].y);
-      a.B[(long)k * r + j] = make_float2((float)z[j].x, (float)z[j].y);
-    }
-    a.cost_k[k] = a.ysq_k[k] - hb;
-    if (!fin) set_error(a.st, 5 /*ENONFINITE*/, k);
-  }
-}
-
 // ===========================================================================
 // gradient fold, 1D Cartesian: per sampled line u (ky) and coil c
 //   K_c(u,x,:) = W_c(u,x,:) S_u - sum_{(k,l) on ky} y'_{k,c}(l,x) conj(b_k),
@@ -466,20 +214,17 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines(FoldArgs a) {
     float2 b = a.B[(long)kl[p].x * r + j];
     bc[p * RT + j] = make_float2(b.x, -b.y);
   }
+  __syncthreads();
+  // S_u[i][j] = sum_p b_i conj(b_j) = sum_p conj(bc_i) bc_j
   for (int e = tid; e < r * r; e += AG_NT) {
     const int i = e / r, j = e % r;
     float2 s = make_float2(0.f, 0.f);
-    for (int p = 0; p < np; ++p) {
-      const float2* b = a.B + (long)kl[p].x * r;
-      s = cadd(s, cmulj(b[i], b[j]));
-    }
+    for (int p = 0; p < np; ++p) s = cadd(s, cjmul(bc[p * RT + i], bc[p * RT + j]));
     S[i * RT + j] = s;
   }
   __syncthreads();
-  const int c0 = blockIdx.y * a.cg;
-  const int c1 = min(a.nc, c0 + a.cg);
-  for (int g = tid; g < (c1 - c0) * nx; g += AG_NT) {
-    const int c = c0 + g / nx, x = g % nx;
+  const int c = blockIdx.y;
+  for (int x = tid; x < nx; x += AG_NT) {
     float2 w[RT], kk[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) w[i] = (i < r) ? a.W[(((long)c * r + i) * a.ua + u) * nx + x] : make_float2(0.f, 0.f);
@@ -491,6 +236,7 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines(FoldArgs a) {
         if (i < r) s = cadd(s, cmul(w[i], S[i * RT + j]));
       kk[j] = s;
     }
+#pragma unroll 4
     for (int p = 0; p < np; ++p) {
       const float2 yv = a.yh[(((long)kl[p].x * a.nc + c) * a.lmax + kl[p].y) * nx + x];
 #pragma unroll
@@ -605,8 +351,9 @@ __device__ double block_sum(double v, double* red) {
 // eigenvectors as columns when non-null.
 __device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch* js, int max_sweeps) {
   const int tid = threadIdx.x, NT = blockDim.x;
-  if (V && tid < n)
-    for (int j = 0; j < n; ++j) V[(long)tid * n + j] = make_double2(tid == j ? 1.0 : 0.0, 0.0);
+  if (V)
+    for (int e = tid; e < n * n; e += NT) V[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
+  __syncthreads();
   const int Q = n + (n & 1);
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double off = 0.0, tot = 0.0;
@@ -619,7 +366,7 @@ __device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch*
     }
     off = block_sum(off, js->red);
     tot = block_sum(tot, js->red);
-    if (!(off > 1e-30 * tot)) break;
+    if (!(off > 1e-26 * tot)) break;
     for (int s = 0; s < Q - 1; ++s) {
       for (int i = tid; i < Q / 2; i += NT) {
         int p, q;
@@ -679,15 +426,16 @@ __device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch*
         A[p * ld + k] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
         A[q * ld + k] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
       }
-      if (V && tid < n) {
-        for (int i = 0; i < Q / 2; ++i) {
+      if (V) {  // V <- V G (columns p, q), V in LDS
+        for (int it = tid; it < n * (Q / 2); it += NT) {
+          const int i = it / n, k = it % n;
           const int p = js->p[i], q = js->q[i];
           if (q >= n || js->s[i] == 0.0) continue;
           const double c = js->c[i], sn = js->s[i];
           const double2 e = js->e[i];
-          const double2 x = V[(long)tid * n + p], y = dmul(V[(long)tid * n + q], e);
-          V[(long)tid * n + p] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
-          V[(long)tid * n + q] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+          const double2 x = V[k * n + p], y = dmul(V[k * n + q], e);
+          V[k * n + p] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+          V[k * n + q] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
         }
       }
       __syncthreads();
@@ -734,7 +482,7 @@ __device__ bool chol_rinv(double2* M, int r, double2* Ri) {
 // from the blocks; R = chol(.)^H, R^{-1}; SD(U, U+) from r x r data.
 // mode 1: plain CholeskyQR of U (no gradient).
 // ===========================================================================
-__global__ __launch_bounds__(AG_NT) void k_qr_small(QrSmallArgs a) {
+__global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
   __shared__ double2 UU[256], UG[256], GG[256], Gh[256], Ri[256], Tm[256];
   __shared__ JacobiScratch js;
   __shared__ int s_ok;
@@ -746,10 +494,23 @@ __global__ __launch_bounds__(AG_NT) void k_qr_small(QrSmallArgs a) {
   }
   const int m = a.mode == 0 ? 2 * r : r;
   const int nout = m * (m + 1) / 2;
-  for (int o = tid; o < nout; o += AG_NT) {
+  // sum the block partials: thread = (output, slice of blocks)
+  __shared__ double2 red2[1024];
+  const int NTH = blockDim.x;
+  const int NS = max(1, NTH / nout);
+  const int OW = NTH / NS;
+  for (int o0 = 0; o0 < nout; o0 += OW) {
+    const int o = o0 + tid % OW, sl = tid / OW;
     double2 s = make_double2(0.0, 0.0);
-    for (int b = 0; b < a.nblk; ++b) s = dadd(s, a.part[(long)b * nout + o]);
-    int i, j;
+    if (o < nout && sl < NS) {
+#pragma unroll 8
+      for (int b = sl; b < a.nblk; b += NS) s = dadd(s, a.part[(long)b * nout + o]);
+    }
+    red2[tid] = s;
+    __syncthreads();
+    if (tid < OW && o < nout) {
+      for (int q2 = 1; q2 < NS; ++q2) s = dadd(s, red2[tid + q2 * OW]);
+      int i, j;
     tri_index(o, m, i, j);
     // entry (i, j), i <= j, of [U G]^H [U G]
     if (j < r) {
@@ -761,6 +522,16 @@ __global__ __launch_bounds__(AG_NT) void k_qr_small(QrSmallArgs a) {
       GG[(i - r) * 16 + (j - r)] = s;
       GG[(j - r) * 16 + (i - r)] = dconj(s);
     }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  __shared__ double s_f;
+  if (a.mode == 0) {  // f = sum_k cost_k, in parallel
+    double v = 0.0;
+    for (int k = tid; k < a.q; k += blockDim.x) v += a.cost_k[k];
+    v = block_sum(v, js.red);
+    if (tid == 0) s_f = v;
   }
   __syncthreads();
   if (a.mode == 1) {
@@ -848,8 +619,7 @@ __global__ __launch_bounds__(AG_NT) void k_qr_small(QrSmallArgs a) {
       const double sd2 = fmax(0.0, (double)r - fro);
       double tr = 0.0;
       for (int i = 0; i < r; ++i) tr += GG[i * 16 + i].x;
-      double f = 0.0;
-      for (int k = 0; k < a.q; ++k) f += a.cost_k[k];
+      const double f = s_f;
       st->sd = sqrt(sd2);
       st->grad_norm = sqrt(tr);
       st->f = f;
@@ -884,7 +654,7 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
       float2 u = a.U[(long)i * a.n + p];
       if (a.U_prev) a.U_prev[(long)i * a.n + p] = u;
       if (a.mode == 0) {
-        const float2 g = a.G[(long)i * a.n + p];
+        const float2 g = a.G[p * r + i];  // gradient is pixel-major
         u = make_float2(u.x - eta * g.x, u.y - eta * g.y);
       }
       uh[i] = u;
@@ -899,6 +669,7 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 #pragma unroll
       for (int i = 0; i <= j; ++i) s = cadd(s, cmul(uh[i], Ri[i * RT + j]));
       a.U[(long)j * a.n + p] = s;
+      if (a.Ui) a.Ui[p * r + j] = s;
     }
   }
 }
@@ -909,8 +680,9 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 // are the top-r left singular vectors of X_0.
 // ===========================================================================
 __global__ __launch_bounds__(AG_NT) void k_init_eig(InitEigArgs a) {
-  extern __shared__ double2 A[];  // q x q
+  extern __shared__ double2 A[];  // q x q matrix, then q x q eigenvectors
   __shared__ JacobiScratch js;
+  double2* V = A + a.q * a.q;
   __shared__ int idx[16];
   __shared__ double lam_s[16];
   const int tid = threadIdx.x, q = a.q, r = a.r;
@@ -926,7 +698,7 @@ __global__ __launch_bounds__(AG_NT) void k_init_eig(InitEigArgs a) {
   __syncthreads();
   if (tid < q) A[tid * q + tid].y = 0.0;
   __syncthreads();
-  jacobi_eig(A, q, q, a.V, &js, 60);
+  jacobi_eig(A, q, q, V, &js, 60);
   __syncthreads();
   if (tid == 0) {
     // top-r eigenvalues, descending
@@ -950,7 +722,7 @@ __global__ __launch_bounds__(AG_NT) void k_init_eig(InitEigArgs a) {
   if (a.st->err) return;
   for (int e = tid; e < q * r; e += AG_NT) {
     const int k = e / r, j = e % r;
-    const double2 v = a.V[(long)k * q + idx[j]];
+    const double2 v = V[k * q + idx[j]];
     const double sc = 1.0 / sqrt(lam_s[j]);
     a.Vs[k * r + j] = make_float2((float)(v.x * sc), (float)(v.y * sc));
   }
@@ -992,31 +764,6 @@ __global__ void k_cost_total(const double* cost_k, int q, double* out, DevState*
 // ---------------------------------------------------------------------------
 // launchers (explicit instantiations behind plain functions)
 // ---------------------------------------------------------------------------
-hipError_t launch_gram_lines(const GramLinesArgs& a, int ny, bool fp64, hipStream_t s) {
-  const size_t lds = (size_t)(a.xc * a.r + a.pc * a.xc) * sizeof(float2);
-  if (fp64)
-    hipLaunchKernelGGL(k_gram_lines<double>, dim3(ny), dim3(AG_NT), lds, s, a);
-  else
-    hipLaunchKernelGGL(k_gram_lines<float>, dim3(ny), dim3(AG_NT), lds, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp64, hipStream_t s) {
-  if (fp64)
-    hipLaunchKernelGGL(k_gram_index<double>, dim3(nchunks, q), dim3(AG_NT), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_gram_index<float>, dim3(nchunks, q), dim3(AG_NT), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s) {
-  if (fp64)
-    hipLaunchKernelGGL(k_solve<double>, dim3(q), dim3(64), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_solve<float>, dim3(q), dim3(64), 0, s, a);
-  return hipGetLastError();
-}
-
 hipError_t launch_fold(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s) {
   const dim3 g(grid_x, grid_y);
   if (lines) {
@@ -1048,12 +795,16 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_qr_small, dim3(1), dim3(AG_NT), 0, s, a);
+  hipLaunchKernelGGL(k_qr_small, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)a.q * a.q * sizeof(double2);
+  const size_t lds = 2 * (size_t)a.q * a.q * sizeof(double2);
+  if (lds > 48 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_init_eig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_init_eig, dim3(1), dim3(AG_NT), lds, s, a);
   return hipGetLastError();
 }

@@ -12,30 +12,33 @@ struct JacobiScratch {
   int p[64], q[64];
   double c[64], s[64];
   double2 e[64];
-  double red[AG_NT];
+  double red[1024];
 };
 
 struct GramLinesArgs {
-  const float2* W;       // [c][j][u][x], ua rows per (c, j)
-  const float2* yh;      // hybrid data [k][c][l][x]
+  const float2* W;       // [c][u][x][j], ua rows per coil
+  const float2* yu;      // per-line data [c][x][p]
   const int2* pairs;
   const int32_t* loc_ptr;
   const int32_t* unit_loc;
   int nc, r, nx, lmax, ua;
-  int xc, pc;            // x-chunk and pair-chunk staged in LDS
-  double2* P;            // [u][r][r]
-  double2* hp;           // [pair][r]
+  int cg;                // coils per workgroup (coil group)
+  int nx_shift;          // log2(nx)
+  long npairs;           // allocated pairs per group in hp
+  double2* P;            // [g][u][r][r]
+  double2* hp;           // [g][pair][r]
   DevState* st;
   int check_halt;
 };
 
 struct GramIndexArgs {
-  const float2* W;       // [c][j][n]
+  const float2* W;       // [c][loc][j]
   const float2* y;       // [k][c][m_max]
   const int32_t* mask;
   const int32_t* m_k;
   int nc, r, n, m_max;
-  double2* part;         // [k][chunk][r(r+1)/2 + r]
+  int chunk;             // samples per workgroup
+  double2* part;         // [k][chunk][r*r + r]
   DevState* st;
   int check_halt;
 };
@@ -47,7 +50,10 @@ struct SolveArgs {
   const int32_t* m_k;
   const int32_t* loc2unit;
   const int32_t* pair_of;
+  const int32_t* unit_of;    // LINES: sampled-line index of (frame k, line l)
   int width, nx, r, kind, nchunks;
+  int ngroups, ua;       // LINES: coil groups and lines allocated per group in P
+  long npairs;           // LINES: pairs allocated per group in hp
   const double* ysq_k;
   float2* B;             // r x q
   double* cost_k;
@@ -55,8 +61,27 @@ struct SolveArgs {
   int check_halt;
 };
 
+struct BasisArgs {
+  const float2* U;       // n x r basis, pixel-major [p][j]
+  float2* W;             // [c][row][x][j]
+  float2* K;             // [c][row][x][j]
+  float2* G;             // [part][p][j]
+  const float2* coils;
+  long n;
+  int nx, r, nc, ua, txx, cgs;
+  long part_stride;
+  const int32_t* rows;        // sampled rows (ky) of W / K, or null: all rows
+  const int32_t* n_rows_ptr;
+  const float2* tw;           // twiddles along y
+  const float2* tw_x;         // twiddles along x
+  float scale, scale_x;
+  DevState* st;
+  int check_halt;
+};
+
 struct FoldArgs {
   const float2* W;
+  const float2* yu;      // LINES: per-line data [c][x][p]
   const float2* yh;      // LINES: hybrid data
   const float2* y;       // INDEX: measurements
   const float2* B;
@@ -75,6 +100,9 @@ struct GramColsArgs {
   int m1, m2;
   long n;
   long rows_per_block;
+  int nparts;            // B is the sum of nparts arrays at stride part_stride
+  long part_stride;
+  int write_sum;         // store the summed B back into part 0
   double2* part;
   DevState* st;
   int check_halt;
@@ -93,8 +121,9 @@ struct QrSmallArgs {
 };
 
 struct ApplyArgs {
-  float2* U;
-  const float2* G;
+  float2* U;             // n x r column-major (C ABI layout)
+  float2* Ui;            // n x r pixel-major copy for the next iteration (may be null)
+  const float2* G;       // pixel-major gradient
   const float2* rinv;
   float2* U_prev;
   long n;
@@ -110,12 +139,28 @@ struct InitEigArgs {
   DevState* st;
 };
 
+__device__ __forceinline__ void set_error(DevState* st, int code, int frame) {
+  if (atomicCAS(&st->err, 0, code) == 0) st->err_frame = frame;
+  st->halt = 1;
+}
+
+__device__ __forceinline__ void tri_index(int o, int r, int& i, int& j) {
+  i = 0;
+  int rem = o;
+  while (rem >= r - i) {
+    rem -= r - i;
+    ++i;
+  }
+  j = i + rem;
+}
+
 __global__ void k_inv_bitmap(const int32_t* mask, const int32_t* m_k, int width, int per, int n_loc,
                              uint32_t* bitmap, int nw, DevState* st);
 __global__ void k_inv_scan(const uint32_t* bitmap, int nw, int n_loc, int32_t* loc_ptr, int32_t* loc2unit,
                            int32_t* unit_loc, DevState* st);
 __global__ void k_inv_fill(const int32_t* mask, const int32_t* m_k, int width, int per, const uint32_t* bitmap,
-                           int nw, const int32_t* loc_ptr, int2* pairs, int32_t* pair_of, const DevState* st);
+                           int nw, const int32_t* loc_ptr, const int32_t* loc2unit, int2* pairs, int32_t* pair_of,
+                           int32_t* unit_of, const DevState* st);
 __global__ void k_ysq(const float2* y, const int32_t* m_k, int nc, int m_max, double* ysq_k);
 __global__ void k_init_stats(const double* ysq_k, const int32_t* m_k, int q, double trunc_c, DevState* st);
 __global__ void k_state_reset(DevState* st, int full);
@@ -126,12 +171,22 @@ __global__ void k_copy(const float2* src, float2* dst, long n);
 __global__ void k_cost_total(const double* cost_k, int q, double* out, DevState* st);
 __global__ void k_init_eig(InitEigArgs a);
 
-hipError_t launch_gram_lines(const GramLinesArgs& a, int ny, bool fp64, hipStream_t s);
+hipError_t launch_gram_lines(const GramLinesArgs& a, int ny, int ngroups, int max_pairs, bool fp64,
+                             hipStream_t s);
 hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp64, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s);
 hipError_t launch_fold(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
 hipError_t launch_gram_cols(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);
+hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);
+__global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* dst, long n);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
+hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s);
+hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
+int basis_txx(int N, int nx, int r);
+__global__ void k_build_yu(const float2* yh, const int2* pairs, const int32_t* mask, const int32_t* loc_ptr,
+                           int n_loc, int width, int nc, int nx, int lmax, float2* yu, const DevState* st);
+__global__ void k_to_colmajor(const float2* src, int r, long n, float2* dst);
+__global__ void k_to_pixmajor(const float2* src, int r, long n, float2* dst);
 hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s);
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s);
 

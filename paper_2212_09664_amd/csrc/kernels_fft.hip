@@ -74,10 +74,23 @@ __global__ __launch_bounds__(AG_NT) void k_cols_fwd(ColFwdArgs a) {
   if (a.st->err || (a.check_halt && a.st->halt)) return;
   const float2* src = a.src + (long)img * a.src_img_stride;
   const float2* coil = a.coils + (long)c * a.n;
-  for (int g = tid; g < N * TX; g += AG_NT) {
-    const int y = g / TX, col = g % TX;
-    const long p = (long)y * a.nx + x0 + col;
-    s[g] = cmul(coil[p], src[p]);
+  {
+    constexpr int IT = (N * TX + AG_NT - 1) / AG_NT;
+    float2 cv[IT], uv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int g = tid + it * AG_NT;
+      if (g < N * TX) {
+        const long p = (long)(g / TX) * a.nx + x0 + (g % TX);
+        cv[it] = coil[p];
+        uv[it] = src[p];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int g = tid + it * AG_NT;
+      if (g < N * TX) s[g] = cmul(cv[it], uv[it]);
+    }
   }
   __syncthreads();
   fft_lds<N, TX, AG_NT, false>(s, a.tw);
@@ -134,16 +147,29 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
   float2 acc[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) acc[it] = make_float2(0.f, 0.f);
-  for (int c = 0; c < a.nc; ++c) {
+  const int cb = blockIdx.z * a.cgs, ce = min(a.nc, cb + a.cgs);
+  for (int c = cb; c < ce; ++c) {
     const float2* src = a.src + (long)c * a.src_c_stride + (long)img * a.src_img_stride;
     if (!full) {
       for (int g = tid; g < N * TX; g += AG_NT) s[g] = make_float2(0.f, 0.f);
       __syncthreads();
     }
-    for (int g = tid; g < n_rows * TX; g += AG_NT) {
-      const int u = g / TX, col = g % TX;
-      const int ky = full ? u : rows[u];
-      s[ky * TX + col] = src[(long)u * a.nx + x0 + col];
+    for (int g0 = 0; g0 < n_rows * TX; g0 += 8 * AG_NT) {
+      float2 v[8];
+      int d[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int g = g0 + tid + j * AG_NT;
+        d[j] = -1;
+        if (g < n_rows * TX) {
+          const int u = g / TX, col = g % TX;
+          d[j] = (full ? u : rows[u]) * TX + col;
+          v[j] = src[(long)u * a.nx + x0 + col];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (d[j] >= 0) s[d[j]] = v[j];
     }
     __syncthreads();
     fft_lds<N, TX, AG_NT, true>(s, a.tw);
@@ -160,7 +186,7 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
   }
   float sc = a.scale;
   if (a.m_k_scale) sc *= (float)(1.0 / sqrt((double)a.m_k_scale[img] * a.st->mbar));
-  float2* dst = a.dst + (long)img * a.dst_img_stride;
+  float2* dst = a.dst + (long)img * a.dst_img_stride + (long)blockIdx.z * a.dst_part_stride;
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int g = tid + it * AG_NT;
@@ -242,21 +268,30 @@ int col_tile(int N, int nx) {
   return tx < nx ? tx : nx;
 }
 
+// the adjoint transform runs half-width tiles: twice the workgroups
+int col_tile_adj(int N, int nx) {
+  int tx = col_tile(N, nx) / 2;
+  return tx < 8 ? (nx < 8 ? nx : 8) : tx;
+}
+
 template <int N, int TX>
 static hipError_t launch_cols_tx(const ColFwdArgs* f, const ColAdjArgs* d, int n_img, int nc, hipStream_t st) {
   if (f) {
     dim3 grid((unsigned)(f->nx / TX), (unsigned)n_img, (unsigned)nc);
     hipLaunchKernelGGL((k_cols_fwd<N, TX>), grid, dim3(AG_NT), 0, st, *f);
   } else {
-    dim3 grid((unsigned)(d->nx / TX), (unsigned)n_img);
-    hipLaunchKernelGGL((k_cols_adj<N, TX>), grid, dim3(AG_NT), 0, st, *d);
+    const int cgs = d->cgs > 0 ? d->cgs : d->nc;
+    dim3 grid((unsigned)(d->nx / TX), (unsigned)n_img, (unsigned)((d->nc + cgs - 1) / cgs));
+    ColAdjArgs dd = *d;
+    dd.cgs = cgs;
+    hipLaunchKernelGGL((k_cols_adj<N, TX>), grid, dim3(AG_NT), 0, st, dd);
   }
   return hipGetLastError();
 }
 
 template <int N>
 static hipError_t launch_cols_n(const ColFwdArgs* f, const ColAdjArgs* d, int nx, int n_img, int nc, hipStream_t st) {
-  const int tx = col_tile(N, nx);
+  const int tx = f ? col_tile(N, nx) : col_tile_adj(N, nx);
   if constexpr (N <= 128) {
     if (tx == 32) return launch_cols_tx<N, 32>(f, d, n_img, nc, st);
   }

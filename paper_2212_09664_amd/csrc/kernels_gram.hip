@@ -1,0 +1,575 @@
+// The LS step of Algorithm 2 on the matrix cores: per-frame Gram
+// G_k = (A_k U)^H (A_k U) and right-hand side h_k = (A_k U)^H y_k, then the
+// batched r x r Cholesky solves b_k = G_k^{-1} h_k.
+//
+// Complex contractions run as real ones on MFMA: with the K sample rows of
+// W (the coil-weighted, transformed basis at the sampled k-space positions)
+// embedded as the real K x 2r matrix A = [Re W, Im W],
+//   A^T A  gives  Re P = C[i][j] + C[r+i][r+j],  Im P = C[i][r+j] - C[r+i][j],
+// and with B = [Re y_1..y_8, Im y_1..y_8] (8 samples' data as 16 columns)
+//   A^T B  gives  Re h_{p,j} = C[j][p] + C[r+j][8+p], Im h_{p,j} = C[j][8+p] - C[r+j][p].
+// Each 16x16 output tile is one v_mfma_*_16x16x4 accumulator (4 rows of K
+// per instruction); the A operand is shared by the P tile and every h tile.
+// FP32 MFMA for the plain form, FP64 MFMA for the mixed form.
+#include <algorithm>
+
+#include "kernels_core.hpp"
+
+namespace ag {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mma;
+template <>
+struct Mma<float> {
+  using V = f4v;
+  __device__ static V zero() { return V{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  // accumulator register v of lane l holds D[row(l, v)][l % 16]
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <>
+struct Mma<double> {
+  using V = d4v;
+  __device__ static V zero() { return V{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+
+// Lane layout of the 16x16x4 MFMA (both types): lane l holds A[l%16][l/16] and
+// B[l/16][l%16].  The accumulator differs: register v of lane l holds
+// D[4*(l/16) + v][l%16] for f32 and D[4*v + l/16][l%16] for f64.
+
+// Sum the 4 waves' tile (one 16x16 accumulator per wave) into LDS buffer t.
+template <typename T>
+__device__ __forceinline__ void tile_reduce(T* t, const typename Mma<T>::V& acc, int wave, int lane) {
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int idx = Mma<T>::row(lane, v) * 16 + (lane & 15);
+        t[idx] = (w == 0) ? acc[v] : t[idx] + acc[v];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1D Cartesian: one workgroup (4 waves) per (sampled line u, tile t of 8 of
+// its samples, coil group g).  Tile 0 also forms the line's Gram P_u.
+// Rows of K are (c, x) for the group's coils; wave w takes rows x = 16s+4w..+3.
+// Loads are unconditional (clamped address, then a select) so the MFMA chain
+// is branch-free.  Outputs (FP64): Ppart[g][u][i][j], hpart[g][pair][j].
+// ---------------------------------------------------------------------------
+template <typename T, int TR, int UN, bool WP>
+__device__ __forceinline__ void gram_lines_loop(const GramLinesArgs& a, int u, int c0, int c1, int np, int pp,
+                                                bool pok, int lane, int wave,
+                                                typename Mma<T>::V (&P)[TR][TR], typename Mma<T>::V (&H)[TR]) {
+  using M = Mma<T>;
+  const int r = a.r, nx = a.nx, col = lane & 15, kk = lane >> 4;
+  const int xl = 4 * wave + kk;
+  int wj[TR], wim[TR];
+  float wmask[TR];
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+    const int i = 16 * t + col;
+    const bool ok = i < 2 * r;
+    wmask[t] = ok ? 1.f : 0.f;
+    wj[t] = ok ? ((i < r) ? i : i - r) : 0;
+    wim[t] = (i >= r) && ok;
+  }
+  const int yim = col >> 3;
+  const float ymask = pok ? 1.f : 0.f;
+  const float* Wf = reinterpret_cast<const float*>(a.W);
+  const float* Yline = reinterpret_cast<const float*>(a.yu);
+  for (int c = c0; c < c1; ++c) {
+    const float* wrow[TR];
+#pragma unroll
+    for (int t = 0; t < TR; ++t) wrow[t] = Wf + 2L * (((long)c * a.ua + u) * nx * r + wj[t]) + wim[t];
+    const float* yrow = Yline + 2L * (((long)c * np + pp) * nx) + yim;
+    for (int x0 = 0; x0 < nx; x0 += 16 * UN) {
+      T av[UN][TR], bv[UN];
+#pragma unroll
+      for (int q2 = 0; q2 < UN; ++q2) {
+        // always load (from a clamped, valid address) and scale by a 0/1 mask,
+        // so that no load sits under a branch
+        const int x = x0 + 16 * q2 + xl;
+        const float rm = (x < nx) ? 1.f : 0.f;
+        const int xc = min(x, nx - 1);
+#pragma unroll
+        for (int t = 0; t < TR; ++t) av[q2][t] = (T)(wrow[t][2L * r * xc] * (rm * wmask[t]));
+        bv[q2] = (T)(yrow[2 * xc] * (rm * ymask));
+      }
+#pragma unroll
+      for (int q2 = 0; q2 < UN; ++q2) {
+        if constexpr (WP) {
+#pragma unroll
+          for (int i = 0; i < TR; ++i)
+#pragma unroll
+            for (int j = 0; j < TR; ++j) P[i][j] = M::mma(av[q2][i], av[q2][j], P[i][j]);
+        }
+#pragma unroll
+        for (int i = 0; i < TR; ++i) H[i] = M::mma(av[q2][i], bv[q2], H[i]);
+      }
+    }
+  }
+}
+
+template <typename T, int TR, int UN>
+__global__ __launch_bounds__(256) void k_gram_lines_mma(GramLinesArgs a) {
+  using M = Mma<T>;
+  __shared__ T red[(TR * TR + TR) * 256];
+  const int u = blockIdx.x, t = blockIdx.y, g = blockIdx.z;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (u >= a.st->n_units) return;
+  const int r = a.r, col = lane & 15;
+  const int ky = a.unit_loc[u];
+  const int p0 = a.loc_ptr[ky], np = a.loc_ptr[ky + 1] - p0;
+  const int nht = (np + 7) / 8;
+  if (t > 0 && t >= nht) return;
+  const int c0 = g * a.cg, c1 = min(a.nc, c0 + a.cg);
+  // this lane's sample (B column) in tile t
+  const int pl = 8 * t + (col & 7);
+  const bool pok = pl < np;
+  const int pp = pok ? pl : 0;
+  GramLinesArgs al = a;
+  al.yu = a.yu + (long)a.nc * a.nx * p0;  // this line's [c][p][x] block
+  typename M::V P[TR][TR], H[TR];
+#pragma unroll
+  for (int i = 0; i < TR; ++i) {
+    H[i] = M::zero();
+#pragma unroll
+    for (int j = 0; j < TR; ++j) P[i][j] = M::zero();
+  }
+  if (t == 0)
+    gram_lines_loop<T, TR, UN, true>(al, u, c0, c1, np, pp, pok, lane, wave, P, H);
+  else
+    gram_lines_loop<T, TR, UN, false>(al, u, c0, c1, np, pp, pok, lane, wave, P, H);
+  // reduce across the 4 waves and form the complex outputs
+  T* Pt = red;                    // TR*TR tiles
+  T* Ht = red + TR * TR * 256;    // TR tiles of the h column block
+  auto C = [&](const T* base, int ntile_cols, int i, int j) -> double {
+    return (double)base[((i / 16) * ntile_cols + (j / 16)) * 256 + (i % 16) * 16 + (j % 16)];
+  };
+  if (t == 0) {
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+      for (int j = 0; j < TR; ++j) tile_reduce<T>(Pt + (i * TR + j) * 256, P[i][j], wave, lane);
+    double2* Pout = a.P + ((long)g * a.ua + u) * r * r;
+    for (int e = tid; e < r * r; e += 256) {
+      const int i = e / r, j = e % r;
+      const double re = C(Pt, TR, i, j) + C(Pt, TR, r + i, r + j);
+      const double im = C(Pt, TR, i, r + j) - C(Pt, TR, r + i, j);
+      Pout[e] = make_double2(re, im);
+    }
+  }
+  if (np == 0) return;
+#pragma unroll
+  for (int i = 0; i < TR; ++i) tile_reduce<T>(Ht + i * 256, H[i], wave, lane);
+  const int npt = min(8, np - 8 * t);
+  for (int e = tid; e < npt * r; e += 256) {
+    const int p = e / r, j = e % r;
+    // rows j and r + j of the TR x 1 column of tiles, columns p (Re y) and 8 + p (Im y)
+    const double re = C(Ht, 1, j, p) + C(Ht, 1, r + j, 8 + p);
+    const double im = C(Ht, 1, j, 8 + p) - C(Ht, 1, r + j, p);
+    a.hp[((long)g * a.npairs + p0 + 8 * t + p) * r + j] = make_double2(re, im);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// general masks: one workgroup per (frame k, chunk of its samples); rows of K
+// are (c, sample).  Output part[k][chunk][r*r + r] (G entries, then h).
+// ---------------------------------------------------------------------------
+template <typename T, int TR>
+__global__ __launch_bounds__(256) void k_gram_index_mma(GramIndexArgs a) {
+  using M = Mma<T>;
+  __shared__ T red[(TR * TR + TR) * 256];
+  const int k = blockIdx.y, ch = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  const int r = a.r, col = lane & 15, kk = lane >> 4;
+  const int mk = a.m_k[k];
+  const int i0 = ch * a.chunk, i1 = min(mk, i0 + a.chunk);
+  const int ns = max(0, i1 - i0);
+  const int rows = ns * a.nc;
+  int wj[TR], wim[TR];
+  bool wok[TR];
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+    const int i = 16 * t + col;
+    wok[t] = i < 2 * r;
+    wj[t] = (i < r) ? i : i - r;
+    wim[t] = (i >= r);
+  }
+  const bool ycol = (col == 0 || col == 8);
+  const int yim = col >> 3;
+  typename M::V P[TR][TR], H[TR];
+#pragma unroll
+  for (int i = 0; i < TR; ++i) {
+    H[i] = M::zero();
+#pragma unroll
+    for (int j = 0; j < TR; ++j) P[i][j] = M::zero();
+  }
+  const float* Wf = reinterpret_cast<const float*>(a.W);
+  for (int rho0 = 4 * wave; rho0 < rows; rho0 += 16) {
+    const int rho = rho0 + kk;
+    const bool rv = rho < rows;
+    const int c = rv ? rho / ns : 0;
+    const int s = rv ? rho % ns : 0;
+    const int loc = rv ? a.mask[(long)k * a.m_max + i0 + s] : 0;
+    T av[TR];
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+      T v = (T)0;
+      if (rv && wok[t]) v = (T)Wf[2 * (((long)c * a.n + loc) * r + wj[t]) + wim[t]];
+      av[t] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+      for (int j = 0; j < TR; ++j) P[i][j] = M::mma(av[i], av[j], P[i][j]);
+    T bv = (T)0;
+    if (rv && ycol) bv = (T)reinterpret_cast<const float*>(a.y + ((long)k * a.nc + c) * a.m_max + i0 + s)[yim];
+#pragma unroll
+    for (int i = 0; i < TR; ++i) H[i] = M::mma(av[i], bv, H[i]);
+  }
+  T* Pt = red;
+  T* Ht = red + TR * TR * 256;
+#pragma unroll
+  for (int i = 0; i < TR; ++i) {
+#pragma unroll
+    for (int j = 0; j < TR; ++j) tile_reduce<T>(Pt + (i * TR + j) * 256, P[i][j], wave, lane);
+    tile_reduce<T>(Ht + i * 256, H[i], wave, lane);
+  }
+  auto C = [&](const T* base, int ntile_cols, int i, int j) -> double {
+    return (double)base[((i / 16) * ntile_cols + (j / 16)) * 256 + (i % 16) * 16 + (j % 16)];
+  };
+  double2* out = a.part + ((long)k * gridDim.x + ch) * (r * r + r);
+  for (int e = tid; e < r * r + r; e += 256) {
+    if (e < r * r) {
+      const int i = e / r, j = e % r;
+      out[e] = make_double2(C(Pt, TR, i, j) + C(Pt, TR, r + i, r + j), C(Pt, TR, i, r + j) - C(Pt, TR, r + i, j));
+    } else {
+      const int j = e - r * r;
+      out[e] = make_double2(C(Ht, 1, j, 0) + C(Ht, 1, r + j, 8), C(Ht, 1, j, 8) - C(Ht, 1, r + j, 0));
+    }
+  }
+}
+
+// ===========================================================================
+// batched LS solve: b_k = G_k^{-1} h_k by Cholesky, one workgroup per frame;
+// also cost_k = ||y_k||^2 - Re(h_k^H b_k).
+// ===========================================================================
+template <typename T>
+struct Cx;
+template <>
+struct Cx<float> {
+  using T2 = float2;
+  __device__ static T2 from(double2 v) { return d2f(v); }
+  __device__ static T2 mul(T2 a, T2 b) { return cmul(a, b); }
+  __device__ static T2 cjm(T2 a, T2 b) { return cjmul(a, b); }
+  __device__ static T2 sub(T2 a, T2 b) { return csub(a, b); }
+  __device__ static T2 scale(T2 a, float s) { return cscale(a, s); }
+  static constexpr double tiny = 1e-5;  // pivot / max diagonal below this: cond(G) beyond FP32 use
+};
+template <>
+struct Cx<double> {
+  using T2 = double2;
+  __device__ static T2 from(double2 v) { return v; }
+  __device__ static T2 mul(T2 a, T2 b) { return dmul(a, b); }
+  __device__ static T2 cjm(T2 a, T2 b) { return djmul(a, b); }
+  __device__ static T2 sub(T2 a, T2 b) { return dsub(a, b); }
+  __device__ static T2 scale(T2 a, double s) { return make_double2(a.x * s, a.y * s); }
+  static constexpr double tiny = 1e-12;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
+  using C = Cx<T>;
+  using T2 = typename C::T2;
+  __shared__ T2 G[16 * 16];
+  __shared__ T2 h[16];
+  __shared__ T2 z[16];
+  __shared__ double2 part[256];
+  __shared__ int bad;
+  const int k = blockIdx.x, tid = threadIdx.x, r = a.r;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (tid == 0) bad = 0;
+  const int E = r * r + r;  // G entries then h entries
+  if (a.kind == 0) {
+    // sum over coil groups and the frame's lines; thread = (entry, slice)
+    const int L = a.m_k[k] / a.nx;
+    const int NS = max(1, 256 / E);
+    const int items = a.ngroups * L;
+    const int32_t* mk = a.unit_of + (long)k * a.width;  // sampled line of (k, l)
+    const int32_t* po = a.pair_of + (long)k * a.width;
+    for (int e0 = 0; e0 < E; e0 += 256 / NS) {
+      const int e = e0 + tid % (256 / NS);
+      const int sl = tid / (256 / NS);
+      double2 s = make_double2(0.0, 0.0);
+      if (e < E && sl < NS) {
+#pragma unroll 8
+        for (int it = sl; it < items; it += NS) {
+          const int gg = it / L, l = it % L;
+          double2 v;
+          if (e < r * r)
+            v = a.P[((long)gg * a.ua + mk[l]) * r * r + e];
+          else
+            v = a.hp[((long)gg * a.npairs + po[l]) * r + (e - r * r)];
+          s = dadd(s, v);
+        }
+      }
+      part[tid] = s;
+      __syncthreads();
+      if (tid < 256 / NS && e < E) {
+        double2 t = part[tid];
+        for (int q2 = 1; q2 < NS; ++q2) t = dadd(t, part[tid + q2 * (256 / NS)]);
+        if (e < r * r)
+          G[(e / r) * 16 + (e % r)] = C::from(t);
+        else
+          h[e - r * r] = C::from(t);
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int e = tid; e < E; e += 256) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int ch = 0; ch < a.nchunks; ++ch) s = dadd(s, a.P[((long)k * a.nchunks + ch) * E + e]);
+      if (e < r * r)
+        G[(e / r) * 16 + (e % r)] = C::from(s);
+      else
+        h[e - r * r] = C::from(s);
+    }
+  }
+  __syncthreads();
+  // right-looking Cholesky G = L L^H (lower part of G overwritten by L)
+  double dmax = 0.0;
+  for (int i = 0; i < r; ++i) dmax = fmax(dmax, (double)G[i * 16 + i].x);
+  for (int j = 0; j < r; ++j) {
+    const double d = (double)G[j * 16 + j].x;
+    if (!(d > C::tiny * dmax) || !isfinite(d)) {
+      if (tid == 0) bad = 1;
+    }
+    __syncthreads();
+    if (bad) break;
+    const T ljj = (T)sqrt(d);
+    __syncthreads();
+    if (tid == 0) G[j * 16 + j] = T2{ljj, (T)0};
+    for (int i = j + 1 + tid; i < r; i += 256) G[i * 16 + j] = C::scale(G[i * 16 + j], (T)1 / ljj);
+    __syncthreads();
+    const int m = r - j - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = j + 1 + e / m, c2 = j + 1 + e % m;
+      if (c2 <= i) {
+        const T2 lij = G[i * 16 + j], lcj = G[c2 * 16 + j];
+        G[i * 16 + c2] = C::sub(G[i * 16 + c2], C::mul(lij, T2{lcj.x, -lcj.y}));
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) set_error(a.st, 4 /*ENOTPD*/, k);
+    return;
+  }
+  if (tid == 0) {
+    for (int i = 0; i < r; ++i) {  // L z = h
+      T2 s = h[i];
+      for (int m = 0; m < i; ++m) s = C::sub(s, C::mul(G[i * 16 + m], z[m]));
+      z[i] = C::scale(s, (T)1 / G[i * 16 + i].x);
+    }
+    for (int i = r - 1; i >= 0; --i) {  // L^H b = z
+      T2 s = z[i];
+      for (int m = i + 1; m < r; ++m) s = C::sub(s, C::cjm(G[m * 16 + i], z[m]));
+      z[i] = C::scale(s, (T)1 / G[i * 16 + i].x);
+    }
+    double hb = 0.0;
+    bool fin = true;
+    for (int j = 0; j < r; ++j) {
+      hb += (double)h[j].x * (double)z[j].x + (double)h[j].y * (double)z[j].y;
+      fin = fin && isfinite((double)z[j].x) && isfinite((double)z[j].y);
+      a.B[(long)k * r + j] = make_float2((float)z[j].x, (float)z[j].y);
+    }
+    a.cost_k[k] = a.ysq_k[k] - hb;
+    if (!fin) set_error(a.st, 5 /*ENONFINITE*/, k);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T, int TR>
+static void launch_lines_tr(const GramLinesArgs& a, int ny, int ngroups, int ht, hipStream_t s) {
+  const dim3 g(ny, ht, ngroups);
+  if (a.nx >= 128) hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 8>), g, dim3(256), 0, s, a);
+  else if (a.nx >= 64) hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 4>), g, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 1>), g, dim3(256), 0, s, a);
+}
+
+hipError_t launch_gram_lines(const GramLinesArgs& a, int ny, int ngroups, int max_pairs, bool fp64,
+                             hipStream_t s) {
+  const int ht = std::max(1, (max_pairs + 7) / 8);
+  const int tr = (2 * a.r + 15) / 16;
+  if (fp64) {
+    if (tr == 1) launch_lines_tr<double, 1>(a, ny, ngroups, ht, s);
+    else launch_lines_tr<double, 2>(a, ny, ngroups, ht, s);
+  } else {
+    if (tr == 1) launch_lines_tr<float, 1>(a, ny, ngroups, ht, s);
+    else launch_lines_tr<float, 2>(a, ny, ngroups, ht, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp64, hipStream_t s) {
+  const int tr = (2 * a.r + 15) / 16;
+  const dim3 g(nchunks, q);
+  if (fp64) {
+    if (tr == 1) hipLaunchKernelGGL((k_gram_index_mma<double, 1>), g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_gram_index_mma<double, 2>), g, dim3(256), 0, s, a);
+  } else {
+    if (tr == 1) hipLaunchKernelGGL((k_gram_index_mma<float, 1>), g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_gram_index_mma<float, 2>), g, dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_solve<double>, dim3(q), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_solve<float>, dim3(q), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace ag
+
+namespace ag {
+
+// ===========================================================================
+// Gram of the columns of [A B] over n pixel rows on MFMA (the QR step):
+// real embedding [Re A, Re B, Im A, Im B] (2m columns, m = m1 + m2), upper
+// 16x16 tiles only.  B may be the sum of nparts partial arrays (stride
+// part_stride); with write_sum the summed B is stored back into part 0.
+// Output: per block, the upper triangle (i <= j, tri order) of the complex
+// m x m Gram, FP64.
+// ===========================================================================
+template <typename T, int TRM>
+__global__ __launch_bounds__(256) void k_qr_gram_mma(GramColsArgs a) {
+  using M = Mma<T>;
+  constexpr int NT = TRM * (TRM + 1) / 2;
+  __shared__ T red[NT * 256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kk = lane >> 4;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  const int m = a.m1 + a.m2;
+  // this lane's real columns, one per row tile
+  int srcB[TRM], cidx[TRM], im[TRM];
+  bool ok[TRM];
+#pragma unroll
+  for (int t = 0; t < TRM; ++t) {
+    const int i = 16 * t + col;
+    ok[t] = i < 2 * m;
+    const int cc = (i < m) ? i : i - m;
+    im[t] = (i >= m);
+    srcB[t] = cc >= a.m1;
+    cidx[t] = srcB[t] ? cc - a.m1 : cc;
+  }
+  typename M::V acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = M::zero();
+  const long pa = (long)blockIdx.x * a.rows_per_block;
+  const long pb = min(a.n, pa + a.rows_per_block);
+  constexpr int UN = sizeof(T) == 4 ? 8 : 4;
+  for (long p00 = pa + 4 * wave; p00 < pb; p00 += 16 * UN) {
+    T v[UN][TRM];
+#pragma unroll
+    for (int q2 = 0; q2 < UN; ++q2) {
+      const long p = p00 + 16 * q2 + kk;
+      const bool rv = p < pb;
+#pragma unroll
+      for (int t = 0; t < TRM; ++t) {
+        float x = 0.f;
+        if (rv && ok[t]) {
+          if (!srcB[t]) {
+            x = reinterpret_cast<const float*>(a.A + p * (long)a.m1 + cidx[t])[im[t]];  // pixel-major
+          } else {
+            const long off = p * (long)a.m2 + cidx[t];   // B is pixel-major [p][j]
+            float2 s2 = a.B[off];
+            for (int g = 1; g < a.nparts; ++g) s2 = cadd(s2, a.B[g * a.part_stride + off]);
+            x = im[t] ? s2.y : s2.x;
+            if (a.write_sum && a.nparts > 1) reinterpret_cast<float*>(const_cast<float2*>(a.B) + off)[im[t]] = x;
+          }
+        }
+        v[q2][t] = (T)x;
+      }
+    }
+#pragma unroll
+    for (int q2 = 0; q2 < UN; ++q2)
+#pragma unroll
+      for (int i = 0; i < TRM; ++i)
+#pragma unroll
+        for (int j = i; j < TRM; ++j) {
+          const int ti = i * TRM - i * (i - 1) / 2 + (j - i);
+          acc[ti] = M::mma(v[q2][i], v[q2][j], acc[ti]);
+        }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) tile_reduce<T>(red + t * 256, acc[t], wave, lane);
+  // C(i, j) of the real 2m x 2m Gram from the upper tiles
+  auto C = [&](int i, int j) -> double {
+    if (i > j) {
+      const int t = i;
+      i = j;
+      j = t;
+    }
+    const int a_ = i / 16, b_ = j / 16;
+    const int ti = a_ * TRM - a_ * (a_ - 1) / 2 + (b_ - a_);
+    return (double)red[ti * 256 + (i % 16) * 16 + (j % 16)];
+  };
+  const int nout = m * (m + 1) / 2;
+  for (int o = tid; o < nout; o += 256) {
+    int i, j;
+    tri_index(o, m, i, j);
+    const double re = C(i, j) + C(m + i, m + j);
+    const double imv = C(i, m + j) - C(m + i, j);
+    a.part[(long)blockIdx.x * nout + o] = make_double2(re, imv);
+  }
+}
+
+hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s) {
+  const int trm = (2 * (a.m1 + a.m2) + 15) / 16;
+  const dim3 g(nblk);
+  if (fp64) {
+    switch (trm) {
+      case 1: hipLaunchKernelGGL((k_qr_gram_mma<double, 1>), g, dim3(256), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_qr_gram_mma<double, 2>), g, dim3(256), 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_qr_gram_mma<double, 3>), g, dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_qr_gram_mma<double, 4>), g, dim3(256), 0, s, a); break;
+    }
+  } else {
+    switch (trm) {
+      case 1: hipLaunchKernelGGL((k_qr_gram_mma<float, 1>), g, dim3(256), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_qr_gram_mma<float, 2>), g, dim3(256), 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_qr_gram_mma<float, 3>), g, dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_qr_gram_mma<float, 4>), g, dim3(256), 0, s, a); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+// dst[i] = sum_g src[g*stride + i] (partial gradients of the coil groups)
+__global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* dst, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long step = (long)gridDim.x * blockDim.x;
+  for (; i < n; i += step) {
+    float2 s = src[i];
+    for (int g = 1; g < nparts; ++g) s = cadd(s, src[g * stride + i]);
+    dst[i] = s;
+  }
+}
+
+}  // namespace ag
