@@ -60,7 +60,8 @@ struct altgdmin_ctx {
   int bound = 0, initialized = 0;
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
-      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_Ui, o_unitof, o_end;
+      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_Ui, o_unitof, o_S, o_bcp,
+      o_end;
   size_t T_bytes;
   // timing
   int timed = TK_NONE;
@@ -101,6 +102,8 @@ void carve(altgdmin_ctx* c) {
   c->o_pairof = take(sizeof(int32_t) * (size_t)q * c->width);
   c->o_unitof = take(sizeof(int32_t) * (size_t)q * c->width);
   c->o_Ui = take(sizeof(float2) * (size_t)n * r);
+  c->o_S = take(sizeof(float2) * (size_t)c->ua * r * r);
+  c->o_bcp = take(sizeof(float2) * (size_t)q * c->width * r);
   const size_t ysz = sizeof(float2) * (size_t)q * nc * p.m_max;
   c->o_yh = take(c->lines ? ysz : 0);
   c->o_ysq = take(sizeof(double) * q);
@@ -333,6 +336,8 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   if (e != hipSuccess) return e;
   // fold the residual over frames
   FoldArgs fa{};
+  fa.S = c->at<float2>(c->o_S);
+  fa.bcp = c->at<float2>(c->o_bcp);
   fa.W = c->at<float2>(c->o_W);
   fa.yu = c->at<float2>(c->o_yh);
   fa.y = c->y;

@@ -40,21 +40,25 @@ __global__ __launch_bounds__(AG_NT) void k_basis_fwd(BasisArgs a) {
   }
   const int n_rows = a.rows ? *a.n_rows_ptr : N;
   const int cb = blockIdx.y * a.cgs, ce = min(a.nc, cb + a.cgs);
-  for (int c = cb; c < ce; ++c) {
+  float2 cv[IT];
+  auto fetch = [&](int c) {
     const float2* coil = a.coils + (long)c * a.n;
-    float2 cv[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int g = tid + it * AG_NT;
       const int y = g / CT, col = g % CT;
       cv[it] = (g < N * CT && col < ctr) ? coil[(long)y * a.nx + x0 + col / r] : make_float2(0.f, 0.f);
     }
+  };
+  if (cb < ce) fetch(cb);
+  for (int c = cb; c < ce; ++c) {
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int g = tid + it * AG_NT;
       if (g < N * CT) s[g] = cmul(cv[it], uv[it]);
     }
     __syncthreads();
+    if (c + 1 < ce) fetch(c + 1);  // in flight during this coil's transform
     fft_lds<N, CT, AG_NT, false>(s, a.tw);
     float2* dst = a.W + (long)c * a.ua * a.nx * r;
     for (int g = tid; g < n_rows * ctr; g += AG_NT) {
@@ -80,53 +84,65 @@ __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
   if (a.st->err || (a.check_halt && a.st->halt)) return;
   const int n_rows = a.rows ? *a.n_rows_ptr : N;
   const bool full = (a.rows == nullptr);
-  float2 acc[IT];
+  const int total = n_rows * ctr;  // <= N * CT
+  // LDS destination of this thread's row items (fixed across coils)
+  int dst[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int g = tid + it * AG_NT;
+    dst[it] = -1;
+    if (g < total) {
+      const int u = g / ctr, col = g - u * ctr;
+      dst[it] = (full ? u : a.rows[u]) * CT + col;
+    }
+  }
+  float2 acc[IT], kv[IT], cv[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) acc[it] = make_float2(0.f, 0.f);
   const int cb = blockIdx.y * a.cgs, ce = min(a.nc, cb + a.cgs);
-  for (int c = cb; c < ce; ++c) {
+  // coil c's K rows and coil values, into registers
+  auto fetch = [&](int c) {
     const float2* src = a.K + (long)c * a.ua * a.nx * r;
-    if (!full) {
-      for (int g = tid; g < N * CT; g += AG_NT) s[g] = make_float2(0.f, 0.f);
-      __syncthreads();
-    }
-    for (int g0 = 0; g0 < n_rows * ctr; g0 += 8 * AG_NT) {
-      float2 v[8];
-      int d[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int g = g0 + tid + q * AG_NT;
-        d[q] = -1;
-        if (g < n_rows * ctr) {
-          const int u = g / ctr, col = g - u * ctr;
-          d[q] = (full ? u : a.rows[u]) * CT + col;
-          v[q] = src[((long)u * a.nx + x0) * r + col];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (d[q] >= 0) s[d[q]] = v[q];
-    }
-    __syncthreads();
-    fft_lds<N, CT, AG_NT, true>(s, a.tw);
     const float2* coil = a.coils + (long)c * a.n;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int g = tid + it * AG_NT;
-      const int y = g / CT, col = g % CT;
-      if (g < N * CT && col < ctr) {
-        const int xx = col / r;
-        acc[it] = cadd(acc[it], cjmul(coil[(long)y * a.nx + x0 + xx], s[g]));
+      if (g < total) {
+        const int u = g / ctr, col = g - u * ctr;
+        kv[it] = src[((long)u * a.nx + x0) * r + col];
       }
+      const int y = g / CT, col = g % CT;
+      cv[it] = (g < N * CT && col < ctr) ? coil[(long)y * a.nx + x0 + col / r] : make_float2(0.f, 0.f);
+    }
+  };
+  if (cb < ce) fetch(cb);
+  for (int c = cb; c < ce; ++c) {
+    if (!full) {
+      for (int g = tid; g < N * CT; g += AG_NT) s[g] = make_float2(0.f, 0.f);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+      if (dst[it] >= 0) s[dst[it]] = kv[it];
+    float2 cc[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) cc[it] = cv[it];
+    __syncthreads();
+    if (c + 1 < ce) fetch(c + 1);  // in flight during this coil's transform
+    fft_lds<N, CT, AG_NT, true>(s, a.tw);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int g = tid + it * AG_NT;
+      if (g < N * CT) acc[it] = cadd(acc[it], cjmul(cc[it], s[g]));
     }
     __syncthreads();
   }
-  float2* dst = a.G + (long)blockIdx.y * a.part_stride;
+  float2* out = a.G + (long)blockIdx.y * a.part_stride;
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int g = tid + it * AG_NT;
     const int y = g / CT, col = g % CT;
-    if (g < N * CT && col < ctr) dst[((long)y * a.nx + x0) * r + col] = cscale(acc[it], a.scale);
+    if (g < N * CT && col < ctr) out[((long)y * a.nx + x0) * r + col] = cscale(acc[it], a.scale);
   }
 }
 
@@ -186,23 +202,14 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
   const int r = a.r, nx = a.nx;
   const int ky = a.unit_loc[u];
   const int p0 = a.loc_ptr[ky], np = a.loc_ptr[ky + 1] - p0;
-  for (int e = tid; e < np * r; e += AG_NT) {
-    const int p = e / r, j = e % r;
-    const float2 b = a.B[(long)a.pairs[p0 + p].x * r + j];
-    bc[p * RT + j] = make_float2(b.x, -b.y);
-  }
-  __syncthreads();
-  for (int e = tid; e < r * r; e += AG_NT) {  // S_u[i][j] = sum_p b_i conj(b_j)
-    const int i = e / r, j = e % r;
-    float2 sacc = make_float2(0.f, 0.f);
-    for (int p = 0; p < np; ++p) sacc = cadd(sacc, cjmul(bc[p * RT + i], bc[p * RT + j]));
-    S[i * RT + j] = sacc;
-  }
+  // S_u and conj(b_k) of the line's samples, prepared once per iteration
+  for (int e = tid; e < r * r; e += AG_NT) S[(e / r) * RT + (e % r)] = a.S[(long)u * r * r + e];
+  for (int e = tid; e < np * r; e += AG_NT) bc[(e / r) * RT + (e % r)] = a.bcp[(long)p0 * r + e];
   const long blk = ((long)c * a.ua + u) * nx * r;
   const float2* Yb = a.yu + (long)a.nc * nx * p0 + (long)c * np * nx;  // [p][x]
   for (int x0 = 0; x0 < nx; x0 += AG_NT) {
     const int nxc = min(AG_NT, nx - x0);
-    __syncthreads();
+    if (x0 > 0) __syncthreads();
     for (int g = tid; g < nxc * r; g += AG_NT) Wl[(g / r) * (RT + 1) + (g % r)] = a.W[blk + (long)x0 * r + g];
     __syncthreads();
     if (tid < nxc) {
@@ -218,7 +225,7 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
           if (i < r) acc = cadd(acc, cmul(w[i], S[i * RT + j]));
         kk[j] = acc;
       }
-#pragma unroll 4
+#pragma unroll 8
       for (int p = 0; p < np; ++p) {
         const float2 yv = Yb[(long)p * nx + x];
 #pragma unroll
@@ -230,6 +237,30 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
     }
     __syncthreads();
     for (int g = tid; g < nxc * r; g += AG_NT) a.K[blk + (long)x0 * r + g] = Wl[(g / r) * (RT + 1) + (g % r)];
+  }
+}
+
+// per sampled line: S_u = sum_{samples on u} b_k b_k^H and conj(b_k) per sample
+__global__ __launch_bounds__(64) void k_line_S(FoldArgs a) {
+  const int u = blockIdx.x, tid = threadIdx.x;
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (u >= a.st->n_units) return;
+  const int r = a.r;
+  const int ky = a.unit_loc[u];
+  const int p0 = a.loc_ptr[ky], np = a.loc_ptr[ky + 1] - p0;
+  for (int e = tid; e < np * r; e += 64) {
+    const int p = e / r, j = e % r;
+    const float2 b = a.B[(long)a.pairs[p0 + p].x * r + j];
+    a.bcp[(long)(p0 + p) * r + j] = make_float2(b.x, -b.y);
+  }
+  for (int e = tid; e < r * r; e += 64) {
+    const int i = e / r, j = e % r;
+    float2 sacc = make_float2(0.f, 0.f);
+    for (int p = 0; p < np; ++p) {
+      const float2* b = a.B + (long)a.pairs[p0 + p].x * r;
+      sacc = cadd(sacc, cmulj(b[i], b[j]));
+    }
+    a.S[(long)u * r * r + e] = sacc;
   }
 }
 
@@ -327,6 +358,7 @@ hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int gr
 hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s) {
   const dim3 g(grid_x, grid_y);
   if (lines) {
+    hipLaunchKernelGGL(k_line_S, dim3(grid_x), dim3(64), 0, s, a);
     if (a.r <= 4) hipLaunchKernelGGL(k_fold_lines2<4>, g, dim3(AG_NT), 0, s, a);
     else if (a.r <= 8) hipLaunchKernelGGL(k_fold_lines2<8>, g, dim3(AG_NT), 0, s, a);
     else hipLaunchKernelGGL(k_fold_lines2<16>, g, dim3(AG_NT), 0, s, a);

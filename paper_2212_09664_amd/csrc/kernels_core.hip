@@ -475,6 +475,40 @@ __device__ bool chol_rinv(double2* M, int r, double2* Ri) {
   return true;
 }
 
+// Cholesky of the Hermitian r x r matrix M (LDS, ld 16) in FP64, lower L in
+// place; one thread.  Returns false if M is not positive definite.
+__device__ bool chol_lower(double2* M, int r) {
+  double dmax = 0.0;
+  for (int i = 0; i < r; ++i) dmax = fmax(dmax, M[i * 16 + i].x);
+  for (int j = 0; j < r; ++j) {
+    double d = M[j * 16 + j].x;
+    for (int m = 0; m < j; ++m) d -= M[j * 16 + m].x * M[j * 16 + m].x + M[j * 16 + m].y * M[j * 16 + m].y;
+    if (!(d > 1e-14 * dmax) || !isfinite(d)) return false;
+    const double ljj = sqrt(d);
+    M[j * 16 + j] = make_double2(ljj, 0.0);
+    for (int i = j + 1; i < r; ++i) {
+      double2 s = M[i * 16 + j];
+      for (int m = 0; m < j; ++m) s = dsub(s, dmul(M[i * 16 + m], dconj(M[j * 16 + m])));
+      M[i * 16 + j] = make_double2(s.x / ljj, s.y / ljj);
+    }
+  }
+  return true;
+}
+
+// Rinv = (L^H)^{-1}, upper triangular, one column per thread (threads < r).
+__device__ void rinv_columns(const double2* L, int r, double2* Ri) {
+  const int j = threadIdx.x;
+  if (j >= r) return;
+  for (int i = j + 1; i < r; ++i) Ri[i * 16 + j] = make_double2(0.0, 0.0);
+  Ri[j * 16 + j] = make_double2(1.0 / L[j * 16 + j].x, 0.0);
+  for (int i = j - 1; i >= 0; --i) {
+    // R[i][m] = conj(L[m][i]); Rinv[i][j] = -(sum_{m=i+1..j} R[i][m] Rinv[m][j]) / R[i][i]
+    double2 s = make_double2(0.0, 0.0);
+    for (int m = i + 1; m <= j; ++m) s = dadd(s, dmul(dconj(L[m * 16 + i]), Ri[m * 16 + j]));
+    Ri[i * 16 + j] = make_double2(-s.x / L[i * 16 + i].x, -s.y / L[i * 16 + i].x);
+  }
+}
+
 // ===========================================================================
 // the QR step's small work (one workgroup): reduce the Gram partials of
 // [U grad]; at the first iteration set eta = eta_c / sigma_max(grad) (with
@@ -535,13 +569,17 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
   }
   __syncthreads();
   if (a.mode == 1) {
-    if (tid == 0) {
-      for (int e = 0; e < 256; ++e) Gh[e] = UU[e];
-      s_ok = chol_rinv(Gh, r, Ri);
-      if (!s_ok) set_error(st, 4, -1);
-      for (int i = 0; i < r; ++i)
-        for (int j = 0; j < r; ++j) a.rinv[i * r + j] = d2f(Ri[i * 16 + j]);
+    for (int e = tid; e < 256; e += blockDim.x) Gh[e] = UU[e];
+    __syncthreads();
+    if (tid == 0) s_ok = chol_lower(Gh, r);
+    __syncthreads();
+    if (!s_ok) {
+      if (tid == 0) set_error(st, 4, -1);
+      return;
     }
+    rinv_columns(Gh, r, Ri);
+    __syncthreads();
+    for (int e = tid; e < r * r; e += blockDim.x) a.rinv[e] = d2f(Ri[(e / r) * 16 + (e % r)]);
     return;
   }
   // first iteration: step size from the spectral norm of grad
@@ -586,49 +624,58 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
       __syncthreads();
     }
   }
-  if (tid == 0) {
-    const double eta = st->eta;
-    // Gram of Uhat = U - eta G
-    for (int i = 0; i < r; ++i)
-      for (int j = 0; j < r; ++j) {
-        const double2 ug = UG[i * 16 + j], gu = dconj(UG[j * 16 + i]);
-        const double2 v = UU[i * 16 + j];
-        const double2 g = GG[i * 16 + j];
-        Gh[i * 16 + j] = make_double2(v.x - eta * (ug.x + gu.x) + eta * eta * g.x,
-                                      v.y - eta * (ug.y + gu.y) + eta * eta * g.y);
-      }
-    s_ok = chol_rinv(Gh, r, Ri);
-    if (!s_ok) {
+  // the step size as thread 0 left it, shared through LDS
+  __shared__ double s_eta;
+  if (tid == 0) s_eta = st->eta;
+  __syncthreads();
+  const double eta = s_eta;
+  // Gram of Uhat = U - eta G, in parallel
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    const int i = e / r, j = e % r;
+    const double2 ug = UG[i * 16 + j], gu = dconj(UG[j * 16 + i]);
+    const double2 v = UU[i * 16 + j];
+    const double2 g = GG[i * 16 + j];
+    Gh[i * 16 + j] = make_double2(v.x - eta * (ug.x + gu.x) + eta * eta * g.x,
+                                  v.y - eta * (ug.y + gu.y) + eta * eta * g.y);
+  }
+  __syncthreads();
+  if (tid == 0) s_ok = chol_lower(Gh, r);
+  __syncthreads();
+  if (!s_ok) {
+    if (tid == 0) {
       set_error(st, 4, -1);
       st->step_ok = 0;
-    } else {
-      for (int i = 0; i < r; ++i)
-        for (int j = 0; j < r; ++j) a.rinv[i * r + j] = d2f(Ri[i * 16 + j]);
-      // U^H U+ = (U^H U - eta U^H G) Rinv; SD^2 = r - ||U^H U+||_F^2
-      double fro = 0.0;
-      for (int i = 0; i < r; ++i)
-        for (int j = 0; j < r; ++j) {
-          double2 s = make_double2(0.0, 0.0);
-          for (int mm = 0; mm <= j; ++mm) {
-            const double2 lhs = make_double2(UU[i * 16 + mm].x - eta * UG[i * 16 + mm].x,
-                                             UU[i * 16 + mm].y - eta * UG[i * 16 + mm].y);
-            s = dadd(s, dmul(lhs, Ri[mm * 16 + j]));
-          }
-          fro += s.x * s.x + s.y * s.y;
-        }
-      const double sd2 = fmax(0.0, (double)r - fro);
-      double tr = 0.0;
-      for (int i = 0; i < r; ++i) tr += GG[i * 16 + i].x;
-      const double f = s_f;
-      st->sd = sqrt(sd2);
-      st->grad_norm = sqrt(tr);
-      st->f = f;
-      st->t += 1;
-      st->step_ok = 1;
-      if (a.eps_exit > 0.0 && sqrt(sd2 / r) < a.eps_exit) {
-        st->exited = 1;
-        st->halt = 1;
-      }
+    }
+    return;
+  }
+  rinv_columns(Gh, r, Ri);
+  __syncthreads();
+  // U^H U+ = (U^H U - eta U^H G) Rinv; SD^2 = r - ||U^H U+||_F^2
+  double fro = 0.0;
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    const int i = e / r, j = e % r;
+    a.rinv[e] = d2f(Ri[i * 16 + j]);
+    double2 sacc = make_double2(0.0, 0.0);
+    for (int mm = 0; mm <= j; ++mm) {
+      const double2 lhs = make_double2(UU[i * 16 + mm].x - eta * UG[i * 16 + mm].x,
+                                       UU[i * 16 + mm].y - eta * UG[i * 16 + mm].y);
+      sacc = dadd(sacc, dmul(lhs, Ri[mm * 16 + j]));
+    }
+    fro += sacc.x * sacc.x + sacc.y * sacc.y;
+  }
+  fro = block_sum(fro, js.red);
+  if (tid == 0) {
+    const double sd2 = fmax(0.0, (double)r - fro);
+    double tr = 0.0;
+    for (int i = 0; i < r; ++i) tr += GG[i * 16 + i].x;
+    st->sd = sqrt(sd2);
+    st->grad_norm = sqrt(tr);
+    st->f = s_f;
+    st->t += 1;
+    st->step_ok = 1;
+    if (a.eps_exit > 0.0 && sqrt(sd2 / r) < a.eps_exit) {
+      st->exited = 1;
+      st->halt = 1;
     }
   }
 }

@@ -80,6 +80,8 @@ struct BasisArgs {
 };
 
 struct FoldArgs {
+  float2* S;             // LINES: per-line S_u (ua x r x r)
+  float2* bcp;           // LINES: conj(b_k) per sample (pairs x r)
   const float2* W;
   const float2* yu;      // LINES: per-line data [c][x][p]
   const float2* yh;      // LINES: hybrid data
