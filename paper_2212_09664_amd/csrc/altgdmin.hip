@@ -60,7 +60,7 @@ struct altgdmin_ctx {
   int bound = 0, initialized = 0;
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
-      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_Ui, o_unitof, o_S, o_bcp,
+      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp,
       o_end;
   size_t T_bytes;
   // timing
@@ -98,12 +98,12 @@ void carve(altgdmin_ctx* c) {
   c->o_locptr = take(sizeof(int32_t) * (size_t)(c->n_loc + 1));
   c->o_loc2unit = take(sizeof(int32_t) * (size_t)c->n_loc);
   c->o_unitloc = take(sizeof(int32_t) * (size_t)c->n_loc);
+  c->o_unitspan = take(sizeof(int2) * (size_t)c->n_loc);
+  c->o_bcp = take(sizeof(float2) * (size_t)q * c->width * r);
   c->o_pairs = take(sizeof(int2) * (size_t)q * c->width);
   c->o_pairof = take(sizeof(int32_t) * (size_t)q * c->width);
   c->o_unitof = take(sizeof(int32_t) * (size_t)q * c->width);
   c->o_Ui = take(sizeof(float2) * (size_t)n * r);
-  c->o_S = take(sizeof(float2) * (size_t)c->ua * r * r);
-  c->o_bcp = take(sizeof(float2) * (size_t)q * c->width * r);
   const size_t ysz = sizeof(float2) * (size_t)q * nc * p.m_max;
   c->o_yh = take(c->lines ? ysz : 0);
   c->o_ysq = take(sizeof(double) * q);
@@ -189,6 +189,7 @@ BasisArgs basis_args(altgdmin_ctx* c, int check_halt) {
   if (c->lines) {
     b.rows = c->at<int32_t>(c->o_unitloc);
     b.n_rows_ptr = &c->st()->n_units;
+    b.row_unit = c->at<int32_t>(c->o_loc2unit);
   }
   b.tw = c->at<float2>(c->o_twy);
   b.tw_x = c->at<float2>(c->o_twx);
@@ -278,6 +279,7 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
   s.npairs = (long)p.q * c->width;
   s.ysq_k = c->at<double>(c->o_ysq);
   s.B = c->at<float2>(c->o_B);
+  s.bcp = c->at<float2>(c->o_bcp);
   s.cost_k = c->at<double>(c->o_cost);
   s.st = c->st();
   s.check_halt = check_halt;
@@ -336,7 +338,7 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   if (e != hipSuccess) return e;
   // fold the residual over frames
   FoldArgs fa{};
-  fa.S = c->at<float2>(c->o_S);
+  fa.unit_span = c->at<int2>(c->o_unitspan);
   fa.bcp = c->at<float2>(c->o_bcp);
   fa.W = c->at<float2>(c->o_W);
   fa.yu = c->at<float2>(c->o_yh);
@@ -357,10 +359,11 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   fa.st = c->st();
   fa.check_halt = check_halt;
   tmark(c, TK_FOLD);
-  if (c->lines)
+  if (c->lines) {
     e = launch_fold2(fa, true, p.ny, p.nc, c->stream);
-  else
+  } else {
     e = launch_fold2(fa, false, (int)((c->n + AG_NT - 1) / AG_NT), p.nc, c->stream);
+  }
   tmark(c, TK_FOLD);
   if (e != hipSuccess) return e;
   // inverse transform + coil combine -> partial gradients per coil group
@@ -598,7 +601,7 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
                      c->width, c->per, c->n_loc, c->at<uint32_t>(c->o_bitmap), c->nw, c->st());
   hipLaunchKernelGGL(k_inv_scan, dim3(1), dim3(1024), 0, s, c->at<uint32_t>(c->o_bitmap), c->nw, c->n_loc,
                      c->at<int32_t>(c->o_locptr), c->at<int32_t>(c->o_loc2unit), c->at<int32_t>(c->o_unitloc),
-                     c->st());
+                     c->at<int2>(c->o_unitspan), c->st());
   hipLaunchKernelGGL(k_inv_fill, dim3((c->width + 255) / 256, p.q), dim3(256), 0, s, c->mask, c->m_k,
                      c->width, c->per, c->at<uint32_t>(c->o_bitmap), c->nw, c->at<int32_t>(c->o_locptr),
                      c->at<int32_t>(c->o_loc2unit), c->at<int2>(c->o_pairs), c->at<int32_t>(c->o_pairof),

@@ -149,7 +149,7 @@ __device__ __forceinline__ void dft_reg(float2* v) {
 // in-register radix-R DFT and writes them at stride Ns.  tw[t] holds
 // exp(-2 pi i t / N) in float (computed in double).  Unnormalised.
 // ---------------------------------------------------------------------------
-template <int N, int R, int TX, int NT, bool INV>
+template <int N, int R, int TX, int NT, bool INV, bool CONJ_TW = INV>
 __device__ __forceinline__ void stockham_pass(float2* s, const float2* __restrict__ tw, int Ns) {
   constexpr int G = TX * (N / R);
   constexpr int IT = (G + NT - 1) / NT;
@@ -167,7 +167,7 @@ __device__ __forceinline__ void stockham_pass(float2* s, const float2* __restric
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           float2 w = tw[step * r];
-          if (INV) w.y = -w.y;
+          if (CONJ_TW) w.y = -w.y;
           v[it][r] = cmul(v[it][r], w);
         }
       }
@@ -211,6 +211,99 @@ __device__ __forceinline__ void fft_lds(float2* s, const float2* __restrict__ tw
     stockham_pass<512, 8, TX, NT, INV>(s, tw, 1);
     stockham_pass<512, 8, TX, NT, INV>(s, tw, 8);
     stockham_pass<512, 8, TX, NT, INV>(s, tw, 64);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same transform with its first pass fed from registers and its last
+// pass left in registers: only the passes in between go through LDS.
+//   input  item (it, r) of thread t, g = t + it*NT: row g/TX + r*(N/R0),
+//          column g%TX;
+//   output item (it, r): row out_row(g, r), column g%TX.
+// tw[t] = exp(-+2 pi i t / N) in the transform's own direction (the caller
+// passes the conjugated table for the inverse).  For N <= 16 (one pass) no
+// LDS is touched.  The function returns with the LDS tile free for reuse
+// (its last LDS read is followed by a barrier).
+// ---------------------------------------------------------------------------
+template <int N> struct FftPlan;
+template <> struct FftPlan<8>   { static constexpr int P = 1, R0 = 8,  RL = 8;  };
+template <> struct FftPlan<16>  { static constexpr int P = 1, R0 = 16, RL = 16; };
+template <> struct FftPlan<32>  { static constexpr int P = 2, R0 = 8,  RL = 4;  };
+template <> struct FftPlan<64>  { static constexpr int P = 2, R0 = 8,  RL = 8;  };
+template <> struct FftPlan<128> { static constexpr int P = 2, R0 = 16, RL = 8;  };
+template <> struct FftPlan<256> { static constexpr int P = 2, R0 = 16, RL = 16; };
+template <> struct FftPlan<512> { static constexpr int P = 3, R0 = 8,  RL = 8;  };
+
+template <int N, int TX, int NT>
+struct FftGeom {
+  using PL = FftPlan<N>;
+  static constexpr int R0 = PL::R0, RL = PL::RL;
+  static constexpr int G0 = TX * (N / R0), IT0 = (G0 + NT - 1) / NT;
+  static constexpr int GL = TX * (N / RL), ITL = (GL + NT - 1) / NT;
+  __device__ static bool in_ok(int g) { return (G0 % NT == 0) || g < G0; }
+  __device__ static bool out_ok(int g) { return (GL % NT == 0) || g < GL; }
+  __device__ static int in_row(int g, int r) { return g / TX + r * (N / R0); }
+  __device__ static int out_row(int g, int r) {
+    return PL::P == 1 ? (g / TX) * R0 + r : g / TX + r * (N / RL);
+  }
+};
+
+template <int N, int TX, int NT, bool INV, int IT0_, int R0_, int ITL_, int RL_>
+__device__ __forceinline__ void fft_regs(float2 (&v0)[IT0_][R0_], float2 (&vo)[ITL_][RL_], float2* s,
+                                         const float2* __restrict__ tw) {
+  using GM = FftGeom<N, TX, NT>;
+  static_assert(IT0_ == GM::IT0 && R0_ == GM::R0 && ITL_ == GM::ITL && RL_ == GM::RL,
+                "register tiles do not match the plan");
+  constexpr int R0 = GM::R0, RL = GM::RL, P = FftPlan<N>::P;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < GM::IT0; ++it)
+    if (GM::in_ok(tid + it * NT)) dft_reg<R0, INV>(v0[it]);
+  if constexpr (P == 1) {
+#pragma unroll
+    for (int it = 0; it < GM::IT0; ++it)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) vo[it][r] = v0[it][out_pos<R0>(r)];
+    return;
+  } else {
+    // first pass: Ns = 1, outputs to rows j*R0 + r
+#pragma unroll
+    for (int it = 0; it < GM::IT0; ++it) {
+      const int g = tid + it * NT;
+      if (GM::in_ok(g)) {
+        const int col = g % TX, j = g / TX;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) s[(j * R0 + r) * TX + col] = v0[it][out_pos<R0>(r)];
+      }
+    }
+    __syncthreads();
+    if constexpr (P == 3) stockham_pass<N, 8, TX, NT, INV, false>(s, tw, R0);
+    // last pass: Ns = N/RL, reads rows j + r*Ns, outputs rows j + r*Ns
+#pragma unroll
+    for (int it = 0; it < GM::ITL; ++it) {
+      const int g = tid + it * NT;
+      if (GM::out_ok(g)) {
+        const int col = g % TX, j = g / TX;
+#pragma unroll
+        for (int r = 0; r < RL; ++r) vo[it][r] = s[(j + r * (N / RL)) * TX + col];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < GM::ITL; ++it) {
+      const int g = tid + it * NT;
+      if (GM::out_ok(g)) {
+        const int j = g / TX;
+#pragma unroll
+        for (int r = 1; r < RL; ++r) vo[it][r] = cmul(vo[it][r], tw[j * r]);
+        dft_reg<RL, INV>(vo[it]);
+        float2 t[RL];
+#pragma unroll
+        for (int r = 0; r < RL; ++r) t[r] = vo[it][out_pos<RL>(r)];
+#pragma unroll
+        for (int r = 0; r < RL; ++r) vo[it][r] = t[r];
+      }
+    }
   }
 }
 

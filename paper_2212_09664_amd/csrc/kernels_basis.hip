@@ -19,130 +19,156 @@
 
 namespace ag {
 
+template <int N>
+__device__ __forceinline__ constexpr bool PL_ONE() { return FftPlan<N>::P == 1; }
+
 // ---------------------------------------------------------------------------
-// forward: grid (nx/txx, coil groups); the U tile stays in registers while
-// the workgroup loops over its coils.
+// forward: grid (nx/txx, coil groups).  The U tile and the coil values feed
+// the transform's first pass straight from registers and the last pass
+// stores straight to W, so per coil only the middle of the transform goes
+// through LDS; the next coil's values are loaded during the transform.
 // ---------------------------------------------------------------------------
 template <int N, int CT>
 __global__ __launch_bounds__(AG_NT) void k_basis_fwd(BasisArgs a) {
-  __shared__ float2 s[N * CT];
-  constexpr int IT = (N * CT + AG_NT - 1) / AG_NT;
+  using GM = FftGeom<N, CT, AG_NT>;
+  constexpr int IT0 = GM::IT0, R0 = GM::R0, ITL = GM::ITL, RL = GM::RL;
+  __shared__ float2 s[FftPlan<N>::P > 1 ? N * CT : 1];
+  __shared__ float2 s_tw[N];
+  __shared__ int s_ro[N];  // k-space row -> offset of its W row within a coil, -1 if not kept
   const int tid = threadIdx.x;
   const int txx = a.txx, r = a.r, ctr = txx * r;
   const int x0 = blockIdx.x * txx;
   if (a.st->err || (a.check_halt && a.st->halt)) return;
-  float2 uv[IT];
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int g = tid + it * AG_NT;
-    const int y = g / CT, col = g % CT;
-    uv[it] = (g < N * CT && col < ctr) ? a.U[((long)y * a.nx + x0) * r + col] : make_float2(0.f, 0.f);
+  for (int e = tid; e < N; e += AG_NT) {
+    s_tw[e] = a.tw[e];
+    const int u = a.row_unit ? a.row_unit[e] : e;
+    s_ro[e] = u >= 0 ? u * a.nx * r : -1;
   }
-  const int n_rows = a.rows ? *a.n_rows_ptr : N;
+  float2 uv[IT0][R0];
+#pragma unroll
+  for (int it = 0; it < IT0; ++it)
+#pragma unroll
+    for (int q = 0; q < R0; ++q) {
+      const int g = tid + it * AG_NT, col = g % CT, y = GM::in_row(g, q);
+      uv[it][q] = (GM::in_ok(g) && col < ctr) ? a.U[((long)y * a.nx + x0) * r + col] : make_float2(0.f, 0.f);
+    }
+  __syncthreads();
   const int cb = blockIdx.y * a.cgs, ce = min(a.nc, cb + a.cgs);
-  float2 cv[IT];
+  float2 cv[IT0][R0];
   auto fetch = [&](int c) {
     const float2* coil = a.coils + (long)c * a.n;
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int g = tid + it * AG_NT;
-      const int y = g / CT, col = g % CT;
-      cv[it] = (g < N * CT && col < ctr) ? coil[(long)y * a.nx + x0 + col / r] : make_float2(0.f, 0.f);
+    for (int it = 0; it < IT0; ++it) {
+      const int g = tid + it * AG_NT, col = g % CT;
+      const bool ok = GM::in_ok(g) && col < ctr;
+      const float2* cp = coil + (g / CT) * a.nx + x0 + col / r;
+#pragma unroll
+      for (int q = 0; q < R0; ++q) cv[it][q] = ok ? cp[q * (N / R0) * a.nx] : make_float2(0.f, 0.f);
     }
   };
   if (cb < ce) fetch(cb);
   for (int c = cb; c < ce; ++c) {
+    float2 v0[IT0][R0], vo[ITL][RL];
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int g = tid + it * AG_NT;
-      if (g < N * CT) s[g] = cmul(cv[it], uv[it]);
+    for (int it = 0; it < IT0; ++it)
+#pragma unroll
+      for (int q = 0; q < R0; ++q) v0[it][q] = cmul(cv[it][q], uv[it][q]);
+    if (c + 1 < ce) fetch(c + 1);
+    fft_regs<N, CT, AG_NT, false>(v0, vo, s, s_tw);
+    float2* dst = a.W + (long)c * a.ua * a.nx * r + x0 * r;
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int g = tid + it * AG_NT, col = g % CT;
+      if (GM::out_ok(g) && col < ctr) {
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+          const int ro = s_ro[GM::out_row(g, q)];
+          if (ro >= 0) dst[ro + col] = cscale(vo[it][q], a.scale);
+        }
+      }
     }
-    __syncthreads();
-    if (c + 1 < ce) fetch(c + 1);  // in flight during this coil's transform
-    fft_lds<N, CT, AG_NT, false>(s, a.tw);
-    float2* dst = a.W + (long)c * a.ua * a.nx * r;
-    for (int g = tid; g < n_rows * ctr; g += AG_NT) {
-      const int u = g / ctr, col = g - u * ctr;
-      const int ky = a.rows ? a.rows[u] : u;
-      dst[((long)u * a.nx + x0) * r + col] = cscale(s[ky * CT + col], a.scale);
-    }
-    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
 // adjoint + coil combine: grid (nx/txx, coil groups); group g writes its
-// partial gradient to G + g*part_stride.
+// partial gradient to G + g*part_stride.  K rows feed the first pass from
+// registers (zero on rows that are not sampled), the coil-weighted sum is
+// taken on the last pass's registers.
 // ---------------------------------------------------------------------------
 template <int N, int CT>
 __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
-  __shared__ float2 s[N * CT];
-  constexpr int IT = (N * CT + AG_NT - 1) / AG_NT;
+  using GM = FftGeom<N, CT, AG_NT>;
+  constexpr int IT0 = GM::IT0, R0 = GM::R0, ITL = GM::ITL, RL = GM::RL;
+  __shared__ float2 s[FftPlan<N>::P > 1 ? N * CT : 1];
+  __shared__ float2 s_tw[N];
+  __shared__ int s_ro[N];  // k-space row -> offset of its K row within a coil, -1 for a zero row
   const int tid = threadIdx.x;
   const int txx = a.txx, r = a.r, ctr = txx * r;
   const int x0 = blockIdx.x * txx;
   if (a.st->err || (a.check_halt && a.st->halt)) return;
-  const int n_rows = a.rows ? *a.n_rows_ptr : N;
-  const bool full = (a.rows == nullptr);
-  const int total = n_rows * ctr;  // <= N * CT
-  // LDS destination of this thread's row items (fixed across coils)
-  int dst[IT];
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int g = tid + it * AG_NT;
-    dst[it] = -1;
-    if (g < total) {
-      const int u = g / ctr, col = g - u * ctr;
-      dst[it] = (full ? u : a.rows[u]) * CT + col;
-    }
+  for (int e = tid; e < N; e += AG_NT) {
+    float2 w = a.tw[e];
+    s_tw[e] = make_float2(w.x, -w.y);
+    const int u = a.row_unit ? a.row_unit[e] : e;
+    s_ro[e] = u >= 0 ? u * a.nx * r : -1;
   }
-  float2 acc[IT], kv[IT], cv[IT];
+  __syncthreads();
+  float2 acc[ITL][RL];
 #pragma unroll
-  for (int it = 0; it < IT; ++it) acc[it] = make_float2(0.f, 0.f);
+  for (int it = 0; it < ITL; ++it)
+#pragma unroll
+    for (int q = 0; q < RL; ++q) acc[it][q] = make_float2(0.f, 0.f);
   const int cb = blockIdx.y * a.cgs, ce = min(a.nc, cb + a.cgs);
-  // coil c's K rows and coil values, into registers
+  float2 kv[IT0][R0];
   auto fetch = [&](int c) {
-    const float2* src = a.K + (long)c * a.ua * a.nx * r;
-    const float2* coil = a.coils + (long)c * a.n;
+    const float2* src = a.K + (long)c * a.ua * a.nx * r + x0 * r;
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int g = tid + it * AG_NT;
-      if (g < total) {
-        const int u = g / ctr, col = g - u * ctr;
-        kv[it] = src[((long)u * a.nx + x0) * r + col];
+    for (int it = 0; it < IT0; ++it) {
+      const int g = tid + it * AG_NT, col = g % CT;
+      const bool ok = GM::in_ok(g) && col < ctr;
+#pragma unroll
+      for (int q = 0; q < R0; ++q) {
+        const int ro = ok ? s_ro[GM::in_row(g, q)] : -1;
+        kv[it][q] = ro >= 0 ? src[ro + col] : make_float2(0.f, 0.f);
       }
-      const int y = g / CT, col = g % CT;
-      cv[it] = (g < N * CT && col < ctr) ? coil[(long)y * a.nx + x0 + col / r] : make_float2(0.f, 0.f);
     }
   };
   if (cb < ce) fetch(cb);
   for (int c = cb; c < ce; ++c) {
-    if (!full) {
-      for (int g = tid; g < N * CT; g += AG_NT) s[g] = make_float2(0.f, 0.f);
-      __syncthreads();
+    float2 v0[IT0][R0], vo[ITL][RL];
+#pragma unroll
+    for (int it = 0; it < IT0; ++it)
+#pragma unroll
+      for (int q = 0; q < R0; ++q) v0[it][q] = kv[it][q];
+    if (c + 1 < ce) fetch(c + 1);
+    // the forward table conjugated in LDS gives the inverse twiddles
+    fft_regs<N, CT, AG_NT, true>(v0, vo, s, s_tw);
+    const float2* coil = a.coils + (long)c * a.n;
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int g = tid + it * AG_NT, col = g % CT;
+      if (GM::out_ok(g) && col < ctr) {
+        const float2* cp = coil + (g / CT) * (PL_ONE<N>() ? RL : 1) * a.nx + x0 + col / r;
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+          const float2 cw = cp[(PL_ONE<N>() ? q : q * (N / RL)) * a.nx];
+          acc[it][q] = cadd(acc[it][q], cjmul(cw, vo[it][q]));
+        }
+      }
     }
-#pragma unroll
-    for (int it = 0; it < IT; ++it)
-      if (dst[it] >= 0) s[dst[it]] = kv[it];
-    float2 cc[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) cc[it] = cv[it];
-    __syncthreads();
-    if (c + 1 < ce) fetch(c + 1);  // in flight during this coil's transform
-    fft_lds<N, CT, AG_NT, true>(s, a.tw);
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int g = tid + it * AG_NT;
-      if (g < N * CT) acc[it] = cadd(acc[it], cjmul(cc[it], s[g]));
-    }
-    __syncthreads();
   }
   float2* out = a.G + (long)blockIdx.y * a.part_stride;
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int g = tid + it * AG_NT;
-    const int y = g / CT, col = g % CT;
-    if (g < N * CT && col < ctr) out[((long)y * a.nx + x0) * r + col] = cscale(acc[it], a.scale);
+  for (int it = 0; it < ITL; ++it) {
+    const int g = tid + it * AG_NT, col = g % CT;
+    if (GM::out_ok(g) && col < ctr) {
+#pragma unroll
+      for (int q = 0; q < RL; ++q) {
+        const int y = GM::out_row(g, q);
+        out[((long)y * a.nx + x0) * r + col] = cscale(acc[it][q], a.scale);
+      }
+    }
   }
 }
 
@@ -200,20 +226,60 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
   if (a.st->err || (a.check_halt && a.st->halt)) return;
   if (u >= a.st->n_units) return;
   const int r = a.r, nx = a.nx;
-  const int ky = a.unit_loc[u];
-  const int p0 = a.loc_ptr[ky], np = a.loc_ptr[ky + 1] - p0;
-  // S_u and conj(b_k) of the line's samples, prepared once per iteration
-  for (int e = tid; e < r * r; e += AG_NT) S[(e / r) * RT + (e % r)] = a.S[(long)u * r * r + e];
-  for (int e = tid; e < np * r; e += AG_NT) bc[(e / r) * RT + (e % r)] = a.bcp[(long)p0 * r + e];
-  const long blk = ((long)c * a.ua + u) * nx * r;
-  const float2* Yb = a.yu + (long)a.nc * nx * p0 + (long)c * np * nx;  // [p][x]
+  // LDS slot of element g of a [x][j] block: x = g / r through a float
+  // reciprocal (exact: g < 2^13 and the fraction of (g + 1/2)/r is >= 1/(2r))
+  const float rinv = 1.0f / (float)r;
+  int slot[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int g = tid + t * AG_NT;
+    const int xx = (int)(((float)g + 0.5f) * rinv);
+    slot[t] = xx * (RT + 1) + (g - xx * r);
+  }
+  const int2 span = a.unit_span[u];
+  const int p0 = span.x, np = span.y;
+  const int np8 = (np + 7) & ~7;  // rows past np are zero, so the data loop runs in whole batches of 8
   for (int x0 = 0; x0 < nx; x0 += AG_NT) {
-    const int nxc = min(AG_NT, nx - x0);
-    if (x0 > 0) __syncthreads();
-    for (int g = tid; g < nxc * r; g += AG_NT) Wl[(g / r) * (RT + 1) + (g % r)] = a.W[blk + (long)x0 * r + g];
+    const int nxc = min(AG_NT, nx - x0), tot = nxc * r;
+    const int x = x0 + tid;
+    const long blk = (((long)c * a.ua + u) * nx + x0) * r;
+    float2 wv[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int g = tid + t * AG_NT;
+      wv[t] = (g < tot) ? a.W[blk + g] : make_float2(0.f, 0.f);
+    }
+    const float2* Yb = a.yu + (long)a.nc * nx * p0 + (long)c * np * nx + x;  // [p][x]
+    auto load_y = [&](int pb, float2 (&yv)[8]) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        yv[t] = (tid < nxc && pb + t < np) ? Yb[(long)(pb + t) * nx] : make_float2(0.f, 0.f);
+    };
+    float2 ya[8], yb[8];
+    load_y(0, ya);
+    if (x0 == 0) {
+      // conj(b_k) of the line's samples, then S_u = sum_k b_k b_k^H
+      for (int e = tid; e < np8 * RT; e += AG_NT) {
+        const int p = e / RT, j = e - p * RT;
+        bc[e] = (p < np && j < r) ? a.bcp[(long)(p0 + p) * r + j] : make_float2(0.f, 0.f);
+      }
+      __syncthreads();
+      for (int e = tid; e < r * r; e += AG_NT) {
+        const int i = e / r, j = e - i * r;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int p = 0; p < np; ++p) acc = cadd(acc, cjmul(bc[p * RT + i], bc[p * RT + j]));
+        S[i * RT + j] = acc;
+      }
+    } else {
+      __syncthreads();  // the previous chunk's store has read Wl
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int g = tid + t * AG_NT;
+      if (g < tot) Wl[slot[t]] = wv[t];
+    }
     __syncthreads();
     if (tid < nxc) {
-      const int x = x0 + tid;
       float2 w[RT], kk[RT];
 #pragma unroll
       for (int i = 0; i < RT; ++i) w[i] = (i < r) ? Wl[tid * (RT + 1) + i] : make_float2(0.f, 0.f);
@@ -221,46 +287,33 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
       for (int j = 0; j < RT; ++j) {
         float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int i = 0; i < RT; ++i)
-          if (i < r) acc = cadd(acc, cmul(w[i], S[i * RT + j]));
+        for (int i = 0; i < RT; ++i) acc = cadd(acc, cmul(w[i], S[i * RT + j]));
         kk[j] = acc;
       }
-#pragma unroll 8
-      for (int p = 0; p < np; ++p) {
-        const float2 yv = Yb[(long)p * nx + x];
+      // data batches of 8, the next batch in flight while this one is used
+      for (int pb = 0; pb < np; pb += 16) {
+        if (pb + 8 < np) load_y(pb + 8, yb);
 #pragma unroll
-        for (int j = 0; j < RT; ++j) kk[j] = csub(kk[j], cmul(yv, bc[p * RT + j]));
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+          for (int j = 0; j < RT; ++j) kk[j] = csub(kk[j], cmul(ya[t], bc[(pb + t) * RT + j]));
+        if (pb + 8 >= np) break;
+        if (pb + 16 < np) load_y(pb + 16, ya);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+          for (int j = 0; j < RT; ++j) kk[j] = csub(kk[j], cmul(yb[t], bc[(pb + 8 + t) * RT + j]));
       }
 #pragma unroll
       for (int j = 0; j < RT; ++j)
         if (j < r) Wl[tid * (RT + 1) + j] = kk[j];
     }
     __syncthreads();
-    for (int g = tid; g < nxc * r; g += AG_NT) a.K[blk + (long)x0 * r + g] = Wl[(g / r) * (RT + 1) + (g % r)];
-  }
-}
-
-// per sampled line: S_u = sum_{samples on u} b_k b_k^H and conj(b_k) per sample
-__global__ __launch_bounds__(64) void k_line_S(FoldArgs a) {
-  const int u = blockIdx.x, tid = threadIdx.x;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
-  if (u >= a.st->n_units) return;
-  const int r = a.r;
-  const int ky = a.unit_loc[u];
-  const int p0 = a.loc_ptr[ky], np = a.loc_ptr[ky + 1] - p0;
-  for (int e = tid; e < np * r; e += 64) {
-    const int p = e / r, j = e % r;
-    const float2 b = a.B[(long)a.pairs[p0 + p].x * r + j];
-    a.bcp[(long)(p0 + p) * r + j] = make_float2(b.x, -b.y);
-  }
-  for (int e = tid; e < r * r; e += 64) {
-    const int i = e / r, j = e % r;
-    float2 sacc = make_float2(0.f, 0.f);
-    for (int p = 0; p < np; ++p) {
-      const float2* b = a.B + (long)a.pairs[p0 + p].x * r;
-      sacc = cadd(sacc, cmulj(b[i], b[j]));
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int g = tid + t * AG_NT;
+      if (g < tot) a.K[blk + g] = Wl[slot[t]];
     }
-    a.S[(long)u * r * r + e] = sacc;
   }
 }
 
@@ -358,7 +411,6 @@ hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int gr
 hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s) {
   const dim3 g(grid_x, grid_y);
   if (lines) {
-    hipLaunchKernelGGL(k_line_S, dim3(grid_x), dim3(64), 0, s, a);
     if (a.r <= 4) hipLaunchKernelGGL(k_fold_lines2<4>, g, dim3(AG_NT), 0, s, a);
     else if (a.r <= 8) hipLaunchKernelGGL(k_fold_lines2<8>, g, dim3(AG_NT), 0, s, a);
     else hipLaunchKernelGGL(k_fold_lines2<16>, g, dim3(AG_NT), 0, s, a);

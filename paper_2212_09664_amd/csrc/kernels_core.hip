@@ -35,7 +35,7 @@ __global__ void k_inv_bitmap(const int32_t* mask, const int32_t* m_k, int width,
 
 __global__ __launch_bounds__(1024) void k_inv_scan(const uint32_t* bitmap, int nw, int n_loc,
                                                    int32_t* loc_ptr, int32_t* loc2unit,
-                                                   int32_t* unit_loc, DevState* st) {
+                                                   int32_t* unit_loc, int2* unit_span, DevState* st) {
   __shared__ int s_cnt[1024], s_un[1024];
   const int tid = threadIdx.x;
   const int chunk = (n_loc + 1023) / 1024;
@@ -66,6 +66,7 @@ __global__ __launch_bounds__(1024) void k_inv_scan(const uint32_t* bitmap, int n
     if (c > 0) {
       loc2unit[l] = pu;
       unit_loc[pu] = l;
+      unit_span[pu] = make_int2(pc, c);  // the unit's samples: pairs [pc, pc + c)
       ++pu;
     } else {
       loc2unit[l] = -1;

@@ -4,6 +4,7 @@
 #include "kernels.hpp"
 
 #define GRAM_OPT 2    // outputs per thread in the per-line Gram kernels
+#define SOLVE_NT 1024  // threads of the per-frame solve
 #define GCOLS_OPT 9   // outputs per thread in the column-Gram kernel (m <= 64)
 
 namespace ag {
@@ -56,6 +57,7 @@ struct SolveArgs {
   long npairs;           // LINES: pairs allocated per group in hp
   const double* ysq_k;
   float2* B;             // r x q
+  float2* bcp;           // LINES: conj(b_k) per pair, for the gradient fold
   double* cost_k;
   DevState* st;
   int check_halt;
@@ -72,6 +74,7 @@ struct BasisArgs {
   long part_stride;
   const int32_t* rows;        // sampled rows (ky) of W / K, or null: all rows
   const int32_t* n_rows_ptr;
+  const int32_t* row_unit;    // k-space row -> row of W / K (-1: not kept), or null: identity
   const float2* tw;           // twiddles along y
   const float2* tw_x;         // twiddles along x
   float scale, scale_x;
@@ -80,8 +83,8 @@ struct BasisArgs {
 };
 
 struct FoldArgs {
-  float2* S;             // LINES: per-line S_u (ua x r x r)
-  float2* bcp;           // LINES: conj(b_k) per sample (pairs x r)
+  const int2* unit_span;  // LINES: per sampled line, its first pair and pair count
+  const float2* bcp;      // LINES: conj(b_k) of every pair, in pair order (written by the solve)
   const float2* W;
   const float2* yu;      // LINES: per-line data [c][x][p]
   const float2* yh;      // LINES: hybrid data
@@ -159,7 +162,7 @@ __device__ __forceinline__ void tri_index(int o, int r, int& i, int& j) {
 __global__ void k_inv_bitmap(const int32_t* mask, const int32_t* m_k, int width, int per, int n_loc,
                              uint32_t* bitmap, int nw, DevState* st);
 __global__ void k_inv_scan(const uint32_t* bitmap, int nw, int n_loc, int32_t* loc_ptr, int32_t* loc2unit,
-                           int32_t* unit_loc, DevState* st);
+                           int32_t* unit_loc, int2* unit_span, DevState* st);
 __global__ void k_inv_fill(const int32_t* mask, const int32_t* m_k, int width, int per, const uint32_t* bitmap,
                            int nw, const int32_t* loc_ptr, const int32_t* loc2unit, int2* pairs, int32_t* pair_of,
                            int32_t* unit_of, const DevState* st);

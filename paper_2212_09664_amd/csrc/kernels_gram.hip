@@ -289,13 +289,14 @@ struct Cx<double> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
+__global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
   using C = Cx<T>;
   using T2 = typename C::T2;
   __shared__ T2 G[16 * 16];
   __shared__ T2 h[16];
   __shared__ T2 z[16];
-  __shared__ double2 part[256];
+  __shared__ double2 part[SOLVE_NT];
+  __shared__ int s_mk[512], s_po[512];
   __shared__ int bad;
   const int k = blockIdx.x, tid = threadIdx.x, r = a.r;
   if (a.st->err || (a.check_halt && a.st->halt)) return;
@@ -304,31 +305,34 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
   if (a.kind == 0) {
     // sum over coil groups and the frame's lines; thread = (entry, slice)
     const int L = a.m_k[k] / a.nx;
-    const int NS = max(1, 256 / E);
+    for (int l = tid; l < L; l += SOLVE_NT) {
+      s_mk[l] = a.unit_of[(long)k * a.width + l];  // sampled line of (k, l)
+      s_po[l] = a.pair_of[(long)k * a.width + l];
+    }
+    __syncthreads();
+    const int NS = max(1, SOLVE_NT / E), SW = SOLVE_NT / NS;
     const int items = a.ngroups * L;
-    const int32_t* mk = a.unit_of + (long)k * a.width;  // sampled line of (k, l)
-    const int32_t* po = a.pair_of + (long)k * a.width;
-    for (int e0 = 0; e0 < E; e0 += 256 / NS) {
-      const int e = e0 + tid % (256 / NS);
-      const int sl = tid / (256 / NS);
+    for (int e0 = 0; e0 < E; e0 += SW) {
+      const int e = e0 + tid % SW;
+      const int sl = tid / SW;
       double2 s = make_double2(0.0, 0.0);
       if (e < E && sl < NS) {
 #pragma unroll 8
         for (int it = sl; it < items; it += NS) {
-          const int gg = it / L, l = it % L;
+          const int gg = it / L, l = it - gg * L;
           double2 v;
           if (e < r * r)
-            v = a.P[((long)gg * a.ua + mk[l]) * r * r + e];
+            v = a.P[((long)gg * a.ua + s_mk[l]) * r * r + e];
           else
-            v = a.hp[((long)gg * a.npairs + po[l]) * r + (e - r * r)];
+            v = a.hp[((long)gg * a.npairs + s_po[l]) * r + (e - r * r)];
           s = dadd(s, v);
         }
       }
       part[tid] = s;
       __syncthreads();
-      if (tid < 256 / NS && e < E) {
+      if (tid < SW && e < E) {
         double2 t = part[tid];
-        for (int q2 = 1; q2 < NS; ++q2) t = dadd(t, part[tid + q2 * (256 / NS)]);
+        for (int q2 = 1; q2 < NS; ++q2) t = dadd(t, part[tid + q2 * SW]);
         if (e < r * r)
           G[(e / r) * 16 + (e % r)] = C::from(t);
         else
@@ -337,7 +341,7 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
       __syncthreads();
     }
   } else {
-    for (int e = tid; e < E; e += 256) {
+    for (int e = tid; e < E; e += SOLVE_NT) {
       double2 s = make_double2(0.0, 0.0);
       for (int ch = 0; ch < a.nchunks; ++ch) s = dadd(s, a.P[((long)k * a.nchunks + ch) * E + e]);
       if (e < r * r)
@@ -360,10 +364,10 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
     const T ljj = (T)sqrt(d);
     __syncthreads();
     if (tid == 0) G[j * 16 + j] = T2{ljj, (T)0};
-    for (int i = j + 1 + tid; i < r; i += 256) G[i * 16 + j] = C::scale(G[i * 16 + j], (T)1 / ljj);
+    for (int i = j + 1 + tid; i < r; i += SOLVE_NT) G[i * 16 + j] = C::scale(G[i * 16 + j], (T)1 / ljj);
     __syncthreads();
     const int m = r - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
+    for (int e = tid; e < m * m; e += SOLVE_NT) {
       const int i = j + 1 + e / m, c2 = j + 1 + e % m;
       if (c2 <= i) {
         const T2 lij = G[i * 16 + j], lcj = G[c2 * 16 + j];
@@ -396,6 +400,14 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
     }
     a.cost_k[k] = a.ysq_k[k] - hb;
     if (!fin) set_error(a.st, 5 /*ENONFINITE*/, k);
+  }
+  if (a.kind == 0) {  // conj(b_k) at each of the frame's pairs
+    __syncthreads();
+    const int L = a.m_k[k] / a.nx;
+    for (int e = tid; e < L * r; e += SOLVE_NT) {
+      const int l = e / r, j = e - l * r;
+      a.bcp[(long)s_po[l] * r + j] = make_float2((float)z[j].x, -(float)z[j].y);
+    }
   }
 }
 
@@ -439,9 +451,9 @@ hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp
 
 hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s) {
   if (fp64)
-    hipLaunchKernelGGL(k_solve<double>, dim3(q), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_solve<double>, dim3(q), dim3(SOLVE_NT), 0, s, a);
   else
-    hipLaunchKernelGGL(k_solve<float>, dim3(q), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_solve<float>, dim3(q), dim3(SOLVE_NT), 0, s, a);
   return hipGetLastError();
 }
 
