@@ -126,7 +126,7 @@ void carve(altgdmin_ctx* c) {
   c->o_qpart = take(sizeof(double2) * qo * c->qr_nblk);
   c->o_rinv = take(sizeof(float2) * r * r);
   c->o_Vs = take(sizeof(float2) * (size_t)q * r);
-  c->o_V = take(sizeof(double2) * (size_t)q * q);
+  c->o_V = take(sizeof(double2) * 2 * (size_t)q * q);
   // temp: X0 plus the truncated hybrid data (LINES) or a chunk of coil images (INDEX)
   size_t tb = sizeof(float2) * (size_t)n * q;
   if (c->lines)
@@ -563,10 +563,6 @@ altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** ou
   c->qr_rows = (c->qr_rows + 63) / 64 * 64;
   c->qr_nblk = (int)((c->n + c->qr_rows - 1) / c->qr_rows);
   c->kc = std::min(p.q, 16);
-  if (p.q > 64) {  // spectral initialisation holds the q x q Gram in one workgroup
-    delete c;
-    return ALTGDMIN_EUNSUPPORTED;
-  }
   carve(c);
   *out = c;
   return ALTGDMIN_OK;
@@ -660,6 +656,7 @@ altgdmin_status altgdmin_init(altgdmin_ctx* c, void* d_U) {
   ie.q = p.q;
   ie.r = p.r;
   ie.V = c->at<double2>(c->o_V);
+  ie.in_lds = p.q <= 64;
   ie.Vs = c->at<float2>(c->o_Vs);
   ie.st = c->st();
   HIPCHK(launch_init_eig(ie, s));

@@ -288,22 +288,23 @@ __global__ __launch_bounds__(AG_NT) void k_fold_index(FoldArgs a) {
 // and n x m2), upper triangle, partial sums per workgroup in FP64.
 // ===========================================================================
 template <typename ACC>
-__global__ __launch_bounds__(AG_NT) void k_gram_cols(GramColsArgs a) {
+__global__ __launch_bounds__(GCOLS_NT) void k_gram_cols(GramColsArgs a) {
   using A2 = Acc2<ACC>;
   __shared__ float2 Xs[64 * 64];
   const int tid = threadIdx.x, blk = blockIdx.x;
   if (a.st->err || (a.check_halt && a.st->halt)) return;
-  const int m = a.m1 + a.m2;
+  const int m = a.m1 + a.m2;  // <= 128
   const int nout = m * (m + 1) / 2;
+  const int RC = m <= 64 ? 64 : 32;  // rows staged per chunk
   typename A2::T acc[GCOLS_OPT];
 #pragma unroll
   for (int t = 0; t < GCOLS_OPT; ++t) acc[t] = A2::zero();
   const long pa = (long)blk * a.rows_per_block;
   const long pb = min((long)a.n, pa + a.rows_per_block);
-  for (long p0 = pa; p0 < pb; p0 += 64) {
-    const int np = (int)min((long)64, pb - p0);
-    for (int g = tid; g < 64 * m; g += AG_NT) {
-      const int j = g / 64, pp = g % 64;
+  for (long p0 = pa; p0 < pb; p0 += RC) {
+    const int np = (int)min((long)RC, pb - p0);
+    for (int g = tid; g < RC * m; g += GCOLS_NT) {
+      const int j = g / RC, pp = g % RC;
       float2 v = make_float2(0.f, 0.f);
       if (pp < np) v = (j < a.m1) ? a.A[(long)j * a.n + p0 + pp] : a.B[(long)(j - a.m1) * a.n + p0 + pp];
       Xs[pp * m + j] = v;
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(AG_NT) void k_gram_cols(GramColsArgs a) {
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < GCOLS_OPT; ++t) {
-      const int o = tid + t * AG_NT;
+      const int o = tid + t * GCOLS_NT;
       if (o < nout) {
         int i, j;
         tri_index(o, m, i, j);
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(AG_NT) void k_gram_cols(GramColsArgs a) {
   }
 #pragma unroll
   for (int t = 0; t < GCOLS_OPT; ++t) {
-    const int o = tid + t * AG_NT;
+    const int o = tid + t * GCOLS_NT;
     if (o < nout) a.part[(long)blk * nout + o] = A2::to_d(acc[t]);
   }
 }
@@ -344,18 +345,63 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Cyclic Jacobi eigen-decomposition of the Hermitian n x n matrix A (LDS,
-// overwritten: eigenvalues end on the diagonal).  Disjoint pairs are rotated
-// together (round-robin ordering); each 2 x 2 rotation removes the phase of
-// A_pq and then applies the real symmetric Jacobi rotation.  V (global
-// memory, row-major n x n, row i owned by thread i) accumulates the
-// eigenvectors as columns when non-null.
+// one complex Jacobi rotation G (c, s, e) that zeroes A[p][q] of the
+// Hermitian 2x2 block [[app, apq], [conj(apq), aqq]]; identity if q >= n or
+// the entry is already negligible
+struct JRot {
+  double c, s;
+  double2 e;
+};
+__device__ __forceinline__ JRot jacobi_rot(const double2* A, int ld, int n, int p, int q) {
+  JRot g{1.0, 0.0, make_double2(1.0, 0.0)};
+  if (q >= n) return g;
+  const double2 apq = A[p * ld + q];
+  const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+  const double app = A[p * ld + p].x, aqq = A[q * ld + q].x;
+  if (mag > 1e-300 && mag > 1e-18 * (fabs(app) + fabs(aqq))) {
+    g.e = make_double2(apq.x / mag, -apq.y / mag);  // exp(-i phi)
+    const double tau = (aqq - app) / (2.0 * mag);
+    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    g.c = 1.0 / sqrt(1.0 + t * t);
+    g.s = t * g.c;
+  }
+  return g;
+}
+
+// pair i of round s of the round-robin ordering over Q (even) indices
+__device__ __forceinline__ void jacobi_pair(int s, int i, int Q, int& p, int& q) {
+  if (i == 0) {
+    p = Q - 1;
+    q = s;
+  } else {
+    p = (s + i) % (Q - 1);
+    q = (s - i + Q - 1) % (Q - 1);
+  }
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+}
+
+// Cyclic complex Jacobi eigensolver for the Hermitian n x n matrix A
+// (row-major, leading dimension ld), parallel round-robin ordering: the
+// Q/2 rotations of a round are disjoint and are applied together.  The
+// matrix splits into 2x2 blocks (pair i rows, pair j columns); each block
+// is updated independently, A_ij <- G_i^H A_ij G_j, with both rotations
+// computed from the matrix as it was at the start of the round, so a round
+// is one read phase and one write phase.  V (if given, ld n) accumulates
+// V <- V G.  A and V may be in LDS or in global memory private to the
+// workgroup.  On return diag(A) holds the eigenvalues and the columns of V
+// the eigenvectors.  Up to JAC_ITEMS*blockDim blocks, i.e. n <= 128 with
+// 1024 threads.
+#define JAC_ITEMS 4
 __device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch* js, int max_sweeps) {
   const int tid = threadIdx.x, NT = blockDim.x;
   if (V)
     for (int e = tid; e < n * n; e += NT) V[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
   __syncthreads();
-  const int Q = n + (n & 1);
+  const int Q = n + (n & 1), H = Q / 2;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < n * n; e += NT) {
@@ -369,74 +415,69 @@ __device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch*
     tot = block_sum(tot, js->red);
     if (!(off > 1e-26 * tot)) break;
     for (int s = 0; s < Q - 1; ++s) {
-      for (int i = tid; i < Q / 2; i += NT) {
-        int p, q;
-        if (i == 0) {
-          p = Q - 1;
-          q = s;
-        } else {
-          p = (s + i) % (Q - 1);
-          q = (s - i + Q - 1) % (Q - 1);
+      double2 na[JAC_ITEMS][4], nv[JAC_ITEMS][4];
+#pragma unroll
+      for (int k = 0; k < JAC_ITEMS; ++k) {
+        const int t = tid + k * NT;
+        if (t >= H * H) break;
+        const int i = t / H, j = t - (t / H) * H;
+        int pi, qi, pj, qj;
+        jacobi_pair(s, i, Q, pi, qi);
+        jacobi_pair(s, j, Q, pj, qj);
+        const JRot gi = jacobi_rot(A, ld, n, pi, qi);
+        const JRot gj = (i == j) ? gi : jacobi_rot(A, ld, n, pj, qj);
+        const bool ri = qi < n, rj = qj < n;  // the second row / column exists
+        const double2 z = make_double2(0.0, 0.0);
+        // the block [[a, b], [c, d]] = A[(pi, qi), (pj, qj)]
+        double2 a = A[pi * ld + pj], b = rj ? A[pi * ld + qj] : z;
+        double2 c = ri ? A[qi * ld + pj] : z, d = (ri && rj) ? A[qi * ld + qj] : z;
+        // columns: (x, y) <- (c x - s y e, s x + c y e) with y e
+        {
+          const double2 y0 = dmul(b, gj.e), y1 = dmul(d, gj.e);
+          const double2 a2 = make_double2(gj.c * a.x - gj.s * y0.x, gj.c * a.y - gj.s * y0.y);
+          const double2 b2 = make_double2(gj.s * a.x + gj.c * y0.x, gj.s * a.y + gj.c * y0.y);
+          const double2 c2 = make_double2(gj.c * c.x - gj.s * y1.x, gj.c * c.y - gj.s * y1.y);
+          const double2 d2 = make_double2(gj.s * c.x + gj.c * y1.x, gj.s * c.y + gj.c * y1.y);
+          a = a2; b = b2; c = c2; d = d2;
         }
-        if (p > q) {
-          int t = p;
-          p = q;
-          q = t;
+        // rows: with conj(e_i)
+        {
+          const double2 ec = dconj(gi.e);
+          const double2 y0 = dmul(c, ec), y1 = dmul(d, ec);
+          na[k][0] = make_double2(gi.c * a.x - gi.s * y0.x, gi.c * a.y - gi.s * y0.y);
+          na[k][1] = make_double2(gi.c * b.x - gi.s * y1.x, gi.c * b.y - gi.s * y1.y);
+          na[k][2] = make_double2(gi.s * a.x + gi.c * y0.x, gi.s * a.y + gi.c * y0.y);
+          na[k][3] = make_double2(gi.s * b.x + gi.c * y1.x, gi.s * b.y + gi.c * y1.y);
         }
-        js->p[i] = p;
-        js->q[i] = q;
-        double c = 1.0, sn = 0.0;
-        double2 e = make_double2(1.0, 0.0);
-        if (q < n) {
-          const double2 apq = A[p * ld + q];
-          const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
-          const double app = A[p * ld + p].x, aqq = A[q * ld + q].x;
-          if (mag > 1e-300 && mag > 1e-18 * (fabs(app) + fabs(aqq))) {
-            e = make_double2(apq.x / mag, -apq.y / mag);  // exp(-i phi)
-            const double tau = (aqq - app) / (2.0 * mag);
-            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = t * c;
-          }
+        if (V) {  // V rows (pi, qi), columns (pj, qj): right rotation only
+          double2 va = V[pi * n + pj], vb = rj ? V[pi * n + qj] : z;
+          double2 vc = ri ? V[qi * n + pj] : z, vd = (ri && rj) ? V[qi * n + qj] : z;
+          const double2 y0 = dmul(vb, gj.e), y1 = dmul(vd, gj.e);
+          nv[k][0] = make_double2(gj.c * va.x - gj.s * y0.x, gj.c * va.y - gj.s * y0.y);
+          nv[k][1] = make_double2(gj.s * va.x + gj.c * y0.x, gj.s * va.y + gj.c * y0.y);
+          nv[k][2] = make_double2(gj.c * vc.x - gj.s * y1.x, gj.c * vc.y - gj.s * y1.y);
+          nv[k][3] = make_double2(gj.s * vc.x + gj.c * y1.x, gj.s * vc.y + gj.c * y1.y);
         }
-        js->c[i] = c;
-        js->s[i] = sn;
-        js->e[i] = e;
       }
       __syncthreads();
-      // A <- A G  (columns p, q)
-      for (int it = tid; it < n * (Q / 2); it += NT) {
-        const int i = it / n, k = it % n;
-        const int p = js->p[i], q = js->q[i];
-        if (q >= n || js->s[i] == 0.0) continue;
-        const double c = js->c[i], sn = js->s[i];
-        const double2 e = js->e[i];
-        const double2 x = A[k * ld + p], y = dmul(A[k * ld + q], e);
-        A[k * ld + p] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
-        A[k * ld + q] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
-      }
-      __syncthreads();
-      // A <- G^H A  (rows p, q)
-      for (int it = tid; it < n * (Q / 2); it += NT) {
-        const int i = it / n, k = it % n;
-        const int p = js->p[i], q = js->q[i];
-        if (q >= n || js->s[i] == 0.0) continue;
-        const double c = js->c[i], sn = js->s[i];
-        const double2 e = dconj(js->e[i]);
-        const double2 x = A[p * ld + k], y = dmul(A[q * ld + k], e);
-        A[p * ld + k] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
-        A[q * ld + k] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
-      }
-      if (V) {  // V <- V G (columns p, q), V in LDS
-        for (int it = tid; it < n * (Q / 2); it += NT) {
-          const int i = it / n, k = it % n;
-          const int p = js->p[i], q = js->q[i];
-          if (q >= n || js->s[i] == 0.0) continue;
-          const double c = js->c[i], sn = js->s[i];
-          const double2 e = js->e[i];
-          const double2 x = V[k * n + p], y = dmul(V[k * n + q], e);
-          V[k * n + p] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
-          V[k * n + q] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+#pragma unroll
+      for (int k = 0; k < JAC_ITEMS; ++k) {
+        const int t = tid + k * NT;
+        if (t >= H * H) break;
+        const int i = t / H, j = t - (t / H) * H;
+        int pi, qi, pj, qj;
+        jacobi_pair(s, i, Q, pi, qi);
+        jacobi_pair(s, j, Q, pj, qj);
+        const bool ri = qi < n, rj = qj < n;
+        A[pi * ld + pj] = na[k][0];
+        if (rj) A[pi * ld + qj] = na[k][1];
+        if (ri) A[qi * ld + pj] = na[k][2];
+        if (ri && rj) A[qi * ld + qj] = na[k][3];
+        if (V) {
+          V[pi * n + pj] = nv[k][0];
+          if (rj) V[pi * n + qj] = nv[k][1];
+          if (ri) V[qi * n + pj] = nv[k][2];
+          if (ri && rj) V[qi * n + qj] = nv[k][3];
         }
       }
       __syncthreads();
@@ -727,15 +768,16 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 // scaled top-r eigenvectors V_r Sigma_r^{-1}, so that X_0 V_r Sigma_r^{-1}
 // are the top-r left singular vectors of X_0.
 // ===========================================================================
-__global__ __launch_bounds__(AG_NT) void k_init_eig(InitEigArgs a) {
-  extern __shared__ double2 A[];  // q x q matrix, then q x q eigenvectors
+__global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
+  extern __shared__ double2 lds_m[];  // q x q matrix, then q x q eigenvectors (when they fit)
   __shared__ JacobiScratch js;
-  double2* V = A + a.q * a.q;
   __shared__ int idx[16];
   __shared__ double lam_s[16];
-  const int tid = threadIdx.x, q = a.q, r = a.r;
+  const int tid = threadIdx.x, NT = blockDim.x, q = a.q, r = a.r;
+  double2* A = a.in_lds ? lds_m : a.V;
+  double2* V = A + q * q;
   const int nout = q * (q + 1) / 2;
-  for (int o = tid; o < nout; o += AG_NT) {
+  for (int o = tid; o < nout; o += NT) {
     double2 s = make_double2(0.0, 0.0);
     for (int b = 0; b < a.nblk; ++b) s = dadd(s, a.part[(long)b * nout + o]);
     int i, j;
@@ -768,7 +810,7 @@ __global__ __launch_bounds__(AG_NT) void k_init_eig(InitEigArgs a) {
   }
   __syncthreads();
   if (a.st->err) return;
-  for (int e = tid; e < q * r; e += AG_NT) {
+  for (int e = tid; e < q * r; e += NT) {
     const int k = e / r, j = e % r;
     const double2 v = V[k * q + idx[j]];
     const double sc = 1.0 / sqrt(lam_s[j]);
@@ -828,9 +870,9 @@ hipError_t launch_fold(const FoldArgs& a, bool lines, int grid_x, int grid_y, hi
 
 hipError_t launch_gram_cols(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s) {
   if (fp64)
-    hipLaunchKernelGGL(k_gram_cols<double>, dim3(nblk), dim3(AG_NT), 0, s, a);
+    hipLaunchKernelGGL(k_gram_cols<double>, dim3(nblk), dim3(GCOLS_NT), 0, s, a);
   else
-    hipLaunchKernelGGL(k_gram_cols<float>, dim3(nblk), dim3(AG_NT), 0, s, a);
+    hipLaunchKernelGGL(k_gram_cols<float>, dim3(nblk), dim3(GCOLS_NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -848,12 +890,12 @@ hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s) {
-  const size_t lds = 2 * (size_t)a.q * a.q * sizeof(double2);
+  const size_t lds = a.in_lds ? 2 * (size_t)a.q * a.q * sizeof(double2) : 0;
   if (lds > 48 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_init_eig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_init_eig, dim3(1), dim3(AG_NT), lds, s, a);
+  hipLaunchKernelGGL(k_init_eig, dim3(1), dim3(1024), lds, s, a);
   return hipGetLastError();
 }
 

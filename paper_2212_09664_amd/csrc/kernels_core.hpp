@@ -5,14 +5,12 @@
 
 #define GRAM_OPT 2    // outputs per thread in the per-line Gram kernels
 #define SOLVE_NT 1024  // threads of the per-frame solve
-#define GCOLS_OPT 9   // outputs per thread in the column-Gram kernel (m <= 64)
+#define GCOLS_OPT 9   // outputs per thread in the column-Gram kernel (m <= 128)
+#define GCOLS_NT 1024
 
 namespace ag {
 
 struct JacobiScratch {
-  int p[64], q[64];
-  double c[64], s[64];
-  double2 e[64];
   double red[1024];
 };
 
@@ -139,7 +137,8 @@ struct ApplyArgs {
 struct InitEigArgs {
   const double2* part;
   int nblk, q, r;
-  double2* V;            // q x q scratch (global)
+  double2* V;            // 2 q x q scratch (global): matrix and eigenvectors when not in LDS
+  int in_lds;            // matrix and eigenvectors in dynamic LDS (q <= 64)
   float2* Vs;            // q x r out: V_r Sigma_r^{-1}
   DevState* st;
 };

@@ -1,0 +1,122 @@
+"""GPU versus the FP64 oracle on the five workload shapes at their full sizes
+(the sizes the throughput benchmark runs), in the library's production launch
+configuration.
+
+Per workload: the spectral initialisation (projector distance bounded by the
+eigen-gap), the LS step and the gradient at a fixed orthonormal basis (the
+operator tolerances of the small-case tests), a few whole iterations against
+the oracle's trajectory, and — for the cine 256 x 256 workload — the full
+70-iteration run checked by properties that hold at any size (orthonormal U,
+U^H grad = 0, the final B equal to the oracle's LS solution for the GPU's own
+U, NMSE below 2e-2).
+"""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import altgdmin as AG
+from oracle import metrics as M
+
+from gpu_cases import GPU_OK, Case, from_gpu_B, from_gpu_U, log, proj_dist, rel, to_gpu_U
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not GPU_OK, reason="needs a GPU")]
+
+if GPU_OK:
+    import torch
+
+SEEDS = {"cine256": 1001, "radial128": 0, "cine256r16": 0, "cine128": 0, "gauss64": 0}
+_CASES = {}
+
+
+def _get(name):
+    if name not in _CASES:
+        _CASES[name] = Case(datagen.make(name, SEEDS[name]))
+    return _CASES[name]
+
+
+@pytest.mark.parametrize("name", ["cine256", "radial128", "cine256r16", "cine128"])
+def test_spectral_init_full_size(name):
+    log(f"init {name}")
+    cs = _get(name)
+    r = cs.prob.r
+    ctx = cs.gpu_ctx()
+    U0 = from_gpu_U(ctx.init())
+    Ytr, gamma, _ = AG.truncation(cs.op, cs.y, 36.0)
+    X0 = AG.backprojection(cs.op, Ytr)
+    s = np.linalg.svd(X0, compute_uv=False)
+    Uref = AG.spectral_init(X0, r)
+    gap = (s[r - 1] - s[r]) / s[0]
+    d = proj_dist(U0, Uref)
+    log(f"  projector distance {d:.2e}, relative gap {gap:.2e}, gamma {ctx.stats()['gamma']:.6e} vs {gamma:.6e}")
+    assert ctx.stats()["gamma"] == pytest.approx(gamma, rel=1e-12)
+    assert np.allclose(U0.conj().T @ U0, np.eye(r), atol=5e-6)
+    assert d < 1e-5 / gap
+
+
+@pytest.mark.parametrize("name", ["cine256", "radial128", "cine256r16", "cine128"])
+def test_ls_step_and_gradient_full_size(name):
+    log(f"gradient {name}")
+    cs = _get(name)
+    ctx = cs.gpu_ctx()
+    rng = np.random.default_rng(11)
+    U, _ = np.linalg.qr(datagen.crandn(rng, cs.prob.n, cs.prob.r))
+    U = U.astype(np.complex64).astype(np.complex128)
+    Bg, Gg = ctx.gradient(to_gpu_U(U))
+    B, G = from_gpu_B(Bg), from_gpu_U(Gg)
+    FU = cs.op.transform_basis(U)
+    Bref = AG.ls_step(cs.op, U, cs.y, FU=FU)
+    Gref = AG.gradient(cs.op, U, Bref, cs.y, FU=FU)
+    t1 = np.linalg.norm(AG.gradient(cs.op, U, Bref, np.zeros_like(cs.y), FU=FU))
+    t2 = np.linalg.norm(AG.gradient(cs.op, np.zeros_like(U), Bref, cs.y))
+    err = np.linalg.norm(G - Gref) / max(t1, t2)
+    log(f"  b rel {rel(B, Bref):.2e}, grad rel/scale {err:.2e}, plain {rel(G, Gref):.2e}")
+    assert rel(B, Bref) < 1e-5
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("name,T", [("cine256", 3), ("radial128", 4), ("cine128", 8), ("gauss64", 20)])
+def test_iterations_full_size(name, T):
+    log(f"iterations {name} T={T}")
+    cs = _get(name)
+    ctx = cs.gpu_ctx()
+    U = ctx.init()
+    Uprev = torch.empty_like(U)
+    B, done = ctx.iterate(T, U, U_prev=Uprev, sync=True)
+    assert done == T
+    Xg = from_gpu_U(Uprev) @ from_gpu_B(B)
+    ref = AG.run(cs.op, cs.y, AG.Params(r=cs.prob.r), t_fixed=T, record=False)
+    n_gpu, n_ref = M.nmse(Xg, cs.prob.zstar), M.nmse(ref.X, cs.prob.zstar)
+    log(f"  NMSE gpu {n_gpu:.6e} oracle {n_ref:.6e}; X rel {rel(Xg, ref.X):.2e}; eta {ctx.get_eta():.6e} vs {ref.eta:.6e}")
+    assert abs(n_gpu - n_ref) <= 1e-4
+    assert ctx.get_eta() == pytest.approx(ref.eta, rel=1e-4)
+
+
+def test_cine256_full_run_properties():
+    """The benchmark's own run: 70 iterations at 256x256x12x40, rank 8."""
+    log("cine256 70 iterations")
+    cs = _get("cine256")
+    ctx = cs.gpu_ctx()
+    U = ctx.init()
+    Uprev = torch.empty_like(U)
+    B, done = ctx.iterate(70, U, U_prev=Uprev, sync=True)
+    assert done == 70
+    Up, Un, Bg = from_gpu_U(Uprev), from_gpu_U(U), from_gpu_B(B)
+    r = cs.prob.r
+    assert np.allclose(Un.conj().T @ Un, np.eye(r), atol=5e-6)
+    # B_70 is the LS solution for U_69: the oracle's, from the GPU's own U_69
+    Up64 = Up.astype(np.complex64).astype(np.complex128)
+    Bref = AG.ls_step(cs.op, Up64, cs.y)
+    log(f"  final B rel {rel(Bg, Bref):.2e}")
+    assert rel(Bg, Bref) < 1e-5
+    nm = M.nmse(Up @ Bg, cs.prob.zstar)
+    log(f"  NMSE {nm:.4e}")
+    assert nm < 2e-2
+    # the gradient at the final basis is orthogonal to it (normal equations),
+    # to FP32 accuracy relative to the two terms it is the difference of
+    Bn, Gn = ctx.gradient(U)
+    G = from_gpu_U(Gn)
+    Bo = AG.ls_step(cs.op, Un, cs.y)
+    scale = max(np.linalg.norm(AG.gradient(cs.op, Un, Bo, np.zeros_like(cs.y))),
+                np.linalg.norm(AG.gradient(cs.op, np.zeros_like(Un), Bo, cs.y)))
+    log(f"  ||U^H grad|| / scale {np.linalg.norm(Un.conj().T @ G) / scale:.2e}")
+    assert np.linalg.norm(Un.conj().T @ G) <= 1e-5 * scale
