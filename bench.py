@@ -53,6 +53,10 @@ def alg_bytes(kernel: str, nx, ny, nc, q, r, n_u, M_total) -> float:
     return 8.0 * table[kernel]
 
 
+# kernel classes of one iteration that have an algorithmic-bytes figure
+LOOP_KERNELS = ("fwd_transform", "gram_rhs", "fold", "adj_transform", "qr_gram", "apply_qr")
+
+
 def make_inputs(seed: int):
     import datagen
     return datagen.make(WORKLOAD, seed)
@@ -110,7 +114,19 @@ def run_gpu(args):
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        ctx.set_timing(args.kernel)
+        kernel = args.kernel
+        if kernel == "auto":
+            # the loop's dominant kernel class: total event time per class over one step
+            tot = {}
+            for name in LOOP_KERNELS:
+                ctx.set_timing(name)
+                step()
+                torch.cuda.synchronize()
+                kn, nl, ms = ctx.kernel_time()
+                tot[name] = ms
+            ctx.set_timing("none")
+            kernel = max(tot, key=tot.get)
+        ctx.set_timing(kernel)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record(stream)
@@ -165,9 +181,11 @@ def run_gpu(args):
         kbytes=kb, achieved=achieved)
 
 
-def cpu_baseline(iters: int = 3, seed: int = 0):
-    """The FP64 oracle (literal Algorithm 2) on the same workload: spectral
-    initialisation plus `iters` iterations, timed on this host."""
+def cpu_baseline(iters: int, seed: int, T: int):
+    """The FP64 oracle (literal Algorithm 2) on the same workload and seed:
+    the truncated spectral initialisation plus `iters` iterations, timed on
+    this host.  Scaled to the GPU figure's unit: one step is the
+    initialisation plus T iterations, so value = T / (init + T * loop/iters)."""
     import datagen
     from oracle import altgdmin as AG
     from oracle import operators as O
@@ -180,7 +198,8 @@ def cpu_baseline(iters: int = 3, seed: int = 0):
     t1 = time.perf_counter()
     AG.run(op, Y, AG.Params(r=prob.r), U0=U0, t_fixed=iters, record=False)
     t2 = time.perf_counter()
-    return dict(value=iters / (t2 - t1), init_s=t1 - t0, loop_s=t2 - t1, iters=iters)
+    step_s = (t1 - t0) + T * (t2 - t1) / iters
+    return dict(value=T / step_s, init_s=t1 - t0, loop_s=t2 - t1, iters=iters, cores=O.WORKERS)
 
 
 def main():
@@ -189,10 +208,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--form", choices=["plain", "mixed"], default="plain")
-    ap.add_argument("--kernel", default="fold", help="kernel class timed for the roofline figure")
+    ap.add_argument("--kernel", default="auto",
+                    help="kernel class timed for the roofline figure (auto: the loop's most expensive)")
     ap.add_argument("--seed", type=int, default=1001)
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -202,6 +224,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        # 256 MiB read + 256 MiB written by one copy kernel, five times
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 5}), flush=True)
+        return
     g = run_gpu(args)
     prob = g["prob"]
     iters = args.steps * g["T"]
@@ -246,12 +277,12 @@ def main():
         },
     }
     if not args.no_cpu:
-        cb = cpu_baseline(args.cpu_iters)
+        cb = cpu_baseline(args.cpu_iters, args.seed, g["T"])
         out["cpu_baseline"] = {
-            "value": round(cb["value"], 4), "unit": "iter/s", "cores": os.cpu_count(), "kind": "oracle",
-            "sample": f"FP64 NumPy/SciPy oracle, literal Algorithm 2 on the same workload: "
-                      f"{cb['iters']} iterations after the spectral init ({cb['loop_s']:.1f} s loop, "
-                      f"init {cb['init_s']:.1f} s)",
+            "value": round(cb["value"], 4), "unit": "iter/s", "cores": cb["cores"], "kind": "oracle",
+            "sample": f"FP64 NumPy/SciPy oracle, literal Algorithm 2, same workload and seed: spectral init "
+                      f"({cb['init_s']:.1f} s) + {cb['iters']} iterations ({cb['loop_s']:.1f} s), scaled to one "
+                      f"step of init + {g['T']} iterations",
         }
     print(json.dumps(out), flush=True)
 

@@ -25,7 +25,9 @@ import os
 import numpy as np
 import scipy.fft as sfft
 
-WORKERS = os.cpu_count() or 1
+# threads for the FFT backend: the OpenMP thread budget if one is set, else
+# the CPUs this process may run on
+WORKERS = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0)) or 1
 
 
 # ---------------------------------------------------------------------------

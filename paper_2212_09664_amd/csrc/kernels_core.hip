@@ -391,93 +391,135 @@ __device__ __forceinline__ void jacobi_pair(int s, int i, int Q, int& p, int& q)
 // is updated independently, A_ij <- G_i^H A_ij G_j, with both rotations
 // computed from the matrix as it was at the start of the round, so a round
 // is one read phase and one write phase.  V (if given, ld n) accumulates
-// V <- V G.  A and V may be in LDS or in global memory private to the
+// V <- V G in place (block (i, j) of V is touched by one thread only).  A and V may be in LDS or in global memory private to the
 // workgroup.  On return diag(A) holds the eigenvalues and the columns of V
-// the eigenvectors.  Up to JAC_ITEMS*blockDim blocks, i.e. n <= 128 with
-// 1024 threads.
-#define JAC_ITEMS 4
-__device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch* js, int max_sweeps) {
+// the eigenvectors.  Up to ITEMS*blockDim blocks: ITEMS = 1 covers n <= 64
+// with 1024 threads, ITEMS = 4 covers n <= 128.
+//
+// With r_top > 0 only the invariant subspace of the r_top largest
+// eigenvalues is wanted.  Partition the indices into the current top r_top
+// diagonal entries and the rest, A = [A11 A12; A21 A22].  Gershgorin discs
+// within each diagonal block bound the spectra of A11 from below and of A22
+// from above; once these bounds are separated by sep > 0 and
+// ||A12||_F <= 1e-10 sep, the span of the top coordinate vectors is within
+// an angle of about 1e-10 of the wanted subspace (Davis-Kahan sin-theta),
+// and the sweeps stop.
+template <int JAC_ITEMS>
+__device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch* js, int max_sweeps,
+                           int r_top = 0) {
   const int tid = threadIdx.x, NT = blockDim.x;
   if (V)
     for (int e = tid; e < n * n; e += NT) V[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
   __syncthreads();
   const int Q = n + (n & 1), H = Q / 2;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double off = 0.0, tot = 0.0;
+    if (r_top > 0) {  // which diagonal entries are currently the top r_top
+      for (int i = tid; i < n; i += NT) {
+        const double di = A[i * ld + i].x;
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+          const double dj = A[j * ld + j].x;
+          rank += (dj > di) || (dj == di && j < i);
+        }
+        js->top[i] = rank < r_top;
+      }
+      __syncthreads();
+      // Gershgorin bound of row i within its own block
+      for (int i = tid; i < n; i += NT) {
+        const int ti = js->top[i];
+        double rad = 0.0;
+        for (int j = 0; j < n; ++j) {
+          if (j == i || js->top[j] != ti) continue;
+          const double2 v = A[i * ld + j];
+          rad += sqrt(v.x * v.x + v.y * v.y);
+        }
+        js->bnd[i] = ti ? A[i * ld + i].x - rad : A[i * ld + i].x + rad;
+      }
+      __syncthreads();
+    }
+    double off = 0.0, tot = 0.0, cross = 0.0;
     for (int e = tid; e < n * n; e += NT) {
       const int i = e / n, j = e % n;
       const double2 v = A[i * ld + j];
       const double m2 = v.x * v.x + v.y * v.y;
       tot += m2;
       if (i != j) off += m2;
+      if (r_top > 0 && js->top[i] && !js->top[j]) cross += m2;
     }
     off = block_sum(off, js->red);
     tot = block_sum(tot, js->red);
     if (!(off > 1e-26 * tot)) break;
+    if (r_top > 0 && r_top < n) {
+      cross = block_sum(cross, js->red);
+      double lo = INFINITY, hi = -INFINITY;  // lower bound of eig(A11), upper bound of eig(A22)
+      for (int i = 0; i < n; ++i) {
+        if (js->top[i]) lo = fmin(lo, js->bnd[i]);
+        else hi = fmax(hi, js->bnd[i]);
+      }
+      const double sep = lo - hi;
+      if (sep > 0.0 && cross <= 1e-20 * sep * sep) break;
+    }
     for (int s = 0; s < Q - 1; ++s) {
-      double2 na[JAC_ITEMS][4], nv[JAC_ITEMS][4];
+      double2 na[JAC_ITEMS][4];
 #pragma unroll
       for (int k = 0; k < JAC_ITEMS; ++k) {
         const int t = tid + k * NT;
-        if (t >= H * H) break;
-        const int i = t / H, j = t - (t / H) * H;
-        int pi, qi, pj, qj;
-        jacobi_pair(s, i, Q, pi, qi);
-        jacobi_pair(s, j, Q, pj, qj);
-        const JRot gi = jacobi_rot(A, ld, n, pi, qi);
-        const JRot gj = (i == j) ? gi : jacobi_rot(A, ld, n, pj, qj);
-        const bool ri = qi < n, rj = qj < n;  // the second row / column exists
-        const double2 z = make_double2(0.0, 0.0);
-        // the block [[a, b], [c, d]] = A[(pi, qi), (pj, qj)]
-        double2 a = A[pi * ld + pj], b = rj ? A[pi * ld + qj] : z;
-        double2 c = ri ? A[qi * ld + pj] : z, d = (ri && rj) ? A[qi * ld + qj] : z;
-        // columns: (x, y) <- (c x - s y e, s x + c y e) with y e
-        {
-          const double2 y0 = dmul(b, gj.e), y1 = dmul(d, gj.e);
-          const double2 a2 = make_double2(gj.c * a.x - gj.s * y0.x, gj.c * a.y - gj.s * y0.y);
-          const double2 b2 = make_double2(gj.s * a.x + gj.c * y0.x, gj.s * a.y + gj.c * y0.y);
-          const double2 c2 = make_double2(gj.c * c.x - gj.s * y1.x, gj.c * c.y - gj.s * y1.y);
-          const double2 d2 = make_double2(gj.s * c.x + gj.c * y1.x, gj.s * c.y + gj.c * y1.y);
-          a = a2; b = b2; c = c2; d = d2;
-        }
-        // rows: with conj(e_i)
-        {
-          const double2 ec = dconj(gi.e);
-          const double2 y0 = dmul(c, ec), y1 = dmul(d, ec);
-          na[k][0] = make_double2(gi.c * a.x - gi.s * y0.x, gi.c * a.y - gi.s * y0.y);
-          na[k][1] = make_double2(gi.c * b.x - gi.s * y1.x, gi.c * b.y - gi.s * y1.y);
-          na[k][2] = make_double2(gi.s * a.x + gi.c * y0.x, gi.s * a.y + gi.c * y0.y);
-          na[k][3] = make_double2(gi.s * b.x + gi.c * y1.x, gi.s * b.y + gi.c * y1.y);
-        }
-        if (V) {  // V rows (pi, qi), columns (pj, qj): right rotation only
-          double2 va = V[pi * n + pj], vb = rj ? V[pi * n + qj] : z;
-          double2 vc = ri ? V[qi * n + pj] : z, vd = (ri && rj) ? V[qi * n + qj] : z;
-          const double2 y0 = dmul(vb, gj.e), y1 = dmul(vd, gj.e);
-          nv[k][0] = make_double2(gj.c * va.x - gj.s * y0.x, gj.c * va.y - gj.s * y0.y);
-          nv[k][1] = make_double2(gj.s * va.x + gj.c * y0.x, gj.s * va.y + gj.c * y0.y);
-          nv[k][2] = make_double2(gj.c * vc.x - gj.s * y1.x, gj.c * vc.y - gj.s * y1.y);
-          nv[k][3] = make_double2(gj.s * vc.x + gj.c * y1.x, gj.s * vc.y + gj.c * y1.y);
+        if (t < H * H) {
+          const int i = t / H, j = t - (t / H) * H;
+          int pi, qi, pj, qj;
+          jacobi_pair(s, i, Q, pi, qi);
+          jacobi_pair(s, j, Q, pj, qj);
+          const JRot gi = jacobi_rot(A, ld, n, pi, qi);
+          const JRot gj = (i == j) ? gi : jacobi_rot(A, ld, n, pj, qj);
+          const bool ri = qi < n, rj = qj < n;  // the second row / column exists
+          const double2 z = make_double2(0.0, 0.0);
+          // the block [[a, b], [c, d]] = A[(pi, qi), (pj, qj)]
+          double2 a = A[pi * ld + pj], b = rj ? A[pi * ld + qj] : z;
+          double2 c = ri ? A[qi * ld + pj] : z, d = (ri && rj) ? A[qi * ld + qj] : z;
+          // columns: (x, y) <- (c x - s y e, s x + c y e)
+          {
+            const double2 y0 = dmul(b, gj.e), y1 = dmul(d, gj.e);
+            const double2 a2 = make_double2(gj.c * a.x - gj.s * y0.x, gj.c * a.y - gj.s * y0.y);
+            const double2 b2 = make_double2(gj.s * a.x + gj.c * y0.x, gj.s * a.y + gj.c * y0.y);
+            const double2 c2 = make_double2(gj.c * c.x - gj.s * y1.x, gj.c * c.y - gj.s * y1.y);
+            const double2 d2 = make_double2(gj.s * c.x + gj.c * y1.x, gj.s * c.y + gj.c * y1.y);
+            a = a2; b = b2; c = c2; d = d2;
+          }
+          // rows: with conj(e_i)
+          {
+            const double2 ec = dconj(gi.e);
+            const double2 y0 = dmul(c, ec), y1 = dmul(d, ec);
+            na[k][0] = make_double2(gi.c * a.x - gi.s * y0.x, gi.c * a.y - gi.s * y0.y);
+            na[k][1] = make_double2(gi.c * b.x - gi.s * y1.x, gi.c * b.y - gi.s * y1.y);
+            na[k][2] = make_double2(gi.s * a.x + gi.c * y0.x, gi.s * a.y + gi.c * y0.y);
+            na[k][3] = make_double2(gi.s * b.x + gi.c * y1.x, gi.s * b.y + gi.c * y1.y);
+          }
+          if (V) {  // V rows (pi, qi), columns (pj, qj), right rotation only: no other
+                    // thread touches these entries this round, so update in place
+            const double2 va = V[pi * n + pj], vb = rj ? V[pi * n + qj] : z;
+            const double2 vc = ri ? V[qi * n + pj] : z, vd = (ri && rj) ? V[qi * n + qj] : z;
+            const double2 y0 = dmul(vb, gj.e), y1 = dmul(vd, gj.e);
+            V[pi * n + pj] = make_double2(gj.c * va.x - gj.s * y0.x, gj.c * va.y - gj.s * y0.y);
+            if (rj) V[pi * n + qj] = make_double2(gj.s * va.x + gj.c * y0.x, gj.s * va.y + gj.c * y0.y);
+            if (ri) V[qi * n + pj] = make_double2(gj.c * vc.x - gj.s * y1.x, gj.c * vc.y - gj.s * y1.y);
+            if (ri && rj) V[qi * n + qj] = make_double2(gj.s * vc.x + gj.c * y1.x, gj.s * vc.y + gj.c * y1.y);
+          }
         }
       }
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < JAC_ITEMS; ++k) {
         const int t = tid + k * NT;
-        if (t >= H * H) break;
-        const int i = t / H, j = t - (t / H) * H;
-        int pi, qi, pj, qj;
-        jacobi_pair(s, i, Q, pi, qi);
-        jacobi_pair(s, j, Q, pj, qj);
-        const bool ri = qi < n, rj = qj < n;
-        A[pi * ld + pj] = na[k][0];
-        if (rj) A[pi * ld + qj] = na[k][1];
-        if (ri) A[qi * ld + pj] = na[k][2];
-        if (ri && rj) A[qi * ld + qj] = na[k][3];
-        if (V) {
-          V[pi * n + pj] = nv[k][0];
-          if (rj) V[pi * n + qj] = nv[k][1];
-          if (ri) V[qi * n + pj] = nv[k][2];
-          if (ri && rj) V[qi * n + qj] = nv[k][3];
+        if (t < H * H) {
+          const int i = t / H, j = t - (t / H) * H;
+          int pi, qi, pj, qj;
+          jacobi_pair(s, i, Q, pi, qi);
+          jacobi_pair(s, j, Q, pj, qj);
+          const bool ri = qi < n, rj = qj < n;
+          A[pi * ld + pj] = na[k][0];
+          if (rj) A[pi * ld + qj] = na[k][1];
+          if (ri) A[qi * ld + pj] = na[k][2];
+          if (ri && rj) A[qi * ld + qj] = na[k][3];
         }
       }
       __syncthreads();
@@ -628,7 +670,7 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
   if (st->eta <= 0.0) {
     for (int e = tid; e < 256; e += AG_NT) Tm[e] = GG[e];
     __syncthreads();
-    jacobi_eig(Tm, r, 16, nullptr, &js, 40);
+    jacobi_eig<1>(Tm, r, 16, nullptr, &js, 40);
     __syncthreads();
     if (tid == 0) {
       double lam = 0.0;
@@ -655,7 +697,7 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
         Tm[i * 16 + j] = s;
       }
       __syncthreads();
-      jacobi_eig(Tm, r, 16, nullptr, &js, 40);
+      jacobi_eig<1>(Tm, r, 16, nullptr, &js, 40);
       __syncthreads();
       if (tid == 0) {
         double lam = 0.0;
@@ -768,6 +810,7 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 // scaled top-r eigenvectors V_r Sigma_r^{-1}, so that X_0 V_r Sigma_r^{-1}
 // are the top-r left singular vectors of X_0.
 // ===========================================================================
+template <int ITEMS>
 __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
   extern __shared__ double2 lds_m[];  // q x q matrix, then q x q eigenvectors (when they fit)
   __shared__ JacobiScratch js;
@@ -788,7 +831,7 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
   __syncthreads();
   if (tid < q) A[tid * q + tid].y = 0.0;
   __syncthreads();
-  jacobi_eig(A, q, q, V, &js, 60);
+  jacobi_eig<ITEMS>(A, q, q, V, &js, 60, r);
   __syncthreads();
   if (tid == 0) {
     // top-r eigenvalues, descending
@@ -829,12 +872,17 @@ __global__ __launch_bounds__(AG_NT) void k_x_times_v(const float2* X, const floa
   const long p = (long)blockIdx.x * AG_NT + tid;
   if (p >= n) return;
   float2 acc[16];
+#pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = make_float2(0.f, 0.f);
   for (int k = 0; k < q; ++k) {
     const float2 x = X[(long)k * n + p];
-    for (int j = 0; j < r; ++j) acc[j] = cadd(acc[j], cmul(x, V[k * r + j]));
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j < r) acc[j] = cadd(acc[j], cmul(x, V[k * r + j]));
   }
-  for (int j = 0; j < r; ++j) U[(long)j * n + p] = acc[j];
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (j < r) U[(long)j * n + p] = acc[j];
 }
 
 __global__ void k_copy(const float2* src, float2* dst, long n) {
@@ -891,11 +939,16 @@ hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
 
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s) {
   const size_t lds = a.in_lds ? 2 * (size_t)a.q * a.q * sizeof(double2) : 0;
-  if (lds > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_init_eig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  if (a.q <= 64) {
+    if (lds > 48 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_init_eig<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_init_eig<1>, dim3(1), dim3(1024), lds, s, a);
+  } else {
+    hipLaunchKernelGGL(k_init_eig<4>, dim3(1), dim3(1024), lds, s, a);
   }
-  hipLaunchKernelGGL(k_init_eig, dim3(1), dim3(1024), lds, s, a);
   return hipGetLastError();
 }
 

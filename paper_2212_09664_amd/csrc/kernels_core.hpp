@@ -12,6 +12,8 @@ namespace ag {
 
 struct JacobiScratch {
   double red[1024];
+  int top[128];     // per index: among the r_top largest diagonal entries
+  double bnd[128];  // per index: Gershgorin bound within its block
 };
 
 struct GramLinesArgs {
