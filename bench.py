@@ -57,6 +57,34 @@ def alg_bytes(kernel: str, nx, ny, nc, q, r, n_u, M_total) -> float:
 LOOP_KERNELS = ("fwd_transform", "gram_rhs", "fold", "adj_transform", "qr_gram", "apply_qr")
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; a stored counter figure is valid only for it."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2212_09664_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of a kernel class from the committed FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None when the summary is absent
+    or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "altgdmin_cine256_hbm_counters.txt")
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    with open(path) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 5 and f[0] == "traffic" and f[1] == kernel and f[3] == "hash":
+                return float(f[2]) if f[4] == want else None
+    return None
+
+
 def make_inputs(seed: int):
     import datagen
     return datagen.make(WORKLOAD, seed)
@@ -270,7 +298,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(g["achieved"] / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(g["kname"]),
             "alg_bytes_per_launch": g["kbytes"],
             "avg_launch_ms": round(g["kavg_ms"], 5),
             "launches": g["klaunch"],
