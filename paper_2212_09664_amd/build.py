@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaltgdmin.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["kernels_fft.hip", "kernels_core.hip", "kernels_gram.hip", "kernels_basis.hip", "altgdmin.hip"]
+SOURCES = ["kernels_fft.hip", "kernels_core.hip", "kernels_gram.hip", "kernels_basis.hip", "kernels_pdft.hip",
+           "altgdmin.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

@@ -37,6 +37,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct altgdmin_ctx {
   altgdmin_params p;
   int n, lines, fp64;
+  int pdft;       // ky transforms as FP16 hi+lo MFMA partial DFTs (mixed form, 1D Cartesian)
   int width;     // mask row width: lines per frame (LINES) or m_max (INDEX)
   int lmax;      // LINES: m_max / nx
   int per;       // samples per mask entry (nx for LINES, 1 for INDEX)
@@ -207,10 +208,35 @@ hipError_t to_pixmajor(altgdmin_ctx* c, const float2* U) {
   return hipGetLastError();
 }
 
+PdftArgs pdft_args(altgdmin_ctx* c, int check_halt) {
+  const altgdmin_params& p = c->p;
+  PdftArgs a{};
+  a.U = c->at<float2>(c->o_Ui);
+  a.coils = c->coils;
+  a.W = c->at<float2>(c->o_W);
+  a.K = c->at<float2>(c->o_K);
+  a.G = c->at<float2>(c->o_G);
+  a.tw = c->at<float2>(c->o_twy);
+  a.unit_loc = c->at<int32_t>(c->o_unitloc);
+  a.nx = p.nx;
+  a.r = p.r;
+  a.nc = p.nc;
+  a.ua = c->ua;
+  a.cgs = c->adj_cgs;
+  a.n = c->n;
+  a.part_stride = (long)c->n * p.r;
+  a.scale = (float)(1.0 / sqrt((double)p.ny));
+  a.st = c->st();
+  a.check_halt = check_halt;
+  return a;
+}
+
 // W_{c,j} = F(s_c o u_j) on the sampled rows (y half only for LINES), from
 // the pixel-major working copy of U
 hipError_t fwd_transform(altgdmin_ctx* c, int check_halt) {
   const altgdmin_params& p = c->p;
+  if (c->pdft)
+    return launch_pdft(0, p.ny, pdft_args(c, check_halt), (p.nx * p.r + 31) / 32, p.nc, c->stream);
   const BasisArgs b = basis_args(c, check_halt);
   hipError_t e = launch_basis(0, p.ny, b, p.nx / c->txx, c->adj_parts, c->stream);
   if (e != hipSuccess || c->lines) return e;
@@ -367,8 +393,13 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   tmark(c, TK_FOLD);
   if (e != hipSuccess) return e;
   // inverse transform + coil combine -> partial gradients per coil group
-  const BasisArgs b = basis_args(c, check_halt);
   tmark(c, TK_ADJ);
+  if (c->pdft) {
+    e = launch_pdft(1, p.ny, pdft_args(c, check_halt), (p.nx * p.r + 31) / 32, c->adj_parts, c->stream);
+    tmark(c, TK_ADJ);
+    return e;
+  }
+  const BasisArgs b = basis_args(c, check_halt);
   if (!c->lines) {
     e = launch_basis(3, p.nx, b, p.nc * p.ny, 1, c->stream);
     if (e != hipSuccess) return e;
@@ -541,6 +572,7 @@ altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** ou
   c->n = p.nx * p.ny;
   c->lines = (p.mask_kind == ALTGDMIN_MASK_LINES);
   c->fp64 = (p.precision == ALTGDMIN_MIXED);
+  c->pdft = c->fp64 && p.mask_kind == ALTGDMIN_MASK_LINES && p.ny >= 32 && p.ny <= 256;
   c->lmax = c->lines ? p.m_max / p.nx : 0;
   c->width = c->lines ? c->lmax : p.m_max;
   c->per = c->lines ? p.nx : 1;

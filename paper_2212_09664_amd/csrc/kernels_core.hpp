@@ -82,6 +82,21 @@ struct BasisArgs {
   int check_halt;
 };
 
+struct PdftArgs {
+  const float2* U;       // pixel-major [p][j]
+  const float2* coils;   // [c][p]
+  float2* W;             // [c][u][x][j], ua rows per coil (forward out)
+  const float2* K;       // [c][u][x][j] (adjoint in)
+  float2* G;             // [part][p][j] (adjoint out)
+  const float2* tw;      // exp(-2 pi i t / ny), t < ny
+  const int32_t* unit_loc;  // sampled row u -> ky
+  int nx, r, nc, ua, cgs;
+  long n, part_stride;
+  float scale;           // 1 / sqrt(ny)
+  DevState* st;
+  int check_halt;
+};
+
 struct FoldArgs {
   const int2* unit_span;  // LINES: per sampled line, its first pair and pair count
   const float2* bcp;      // LINES: conj(b_k) of every pair, in pair order (written by the solve)
@@ -188,6 +203,8 @@ __global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* 
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s);
 hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
+// mixed form, 1D Cartesian masks: which 0 forward, 1 adjoint + coil combine
+hipError_t launch_pdft(int which, int ny, const PdftArgs& a, int grid_x, int grid_y, hipStream_t s);
 int basis_txx(int N, int nx, int r);
 __global__ void k_build_yu(const float2* yh, const int2* pairs, const int32_t* mask, const int32_t* loc_ptr,
                            int n_loc, int width, int nc, int nx, int lmax, float2* yu, const DevState* st);

@@ -120,3 +120,39 @@ def test_cine256_full_run_properties():
                 np.linalg.norm(AG.gradient(cs.op, np.zeros_like(Un), Bo, cs.y)))
     log(f"  ||U^H grad|| / scale {np.linalg.norm(Un.conj().T @ G) / scale:.2e}")
     assert np.linalg.norm(Un.conj().T @ G) <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("name", ["cine256r16", "cine256"])
+def test_mixed_form_error_table(name):
+    """Both forms against the FP64 oracle on the same inputs: relative error
+    of every output the loop produces (b_k, the gradient, X after a few
+    iterations, eta, NMSE).  The mixed form runs its ky transforms as FP16
+    hi+lo MFMA partial DFTs and its Grams / Cholesky in FP64."""
+    cs = _get(name)
+    rng = np.random.default_rng(13)
+    U, _ = np.linalg.qr(datagen.crandn(rng, cs.prob.n, cs.prob.r))
+    U = U.astype(np.complex64).astype(np.complex128)
+    FU = cs.op.transform_basis(U)
+    Bref = AG.ls_step(cs.op, U, cs.y, FU=FU)
+    Gref = AG.gradient(cs.op, U, Bref, cs.y, FU=FU)
+    t1 = np.linalg.norm(AG.gradient(cs.op, U, Bref, np.zeros_like(cs.y), FU=FU))
+    t2 = np.linalg.norm(AG.gradient(cs.op, np.zeros_like(U), Bref, cs.y))
+    T = 3
+    ref = AG.run(cs.op, cs.y, AG.Params(r=cs.prob.r), t_fixed=T, record=False)
+    n_ref = M.nmse(ref.X, cs.prob.zstar)
+    rows = []
+    for precision, form in ((0, "plain"), (1, "mixed")):
+        ctx = cs.gpu_ctx(precision=precision)
+        Bg, Gg = ctx.gradient(to_gpu_U(U))
+        eb = rel(from_gpu_B(Bg), Bref)
+        eg = np.linalg.norm(from_gpu_U(Gg) - Gref) / max(t1, t2)
+        U0 = ctx.init()
+        Up = torch.empty_like(U0)
+        B, _ = ctx.iterate(T, U0, U_prev=Up, sync=True)
+        Xg = from_gpu_U(Up) @ from_gpu_B(B)
+        ex = rel(Xg, ref.X)
+        ee = abs(ctx.get_eta() - ref.eta) / ref.eta
+        dn = abs(M.nmse(Xg, cs.prob.zstar) - n_ref)
+        rows.append((form, eb, eg, ex, ee, dn))
+        log(f"  {name} {form:6s} b_k {eb:.2e}  grad {eg:.2e}  X_{T} {ex:.2e}  eta {ee:.2e}  |dNMSE| {dn:.2e}")
+        assert eb < 1e-5 and eg < 1e-5 and ex < 1e-4 and ee < 1e-4 and dn < 1e-4
