@@ -151,6 +151,23 @@ altgdmin_status altgdmin_init(altgdmin_ctx* ctx, void* d_U);
  * initialiser).  d_U0 and d_U may alias.  Resets t and eta. */
 altgdmin_status altgdmin_init_from(altgdmin_ctx* ctx, const void* d_U0, void* d_U);
 
+/* Input of the learned initialiser: the zero-filled, coil-combined frames
+ * A_k^H y_k (no truncation, no 1/sqrt(m_k m) scaling), as 2q real planes
+ * d_in[2k] = Re, d_in[2k+1] = Im, each ny x nx with x fastest, all divided
+ * by the root mean square of the 2q*n values (FP32, caller-allocated,
+ * 2q*n floats).  Requires a bound problem with measurements. */
+altgdmin_status altgdmin_cnn_input(altgdmin_ctx* ctx, float* d_in);
+
+/* Initialisation with a learned guess and the spectral fallback: the
+ * spectral U_0 (as altgdmin_init) and the CholeskyQR of d_M (n x r, e.g. the
+ * network output; a small ridge is added if its Gram is numerically
+ * singular) are both scored by f(U) = sum_k (||y_k||^2 - h_k^H G_k^-1 h_k),
+ * the cost after the exact LS step (Sec. III-B), and the one with the
+ * strictly lower cost is written to d_U.  No host synchronisation: if
+ * d_choice is not NULL, the device int it points to receives 1 when the
+ * learned guess was kept, 0 otherwise.  Resets t and eta. */
+altgdmin_status altgdmin_init_warm(altgdmin_ctx* ctx, const void* d_M, void* d_U, int32_t* d_choice);
+
 /* n_iter iterations of the alternating loop (Algorithm 2), continuing from
  * d_U (in/out, n x r orthonormal).  d_B (out, r x q) receives B_T computed
  * from U_{T-1}; d_U_prev (out, may be NULL) receives U_{T-1}, so that

@@ -16,4 +16,4 @@ There is no CPU path: constructing a context without the built library, or
 with tensors not on a GPU, raises.
 """
 from ._lib import (AltGDmin, AltGDminError, Params, Stats, MASK_LINES, MASK_INDEX, FP32, MIXED,  # noqa: F401
-                   TIMED_KERNELS, lib_path, load_library)
+                   TIMED_KERNELS, WsInit, lib_path, load_library)

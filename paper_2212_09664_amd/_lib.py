@@ -77,6 +77,15 @@ def load_library():
         "altgdmin_kernel_time": ([vp, ctypes.POINTER(ctypes.c_char_p), pi32, ctypes.POINTER(dbl)], i32),
         "altgdmin_status_string": ([i32], ctypes.c_char_p),
         "altgdmin_destroy": ([vp], None),
+        "altgdmin_cnn_input": ([vp, vp], i32),
+        "altgdmin_init_warm": ([vp, vp, vp, vp], i32),
+        "wsinit_create": ([i32, i32, i32, i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
+        "wsinit_param_count": ([vp, ctypes.POINTER(ctypes.c_int64)], i32),
+        "wsinit_workspace_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "wsinit_forward": ([vp, vp, vp, i32, vp, vp], i32),
+        "wsinit_loss_backward": ([vp, vp, vp, vp, i32, vp, vp, vp], i32),
+        "wsinit_adam_step": ([vp, vp, vp, vp, vp, ctypes.c_float, i32], i32),
+        "wsinit_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -167,6 +176,20 @@ class AltGDmin:
         self._check(self._L.altgdmin_init_from(self._h, _ptr(U0), _ptr(U)), "init_from")
         return U
 
+    def cnn_input(self, out=None):
+        """The learned initialiser's input: (2q, ny, nx) float32 planes."""
+        out = torch.empty(2 * self.p.q, self.p.ny, self.p.nx, dtype=torch.float32, device=self.device) \
+            if out is None else out
+        self._check(self._L.altgdmin_cnn_input(self._h, _ptr(out)), "cnn_input")
+        return out
+
+    def init_warm(self, M, U=None, choice=None):
+        """Spectral U_0 vs QR(M), the lower-cost one into U; choice (device
+        int32, optional) receives 1 if M's basis was kept."""
+        U = self._new(self.p.r, self.n) if U is None else U
+        self._check(self._L.altgdmin_init_warm(self._h, _ptr(M), _ptr(U), _ptr(choice)), "init_warm")
+        return U
+
     def iterate(self, n_iter, U, B=None, U_prev=None, sync=False):
         B = self._new(self.p.q, self.p.r) if B is None else B
         done = ctypes.c_int32(0)
@@ -224,3 +247,62 @@ class AltGDmin:
         self._check(self._L.altgdmin_kernel_time(self._h, ctypes.byref(name), ctypes.byref(cnt),
                                                  ctypes.byref(ms)), "kernel_time")
         return name.value.decode(), cnt.value, ms.value
+
+
+class WsInit:
+    """The warm-start CNN (include/wsinit.h): forward, loss + backward, Adam.
+    Parameters, gradients and moments are flat float32 tensors."""
+
+    def __init__(self, nx, ny, q, r, width=32, layers=4, batch=16, stream=None):
+        self._L = load_library()
+        self.nx, self.ny, self.q, self.r, self.width, self.batch = nx, ny, q, r, width, batch
+        self.n = nx * ny
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        st = self._L.wsinit_create(nx, ny, q, r, width, layers, batch, ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(h))
+        if st != 0:
+            raise AltGDminError(st, "wsinit_create", None)
+        self._h = h
+        c = ctypes.c_int64()
+        self._L.wsinit_param_count(self._h, ctypes.byref(c))
+        self.param_count = c.value
+        nb = ctypes.c_size_t()
+        self._L.wsinit_workspace_bytes(self._h, ctypes.byref(nb))
+        self.workspace_bytes = nb.value
+        buf = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+        off = (-buf.data_ptr()) % 256
+        self._buf = buf
+        self.ws = buf[off: off + nb.value]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._L.wsinit_destroy(h)
+            self._h = None
+
+    def _check(self, st, where):
+        if st != 0:
+            raise AltGDminError(st, where, None)
+
+    def forward(self, params, x, M=None):
+        """x (B, 2q, ny, nx) -> M (B, r, n) complex64."""
+        b = x.shape[0]
+        M = torch.empty(b, self.r, self.n, dtype=torch.complex64, device=x.device) if M is None else M
+        self._check(self._L.wsinit_forward(self._h, _ptr(params), _ptr(x), b, _ptr(M),
+                                           ctypes.c_void_p(self.ws.data_ptr())), "wsinit_forward")
+        return M
+
+    def loss_backward(self, params, x, Ut, grads=None, loss=None):
+        """Mean loss (device float64 scalar) and mean gradient over the batch."""
+        b = x.shape[0]
+        grads = torch.empty_like(params) if grads is None else grads
+        loss = torch.empty(1, dtype=torch.float64, device=x.device) if loss is None else loss
+        self._check(self._L.wsinit_loss_backward(self._h, _ptr(params), _ptr(x), _ptr(Ut), b, _ptr(grads),
+                                                 _ptr(loss), ctypes.c_void_p(self.ws.data_ptr())),
+                    "wsinit_loss_backward")
+        return loss, grads
+
+    def adam_step(self, params, grads, m, v, lr, step):
+        self._check(self._L.wsinit_adam_step(self._h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
+                                             ctypes.c_float(lr), int(step)), "wsinit_adam_step")

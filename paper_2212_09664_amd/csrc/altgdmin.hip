@@ -61,8 +61,8 @@ struct altgdmin_ctx {
   int bound = 0, initialized = 0;
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
-      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp,
-      o_end;
+      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
+      o_fcmp, o_planes, o_end;
   size_t T_bytes;
   // timing
   int timed = TK_NONE;
@@ -101,6 +101,9 @@ void carve(altgdmin_ctx* c) {
   c->o_unitloc = take(sizeof(int32_t) * (size_t)c->n_loc);
   c->o_unitspan = take(sizeof(int2) * (size_t)c->n_loc);
   c->o_bcp = take(sizeof(float2) * (size_t)q * c->width * r);
+  c->o_Uc = take(sizeof(float2) * (size_t)n * r);
+  c->o_fcmp = take(sizeof(double) * 2);
+  c->o_planes = take(sizeof(double) * 256);
   c->o_pairs = take(sizeof(int2) * (size_t)q * c->width);
   c->o_pairof = take(sizeof(int32_t) * (size_t)q * c->width);
   c->o_unitof = take(sizeof(int32_t) * (size_t)q * c->width);
@@ -713,6 +716,44 @@ altgdmin_status altgdmin_init_from(altgdmin_ctx* c, const void* d_U0, void* d_U)
   HIPCHK(hipGetLastError());
   HIPCHK(cholqr(c, static_cast<float2*>(d_U)));
   HIPCHK(cholqr(c, static_cast<float2*>(d_U)));
+  c->initialized = 1;
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_cnn_input(altgdmin_ctx* c, float* d_in) {
+  if (!c || !d_in) return ALTGDMIN_EINVAL;
+  if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
+  const altgdmin_params& p = c->p;
+  float2* X = c->at<float2>(c->o_T);
+  HIPCHK(adjoint_op(c, c->y, X, 0, 0));
+  HIPCHK(launch_cnn_planes(X, c->n, p.q, c->at<double>(c->o_planes), d_in, c->stream));
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_init_warm(altgdmin_ctx* c, const void* d_M, void* d_U, int32_t* d_choice) {
+  if (!c || !d_M || !d_U) return ALTGDMIN_EINVAL;
+  if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
+  const altgdmin_params& p = c->p;
+  hipStream_t s = c->stream;
+  const altgdmin_status st = altgdmin_init(c, d_U);
+  if (st != ALTGDMIN_OK) return st;
+  float2* Uc = c->at<float2>(c->o_Uc);
+  hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, static_cast<const float2*>(d_M), Uc, (long)c->n * p.r);
+  HIPCHK(hipGetLastError());
+  HIPCHK(cholqr(c, Uc));
+  HIPCHK(cholqr(c, Uc));
+  double* f = c->at<double>(c->o_fcmp);
+  HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
+  HIPCHK(fwd_transform(c, 0));
+  HIPCHK(gram_solve(c, 0));
+  hipLaunchKernelGGL(k_cost_total, dim3(1), dim3(1), 0, s, c->at<double>(c->o_cost), p.q, f, c->st());
+  HIPCHK(to_pixmajor(c, Uc));
+  HIPCHK(fwd_transform(c, 0));
+  HIPCHK(gram_solve(c, 0));
+  hipLaunchKernelGGL(k_cost_total, dim3(1), dim3(1), 0, s, c->at<double>(c->o_cost), p.q, f + 1, c->st());
+  hipLaunchKernelGGL(k_pick_init, dim3(256), dim3(256), 0, s, f, Uc, static_cast<float2*>(d_U), (long)c->n * p.r,
+                     d_choice, c->st());
+  HIPCHK(hipGetLastError());
   c->initialized = 1;
   return ALTGDMIN_OK;
 }

@@ -657,6 +657,17 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
     __syncthreads();
     if (tid == 0) s_ok = chol_lower(Gh, r);
     __syncthreads();
+    if (!s_ok) {  // numerically rank-deficient basis: retry with a small ridge
+      for (int e = tid; e < 256; e += blockDim.x) Gh[e] = UU[e];
+      __syncthreads();
+      if (tid == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < r; ++i) tr += UU[i * 16 + i].x;
+        for (int i = 0; i < r; ++i) Gh[i * 16 + i].x += 1e-6 * tr / r;
+        s_ok = (tr > 0.0) && isfinite(tr) && chol_lower(Gh, r);
+      }
+      __syncthreads();
+    }
     if (!s_ok) {
       if (tid == 0) set_error(st, 4, -1);
       return;
@@ -883,6 +894,17 @@ __global__ __launch_bounds__(AG_NT) void k_x_times_v(const float2* X, const floa
 #pragma unroll
   for (int j = 0; j < 16; ++j)
     if (j < r) U[(long)j * n + p] = acc[j];
+}
+
+// keep the learned U (src) only if its cost f[1] is strictly below the
+// spectral one f[0]; a non-finite learned cost keeps the spectral U
+__global__ void k_pick_init(const double* f, const float2* src, float2* dst, long n, int32_t* choice,
+                            const DevState* st) {
+  if (st->err) return;
+  const bool take = f[1] < f[0];
+  if (choice && blockIdx.x == 0 && threadIdx.x == 0) *choice = take ? 1 : 0;
+  if (!take) return;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) dst[i] = src[i];
 }
 
 __global__ void k_copy(const float2* src, float2* dst, long n) {

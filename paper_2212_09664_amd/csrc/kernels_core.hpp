@@ -97,6 +97,34 @@ struct PdftArgs {
   int check_halt;
 };
 
+// warm-start CNN
+struct ConvArgs {
+  const float* X;        // [b][cin][H][W]
+  const float* Wp;       // packed weights [kappa][32], kappa = tap*cin + ci, then the bias row
+  float* Y;              // [b][cout][H][W]
+  const float* mask;     // optional [b][cout][H][W]: Y = 0 where mask <= 0
+  int cin, cout, H, W, bias, relu;
+};
+
+struct WgradArgs {
+  const float* X;        // layer input [b][cin][H][W]
+  const float* dY;       // gradient at the layer output [b][cout][H][W]
+  float* part;           // [b][band][kp][32] partial weight gradients
+  int cin, cout, H, W, kp, rows_per_band;
+};
+
+struct LossArgs {
+  const float* Y4;       // network output [b][2r][n]
+  const float2* Ut;      // targets [b][r][n] (column-major n x r)
+  double2* part;         // [b][chunk][tri(2r)] Gram partials of [M Ut]
+  double2* P;            // [b][2][r][r]: C^H G^-1, G^-1 C C^H G^-1
+  double* loss_b;        // [b]
+  float* dY4;            // [b][2r][n]
+  long n, chunk;
+  int r, nchunks;
+  float scale;           // 1 / batch
+};
+
 struct FoldArgs {
   const int2* unit_span;  // LINES: per sampled line, its first pair and pair count
   const float2* bcp;      // LINES: conj(b_k) of every pair, in pair order (written by the solve)
@@ -188,6 +216,8 @@ __global__ void k_state_reset(DevState* st, int full);
 __global__ void k_state_set_eta(DevState* st, double eta);
 __global__ void k_x_times_v(const float2* X, const float2* Vs, int n, int q, int r, float2* U,
                             const DevState* st);
+__global__ void k_pick_init(const double* f, const float2* src, float2* dst, long n, int32_t* choice,
+                            const DevState* st);
 __global__ void k_copy(const float2* src, float2* dst, long n);
 __global__ void k_cost_total(const double* cost_k, int q, double* out, DevState* st);
 __global__ void k_init_eig(InitEigArgs a);
@@ -203,6 +233,14 @@ __global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* 
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s);
 hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
+hipError_t launch_cnn_pack(const float* Wl, int cin, int cout, int kp, int kpb, float* Wf, float* Wb, hipStream_t s);
+hipError_t launch_conv(const ConvArgs& a, int batch, hipStream_t s);
+hipError_t launch_wgrad(const WgradArgs& a, int bands, int batch, int nparam_layer, float* g, float scale,
+                        hipStream_t s);
+hipError_t launch_loss(const LossArgs& a, int batch, double* d_loss, hipStream_t s);
+hipError_t launch_cnn_to_M(const float* Y4, int r, long n, int batch, float2* M, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, long n, float lr, int step, hipStream_t s);
+hipError_t launch_cnn_planes(const float2* X, long n, int q, double* partial, float* out, hipStream_t s);
 // mixed form, 1D Cartesian masks: which 0 forward, 1 adjoint + coil combine
 hipError_t launch_pdft(int which, int ny, const PdftArgs& a, int grid_x, int grid_y, hipStream_t s);
 int basis_txx(int N, int nx, int r);

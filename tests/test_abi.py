@@ -1,6 +1,6 @@
 """The C ABI: the built library loads and exports every function that
-include/altgdmin.h declares; the Python binding names them all.  No GPU
-calls are made (host-only entry points only)."""
+include/*.h declares; the Python binding names them all.  No GPU calls are
+made (host-only entry points only)."""
 import ctypes
 import os
 import re
@@ -8,20 +8,25 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "altgdmin.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 LIB = os.path.join(ROOT, "paper_2212_09664_amd", "libaltgdmin.so")
 
 
 def declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(altgdmin_[a-z_A-Z0-9]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:altgdmin|wsinit)_[a-z_A-Z0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
     names = declared()
     for must in ("altgdmin_init", "altgdmin_iterate", "altgdmin_apply_A", "altgdmin_apply_AH",
-                 "altgdmin_create", "altgdmin_set_problem", "altgdmin_destroy"):
+                 "altgdmin_create", "altgdmin_set_problem", "altgdmin_destroy", "altgdmin_cnn_input",
+                 "altgdmin_init_warm", "wsinit_create", "wsinit_forward", "wsinit_loss_backward",
+                 "wsinit_adam_step"):
         assert must in names
 
 
@@ -60,3 +65,20 @@ def test_host_only_argument_checks():
                 P(64, 64, 4, 16, 4, 1024, 0, 0, 36.0, 0.0, 0.0, 0.0, 70)):   # eta_c
         assert L.altgdmin_create(ctypes.byref(bad), ctypes.byref(h)) == 1
     assert L.altgdmin_status_string(4) == b"Gram matrix not positive definite"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_wsinit_host_checks_and_parameter_count():
+    from paper_2212_09664_amd import _lib
+    L = _lib.load_library()
+    h = ctypes.c_void_p()
+    assert L.wsinit_create(128, 128, 48, 6, 32, 4, 4, None, ctypes.byref(h)) == 0
+    c = ctypes.c_int64()
+    assert L.wsinit_param_count(h, ctypes.byref(c)) == 0 and c.value == 49644
+    nb = ctypes.c_size_t()
+    assert L.wsinit_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
+    L.wsinit_destroy(h)
+    for bad in ((100, 128, 48, 6, 32, 4, 4), (128, 128, 48, 17, 32, 4, 4), (128, 128, 48, 6, 33, 4, 4),
+                (128, 128, 48, 6, 32, 3, 4), (128, 128, 48, 6, 32, 4, 0), (128, 128, 129, 6, 32, 4, 4)):
+        h = ctypes.c_void_p()
+        assert L.wsinit_create(*bad, None, ctypes.byref(h)) == 1, bad
