@@ -264,11 +264,13 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
         bc[e] = (p < np && j < r) ? a.bcp[(long)(p0 + p) * r + j] : make_float2(0.f, 0.f);
       }
       __syncthreads();
-      for (int e = tid; e < r * r; e += AG_NT) {
-        const int i = e / r, j = e - i * r;
+      // all RT x RT entries: the padding rows and columns are zero
+      for (int e = tid; e < RT * RT; e += AG_NT) {
+        const int i = e / RT, j = e % RT;
         float2 acc = make_float2(0.f, 0.f);
-        for (int p = 0; p < np; ++p) acc = cadd(acc, cjmul(bc[p * RT + i], bc[p * RT + j]));
-        S[i * RT + j] = acc;
+        if (i < r && j < r)
+          for (int p = 0; p < np; ++p) acc = cadd(acc, cjmul(bc[p * RT + i], bc[p * RT + j]));
+        S[e] = acc;
       }
     } else {
       __syncthreads();  // the previous chunk's store has read Wl
@@ -287,7 +289,8 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
       for (int j = 0; j < RT; ++j) {
         float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int i = 0; i < RT; ++i) acc = cadd(acc, cmul(w[i], S[i * RT + j]));
+        for (int i = 0; i < RT; ++i)
+          if (i < r) acc = cadd(acc, cmul(w[i], S[i * RT + j]));
         kk[j] = acc;
       }
       // data batches of 8, the next batch in flight while this one is used

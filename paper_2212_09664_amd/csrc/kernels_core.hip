@@ -193,97 +193,6 @@ struct Acc2<double> {
 };
 
 // ===========================================================================
-// gradient fold, 1D Cartesian: per sampled line u (ky) and coil c
-//   K_c(u,x,:) = W_c(u,x,:) S_u - sum_{(k,l) on ky} y'_{k,c}(l,x) conj(b_k),
-//   S_u = sum_{(k,l) on ky} b_k b_k^H.
-// ===========================================================================
-template <int RT>
-__global__ __launch_bounds__(AG_NT) void k_fold_lines(FoldArgs a) {
-  __shared__ float2 S[RT * RT];
-  __shared__ float2 bc[128 * RT];
-  __shared__ int2 kl[128];
-  const int u = blockIdx.x, tid = threadIdx.x;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
-  if (u >= a.st->n_units) return;
-  const int r = a.r, nx = a.nx;
-  const int ky = a.unit_loc[u];
-  const int p0 = a.loc_ptr[ky], np = a.loc_ptr[ky + 1] - p0;
-  for (int e = tid; e < np; e += AG_NT) kl[e] = a.pairs[p0 + e];
-  __syncthreads();
-  for (int e = tid; e < np * r; e += AG_NT) {
-    const int p = e / r, j = e % r;
-    float2 b = a.B[(long)kl[p].x * r + j];
-    bc[p * RT + j] = make_float2(b.x, -b.y);
-  }
-  __syncthreads();
-  // S_u[i][j] = sum_p b_i conj(b_j) = sum_p conj(bc_i) bc_j
-  for (int e = tid; e < r * r; e += AG_NT) {
-    const int i = e / r, j = e % r;
-    float2 s = make_float2(0.f, 0.f);
-    for (int p = 0; p < np; ++p) s = cadd(s, cjmul(bc[p * RT + i], bc[p * RT + j]));
-    S[i * RT + j] = s;
-  }
-  __syncthreads();
-  const int c = blockIdx.y;
-  for (int x = tid; x < nx; x += AG_NT) {
-    float2 w[RT], kk[RT];
-#pragma unroll
-    for (int i = 0; i < RT; ++i) w[i] = (i < r) ? a.W[(((long)c * r + i) * a.ua + u) * nx + x] : make_float2(0.f, 0.f);
-#pragma unroll
-    for (int j = 0; j < RT; ++j) {
-      float2 s = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-        if (i < r) s = cadd(s, cmul(w[i], S[i * RT + j]));
-      kk[j] = s;
-    }
-#pragma unroll 4
-    for (int p = 0; p < np; ++p) {
-      const float2 yv = a.yh[(((long)kl[p].x * a.nc + c) * a.lmax + kl[p].y) * nx + x];
-#pragma unroll
-      for (int j = 0; j < RT; ++j) kk[j] = csub(kk[j], cmul(yv, bc[p * RT + j]));
-    }
-#pragma unroll
-    for (int j = 0; j < RT; ++j)
-      if (j < r) a.K[(((long)c * r + j) * a.ua + u) * nx + x] = kk[j];
-  }
-}
-
-// gradient fold, general masks: per location and coil,
-//   K_c(loc,:) = sum_{(k,e) at loc} (W_c(loc,:) b_k - y_{k,c}(e)) conj(b_k)
-template <int RT>
-__global__ __launch_bounds__(AG_NT) void k_fold_index(FoldArgs a) {
-  const int loc = blockIdx.x * AG_NT + threadIdx.x, c = blockIdx.y;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
-  if (loc >= a.n) return;
-  const int r = a.r;
-  float2 w[RT], kk[RT];
-#pragma unroll
-  for (int i = 0; i < RT; ++i) {
-    w[i] = (i < r) ? a.W[((long)c * r + i) * a.n + loc] : make_float2(0.f, 0.f);
-    kk[i] = make_float2(0.f, 0.f);
-  }
-  const int p0 = a.loc_ptr[loc], p1 = a.loc_ptr[loc + 1];
-  for (int p = p0; p < p1; ++p) {
-    const int2 ke = a.pairs[p];
-    const float2* b = a.B + (long)ke.x * r;
-    float2 bb[RT];
-    float2 res = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int i = 0; i < RT; ++i) {
-      bb[i] = (i < r) ? b[i] : make_float2(0.f, 0.f);
-      res = cadd(res, cmul(w[i], bb[i]));
-    }
-    res = csub(res, a.y[((long)ke.x * a.nc + c) * a.m_max + ke.y]);
-#pragma unroll
-    for (int j = 0; j < RT; ++j) kk[j] = cadd(kk[j], cmulj(res, bb[j]));
-  }
-#pragma unroll
-  for (int j = 0; j < RT; ++j)
-    if (j < r) a.K[((long)c * r + j) * a.n + loc] = kk[j];
-}
-
-// ===========================================================================
 // Gram of column blocks: C = [A B]^H [A B] over n rows (column-major n x m1
 // and n x m2), upper triangle, partial sums per workgroup in FP64.
 // ===========================================================================
@@ -924,20 +833,6 @@ __global__ void k_cost_total(const double* cost_k, int q, double* out, DevState*
 // ---------------------------------------------------------------------------
 // launchers (explicit instantiations behind plain functions)
 // ---------------------------------------------------------------------------
-hipError_t launch_fold(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s) {
-  const dim3 g(grid_x, grid_y);
-  if (lines) {
-    if (a.r <= 4) hipLaunchKernelGGL(k_fold_lines<4>, g, dim3(AG_NT), 0, s, a);
-    else if (a.r <= 8) hipLaunchKernelGGL(k_fold_lines<8>, g, dim3(AG_NT), 0, s, a);
-    else hipLaunchKernelGGL(k_fold_lines<16>, g, dim3(AG_NT), 0, s, a);
-  } else {
-    if (a.r <= 4) hipLaunchKernelGGL(k_fold_index<4>, g, dim3(AG_NT), 0, s, a);
-    else if (a.r <= 8) hipLaunchKernelGGL(k_fold_index<8>, g, dim3(AG_NT), 0, s, a);
-    else hipLaunchKernelGGL(k_fold_index<16>, g, dim3(AG_NT), 0, s, a);
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_gram_cols(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s) {
   if (fp64)
     hipLaunchKernelGGL(k_gram_cols<double>, dim3(nblk), dim3(GCOLS_NT), 0, s, a);

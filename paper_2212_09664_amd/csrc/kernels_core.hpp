@@ -226,7 +226,6 @@ hipError_t launch_gram_lines(const GramLinesArgs& a, int ny, int ngroups, int ma
                              hipStream_t s);
 hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp64, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s);
-hipError_t launch_fold(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
 hipError_t launch_gram_cols(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);
 hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);
 __global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* dst, long n);

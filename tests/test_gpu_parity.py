@@ -179,3 +179,26 @@ def test_mixed_precision_end_to_end_gauss64():
     cs = Case(datagen.make("gauss64", 0))
     ctx, Xg, ref = _end_to_end(cs, 20, precision=1)
     assert abs(M.nmse(Xg, cs.prob.zstar) - M.nmse(ref.X, cs.prob.zstar)) <= 1e-4
+
+
+@pytest.mark.parametrize("r", [5, 6, 7, 10])
+def test_gradient_with_rank_below_the_register_tile(r):
+    """Ranks below the kernels' register tile (4, 8, 16): the padded rows and
+    columns of the per-line S_u must not enter the fold."""
+    log(f"gradient r={r}")
+    p = datagen.make_small(64, 64, 3, 12, r, seed=20 + r, kind="lines", n_lines=14, lowrank=False,
+                           snr_db=30.0, coils="random", variable_m=True)
+    cs = Case(p)
+    ctx = cs.gpu_ctx()
+    rng = np.random.default_rng(r)
+    U, _ = np.linalg.qr(datagen.crandn(rng, cs.prob.n, r))
+    U = U.astype(np.complex64).astype(np.complex128)
+    for rep in range(3):  # repeated launches see different leftover LDS contents
+        Bg, Gg = ctx.gradient(to_gpu_U(U))
+        G = from_gpu_U(Gg)
+        assert np.all(np.isfinite(G))
+    Bref = AG.ls_step(cs.op, U, cs.y)
+    Gref = AG.gradient(cs.op, U, Bref, cs.y)
+    t1 = np.linalg.norm(AG.gradient(cs.op, U, Bref, np.zeros_like(cs.y)))
+    t2 = np.linalg.norm(AG.gradient(cs.op, np.zeros_like(U), Bref, cs.y))
+    assert np.linalg.norm(G - Gref) / max(t1, t2) < 1e-5
