@@ -105,7 +105,7 @@ def gpu_problem(prob, form: str):
     dev = torch.device("cuda:0")
     m_k = prob.m_k()
     m_max = int(m_k.max())
-    precision = ag.MIXED if form == "mixed" else ag.FP32
+    precision = ag.MIXED if form in ("mixed", "mixed_warm") else ag.FP32
     kind = ag.MASK_LINES if prob.kind == "lines" else ag.MASK_INDEX
     ctx = ag.AltGDmin(prob.nx, prob.ny, prob.nc, prob.q, prob.r, m_max, kind, precision,
                       t_max=prob.t_iters)
@@ -143,9 +143,30 @@ def run_gpu(args):
     U = torch.empty(prob.r, prob.n, dtype=torch.complex64, device="cuda:0")
     B = torch.empty(prob.q, prob.r, dtype=torch.complex64, device="cuda:0")
 
+    warm = None
+    if args.form in ("warm", "mixed_warm"):
+        wpath = os.path.join(ROOT, "paper_2212_09664_amd", "weights", f"wsinit_{WORKLOAD}.npy")
+        if not os.path.exists(wpath):
+            print(f"no trained warm-start weights for {WORKLOAD} ({wpath})", file=sys.stderr)
+            sys.exit(1)
+        import paper_2212_09664_amd as ag
+        params = torch.from_numpy(np.load(wpath)).to("cuda:0")
+        net = ag.WsInit(prob.nx, prob.ny, prob.q, prob.r, width=32, batch=1, stream=stream)
+        xbuf = torch.empty(1, 2 * prob.q, prob.ny, prob.nx, dtype=torch.float32, device="cuda:0")
+        warm = (net, params, xbuf)
+
+    def initialise():
+        if warm is None:
+            ctx.init(U)
+        else:
+            net, params, xbuf = warm
+            ctx.cnn_input(xbuf[0])
+            M = net.forward(params, xbuf)
+            ctx.init_warm(M[0], U)
+
     def step():
         ctx.set_problem(t["coils"], t["mask"], t["m_k"], t["y"], workspace=ctx._keep[4])
-        ctx.init(U)
+        initialise()
         ctx.iterate(T, U, B)
 
     with torch.cuda.stream(stream):
@@ -177,7 +198,7 @@ def run_gpu(args):
         ctx.set_timing("none")
         # the loop alone
         ctx.set_problem(t["coils"], t["mask"], t["m_k"], t["y"], workspace=ctx._keep[4])
-        ctx.init(U)
+        initialise()
         torch.cuda.synchronize()
         l0, l1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         l0.record(stream)
@@ -191,7 +212,7 @@ def run_gpu(args):
         evs[0].record(stream)
         ctx.set_problem(t["coils"], t["mask"], t["m_k"], t["y"], workspace=ctx._keep[4])
         evs[1].record(stream)
-        ctx.init(U)
+        initialise()
         evs[2].record(stream)
         for i in range(T):
             ctx.iterate(1, U, B)
@@ -200,7 +221,7 @@ def run_gpu(args):
         stamps = [evs[0].elapsed_time(e) for e in evs[1:]]
         zz = float(torch.sum(torch.abs(t["zstar"].to(torch.complex128)) ** 2).item())
         ctx.set_problem(t["coils"], t["mask"], t["m_k"], t["y"], workspace=ctx._keep[4])
-        ctx.init(U)
+        initialise()
         Up = torch.empty_like(U)
         nm = []
         for i in range(T):
@@ -245,7 +266,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", choices=["plain", "mixed"], default="plain")
+    ap.add_argument("--form", choices=["plain", "mixed", "warm", "mixed_warm"], default="plain",
+                    help="plain FP32; mixed (FP16 hi+lo MFMA ky transforms, FP64 Grams); warm / mixed_warm: "
+                         "learned initial basis with the spectral fallback")
     ap.add_argument("--kernel", default="auto",
                     help="kernel class timed for the roofline figure (auto: the loop's most expensive)")
     ap.add_argument("--seed", type=int, default=1001)
@@ -290,7 +313,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.form == "plain" else "f32+f64",
+        "dtype": "f32" if args.form in ("plain", "warm") else "f32+f16x2+f64",
         "data": "synthetic",
         "config": {
             "workload": WORKLOAD_TEXT[WORKLOAD],

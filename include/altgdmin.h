@@ -163,9 +163,12 @@ altgdmin_status altgdmin_cnn_input(altgdmin_ctx* ctx, float* d_in);
  * network output; a small ridge is added if its Gram is numerically
  * singular) are both scored by f(U) = sum_k (||y_k||^2 - h_k^H G_k^-1 h_k),
  * the cost after the exact LS step (Sec. III-B), and the one with the
- * strictly lower cost is written to d_U.  No host synchronisation: if
- * d_choice is not NULL, the device int it points to receives 1 when the
- * learned guess was kept, 0 otherwise.  Resets t and eta. */
+ * strictly lower cost is written to d_U.  The step size is set by
+ * Algorithm 2's first-iteration rule at the spectral basis (the rule at a
+ * good learned basis, whose gradient is small, would overshoot), so with
+ * the fallback the run is exactly the plain one.  No host synchronisation:
+ * if d_choice is not NULL, the device int it points to receives 1 when the
+ * learned guess was kept, 0 otherwise.  Resets t. */
 altgdmin_status altgdmin_init_warm(altgdmin_ctx* ctx, const void* d_M, void* d_U, int32_t* d_choice);
 
 /* n_iter iterations of the alternating loop (Algorithm 2), continuing from

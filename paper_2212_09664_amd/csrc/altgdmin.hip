@@ -412,11 +412,10 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   return e;
 }
 
-hipError_t one_iteration(altgdmin_ctx* c, float2* U, float2* U_prev) {
+// Gram of [U grad] (summing the partial gradients) and the small QR-step
+// work; mode 0 a step, mode 2 only the step size at the first iteration
+hipError_t qr_step_small(altgdmin_ctx* c, int mode, int check_halt) {
   const altgdmin_params& p = c->p;
-  hipError_t e = gradient_pieces(c, 1);
-  if (e != hipSuccess) return e;
-  // Gram of [U grad], then the small QR work, then the update
   GramColsArgs g{};
   g.A = c->at<float2>(c->o_Ui);
   g.B = c->at<float2>(c->o_G);
@@ -429,16 +428,16 @@ hipError_t one_iteration(altgdmin_ctx* c, float2* U, float2* U_prev) {
   g.write_sum = 1;
   g.part = c->at<double2>(c->o_qpart);
   g.st = c->st();
-  g.check_halt = 1;
+  g.check_halt = check_halt;
   tmark(c, TK_QRGRAM);
-  e = launch_qr_gram(g, c->qr_nblk, c->fp64, c->stream);
+  hipError_t e = launch_qr_gram(g, c->qr_nblk, c->fp64, c->stream);
   tmark(c, TK_QRGRAM);
   if (e != hipSuccess) return e;
   QrSmallArgs qa{};
   qa.part = c->at<double2>(c->o_qpart);
   qa.nblk = c->qr_nblk;
   qa.r = p.r;
-  qa.mode = 0;
+  qa.mode = mode;
   qa.n = c->n;
   qa.q = p.q;
   qa.eta_c = p.eta_c;
@@ -449,10 +448,18 @@ hipError_t one_iteration(altgdmin_ctx* c, float2* U, float2* U_prev) {
   qa.cost_k = c->at<double>(c->o_cost);
   qa.rinv = c->at<float2>(c->o_rinv);
   qa.st = c->st();
-  qa.check_halt = 1;
+  qa.check_halt = check_halt;
   tmark(c, TK_QRSMALL);
   e = launch_qr_small(qa, c->stream);
   tmark(c, TK_QRSMALL);
+  return e;
+}
+
+hipError_t one_iteration(altgdmin_ctx* c, float2* U, float2* U_prev) {
+  const altgdmin_params& p = c->p;
+  hipError_t e = gradient_pieces(c, 1);
+  if (e != hipSuccess) return e;
+  e = qr_step_small(c, 0, 1);
   if (e != hipSuccess) return e;
   ApplyArgs aa{};
   aa.U = U;
@@ -737,6 +744,12 @@ altgdmin_status altgdmin_init_warm(altgdmin_ctx* c, const void* d_M, void* d_U, 
   hipStream_t s = c->stream;
   const altgdmin_status st = altgdmin_init(c, d_U);
   if (st != ALTGDMIN_OK) return st;
+  // the step size of Algorithm 2 (first-iteration rule) at the spectral basis:
+  // a good learned basis has a much smaller first gradient, and the rule
+  // evaluated there would overshoot
+  HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
+  HIPCHK(gradient_pieces(c, 0));
+  HIPCHK(qr_step_small(c, 2, 0));
   float2* Uc = c->at<float2>(c->o_Uc);
   hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, static_cast<const float2*>(d_M), Uc, (long)c->n * p.r);
   HIPCHK(hipGetLastError());

@@ -519,7 +519,7 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
     if (tid == 0 && a.mode == 0) st->step_ok = 0;
     return;
   }
-  const int m = a.mode == 0 ? 2 * r : r;
+  const int m = a.mode == 1 ? r : 2 * r;  // mode 0 step, 1 CholeskyQR of U, 2 step size only
   const int nout = m * (m + 1) / 2;
   // sum the block partials: thread = (output, slice of blocks)
   __shared__ double2 red2[1024];
@@ -628,6 +628,7 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
       __syncthreads();
     }
   }
+  if (a.mode == 2) return;  // only the step size was wanted
   // the step size as thread 0 left it, shared through LDS
   __shared__ double s_eta;
   if (tid == 0) s_eta = st->eta;

@@ -15,7 +15,8 @@ in the library's HIP kernels; this module only orchestrates.
 
 Evaluation on held-out seeds: iterations and GPU time to NMSE <= 2e-2 for
 the spectral initialisation and for the warm start (network input, forward
-pass, init_warm with its cost-based fallback), the fallback rate and the
+pass, init_warm with its cost-based fallback and the step size of
+Algorithm 2's rule at the spectral basis), the fallback rate and the
 held-out loss.  NMSE is evaluated off the clock.
 """
 from __future__ import annotations

@@ -124,3 +124,10 @@ def test_warm_init_keeps_the_lower_cost_basis():
         assert proj_dist(U, ref) < 1e-5
         assert np.allclose(U.conj().T @ U, np.eye(p.r), atol=2e-6)
     assert ch == 0  # the random guess lost
+    # the step size is Algorithm 2's rule at the spectral basis, whichever basis is kept
+    U = ctx.init()
+    ctx.iterate(1, U, sync=True)
+    eta_plain = ctx.get_eta()
+    ctx.init_warm(to_gpu_U(Ugood))
+    ctx.iterate(1, to_gpu_U(Ugood), sync=True)
+    assert ctx.get_eta() == pytest.approx(eta_plain, rel=1e-6)
