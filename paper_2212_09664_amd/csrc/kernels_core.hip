@@ -257,21 +257,39 @@ __device__ double block_sum(double v, double* red) {
 // one complex Jacobi rotation G (c, s, e) that zeroes A[p][q] of the
 // Hermitian 2x2 block [[app, apq], [conj(apq), aqq]]; identity if q >= n or
 // the entry is already negligible
-struct JRot {
-  double c, s;
-  double2 e;
-};
+// reciprocal and reciprocal square root in FP64 from the hardware estimates
+// (v_rcp_f64, v_rsq_f64) refined by two Newton steps each, to about one ulp:
+// shorter dependent chains than the IEEE-exact division and square root
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
 __device__ __forceinline__ JRot jacobi_rot(const double2* A, int ld, int n, int p, int q) {
   JRot g{1.0, 0.0, make_double2(1.0, 0.0)};
   if (q >= n) return g;
   const double2 apq = A[p * ld + q];
-  const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+  const double m2 = apq.x * apq.x + apq.y * apq.y;
   const double app = A[p * ld + p].x, aqq = A[q * ld + q].x;
-  if (mag > 1e-300 && mag > 1e-18 * (fabs(app) + fabs(aqq))) {
-    g.e = make_double2(apq.x / mag, -apq.y / mag);  // exp(-i phi)
-    const double tau = (aqq - app) / (2.0 * mag);
-    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-    g.c = 1.0 / sqrt(1.0 + t * t);
+  const double scale = fabs(app) + fabs(aqq);
+  if (m2 > 1e-280 && m2 > 1e-36 * scale * scale) {
+    const double rm = rsq_nr(m2);  // 1 / |a_pq|
+    g.e = make_double2(apq.x * rm, -apq.y * rm);  // exp(-i phi)
+    const double tau = (aqq - app) * 0.5 * rm;
+    const double at = fabs(tau);
+    // t = sign(tau) / (|tau| + sqrt(1 + tau^2)); for huge |tau|, t ~ 1 / (2 tau)
+    const double h = (at < 1e150) ? (1.0 + tau * tau) * rsq_nr(1.0 + tau * tau) : at;
+    const double t = (tau >= 0 ? 1.0 : -1.0) * rcp_nr(at + h);
+    g.c = rsq_nr(1.0 + t * t);
     g.s = t * g.c;
   }
   return g;
@@ -297,9 +315,9 @@ __device__ __forceinline__ void jacobi_pair(int s, int i, int Q, int& p, int& q)
 // (row-major, leading dimension ld), parallel round-robin ordering: the
 // Q/2 rotations of a round are disjoint and are applied together.  The
 // matrix splits into 2x2 blocks (pair i rows, pair j columns); each block
-// is updated independently, A_ij <- G_i^H A_ij G_j, with both rotations
-// computed from the matrix as it was at the start of the round, so a round
-// is one read phase and one write phase.  V (if given, ld n) accumulates
+// is updated independently, A_ij <- G_i^H A_ij G_j, with the rotations
+// computed first (one thread per pair) from the matrix as it was at the
+// start of the round; then a read phase and a write phase.  V (if given, ld n) accumulates
 // V <- V G in place (block (i, j) of V is touched by one thread only).  A and V may be in LDS or in global memory private to the
 // workgroup.  On return diag(A) holds the eigenvalues and the columns of V
 // the eigenvectors.  Up to ITEMS*blockDim blocks: ITEMS = 1 covers n <= 64
@@ -314,8 +332,8 @@ __device__ __forceinline__ void jacobi_pair(int s, int i, int Q, int& p, int& q)
 // an angle of about 1e-10 of the wanted subspace (Davis-Kahan sin-theta),
 // and the sweeps stop.
 template <int JAC_ITEMS>
-__device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch* js, int max_sweeps,
-                           int r_top = 0) {
+__device__ __forceinline__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch* js,
+                                           int max_sweeps, int r_top = 0) {
   const int tid = threadIdx.x, NT = blockDim.x;
   if (V)
     for (int e = tid; e < n * n; e += NT) V[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
@@ -340,7 +358,7 @@ __device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch*
         for (int j = 0; j < n; ++j) {
           if (j == i || js->top[j] != ti) continue;
           const double2 v = A[i * ld + j];
-          rad += sqrt(v.x * v.x + v.y * v.y);
+          rad += fabs(v.x) + fabs(v.y);  // >= |v|: still a Gershgorin bound
         }
         js->bnd[i] = ti ? A[i * ld + i].x - rad : A[i * ld + i].x + rad;
       }
@@ -369,17 +387,23 @@ __device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch*
       if (sep > 0.0 && cross <= 1e-20 * sep * sep) break;
     }
     for (int s = 0; s < Q - 1; ++s) {
+      // this round's rotations, one thread per pair, from the matrix as it is
+      for (int i = tid; i < H; i += NT) {
+        int p, q;
+        jacobi_pair(s, i, Q, p, q);
+        js->rot[i] = jacobi_rot(A, ld, n, p, q);
+        js->pq[i] = make_int2(p, q);
+      }
+      __syncthreads();
       double2 na[JAC_ITEMS][4];
 #pragma unroll
       for (int k = 0; k < JAC_ITEMS; ++k) {
         const int t = tid + k * NT;
         if (t < H * H) {
           const int i = t / H, j = t - (t / H) * H;
-          int pi, qi, pj, qj;
-          jacobi_pair(s, i, Q, pi, qi);
-          jacobi_pair(s, j, Q, pj, qj);
-          const JRot gi = jacobi_rot(A, ld, n, pi, qi);
-          const JRot gj = (i == j) ? gi : jacobi_rot(A, ld, n, pj, qj);
+          const int pi = js->pq[i].x, qi = js->pq[i].y, pj = js->pq[j].x, qj = js->pq[j].y;
+          const JRot gi = js->rot[i];
+          const JRot gj = js->rot[j];
           const bool ri = qi < n, rj = qj < n;  // the second row / column exists
           const double2 z = make_double2(0.0, 0.0);
           // the block [[a, b], [c, d]] = A[(pi, qi), (pj, qj)]
@@ -421,9 +445,7 @@ __device__ void jacobi_eig(double2* A, int n, int ld, double2* V, JacobiScratch*
         const int t = tid + k * NT;
         if (t < H * H) {
           const int i = t / H, j = t - (t / H) * H;
-          int pi, qi, pj, qj;
-          jacobi_pair(s, i, Q, pi, qi);
-          jacobi_pair(s, j, Q, pj, qj);
+          const int pi = js->pq[i].x, qi = js->pq[i].y, pj = js->pq[j].x, qj = js->pq[j].y;
           const bool ri = qi < n, rj = qj < n;
           A[pi * ld + pj] = na[k][0];
           if (rj) A[pi * ld + qj] = na[k][1];
@@ -731,14 +753,16 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 // scaled top-r eigenvectors V_r Sigma_r^{-1}, so that X_0 V_r Sigma_r^{-1}
 // are the top-r left singular vectors of X_0.
 // ===========================================================================
-template <int ITEMS>
+// IN_LDS: matrix and eigenvectors in dynamic LDS (q <= 64; the accesses are
+// then LDS instructions), else in the workspace
+template <int ITEMS, bool IN_LDS>
 __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
   extern __shared__ double2 lds_m[];  // q x q matrix, then q x q eigenvectors (when they fit)
   __shared__ JacobiScratch js;
   __shared__ int idx[16];
   __shared__ double lam_s[16];
   const int tid = threadIdx.x, NT = blockDim.x, q = a.q, r = a.r;
-  double2* A = a.in_lds ? lds_m : a.V;
+  double2* A = IN_LDS ? lds_m : a.V;
   double2* V = A + q * q;
   const int nout = q * (q + 1) / 2;
   for (int o = tid; o < nout; o += NT) {
@@ -857,15 +881,15 @@ hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
 
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s) {
   const size_t lds = a.in_lds ? 2 * (size_t)a.q * a.q * sizeof(double2) : 0;
-  if (a.q <= 64) {
+  if (a.in_lds) {
     if (lds > 48 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_init_eig<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)lds);
+      hipError_t e = hipFuncSetAttribute((const void*)k_init_eig<1, true>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_init_eig<1>, dim3(1), dim3(1024), lds, s, a);
+    hipLaunchKernelGGL((k_init_eig<1, true>), dim3(1), dim3(1024), lds, s, a);
   } else {
-    hipLaunchKernelGGL(k_init_eig<4>, dim3(1), dim3(1024), lds, s, a);
+    hipLaunchKernelGGL((k_init_eig<4, false>), dim3(1), dim3(1024), 0, s, a);
   }
   return hipGetLastError();
 }

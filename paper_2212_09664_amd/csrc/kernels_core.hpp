@@ -10,8 +10,16 @@
 
 namespace ag {
 
+// one complex Jacobi rotation: c, s and the phase e = exp(-i phi)
+struct JRot {
+  double c, s;
+  double2 e;
+};
+
 struct JacobiScratch {
   double red[1024];
+  JRot rot[64];     // this round's rotations, one per pair
+  int2 pq[64];      // and their index pairs
   int top[128];     // per index: among the r_top largest diagonal entries
   double bnd[128];  // per index: Gershgorin bound within its block
 };
