@@ -58,7 +58,9 @@ struct DevState {
   double sd;          // SD(U_{t-1}, U_t)
   double grad_norm;   // ||grad||_F of the last iteration
   double cost_out;    // scratch for altgdmin_cost
-  double pad[6];
+  int32_t n_gwork;    // LINES: (line, sample tile) work items of the Gram kernel
+  int32_t pad_i;
+  double pad[5];
 };
 
 // ---------------------------------------------------------------------------

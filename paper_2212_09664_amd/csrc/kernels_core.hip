@@ -140,6 +140,7 @@ __global__ void k_state_reset(DevState* st, int full) {
     st->err = 0;
     st->err_frame = -1;
     st->n_units = 0;
+    st->n_gwork = 0;
   }
   st->halt = 0;
   st->step_ok = 0;

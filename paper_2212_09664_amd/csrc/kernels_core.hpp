@@ -27,6 +27,8 @@ struct JacobiScratch {
 struct GramLinesArgs {
   const float2* W;       // [c][u][x][j], ua rows per coil
   const float2* yu;      // per-line data [c][x][p]
+  const int2* unit_span; // per sampled line: first pair, pair count
+  const int2* items;     // work items (line, sample tile of 8)
   const int2* pairs;
   const int32_t* loc_ptr;
   const int32_t* unit_loc;
@@ -240,6 +242,7 @@ __global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* 
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s);
 hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
+hipError_t launch_gram_work(const int2* unit_span, int2* items, DevState* st, hipStream_t s);
 hipError_t launch_cnn_pack(const float* Wl, int cin, int cout, int kp, int kpb, float* Wf, float* Wb, hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, int batch, hipStream_t s);
 hipError_t launch_wgrad(const WgradArgs& a, int bands, int batch, int nparam_layer, float* g, float scale,

@@ -118,19 +118,45 @@ __device__ __forceinline__ void gram_lines_loop(const GramLinesArgs& a, int u, i
   }
 }
 
+// the Gram kernel's work items (line u, sample tile t), one block of 1024
+// threads at setup: every sampled line contributes ceil(np_u / 8) items
+__global__ __launch_bounds__(1024) void k_gram_work(const int2* unit_span, int2* items, DevState* st) {
+  __shared__ int s_off[1024];
+  const int tid = threadIdx.x, nu = st->n_units;
+  int cnt = 0;
+  const int per = (nu + 1023) / 1024;
+  for (int u = tid * per; u < min(nu, (tid + 1) * per); ++u) cnt += max(1, (unit_span[u].y + 7) / 8);
+  s_off[tid] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
+    const int v = (tid >= off) ? s_off[tid - off] : 0;
+    __syncthreads();
+    s_off[tid] += v;
+    __syncthreads();
+  }
+  int o = s_off[tid] - cnt;
+  for (int u = tid * per; u < min(nu, (tid + 1) * per); ++u) {
+    const int nt = max(1, (unit_span[u].y + 7) / 8);
+    for (int t = 0; t < nt; ++t) items[o++] = make_int2(u, t);
+  }
+  if (tid == 1023) st->n_gwork = s_off[1023];
+}
+
 template <typename T, int TR, int UN>
 __global__ __launch_bounds__(256) void k_gram_lines_mma(GramLinesArgs a) {
   using M = Mma<T>;
   __shared__ T red[(TR * TR + TR) * 256];
-  const int u = blockIdx.x, t = blockIdx.y, g = blockIdx.z;
+  const int g = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (a.st->err || (a.check_halt && a.st->halt)) return;
-  if (u >= a.st->n_units) return;
+  const int nwork = a.st->n_gwork;
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+  if (w > blockIdx.x) __syncthreads();  // the previous item's LDS reductions are complete
+  const int2 item = a.items[w];
+  const int u = item.x, t = item.y;
   const int r = a.r, col = lane & 15;
-  const int ky = a.unit_loc[u];
-  const int p0 = a.loc_ptr[ky], np = a.loc_ptr[ky + 1] - p0;
-  const int nht = (np + 7) / 8;
-  if (t > 0 && t >= nht) return;
+  const int2 span = a.unit_span[u];
+  const int p0 = span.x, np = span.y;
   const int c0 = g * a.cg, c1 = min(a.nc, c0 + a.cg);
   // this lane's sample (B column) in tile t
   const int pl = 8 * t + (col & 7);
@@ -168,7 +194,6 @@ __global__ __launch_bounds__(256) void k_gram_lines_mma(GramLinesArgs a) {
       Pout[e] = make_double2(re, im);
     }
   }
-  if (np == 0) return;
 #pragma unroll
   for (int i = 0; i < TR; ++i) tile_reduce<T>(Ht + i * 256, H[i], wave, lane);
   const int npt = min(8, np - 8 * t);
@@ -178,6 +203,7 @@ __global__ __launch_bounds__(256) void k_gram_lines_mma(GramLinesArgs a) {
     const double re = C(Ht, 1, j, p) + C(Ht, 1, r + j, 8 + p);
     const double im = C(Ht, 1, j, 8 + p) - C(Ht, 1, r + j, p);
     a.hp[((long)g * a.npairs + p0 + 8 * t + p) * r + j] = make_double2(re, im);
+  }
   }
 }
 
@@ -416,10 +442,18 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
 // ---------------------------------------------------------------------------
 template <typename T, int TR>
 static void launch_lines_tr(const GramLinesArgs& a, int ny, int ngroups, int ht, hipStream_t s) {
-  const dim3 g(ny, ht, ngroups);
+  // about one work item per workgroup: every sampled line plus a few extra
+  // sample tiles; a grid-stride loop takes any remainder
+  (void)ht;
+  const dim3 g(ny + 64, ngroups);
   if (a.nx >= 128) hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 8>), g, dim3(256), 0, s, a);
   else if (a.nx >= 64) hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 4>), g, dim3(256), 0, s, a);
   else hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 1>), g, dim3(256), 0, s, a);
+}
+
+hipError_t launch_gram_work(const int2* unit_span, int2* items, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_work, dim3(1), dim3(1024), 0, s, unit_span, items, st);
+  return hipGetLastError();
 }
 
 hipError_t launch_gram_lines(const GramLinesArgs& a, int ny, int ngroups, int max_pairs, bool fp64,
