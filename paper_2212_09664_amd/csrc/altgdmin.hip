@@ -62,7 +62,7 @@ struct altgdmin_ctx {
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
       o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
-      o_fcmp, o_planes, o_gwork, o_end;
+      o_fcmp, o_planes, o_gwork, o_coilb, o_end;
   size_t T_bytes;
   // timing
   int timed = TK_NONE;
@@ -103,8 +103,11 @@ void carve(altgdmin_ctx* c) {
   c->o_bcp = take(sizeof(float2) * (size_t)q * c->width * r);
   c->o_Uc = take(sizeof(float2) * (size_t)n * r);
   c->o_fcmp = take(sizeof(double) * 2);
-  c->o_gwork = take(sizeof(int2) * (size_t)c->n_loc * ((q + 7) / 8));
+  // Gram work list: at most ceil(q/8) items per line, and at least one entry per
+  // workgroup of the Gram launch (ny + 64 of them)
+  c->o_gwork = take(sizeof(int4) * ((size_t)c->n_loc * ((q + 7) / 8) + (c->lines ? p.ny + 64 : 0)));
   c->o_planes = take(sizeof(double) * 256);
+  c->o_coilb = take(sizeof(float2) * (size_t)n * nc);
   c->o_pairs = take(sizeof(int2) * (size_t)q * c->width);
   c->o_pairof = take(sizeof(int32_t) * (size_t)q * c->width);
   c->o_unitof = take(sizeof(int32_t) * (size_t)q * c->width);
@@ -182,7 +185,7 @@ BasisArgs basis_args(altgdmin_ctx* c, int check_halt) {
   b.W = c->at<float2>(c->o_W);
   b.K = c->at<float2>(c->o_K);
   b.G = c->at<float2>(c->o_G);
-  b.coils = c->coils;
+  b.coils = c->at<float2>(c->o_coilb);
   b.n = c->n;
   b.nx = p.nx;
   b.r = p.r;
@@ -254,8 +257,7 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
     GramLinesArgs g{};
     g.W = c->at<float2>(c->o_W);
     g.yu = c->at<float2>(c->o_yh);
-    g.unit_span = c->at<int2>(c->o_unitspan);
-    g.items = c->at<int2>(c->o_gwork);
+    g.items = c->at<int4>(c->o_gwork);
     g.pairs = c->at<int2>(c->o_pairs);
     g.loc_ptr = c->at<int32_t>(c->o_locptr);
     g.unit_loc = c->at<int32_t>(c->o_unitloc);
@@ -636,6 +638,8 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
   hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, c->st(), 1);
   hipLaunchKernelGGL(k_twiddle, dim3((p.nx + 255) / 256), dim3(256), 0, s, c->at<float2>(c->o_twx), p.nx);
   hipLaunchKernelGGL(k_twiddle, dim3((p.ny + 255) / 256), dim3(256), 0, s, c->at<float2>(c->o_twy), p.ny);
+  hipLaunchKernelGGL(k_coil_block, dim3(1024), dim3(256), 0, s, c->coils, c->at<float2>(c->o_coilb), p.nx, p.ny,
+                     c->txx, c->n, p.nc);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemsetAsync(c->at<uint32_t>(c->o_bitmap), 0, sizeof(uint32_t) * (size_t)c->n_loc * c->nw, s));
   hipLaunchKernelGGL(k_inv_bitmap, dim3((c->width + 255) / 256, p.q), dim3(256), 0, s, c->mask, c->m_k,
@@ -643,7 +647,7 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
   hipLaunchKernelGGL(k_inv_scan, dim3(1), dim3(1024), 0, s, c->at<uint32_t>(c->o_bitmap), c->nw, c->n_loc,
                      c->at<int32_t>(c->o_locptr), c->at<int32_t>(c->o_loc2unit), c->at<int32_t>(c->o_unitloc),
                      c->at<int2>(c->o_unitspan), c->st());
-  if (c->lines) HIPCHK(launch_gram_work(c->at<int2>(c->o_unitspan), c->at<int2>(c->o_gwork), c->st(), s));
+  if (c->lines) HIPCHK(launch_gram_work(c->at<int2>(c->o_unitspan), c->at<int4>(c->o_gwork), c->st(), s));
   hipLaunchKernelGGL(k_inv_fill, dim3((c->width + 255) / 256, p.q), dim3(256), 0, s, c->mask, c->m_k,
                      c->width, c->per, c->at<uint32_t>(c->o_bitmap), c->nw, c->at<int32_t>(c->o_locptr),
                      c->at<int32_t>(c->o_loc2unit), c->at<int2>(c->o_pairs), c->at<int32_t>(c->o_pairof),

@@ -38,7 +38,6 @@ __global__ __launch_bounds__(AG_NT) void k_basis_fwd(BasisArgs a) {
   const int tid = threadIdx.x;
   const int txx = a.txx, r = a.r, ctr = txx * r;
   const int x0 = blockIdx.x * txx;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
   for (int e = tid; e < N; e += AG_NT) {
     s_tw[e] = a.tw[e];
     const int u = a.row_unit ? a.row_unit[e] : e;
@@ -52,6 +51,8 @@ __global__ __launch_bounds__(AG_NT) void k_basis_fwd(BasisArgs a) {
       const int g = tid + it * AG_NT, col = g % CT, y = GM::in_row(g, q);
       uv[it][q] = (GM::in_ok(g) && col < ctr) ? a.U[((long)y * a.nx + x0) * r + col] : make_float2(0.f, 0.f);
     }
+  // the state is read once the first loads are in flight (their addresses are valid either way)
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
   __syncthreads();
   const int cb = blockIdx.y * a.cgs, ce = min(a.nc, cb + a.cgs);
   float2 cv[IT0][R0];
@@ -61,9 +62,9 @@ __global__ __launch_bounds__(AG_NT) void k_basis_fwd(BasisArgs a) {
     for (int it = 0; it < IT0; ++it) {
       const int g = tid + it * AG_NT, col = g % CT;
       const bool ok = GM::in_ok(g) && col < ctr;
-      const float2* cp = coil + (g / CT) * a.nx + x0 + col / r;
+      const float2* cp = coil + (long)blockIdx.x * N * txx + (g / CT) * txx + col / r;  // [x/txx][y][x%txx]
 #pragma unroll
-      for (int q = 0; q < R0; ++q) cv[it][q] = ok ? cp[q * (N / R0) * a.nx] : make_float2(0.f, 0.f);
+      for (int q = 0; q < R0; ++q) cv[it][q] = ok ? cp[q * (N / R0) * txx] : make_float2(0.f, 0.f);
     }
   };
   if (cb < ce) fetch(cb);
@@ -106,7 +107,6 @@ __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
   const int tid = threadIdx.x;
   const int txx = a.txx, r = a.r, ctr = txx * r;
   const int x0 = blockIdx.x * txx;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
   for (int e = tid; e < N; e += AG_NT) {
     float2 w = a.tw[e];
     s_tw[e] = make_float2(w.x, -w.y);
@@ -135,6 +135,8 @@ __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
     }
   };
   if (cb < ce) fetch(cb);
+  // the state is read once the first loads are in flight (their addresses are valid either way)
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
   for (int c = cb; c < ce; ++c) {
     float2 v0[IT0][R0], vo[ITL][RL];
 #pragma unroll
@@ -149,10 +151,10 @@ __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
     for (int it = 0; it < ITL; ++it) {
       const int g = tid + it * AG_NT, col = g % CT;
       if (GM::out_ok(g) && col < ctr) {
-        const float2* cp = coil + (g / CT) * (PL_ONE<N>() ? RL : 1) * a.nx + x0 + col / r;
+        const float2* cp = coil + (long)blockIdx.x * N * txx + (g / CT) * (PL_ONE<N>() ? RL : 1) * txx + col / r;
 #pragma unroll
         for (int q = 0; q < RL; ++q) {
-          const float2 cw = cp[(PL_ONE<N>() ? q : q * (N / RL)) * a.nx];
+          const float2 cw = cp[(PL_ONE<N>() ? q : q * (N / RL)) * txx];
           acc[it][q] = cadd(acc[it][q], cjmul(cw, vo[it][q]));
         }
       }
@@ -212,110 +214,95 @@ __global__ void k_build_yu(const float2* yh, const int2* pairs, const int32_t* m
 }
 
 // ---------------------------------------------------------------------------
-// gradient fold, 1D Cartesian: grid (sampled lines, nc).  The (coil, line)
-// block of W (nx x r, contiguous) is staged through LDS with coalesced
-// loads, every thread forms one x row of K, and the K block leaves through
-// LDS again; the samples' data are read along x.
+// gradient fold, 1D Cartesian: per sampled line u and coil c,
+//   K_c[u][x][:] = sum_{p in u} (W_c[u][x][:] . b_p - y_p(c, x)) conj(b_p)^T
+// over the line's (frame, line) pairs p: the residual of every sample times
+// conj(b) of its frame.  One workgroup per (line, coil); thread = readout
+// position x, holding its row of r values in registers (rows of even r move
+// as float4).  conj(b_p) of the line's pairs are staged in LDS.
 // ---------------------------------------------------------------------------
 template <int RT>
 __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
-  __shared__ float2 S[RT * RT];
-  __shared__ float2 bc[128 * RT];
-  __shared__ float2 Wl[AG_NT * (RT + 1)];
+  __shared__ float2 bc[128 * RT];  // conj(b_p) of the line's pairs (at most q <= 128)
   const int u = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
-  if (u >= a.st->n_units) return;
   const int r = a.r, nx = a.nx;
-  // LDS slot of element g of a [x][j] block: x = g / r through a float
-  // reciprocal (exact: g < 2^13 and the fraction of (g + 1/2)/r is >= 1/(2r))
-  const float rinv = 1.0f / (float)r;
-  int slot[RT];
+  const bool vec = (r & 1) == 0;
+  float2 w[RT];
+  auto load_w = [&](int x0) {
+    const float2* src = a.W + (((long)c * a.ua + u) * nx + min(x0 + tid, nx - 1)) * r;
+    if (vec) {
 #pragma unroll
-  for (int t = 0; t < RT; ++t) {
-    const int g = tid + t * AG_NT;
-    const int xx = (int)(((float)g + 0.5f) * rinv);
-    slot[t] = xx * (RT + 1) + (g - xx * r);
-  }
-  const int2 span = a.unit_span[u];
-  const int p0 = span.x, np = span.y;
-  const int np8 = (np + 7) & ~7;  // rows past np are zero, so the data loop runs in whole batches of 8
-  for (int x0 = 0; x0 < nx; x0 += AG_NT) {
-    const int nxc = min(AG_NT, nx - x0), tot = nxc * r;
-    const int x = x0 + tid;
-    const long blk = (((long)c * a.ua + u) * nx + x0) * r;
-    float2 wv[RT];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int g = tid + t * AG_NT;
-      wv[t] = (g < tot) ? a.W[blk + g] : make_float2(0.f, 0.f);
-    }
-    const float2* Yb = a.yu + (long)a.nc * nx * p0 + (long)c * np * nx + x;  // [p][x]
-    auto load_y = [&](int pb, float2 (&yv)[8]) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t)
-        yv[t] = (tid < nxc && pb + t < np) ? Yb[(long)(pb + t) * nx] : make_float2(0.f, 0.f);
-    };
-    float2 ya[8], yb[8];
-    load_y(0, ya);
-    if (x0 == 0) {
-      // conj(b_k) of the line's samples, then S_u = sum_k b_k b_k^H
-      for (int e = tid; e < np8 * RT; e += AG_NT) {
-        const int p = e / RT, j = e - p * RT;
-        bc[e] = (p < np && j < r) ? a.bcp[(long)(p0 + p) * r + j] : make_float2(0.f, 0.f);
-      }
-      __syncthreads();
-      // all RT x RT entries: the padding rows and columns are zero
-      for (int e = tid; e < RT * RT; e += AG_NT) {
-        const int i = e / RT, j = e % RT;
-        float2 acc = make_float2(0.f, 0.f);
-        if (i < r && j < r)
-          for (int p = 0; p < np; ++p) acc = cadd(acc, cjmul(bc[p * RT + i], bc[p * RT + j]));
-        S[e] = acc;
+      for (int i = 0; i < RT; i += 2) {
+        const float4 v = (i < r) ? *reinterpret_cast<const float4*>(src + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+        w[i] = make_float2(v.x, v.y);
+        w[i + 1] = make_float2(v.z, v.w);
       }
     } else {
-      __syncthreads();  // the previous chunk's store has read Wl
+#pragma unroll
+      for (int i = 0; i < RT; ++i) w[i] = (i < r) ? src[i] : make_float2(0.f, 0.f);
     }
+  };
+  // the first chunk's W rows and the line's span are requested before the
+  // state is read (every address is valid either way), so that the latencies
+  // overlap; the span is used only once the line is known to be sampled
+  const int2 span = a.unit_span[u];
+  load_w(0);
+  if (a.st->err || (a.check_halt && a.st->halt) || u >= a.st->n_units) return;
+  const int p0 = span.x, np = span.y;
+  const float2* Yc = a.yu + (long)a.nc * nx * p0 + (long)c * np * nx;  // this line and coil, [p][x]
+  float2 ya[8], yb[8];
+  auto load_y = [&](int x0, int pb, float2 (&yv)[8]) {
+    const int x = min(x0 + tid, nx - 1);
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int g = tid + t * AG_NT;
-      if (g < tot) Wl[slot[t]] = wv[t];
+    for (int t = 0; t < 8; ++t) yv[t] = (pb + t < np) ? Yc[(long)(pb + t) * nx + x] : make_float2(0.f, 0.f);
+  };
+  load_y(0, 0, ya);
+  // padding entries (j >= r) are zero, so whole RT-wide rows can be used
+  for (int e = tid; e < np * RT; e += AG_NT) {
+    const int p = e / RT, j = e - p * RT;
+    bc[e] = (j < r) ? a.bcp[(long)(p0 + p) * r + j] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  // one pair: kk += (w . b_p - y) conj(b_p)
+  auto pair = [&](int p, float2 yv, float2 (&kk)[RT]) {
+    const float2* bp = bc + p * RT;
+    float2 res = make_float2(-yv.x, -yv.y);
+#pragma unroll
+    for (int i = 0; i < RT; ++i) res = cadd(res, cmulj(w[i], bp[i]));
+#pragma unroll
+    for (int j = 0; j < RT; ++j) kk[j] = cadd(kk[j], cmul(res, bp[j]));
+  };
+  for (int x0 = 0; x0 < nx; x0 += AG_NT) {
+    if (x0 > 0) {
+      load_w(x0);
+      load_y(x0, 0, ya);
     }
-    __syncthreads();
-    if (tid < nxc) {
-      float2 w[RT], kk[RT];
+    float2 kk[RT];
 #pragma unroll
-      for (int i = 0; i < RT; ++i) w[i] = (i < r) ? Wl[tid * (RT + 1) + i] : make_float2(0.f, 0.f);
+    for (int j = 0; j < RT; ++j) kk[j] = make_float2(0.f, 0.f);
+    // data batches of 8, the next batch in flight while this one is used
+    for (int pb = 0; pb < np; pb += 16) {
+      if (pb + 8 < np) load_y(x0, pb + 8, yb);
 #pragma unroll
-      for (int j = 0; j < RT; ++j) {
-        float2 acc = make_float2(0.f, 0.f);
+      for (int t = 0; t < 8; ++t)
+        if (pb + t < np) pair(pb + t, ya[t], kk);
+      if (pb + 8 >= np) break;
+      if (pb + 16 < np) load_y(x0, pb + 16, ya);
 #pragma unroll
-        for (int i = 0; i < RT; ++i)
-          if (i < r) acc = cadd(acc, cmul(w[i], S[i * RT + j]));
-        kk[j] = acc;
+      for (int t = 0; t < 8; ++t)
+        if (pb + 8 + t < np) pair(pb + 8 + t, yb[t], kk);
+    }
+    if (x0 + tid < nx) {
+      float2* dst = a.K + (((long)c * a.ua + u) * nx + x0 + tid) * r;
+      if (vec) {
+#pragma unroll
+        for (int j = 0; j < RT; j += 2)
+          if (j < r) *reinterpret_cast<float4*>(dst + j) = make_float4(kk[j].x, kk[j].y, kk[j + 1].x, kk[j + 1].y);
+      } else {
+#pragma unroll
+        for (int j = 0; j < RT; ++j)
+          if (j < r) dst[j] = kk[j];
       }
-      // data batches of 8, the next batch in flight while this one is used
-      for (int pb = 0; pb < np; pb += 16) {
-        if (pb + 8 < np) load_y(pb + 8, yb);
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-#pragma unroll
-          for (int j = 0; j < RT; ++j) kk[j] = csub(kk[j], cmul(ya[t], bc[(pb + t) * RT + j]));
-        if (pb + 8 >= np) break;
-        if (pb + 16 < np) load_y(pb + 16, ya);
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-#pragma unroll
-          for (int j = 0; j < RT; ++j) kk[j] = csub(kk[j], cmul(yb[t], bc[(pb + 8 + t) * RT + j]));
-      }
-#pragma unroll
-      for (int j = 0; j < RT; ++j)
-        if (j < r) Wl[tid * (RT + 1) + j] = kk[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int g = tid + t * AG_NT;
-      if (g < tot) a.K[blk + g] = Wl[slot[t]];
     }
   }
 }
@@ -379,6 +366,18 @@ __global__ void k_to_colmajor(const float2* src, int r, long n, float2* dst) {
 // launchers
 // ---------------------------------------------------------------------------
 int basis_ct(int N) { return N >= 256 ? 16 : (N >= 128 ? 32 : 64); }
+
+// coil maps in the layout the transforms read: [c][x / txx][y][x % txx], so
+// that a workgroup's txx columns are one contiguous block per coil
+__global__ void k_coil_block(const float2* coils, float2* dst, int nx, int ny, int txx, long n, int nc) {
+  const long tot = n * nc;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    const long c = e / n, rem = e - c * n;
+    const long xg = rem / ((long)ny * txx), rem2 = rem - xg * ny * txx;
+    const int y = (int)(rem2 / txx), xl = (int)(rem2 - (long)y * txx);
+    dst[e] = coils[c * n + (long)y * nx + xg * txx + xl];
+  }
+}
 
 int basis_txx(int N, int nx, int r) {
   const int ct = basis_ct(N);

@@ -460,53 +460,26 @@ __device__ __forceinline__ void jacobi_eig(double2* A, int n, int ld, double2* V
 }
 
 // Cholesky of the Hermitian r x r matrix M (LDS, ld 16) in FP64, lower L in
-// place; then R = L^H and Rinv = R^{-1} (upper triangular) into Ri.  Run by
-// one thread.  Returns false if M is not positive definite.
-__device__ bool chol_rinv(double2* M, int r, double2* Ri) {
-  double dmax = 0.0;
-  for (int i = 0; i < r; ++i) dmax = fmax(dmax, M[i * 16 + i].x);
-  for (int j = 0; j < r; ++j) {
-    double d = M[j * 16 + j].x;
-    for (int m = 0; m < j; ++m) d -= M[j * 16 + m].x * M[j * 16 + m].x + M[j * 16 + m].y * M[j * 16 + m].y;
-    if (!(d > 1e-14 * dmax) || !isfinite(d)) return false;
-    const double ljj = sqrt(d);
-    M[j * 16 + j] = make_double2(ljj, 0.0);
-    for (int i = j + 1; i < r; ++i) {
-      double2 s = M[i * 16 + j];
-      for (int m = 0; m < j; ++m) s = dsub(s, dmul(M[i * 16 + m], dconj(M[j * 16 + m])));
-      M[i * 16 + j] = make_double2(s.x / ljj, s.y / ljj);
-    }
-  }
-  // R = L^H upper; Rinv upper with R Rinv = I, column by column
-  for (int j = 0; j < r; ++j) {
-    for (int i = j + 1; i < r; ++i) Ri[i * 16 + j] = make_double2(0.0, 0.0);
-    Ri[j * 16 + j] = make_double2(1.0 / M[j * 16 + j].x, 0.0);
-    for (int i = j - 1; i >= 0; --i) {
-      // sum_{m=i+1..j} R[i][m] Rinv[m][j], R[i][m] = conj(L[m][i])
-      double2 s = make_double2(0.0, 0.0);
-      for (int m = i + 1; m <= j; ++m) s = dadd(s, dmul(dconj(M[m * 16 + i]), Ri[m * 16 + j]));
-      Ri[i * 16 + j] = make_double2(-s.x / M[i * 16 + i].x, -s.y / M[i * 16 + i].x);
-    }
-  }
-  return true;
-}
-
-// Cholesky of the Hermitian r x r matrix M (LDS, ld 16) in FP64, lower L in
-// place; one thread.  Returns false if M is not positive definite.
+// place, right-looking, by the whole workgroup (every thread must call it).
+// Returns false (in every thread) if M is not positive definite.
 __device__ bool chol_lower(double2* M, int r) {
+  const int tid = threadIdx.x, nt = blockDim.x;
   double dmax = 0.0;
   for (int i = 0; i < r; ++i) dmax = fmax(dmax, M[i * 16 + i].x);
   for (int j = 0; j < r; ++j) {
-    double d = M[j * 16 + j].x;
-    for (int m = 0; m < j; ++m) d -= M[j * 16 + m].x * M[j * 16 + m].x + M[j * 16 + m].y * M[j * 16 + m].y;
+    const double d = M[j * 16 + j].x;  // every thread reads the same pivot
     if (!(d > 1e-14 * dmax) || !isfinite(d)) return false;
-    const double ljj = sqrt(d);
-    M[j * 16 + j] = make_double2(ljj, 0.0);
-    for (int i = j + 1; i < r; ++i) {
-      double2 s = M[i * 16 + j];
-      for (int m = 0; m < j; ++m) s = dsub(s, dmul(M[i * 16 + m], dconj(M[j * 16 + m])));
-      M[i * 16 + j] = make_double2(s.x / ljj, s.y / ljj);
+    const double ljj = sqrt(d), inv = 1.0 / ljj;
+    __syncthreads();
+    if (tid == 0) M[j * 16 + j] = make_double2(ljj, 0.0);
+    for (int i = j + 1 + tid; i < r; i += nt) M[i * 16 + j] = make_double2(M[i * 16 + j].x * inv, M[i * 16 + j].y * inv);
+    __syncthreads();
+    // trailing update of the lower triangle: M[i][k] -= L[i][j] conj(L[k][j]), j < k <= i
+    for (int e = tid; e < 256; e += nt) {
+      const int i = e >> 4, k = e & 15;
+      if (k > j && k <= i && i < r) M[i * 16 + k] = dsub(M[i * 16 + k], dmul(M[i * 16 + j], dconj(M[k * 16 + j])));
     }
+    __syncthreads();
   }
   return true;
 }
@@ -576,31 +549,23 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
     __syncthreads();
   }
   __syncthreads();
-  __shared__ double s_f;
-  if (a.mode == 0) {  // f = sum_k cost_k, in parallel
-    double v = 0.0;
-    for (int k = tid; k < a.q; k += blockDim.x) v += a.cost_k[k];
-    v = block_sum(v, js.red);
-    if (tid == 0) s_f = v;
-  }
-  __syncthreads();
   if (a.mode == 1) {
     for (int e = tid; e < 256; e += blockDim.x) Gh[e] = UU[e];
     __syncthreads();
-    if (tid == 0) s_ok = chol_lower(Gh, r);
+    bool ok = chol_lower(Gh, r);
     __syncthreads();
-    if (!s_ok) {  // numerically rank-deficient basis: retry with a small ridge
+    if (!ok) {  // numerically rank-deficient basis: retry with a small ridge
       for (int e = tid; e < 256; e += blockDim.x) Gh[e] = UU[e];
       __syncthreads();
-      if (tid == 0) {
-        double tr = 0.0;
-        for (int i = 0; i < r; ++i) tr += UU[i * 16 + i].x;
-        for (int i = 0; i < r; ++i) Gh[i * 16 + i].x += 1e-6 * tr / r;
-        s_ok = (tr > 0.0) && isfinite(tr) && chol_lower(Gh, r);
-      }
+      double tr = 0.0;
+      for (int i = 0; i < r; ++i) tr += UU[i * 16 + i].x;
+      __syncthreads();
+      if (tid < r) Gh[tid * 16 + tid].x += 1e-6 * tr / r;
+      __syncthreads();
+      ok = (tr > 0.0) && isfinite(tr) && chol_lower(Gh, r);
       __syncthreads();
     }
-    if (!s_ok) {
+    if (!ok) {
       if (tid == 0) set_error(st, 4, -1);
       return;
     }
@@ -656,49 +621,58 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
   __shared__ double s_eta;
   if (tid == 0) s_eta = st->eta;
   __syncthreads();
+  // one wave from here on: Cholesky of Uhat^H Uhat, Uhat = U - eta G, from the
+  // blocks (rows in lanes), R^{-1}, SD(U, U+) and the cost
+  if (tid >= 64) return;
+  const int i = tid;
   const double eta = s_eta;
-  // Gram of Uhat = U - eta G, in parallel
-  for (int e = tid; e < r * r; e += blockDim.x) {
-    const int i = e / r, j = e % r;
-    const double2 ug = UG[i * 16 + j], gu = dconj(UG[j * 16 + i]);
-    const double2 v = UU[i * 16 + j];
-    const double2 g = GG[i * 16 + j];
-    Gh[i * 16 + j] = make_double2(v.x - eta * (ug.x + gu.x) + eta * eta * g.x,
-                                  v.y - eta * (ug.y + gu.y) + eta * eta * g.y);
-  }
-  __syncthreads();
-  if (tid == 0) s_ok = chol_lower(Gh, r);
-  __syncthreads();
-  if (!s_ok) {
-    if (tid == 0) {
+  auto gh = [&](int a_, int b_) -> double2 {  // (Uhat^H Uhat)[a_][b_]
+    const double2 ug = UG[a_ * 16 + b_], gu = dconj(UG[b_ * 16 + a_]);
+    const double2 v = UU[a_ * 16 + b_], g = GG[a_ * 16 + b_];
+    return make_double2(v.x - eta * (ug.x + gu.x) + eta * eta * g.x, v.y - eta * (ug.y + gu.y) + eta * eta * g.y);
+  };
+  double2 g[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) g[m] = (i < r && m < r) ? gh(i, m) : make_double2(0.0, 0.0);
+  double dmax = 0.0;
+  for (int m = 0; m < r; ++m) dmax = fmax(dmax, gh(m, m).x);
+  if (!wave_chol<double, double2>(g, r, 1e-14 * dmax)) {
+    if (i == 0) {
       set_error(st, 4, -1);
       st->step_ok = 0;
     }
     return;
   }
+#pragma unroll
+  for (int m = 0; m < 16; ++m)
+    if (i < r && m <= i) Gh[i * 16 + m] = g[m];
+  wave_sync();
   rinv_columns(Gh, r, Ri);
-  __syncthreads();
+  wave_sync();
   // U^H U+ = (U^H U - eta U^H G) Rinv; SD^2 = r - ||U^H U+||_F^2
   double fro = 0.0;
-  for (int e = tid; e < r * r; e += blockDim.x) {
-    const int i = e / r, j = e % r;
-    a.rinv[e] = d2f(Ri[i * 16 + j]);
+  for (int e = i; e < r * r; e += 64) {
+    const int i2 = e / r, j = e % r;
+    a.rinv[e] = d2f(Ri[i2 * 16 + j]);
     double2 sacc = make_double2(0.0, 0.0);
     for (int mm = 0; mm <= j; ++mm) {
-      const double2 lhs = make_double2(UU[i * 16 + mm].x - eta * UG[i * 16 + mm].x,
-                                       UU[i * 16 + mm].y - eta * UG[i * 16 + mm].y);
+      const double2 lhs = make_double2(UU[i2 * 16 + mm].x - eta * UG[i2 * 16 + mm].x,
+                                       UU[i2 * 16 + mm].y - eta * UG[i2 * 16 + mm].y);
       sacc = dadd(sacc, dmul(lhs, Ri[mm * 16 + j]));
     }
     fro += sacc.x * sacc.x + sacc.y * sacc.y;
   }
-  fro = block_sum(fro, js.red);
-  if (tid == 0) {
+  fro = wave_sum(fro);
+  double fv = 0.0;  // f = sum_k cost_k
+  for (int k = i; k < a.q; k += 64) fv += a.cost_k[k];
+  fv = wave_sum(fv);
+  if (i == 0) {
     const double sd2 = fmax(0.0, (double)r - fro);
     double tr = 0.0;
-    for (int i = 0; i < r; ++i) tr += GG[i * 16 + i].x;
+    for (int m = 0; m < r; ++m) tr += GG[m * 16 + m].x;
     st->sd = sqrt(sd2);
     st->grad_norm = sqrt(tr);
-    st->f = s_f;
+    st->f = fv;
     st->t += 1;
     st->step_ok = 1;
     if (a.eps_exit > 0.0 && sqrt(sd2 / r) < a.eps_exit) {
@@ -715,10 +689,19 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
   __shared__ float2 Ri[RT * RT];
   const int tid = threadIdx.x;
   const long p = (long)blockIdx.x * AG_NT + tid;
+  const int r = a.r;
+  // this pixel's basis row and gradient are requested before the state is
+  // read (clamped addresses, valid either way)
+  const long pc = min(p, a.n - 1);
+  float2 u0[RT], g0[RT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i) {
+    u0[i] = (i < r) ? a.U[(long)i * a.n + pc] : make_float2(0.f, 0.f);
+    g0[i] = (i < r && a.mode == 0) ? a.G[pc * r + i] : make_float2(0.f, 0.f);  // gradient is pixel-major
+  }
+  for (int e = tid; e < r * r; e += AG_NT) Ri[(e / r) * RT + (e % r)] = a.rinv[e];
   if (a.mode == 0 && !a.st->step_ok) return;
   if (a.st->err) return;
-  const int r = a.r;
-  for (int e = tid; e < r * r; e += AG_NT) Ri[(e / r) * RT + (e % r)] = a.rinv[e];
   __syncthreads();
   if (p >= a.n) return;
   const float eta = (a.mode == 0) ? (float)a.st->eta : 0.f;
@@ -726,13 +709,8 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 #pragma unroll
   for (int i = 0; i < RT; ++i) {
     if (i < r) {
-      float2 u = a.U[(long)i * a.n + p];
-      if (a.U_prev) a.U_prev[(long)i * a.n + p] = u;
-      if (a.mode == 0) {
-        const float2 g = a.G[p * r + i];  // gradient is pixel-major
-        u = make_float2(u.x - eta * g.x, u.y - eta * g.y);
-      }
-      uh[i] = u;
+      if (a.U_prev) a.U_prev[(long)i * a.n + p] = u0[i];
+      uh[i] = make_float2(u0[i].x - eta * g0[i].x, u0[i].y - eta * g0[i].y);
     } else {
       uh[i] = make_float2(0.f, 0.f);
     }

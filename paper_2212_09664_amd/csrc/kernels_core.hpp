@@ -26,9 +26,8 @@ struct JacobiScratch {
 
 struct GramLinesArgs {
   const float2* W;       // [c][u][x][j], ua rows per coil
-  const float2* yu;      // per-line data [c][x][p]
-  const int2* unit_span; // per sampled line: first pair, pair count
-  const int2* items;     // work items (line, sample tile of 8)
+  const float2* yu;      // per-line data [c][p][x]
+  const int4* items;     // work items (line, sample tile of 8, first pair, pair count)
   const int2* pairs;
   const int32_t* loc_ptr;
   const int32_t* unit_loc;
@@ -78,7 +77,7 @@ struct BasisArgs {
   float2* W;             // [c][row][x][j]
   float2* K;             // [c][row][x][j]
   float2* G;             // [part][p][j]
-  const float2* coils;
+  const float2* coils;   // blocked [c][x / txx][y][x % txx]
   long n;
   int nx, r, nc, ua, txx, cgs;
   long part_stride;
@@ -139,7 +138,7 @@ struct FoldArgs {
   const int2* unit_span;  // LINES: per sampled line, its first pair and pair count
   const float2* bcp;      // LINES: conj(b_k) of every pair, in pair order (written by the solve)
   const float2* W;
-  const float2* yu;      // LINES: per-line data [c][x][p]
+  const float2* yu;      // LINES: per-line data [c][p][x]
   const float2* yh;      // LINES: hybrid data
   const float2* y;       // INDEX: measurements
   const float2* B;
@@ -161,7 +160,7 @@ struct GramColsArgs {
   int nparts;            // B is the sum of nparts arrays at stride part_stride
   long part_stride;
   int write_sum;         // store the summed B back into part 0
-  double2* part;
+  double2* part;         // per workgroup: its partial Gram
   DevState* st;
   int check_halt;
 };
@@ -203,6 +202,78 @@ __device__ __forceinline__ void set_error(DevState* st, int code, int frame) {
   st->halt = 1;
 }
 
+// ---------------------------------------------------------------------------
+// one-wave helpers for the small factorizations: a single wave works on
+// registers and LDS with no workgroup barrier (lane = threadIdx.x & 63)
+// ---------------------------------------------------------------------------
+// value of v in lane src (src uniform)
+__device__ __forceinline__ float lane_get(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_get(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float2 lane_get(float2 v, int src) { return make_float2(lane_get(v.x, src), lane_get(v.y, src)); }
+__device__ __forceinline__ double2 lane_get(double2 v, int src) {
+  return make_double2(lane_get(v.x, src), lane_get(v.y, src));
+}
+// sum over the 64 lanes
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+// this wave's LDS writes are seen by its later LDS reads in any lane
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// complex helpers over float2 / double2
+__device__ __forceinline__ float2 cx_mul(float2 a, float2 b) { return cmul(a, b); }
+__device__ __forceinline__ double2 cx_mul(double2 a, double2 b) { return dmul(a, b); }
+__device__ __forceinline__ float2 cx_cjm(float2 a, float2 b) { return cjmul(a, b); }    // conj(a) b
+__device__ __forceinline__ double2 cx_cjm(double2 a, double2 b) { return djmul(a, b); }
+__device__ __forceinline__ float2 cx_sub(float2 a, float2 b) { return csub(a, b); }
+__device__ __forceinline__ double2 cx_sub(double2 a, double2 b) { return dsub(a, b); }
+__device__ __forceinline__ float2 cx_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cx_scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// Cholesky G = L L^H of a Hermitian positive definite r x r matrix (r <= 16)
+// by one wave: lane i < r holds row i of G in g[0..15] on entry and row i of
+// L (entries 0..i) on return.  False if a pivot is not above tol (all lanes
+// agree).  Right-looking; column j of L is broadcast from lanes j+1..r-1.
+template <typename T, typename T2>
+__device__ __forceinline__ bool wave_chol(T2 (&g)[16], int r, T tol) {
+  const int i = threadIdx.x & 63;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {  // fixed trip counts: g stays in registers
+    if (j < r && ok) {
+      const T d = lane_get(g[j].x, j);
+      ok = (d > tol) && isfinite((double)d);
+      const T ljj = sqrt(ok ? d : (T)1), inv = (T)1 / ljj;
+      if (i == j) {
+        g[j].x = ljj;
+        g[j].y = (T)0;
+      } else if (i > j) {
+        g[j] = cx_scale(g[j], inv);
+      }
+#pragma unroll
+      for (int k = j + 1; k < 16; ++k) {
+        if (k < r) {
+          const T2 lkj = lane_get(g[j], k);
+          if (i >= k) g[k] = cx_sub(g[k], cx_mul(g[j], T2{lkj.x, -lkj.y}));
+        }
+      }
+    }
+  }
+  return ok;
+}
+
 __device__ __forceinline__ void tri_index(int o, int r, int& i, int& j) {
   i = 0;
   int rem = o;
@@ -242,7 +313,7 @@ __global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* 
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s);
 hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
-hipError_t launch_gram_work(const int2* unit_span, int2* items, DevState* st, hipStream_t s);
+hipError_t launch_gram_work(const int2* unit_span, int4* items, DevState* st, hipStream_t s);
 hipError_t launch_cnn_pack(const float* Wl, int cin, int cout, int kp, int kpb, float* Wf, float* Wb, hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, int batch, hipStream_t s);
 hipError_t launch_wgrad(const WgradArgs& a, int bands, int batch, int nparam_layer, float* g, float scale,
@@ -254,6 +325,7 @@ hipError_t launch_cnn_planes(const float2* X, long n, int q, double* partial, fl
 // mixed form, 1D Cartesian masks: which 0 forward, 1 adjoint + coil combine
 hipError_t launch_pdft(int which, int ny, const PdftArgs& a, int grid_x, int grid_y, hipStream_t s);
 int basis_txx(int N, int nx, int r);
+__global__ void k_coil_block(const float2* coils, float2* dst, int nx, int ny, int txx, long n, int nc);
 __global__ void k_build_yu(const float2* yh, const int2* pairs, const int32_t* mask, const int32_t* loc_ptr,
                            int n_loc, int width, int nc, int nx, int lmax, float2* yu, const DevState* st);
 __global__ void k_to_colmajor(const float2* src, int r, long n, float2* dst);

@@ -85,42 +85,61 @@ __device__ __forceinline__ void gram_lines_loop(const GramLinesArgs& a, int u, i
   const float ymask = pok ? 1.f : 0.f;
   const float* Wf = reinterpret_cast<const float*>(a.W);
   const float* Yline = reinterpret_cast<const float*>(a.yu);
-  for (int c = c0; c < c1; ++c) {
-    const float* wrow[TR];
-#pragma unroll
-    for (int t = 0; t < TR; ++t) wrow[t] = Wf + 2L * (((long)c * a.ua + u) * nx * r + wj[t]) + wim[t];
+  // one flat loop over (coil, block of 16*UN rows x); the next block's
+  // operands are loaded while the current one feeds the matrix cores
+  constexpr int XB = 16 * UN;
+  const int nxb = (nx + XB - 1) / XB;
+  const int niter = max(0, c1 - c0) * nxb;
+  T av[UN][TR], bv[UN];
+  auto load = [&](int c, int x0, T (&A)[UN][TR], T (&Bv)[UN]) {
     const float* yrow = Yline + 2L * (((long)c * np + pp) * nx) + yim;
-    for (int x0 = 0; x0 < nx; x0 += 16 * UN) {
-      T av[UN][TR], bv[UN];
+    const long wbase = 2L * (((long)c * a.ua + u) * nx * r);
 #pragma unroll
-      for (int q2 = 0; q2 < UN; ++q2) {
-        // always load (from a clamped, valid address) and scale by a 0/1 mask,
-        // so that no load sits under a branch
-        const int x = x0 + 16 * q2 + xl;
-        const float rm = (x < nx) ? 1.f : 0.f;
-        const int xc = min(x, nx - 1);
+    for (int q2 = 0; q2 < UN; ++q2) {
+      // always load (from a clamped, valid address) and scale by a 0/1 mask,
+      // so that no load sits under a branch
+      const int x = x0 + 16 * q2 + xl;
+      const float rm = (x < nx) ? 1.f : 0.f;
+      const int xc = min(x, nx - 1);
 #pragma unroll
-        for (int t = 0; t < TR; ++t) av[q2][t] = (T)(wrow[t][2L * r * xc] * (rm * wmask[t]));
-        bv[q2] = (T)(yrow[2 * xc] * (rm * ymask));
+      for (int t = 0; t < TR; ++t)
+        A[q2][t] = (T)(Wf[wbase + 2L * (r * xc + wj[t]) + wim[t]] * (rm * wmask[t]));
+      Bv[q2] = (T)(yrow[2 * xc] * (rm * ymask));
+    }
+  };
+  if (niter > 0) load(c0, 0, av, bv);
+  int cn = c0, xn = 0;
+  for (int it = 0; it < niter; ++it) {
+    T an[UN][TR], bn[UN];
+    xn += XB;
+    if (xn >= nx) {
+      xn = 0;
+      ++cn;
+    }
+    if (it + 1 < niter) load(cn, xn, an, bn);
+#pragma unroll
+    for (int q2 = 0; q2 < UN; ++q2) {
+      if constexpr (WP) {
+#pragma unroll
+        for (int i = 0; i < TR; ++i)
+#pragma unroll
+          for (int j = 0; j < TR; ++j) P[i][j] = M::mma(av[q2][i], av[q2][j], P[i][j]);
       }
 #pragma unroll
-      for (int q2 = 0; q2 < UN; ++q2) {
-        if constexpr (WP) {
+      for (int i = 0; i < TR; ++i) H[i] = M::mma(av[q2][i], bv[q2], H[i]);
+    }
 #pragma unroll
-          for (int i = 0; i < TR; ++i)
+    for (int q2 = 0; q2 < UN; ++q2) {
+      bv[q2] = bn[q2];
 #pragma unroll
-            for (int j = 0; j < TR; ++j) P[i][j] = M::mma(av[q2][i], av[q2][j], P[i][j]);
-        }
-#pragma unroll
-        for (int i = 0; i < TR; ++i) H[i] = M::mma(av[q2][i], bv[q2], H[i]);
-      }
+      for (int t = 0; t < TR; ++t) av[q2][t] = an[q2][t];
     }
   }
 }
 
 // the Gram kernel's work items (line u, sample tile t), one block of 1024
 // threads at setup: every sampled line contributes ceil(np_u / 8) items
-__global__ __launch_bounds__(1024) void k_gram_work(const int2* unit_span, int2* items, DevState* st) {
+__global__ __launch_bounds__(1024) void k_gram_work(const int2* unit_span, int4* items, DevState* st) {
   __shared__ int s_off[1024];
   const int tid = threadIdx.x, nu = st->n_units;
   int cnt = 0;
@@ -136,8 +155,9 @@ __global__ __launch_bounds__(1024) void k_gram_work(const int2* unit_span, int2*
   }
   int o = s_off[tid] - cnt;
   for (int u = tid * per; u < min(nu, (tid + 1) * per); ++u) {
-    const int nt = max(1, (unit_span[u].y + 7) / 8);
-    for (int t = 0; t < nt; ++t) items[o++] = make_int2(u, t);
+    const int2 sp = unit_span[u];
+    const int nt = max(1, (sp.y + 7) / 8);
+    for (int t = 0; t < nt; ++t) items[o++] = make_int4(u, t, sp.x, sp.y);
   }
   if (tid == 1023) st->n_gwork = s_off[1023];
 }
@@ -148,15 +168,17 @@ __global__ __launch_bounds__(256) void k_gram_lines_mma(GramLinesArgs a) {
   __shared__ T red[(TR * TR + TR) * 256];
   const int g = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the first item is requested together with the state (the list holds
+  // gridDim.x entries at least; one past the count is not used)
+  const int4 first = a.items[blockIdx.x];
   if (a.st->err || (a.check_halt && a.st->halt)) return;
   const int nwork = a.st->n_gwork;
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
   if (w > blockIdx.x) __syncthreads();  // the previous item's LDS reductions are complete
-  const int2 item = a.items[w];
+  const int4 item = (w == blockIdx.x) ? first : a.items[w];
   const int u = item.x, t = item.y;
   const int r = a.r, col = lane & 15;
-  const int2 span = a.unit_span[u];
-  const int p0 = span.x, np = span.y;
+  const int p0 = item.z, np = item.w;
   const int c0 = g * a.cg, c1 = min(a.nc, c0 + a.cg);
   // this lane's sample (B column) in tile t
   const int pl = 8 * t + (col & 7);
@@ -323,34 +345,35 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
   __shared__ T2 z[16];
   __shared__ double2 part[SOLVE_NT];
   __shared__ int s_mk[512], s_po[512];
-  __shared__ int bad;
   const int k = blockIdx.x, tid = threadIdx.x, r = a.r;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
-  if (tid == 0) bad = 0;
-  const int E = r * r + r;  // G entries then h entries
+  // requested before the state is read (valid addresses either way): the
+  // frame's sample count and, for lines, its line and pair indices over the
+  // whole padded width (entries past the frame's count are not used)
+  const int mk = a.m_k[k];
   if (a.kind == 0) {
-    // sum over coil groups and the frame's lines; thread = (entry, slice)
-    const int L = a.m_k[k] / a.nx;
-    for (int l = tid; l < L; l += SOLVE_NT) {
+    for (int l = tid; l < a.width; l += SOLVE_NT) {
       s_mk[l] = a.unit_of[(long)k * a.width + l];  // sampled line of (k, l)
       s_po[l] = a.pair_of[(long)k * a.width + l];
     }
+  }
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  const int E = r * r + r;  // G entries then h entries
+  if (a.kind == 0) {
+    // sum over coil groups and the frame's lines; thread = (entry, slice of lines)
+    const int L = mk / a.nx;
     __syncthreads();
     const int NS = max(1, SOLVE_NT / E), SW = SOLVE_NT / NS;
-    const int items = a.ngroups * L;
     for (int e0 = 0; e0 < E; e0 += SW) {
       const int e = e0 + tid % SW;
       const int sl = tid / SW;
       double2 s = make_double2(0.0, 0.0);
       if (e < E && sl < NS) {
+        const int items = a.ngroups * L;
 #pragma unroll 8
         for (int it = sl; it < items; it += NS) {
           const int gg = it / L, l = it - gg * L;
-          double2 v;
-          if (e < r * r)
-            v = a.P[((long)gg * a.ua + s_mk[l]) * r * r + e];
-          else
-            v = a.hp[((long)gg * a.npairs + s_po[l]) * r + (e - r * r)];
+          const double2 v = (e < r * r) ? a.P[((long)gg * a.ua + s_mk[l]) * r * r + e]
+                                        : a.hp[((long)gg * a.npairs + s_po[l]) * r + (e - r * r)];
           s = dadd(s, v);
         }
       }
@@ -377,60 +400,59 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
     }
   }
   __syncthreads();
-  // right-looking Cholesky G = L L^H (lower part of G overwritten by L)
+  // the factorization and the two triangular solves: one wave, rows in lanes
+  if (tid >= 64) return;
+  const int i = tid;
+  T2 g[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) g[m] = (i < r && m < r) ? G[i * 16 + m] : T2{(T)0, (T)0};
   double dmax = 0.0;
-  for (int i = 0; i < r; ++i) dmax = fmax(dmax, (double)G[i * 16 + i].x);
-  for (int j = 0; j < r; ++j) {
-    const double d = (double)G[j * 16 + j].x;
-    if (!(d > C::tiny * dmax) || !isfinite(d)) {
-      if (tid == 0) bad = 1;
-    }
-    __syncthreads();
-    if (bad) break;
-    const T ljj = (T)sqrt(d);
-    __syncthreads();
-    if (tid == 0) G[j * 16 + j] = T2{ljj, (T)0};
-    for (int i = j + 1 + tid; i < r; i += SOLVE_NT) G[i * 16 + j] = C::scale(G[i * 16 + j], (T)1 / ljj);
-    __syncthreads();
-    const int m = r - j - 1;
-    for (int e = tid; e < m * m; e += SOLVE_NT) {
-      const int i = j + 1 + e / m, c2 = j + 1 + e % m;
-      if (c2 <= i) {
-        const T2 lij = G[i * 16 + j], lcj = G[c2 * 16 + j];
-        G[i * 16 + c2] = C::sub(G[i * 16 + c2], C::mul(lij, T2{lcj.x, -lcj.y}));
-      }
-    }
-    __syncthreads();
-  }
-  if (bad) {
-    if (tid == 0) set_error(a.st, 4 /*ENOTPD*/, k);
+  for (int m = 0; m < r; ++m) dmax = fmax(dmax, (double)G[m * 16 + m].x);
+  if (!wave_chol<T, T2>(g, r, (T)(C::tiny * dmax))) {
+    if (i == 0) set_error(a.st, 4 /*ENOTPD*/, k);
     return;
   }
-  if (tid == 0) {
-    for (int i = 0; i < r; ++i) {  // L z = h
-      T2 s = h[i];
-      for (int m = 0; m < i; ++m) s = C::sub(s, C::mul(G[i * 16 + m], z[m]));
-      z[i] = C::scale(s, (T)1 / G[i * 16 + i].x);
+  // L y = h, then L^H b = y; lane i ends with b_i
+  T2 sv = (i < r) ? h[i] : T2{(T)0, (T)0};
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (j < r) {
+      const T2 yj = C::scale(lane_get(sv, j), (T)1 / lane_get(g[j].x, j));
+      if (i == j) sv = yj;
+      else if (i > j) sv = C::sub(sv, C::mul(g[j], yj));
     }
-    for (int i = r - 1; i >= 0; --i) {  // L^H b = z
-      T2 s = z[i];
-      for (int m = i + 1; m < r; ++m) s = C::sub(s, C::cjm(G[m * 16 + i], z[m]));
-      z[i] = C::scale(s, (T)1 / G[i * 16 + i].x);
+  }
+#pragma unroll
+  for (int j = 15; j >= 0; --j) {
+    if (j < r) {
+      const T2 bj = C::scale(lane_get(sv, j), (T)1 / lane_get(g[j].x, j));
+      if (i == j) sv = bj;
+#pragma unroll
+      for (int m = 0; m < j; ++m) {
+        const T2 ljm = lane_get(g[m], j);  // L[j][m]
+        if (i == m) sv = C::sub(sv, C::cjm(ljm, bj));
+      }
     }
-    double hb = 0.0;
-    bool fin = true;
-    for (int j = 0; j < r; ++j) {
-      hb += (double)h[j].x * (double)z[j].x + (double)h[j].y * (double)z[j].y;
-      fin = fin && isfinite((double)z[j].x) && isfinite((double)z[j].y);
-      a.B[(long)k * r + j] = make_float2((float)z[j].x, (float)z[j].y);
-    }
+  }
+  double hb = 0.0;
+  bool fin = true;
+  if (i < r) {
+    const T2 hi = h[i];
+    hb = (double)hi.x * (double)sv.x + (double)hi.y * (double)sv.y;
+    fin = isfinite((double)sv.x) && isfinite((double)sv.y);
+    a.B[(long)k * r + i] = make_float2((float)sv.x, (float)sv.y);
+    z[i] = sv;
+  }
+  hb = wave_sum(hb);
+  const bool allfin = __all(fin);
+  if (i == 0) {
     a.cost_k[k] = a.ysq_k[k] - hb;
-    if (!fin) set_error(a.st, 5 /*ENONFINITE*/, k);
+    if (!allfin) set_error(a.st, 5 /*ENONFINITE*/, k);
   }
   if (a.kind == 0) {  // conj(b_k) at each of the frame's pairs
-    __syncthreads();
-    const int L = a.m_k[k] / a.nx;
-    for (int e = tid; e < L * r; e += SOLVE_NT) {
+    wave_sync();
+    const int L = mk / a.nx;
+    for (int e = i; e < L * r; e += 64) {
       const int l = e / r, j = e - l * r;
       a.bcp[(long)s_po[l] * r + j] = make_float2((float)z[j].x, -(float)z[j].y);
     }
@@ -446,12 +468,12 @@ static void launch_lines_tr(const GramLinesArgs& a, int ny, int ngroups, int ht,
   // sample tiles; a grid-stride loop takes any remainder
   (void)ht;
   const dim3 g(ny + 64, ngroups);
-  if (a.nx >= 128) hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 8>), g, dim3(256), 0, s, a);
+  if (a.nx >= 128) hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 4>), g, dim3(256), 0, s, a);
   else if (a.nx >= 64) hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 4>), g, dim3(256), 0, s, a);
   else hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 1>), g, dim3(256), 0, s, a);
 }
 
-hipError_t launch_gram_work(const int2* unit_span, int2* items, DevState* st, hipStream_t s) {
+hipError_t launch_gram_work(const int2* unit_span, int4* items, DevState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_gram_work, dim3(1), dim3(1024), 0, s, unit_span, items, st);
   return hipGetLastError();
 }
@@ -507,61 +529,101 @@ template <typename T, int TRM>
 __global__ __launch_bounds__(256) void k_qr_gram_mma(GramColsArgs a) {
   using M = Mma<T>;
   constexpr int NT = TRM * (TRM + 1) / 2;
+  constexpr int RC = 64;  // rows per chunk staged in LDS
+  // row pitch of the staged real embedding: the 4 rows one MFMA step reads
+  // land in disjoint quarters of the 64 LDS banks
+  constexpr int LDX = (16 * TRM) % 64 == 0 || (16 * TRM) % 64 == 32 ? 16 * TRM + 16 : 16 * TRM;
+  constexpr int EM = RC * 8 * TRM / 256;  // complex elements per thread per chunk (m <= 8 TRM)
+  __shared__ T X[RC * LDX];
   __shared__ T red[NT * 256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kk = lane >> 4;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
-  const int m = a.m1 + a.m2;
-  // this lane's real columns, one per row tile
-  int srcB[TRM], cidx[TRM], im[TRM];
-  bool ok[TRM];
+  const int m1 = a.m1, m2 = a.m2, m = m1 + m2;
+  const long pa = (long)blockIdx.x * a.rows_per_block;
+  const long pb = min(a.n, pa + a.rows_per_block);
+  for (int e = tid; e < RC * LDX; e += 256) X[e] = (T)0;  // columns >= 2m stay zero
+  // this thread's elements of a chunk: e < RC*m1 from A, then RC*m2 from B,
+  // both contiguous in the pixel-major arrays
+  int erow[EM], ecol[EM];
 #pragma unroll
-  for (int t = 0; t < TRM; ++t) {
-    const int i = 16 * t + col;
-    ok[t] = i < 2 * m;
-    const int cc = (i < m) ? i : i - m;
-    im[t] = (i >= m);
-    srcB[t] = cc >= a.m1;
-    cidx[t] = srcB[t] ? cc - a.m1 : cc;
+  for (int q = 0; q < EM; ++q) {
+    const int e = tid + 256 * q;
+    if (e < RC * m1) {
+      erow[q] = e / m1;
+      ecol[q] = e - erow[q] * m1;
+    } else if (e < RC * m) {
+      const int f = e - RC * m1;
+      erow[q] = f / m2;
+      ecol[q] = m1 + (f - (f / m2) * m2);
+    } else {
+      erow[q] = RC;  // no element
+      ecol[q] = 0;
+    }
   }
+  float2 v[EM];
+  // load (and for B, sum over the partial arrays) the chunk at row p0
+  auto load = [&](long p0) {
+    float2 w[EM][4];
+#pragma unroll
+    for (int q = 0; q < EM; ++q) {
+      const long p = p0 + erow[q];
+      const bool ok = erow[q] < RC && p < pb;
+      const bool isb = ecol[q] >= m1;
+      const long off = isb ? p * m2 + (ecol[q] - m1) : p * m1 + ecol[q];
+      const float2* src = isb ? a.B : a.A;
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        w[q][g] = (ok && (g == 0 || (isb && g < a.nparts))) ? src[g * a.part_stride + off] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < EM; ++q) v[q] = cadd(cadd(w[q][0], w[q][1]), cadd(w[q][2], w[q][3]));
+    for (int g0 = 4; g0 < a.nparts; g0 += 4) {  // more than four partial arrays
+#pragma unroll
+      for (int q = 0; q < EM; ++q) {
+        const long p = p0 + erow[q];
+        if (erow[q] < RC && p < pb && ecol[q] >= m1) {
+          const long off = p * m2 + (ecol[q] - m1);
+#pragma unroll
+          for (int g = 0; g < 4; ++g)
+            if (g0 + g < a.nparts) v[q] = cadd(v[q], a.B[(g0 + g) * a.part_stride + off]);
+        }
+      }
+    }
+  };
   typename M::V acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = M::zero();
-  const long pa = (long)blockIdx.x * a.rows_per_block;
-  const long pb = min(a.n, pa + a.rows_per_block);
-  constexpr int UN = sizeof(T) == 4 ? 8 : 4;
-  for (long p00 = pa + 4 * wave; p00 < pb; p00 += 16 * UN) {
-    T v[UN][TRM];
+  if (pa < pb) load(pa);
+  // the state is read once the first chunk's loads are in flight
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  for (long p0 = pa; p0 < pb; p0 += RC) {
+    __syncthreads();  // the previous chunk's MFMA reads of X are done
 #pragma unroll
-    for (int q2 = 0; q2 < UN; ++q2) {
-      const long p = p00 + 16 * q2 + kk;
-      const bool rv = p < pb;
-#pragma unroll
-      for (int t = 0; t < TRM; ++t) {
-        float x = 0.f;
-        if (rv && ok[t]) {
-          if (!srcB[t]) {
-            x = reinterpret_cast<const float*>(a.A + p * (long)a.m1 + cidx[t])[im[t]];  // pixel-major
-          } else {
-            const long off = p * (long)a.m2 + cidx[t];   // B is pixel-major [p][j]
-            float2 s2 = a.B[off];
-            for (int g = 1; g < a.nparts; ++g) s2 = cadd(s2, a.B[g * a.part_stride + off]);
-            x = im[t] ? s2.y : s2.x;
-            if (a.write_sum && a.nparts > 1) reinterpret_cast<float*>(const_cast<float2*>(a.B) + off)[im[t]] = x;
-          }
-        }
-        v[q2][t] = (T)x;
+    for (int q = 0; q < EM; ++q) {
+      if (erow[q] < RC) {
+        const long p = p0 + erow[q];
+        X[erow[q] * LDX + ecol[q]] = (T)v[q].x;
+        X[erow[q] * LDX + m + ecol[q]] = (T)v[q].y;
+        if (a.write_sum && a.nparts > 1 && ecol[q] >= m1 && p < pb)
+          const_cast<float2*>(a.B)[p * m2 + (ecol[q] - m1)] = v[q];
       }
     }
+    __syncthreads();
+    if (p0 + RC < pb) load(p0 + RC);  // in flight during this chunk's MFMAs
 #pragma unroll
-    for (int q2 = 0; q2 < UN; ++q2)
+    for (int st = 0; st < 4; ++st) {
+      const T* xr = X + (16 * wave + 4 * st + kk) * LDX + col;
+      T xv[TRM];
+#pragma unroll
+      for (int t = 0; t < TRM; ++t) xv[t] = xr[16 * t];
 #pragma unroll
       for (int i = 0; i < TRM; ++i)
 #pragma unroll
         for (int j = i; j < TRM; ++j) {
           const int ti = i * TRM - i * (i - 1) / 2 + (j - i);
-          acc[ti] = M::mma(v[q2][i], v[q2][j], acc[ti]);
+          acc[ti] = M::mma(xv[i], xv[j], acc[ti]);
         }
+    }
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) tile_reduce<T>(red + t * 256, acc[t], wave, lane);
