@@ -61,7 +61,7 @@ struct altgdmin_ctx {
   int bound = 0, initialized = 0;
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
-      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rinv, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
+      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rfac, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
       o_fcmp, o_planes, o_gwork, o_coilb, o_end;
   size_t T_bytes;
   // timing
@@ -132,7 +132,7 @@ void carve(altgdmin_ctx* c) {
   const int m_iter = 2 * r;
   const size_t qo = (size_t)std::max(m_iter * (m_iter + 1) / 2, q * (q + 1) / 2);
   c->o_qpart = take(sizeof(double2) * qo * c->qr_nblk);
-  c->o_rinv = take(sizeof(float2) * r * r);
+  c->o_rfac = take(sizeof(float2) * r * r);
   c->o_Vs = take(sizeof(float2) * (size_t)q * r);
   c->o_V = take(sizeof(double2) * 2 * (size_t)q * q);
   // temp: X0 plus the truncated hybrid data (LINES) or a chunk of coil images (INDEX)
@@ -345,14 +345,14 @@ hipError_t cholqr(altgdmin_ctx* c, float2* U) {
   qa.mode = 1;
   qa.n = c->n;
   qa.q = p.q;
-  qa.rinv = c->at<float2>(c->o_rinv);
+  qa.rfac = c->at<float2>(c->o_rfac);
   qa.st = c->st();
   e = launch_qr_small(qa, c->stream);
   if (e != hipSuccess) return e;
   ApplyArgs aa{};
   aa.U = U;
   aa.Ui = c->at<float2>(c->o_Ui);
-  aa.rinv = c->at<float2>(c->o_rinv);
+  aa.rfac = c->at<float2>(c->o_rfac);
   aa.n = c->n;
   aa.r = p.r;
   aa.mode = 1;
@@ -440,6 +440,7 @@ hipError_t qr_step_small(altgdmin_ctx* c, int mode, int check_halt) {
   if (e != hipSuccess) return e;
   QrSmallArgs qa{};
   qa.part = c->at<double2>(c->o_qpart);
+  qa.part_f32 = !c->fp64;
   qa.nblk = c->qr_nblk;
   qa.r = p.r;
   qa.mode = mode;
@@ -451,7 +452,7 @@ hipError_t qr_step_small(altgdmin_ctx* c, int mode, int check_halt) {
   qa.guard = 1e-6;  // FP32 gradient: below this it is rounding noise
   qa.B = c->at<float2>(c->o_B);
   qa.cost_k = c->at<double>(c->o_cost);
-  qa.rinv = c->at<float2>(c->o_rinv);
+  qa.rfac = c->at<float2>(c->o_rfac);
   qa.st = c->st();
   qa.check_halt = check_halt;
   tmark(c, TK_QRSMALL);
@@ -470,7 +471,7 @@ hipError_t one_iteration(altgdmin_ctx* c, float2* U, float2* U_prev) {
   aa.U = U;
   aa.Ui = c->at<float2>(c->o_Ui);
   aa.G = c->at<float2>(c->o_G);
-  aa.rinv = c->at<float2>(c->o_rinv);
+  aa.rfac = c->at<float2>(c->o_rfac);
   aa.U_prev = U_prev;
   aa.n = c->n;
   aa.r = p.r;
@@ -605,9 +606,9 @@ altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** ou
     c->adj_cgs = (p.nc + parts - 1) / parts;
     c->adj_parts = (p.nc + c->adj_cgs - 1) / c->adj_cgs;
   }
-  c->qr_nblk = std::max(1, std::min(256, c->n / 256));
+  c->qr_nblk = std::max(1, std::min(128, c->n / 512));
   c->qr_rows = ((long)c->n + c->qr_nblk - 1) / c->qr_nblk;
-  c->qr_rows = (c->qr_rows + 63) / 64 * 64;
+  c->qr_rows = (c->qr_rows + 127) / 128 * 128;
   c->qr_nblk = (int)((c->n + c->qr_rows - 1) / c->qr_rows);
   c->kc = std::min(p.q, 16);
   carve(c);

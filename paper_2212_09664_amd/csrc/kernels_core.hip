@@ -484,18 +484,13 @@ __device__ bool chol_lower(double2* M, int r) {
   return true;
 }
 
-// Rinv = (L^H)^{-1}, upper triangular, one column per thread (threads < r).
-__device__ void rinv_columns(const double2* L, int r, double2* Ri) {
-  const int j = threadIdx.x;
-  if (j >= r) return;
-  for (int i = j + 1; i < r; ++i) Ri[i * 16 + j] = make_double2(0.0, 0.0);
-  Ri[j * 16 + j] = make_double2(1.0 / L[j * 16 + j].x, 0.0);
-  for (int i = j - 1; i >= 0; --i) {
-    // R[i][m] = conj(L[m][i]); Rinv[i][j] = -(sum_{m=i+1..j} R[i][m] Rinv[m][j]) / R[i][i]
-    double2 s = make_double2(0.0, 0.0);
-    for (int m = i + 1; m <= j; ++m) s = dadd(s, dmul(dconj(L[m * 16 + i]), Ri[m * 16 + j]));
-    Ri[i * 16 + j] = make_double2(-s.x / L[i * 16 + i].x, -s.y / L[i * 16 + i].x);
-  }
+// entry e = (i, j) of R = L^H with the reciprocal on the diagonal, from the
+// lower Cholesky factor L (LDS, ld 16): the form the update kernel solves with
+__device__ __forceinline__ float2 rfac_entry(const double2* L, int r, int e) {
+  const int i = e / r, j = e - (e / r) * r;
+  if (i < j) return make_float2((float)L[j * 16 + i].x, -(float)L[j * 16 + i].y);
+  if (i == j) return make_float2((float)(1.0 / L[i * 16 + i].x), 0.f);
+  return make_float2(0.f, 0.f);
 }
 
 // ===========================================================================
@@ -505,8 +500,9 @@ __device__ void rinv_columns(const double2* L, int r, double2* Ri) {
 // from the blocks; R = chol(.)^H, R^{-1}; SD(U, U+) from r x r data.
 // mode 1: plain CholeskyQR of U (no gradient).
 // ===========================================================================
+template <int RT>
 __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
-  __shared__ double2 UU[256], UG[256], GG[256], Gh[256], Ri[256], Tm[256];
+  __shared__ double2 UU[256], UG[256], GG[256], Gh[256], Tm[256];
   __shared__ JacobiScratch js;
   __shared__ int s_ok;
   const int tid = threadIdx.x, r = a.r;
@@ -526,8 +522,14 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
     const int o = o0 + tid % OW, sl = tid / OW;
     double2 s = make_double2(0.0, 0.0);
     if (o < nout && sl < NS) {
+      if (a.part_f32) {
+        const float2* pf = reinterpret_cast<const float2*>(a.part);
 #pragma unroll 8
-      for (int b = sl; b < a.nblk; b += NS) s = dadd(s, a.part[(long)b * nout + o]);
+        for (int b = sl; b < a.nblk; b += NS) s = dadd(s, f2d(pf[(long)b * nout + o]));
+      } else {
+#pragma unroll 8
+        for (int b = sl; b < a.nblk; b += NS) s = dadd(s, a.part[(long)b * nout + o]);
+      }
     }
     red2[tid] = s;
     __syncthreads();
@@ -569,9 +571,7 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
       if (tid == 0) set_error(st, 4, -1);
       return;
     }
-    rinv_columns(Gh, r, Ri);
-    __syncthreads();
-    for (int e = tid; e < r * r; e += blockDim.x) a.rinv[e] = d2f(Ri[(e / r) * 16 + (e % r)]);
+    for (int e = tid; e < r * r; e += blockDim.x) a.rfac[e] = rfac_entry(Gh, r, e);
     return;
   }
   // first iteration: step size from the spectral norm of grad
@@ -631,12 +631,13 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
     const double2 v = UU[a_ * 16 + b_], g = GG[a_ * 16 + b_];
     return make_double2(v.x - eta * (ug.x + gu.x) + eta * eta * g.x, v.y - eta * (ug.y + gu.y) + eta * eta * g.y);
   };
-  double2 g[16];
+  double2 g[RT];  // padded to RT with the identity
 #pragma unroll
-  for (int m = 0; m < 16; ++m) g[m] = (i < r && m < r) ? gh(i, m) : make_double2(0.0, 0.0);
-  double dmax = 0.0;
-  for (int m = 0; m < r; ++m) dmax = fmax(dmax, gh(m, m).x);
-  if (!wave_chol<double, double2>(g, r, 1e-14 * dmax)) {
+  for (int m = 0; m < RT; ++m) g[m] = (i < r && m < r) ? gh(i, m) : make_double2(i == m ? 1.0 : 0.0, 0.0);
+  double dmax = (i < r) ? gh(i, i).x : 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
+  if (!wave_chol<double, double2, RT>(g, r, 1e-14 * dmax)) {
     if (i == 0) {
       set_error(st, 4, -1);
       st->step_ok = 0;
@@ -644,25 +645,28 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
     return;
   }
 #pragma unroll
-  for (int m = 0; m < 16; ++m)
-    if (i < r && m <= i) Gh[i * 16 + m] = g[m];
+  for (int m = 0; m < RT; ++m)
+    if (i < RT && m <= i) Gh[i * 16 + m] = g[m];
   wave_sync();
-  rinv_columns(Gh, r, Ri);
-  wave_sync();
-  // U^H U+ = (U^H U - eta U^H G) Rinv; SD^2 = r - ||U^H U+||_F^2
+  // U^H U+ = (U^H U - eta U^H G) R^{-1}: lane i solves x R = row i by forward
+  // substitution (R = L^H); SD^2 = r - ||U^H U+||_F^2
   double fro = 0.0;
-  for (int e = i; e < r * r; e += 64) {
-    const int i2 = e / r, j = e % r;
-    a.rinv[e] = d2f(Ri[i2 * 16 + j]);
-    double2 sacc = make_double2(0.0, 0.0);
-    for (int mm = 0; mm <= j; ++mm) {
-      const double2 lhs = make_double2(UU[i2 * 16 + mm].x - eta * UG[i2 * 16 + mm].x,
-                                       UU[i2 * 16 + mm].y - eta * UG[i2 * 16 + mm].y);
-      sacc = dadd(sacc, dmul(lhs, Ri[mm * 16 + j]));
+  if (i < r) {
+    double2 x[RT];
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+      double2 acc = (j < r) ? make_double2(UU[i * 16 + j].x - eta * UG[i * 16 + j].x,
+                                           UU[i * 16 + j].y - eta * UG[i * 16 + j].y)
+                            : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < j; ++k) acc = dsub(acc, dmul(x[k], dconj(Gh[j * 16 + k])));  // R[k][j] = conj(L[j][k])
+      const double rd = 1.0 / Gh[j * 16 + j].x;
+      x[j] = make_double2(acc.x * rd, acc.y * rd);
+      fro += x[j].x * x[j].x + x[j].y * x[j].y;
     }
-    fro += sacc.x * sacc.x + sacc.y * sacc.y;
   }
   fro = wave_sum(fro);
+  for (int e = i; e < r * r; e += 64) a.rfac[e] = rfac_entry(Gh, r, e);
   double fv = 0.0;  // f = sum_k cost_k
   for (int k = i; k < a.q; k += 64) fv += a.cost_k[k];
   fv = wave_sum(fv);
@@ -699,7 +703,7 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
     u0[i] = (i < r) ? a.U[(long)i * a.n + pc] : make_float2(0.f, 0.f);
     g0[i] = (i < r && a.mode == 0) ? a.G[pc * r + i] : make_float2(0.f, 0.f);  // gradient is pixel-major
   }
-  for (int e = tid; e < r * r; e += AG_NT) Ri[(e / r) * RT + (e % r)] = a.rinv[e];
+  for (int e = tid; e < r * r; e += AG_NT) Ri[(e / r) * RT + (e % r)] = a.rfac[e];
   if (a.mode == 0 && !a.st->step_ok) return;
   if (a.st->err) return;
   __syncthreads();
@@ -715,14 +719,18 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
       uh[i] = make_float2(0.f, 0.f);
     }
   }
+  // U+ R = Uhat, row by row: forward substitution (the diagonal holds 1 / R_jj)
+  float2 un[RT];
 #pragma unroll
   for (int j = 0; j < RT; ++j) {
+    un[j] = make_float2(0.f, 0.f);
     if (j < r) {
-      float2 s = make_float2(0.f, 0.f);
+      float2 s = uh[j];
 #pragma unroll
-      for (int i = 0; i <= j; ++i) s = cadd(s, cmul(uh[i], Ri[i * RT + j]));
-      a.U[(long)j * a.n + p] = s;
-      if (a.Ui) a.Ui[p * r + j] = s;
+      for (int i = 0; i < j; ++i) s = csub(s, cmul(un[i], Ri[i * RT + j]));
+      un[j] = cscale(s, Ri[j * RT + j].x);
+      a.U[(long)j * a.n + p] = un[j];
+      if (a.Ui) a.Ui[p * r + j] = un[j];
     }
   }
 }
@@ -854,7 +862,8 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_qr_small, dim3(1), dim3(1024), 0, s, a);
+  if (a.r <= 8) hipLaunchKernelGGL(k_qr_small<8>, dim3(1), dim3(1024), 0, s, a);
+  else hipLaunchKernelGGL(k_qr_small<16>, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 
 #define GRAM_OPT 2    // outputs per thread in the per-line Gram kernels
 #define SOLVE_NT 1024  // threads of the per-frame solve
+#define QR_NSM 2       // QR Gram: streams of 4 waves per workgroup
 #define GCOLS_OPT 9   // outputs per thread in the column-Gram kernel (m <= 128)
 #define GCOLS_NT 1024
 
@@ -160,19 +161,20 @@ struct GramColsArgs {
   int nparts;            // B is the sum of nparts arrays at stride part_stride
   long part_stride;
   int write_sum;         // store the summed B back into part 0
-  double2* part;         // per workgroup: its partial Gram
+  double2* part;         // per workgroup: its partial Gram (the QR Gram of FP32 MFMA stores float2 pairs)
   DevState* st;
   int check_halt;
 };
 
 struct QrSmallArgs {
-  const double2* part;
+  const double2* part;   // per QR Gram workgroup: its partial (FP32 pairs when part_f32)
+  int part_f32;
   int nblk, r, mode, n, q;
   double eta_c, eta_cap_c, eps_exit;
   double guard;          // stationary start: ||grad_0||_2 <= guard * sum_k ||y_k||^2
   const float2* B;
   const double* cost_k;
-  float2* rinv;
+  float2* rfac;          // R = L^H (Uhat^H Uhat = L L^H), row-major r x r, upper, 1 / R_jj on the diagonal
   DevState* st;
   int check_halt;
 };
@@ -181,7 +183,7 @@ struct ApplyArgs {
   float2* U;             // n x r column-major (C ABI layout)
   float2* Ui;            // n x r pixel-major copy for the next iteration (may be null)
   const float2* G;       // pixel-major gradient
-  const float2* rinv;
+  const float2* rfac;    // R as written by the small QR step
   float2* U_prev;
   long n;
   int r, mode;
@@ -242,33 +244,40 @@ __device__ __forceinline__ double2 cx_sub(double2 a, double2 b) { return dsub(a,
 __device__ __forceinline__ float2 cx_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ double2 cx_scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
-// Cholesky G = L L^H of a Hermitian positive definite r x r matrix (r <= 16)
-// by one wave: lane i < r holds row i of G in g[0..15] on entry and row i of
-// L (entries 0..i) on return.  False if a pivot is not above tol (all lanes
-// agree).  Right-looking; column j of L is broadcast from lanes j+1..r-1.
-template <typename T, typename T2>
-__device__ __forceinline__ bool wave_chol(T2 (&g)[16], int r, T tol) {
+// reciprocal square root: the hardware estimate, refined by Newton steps in FP64
+__device__ __forceinline__ float cx_rsqrt(float d) { return rsqrtf(d); }
+__device__ __forceinline__ double cx_rsqrt(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  return y;
+}
+
+// Cholesky G = L L^H of a Hermitian positive definite RT x RT matrix by one
+// wave: lane i < RT holds row i of G in g[0..RT-1] on entry and row i of L
+// (entries 0..i) on return.  A problem of size r < RT is padded with the
+// identity (rows and columns r..RT-1), so the code is straight-line and
+// short.  False if a pivot of the r x r problem is not above tol (all lanes
+// agree).
+template <typename T, typename T2, int RT>
+__device__ __forceinline__ bool wave_chol(T2 (&g)[RT], int r, T tol) {
   const int i = threadIdx.x & 63;
   bool ok = true;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {  // fixed trip counts: g stays in registers
-    if (j < r && ok) {
-      const T d = lane_get(g[j].x, j);
-      ok = (d > tol) && isfinite((double)d);
-      const T ljj = sqrt(ok ? d : (T)1), inv = (T)1 / ljj;
-      if (i == j) {
-        g[j].x = ljj;
-        g[j].y = (T)0;
-      } else if (i > j) {
-        g[j] = cx_scale(g[j], inv);
-      }
+  for (int j = 0; j < RT; ++j) {
+    const T d = lane_get(g[j].x, j);
+    ok = ok && (j >= r || ((d > tol) && isfinite((double)d)));  // padding pivots are 1
+    const T inv = cx_rsqrt(d > (T)0 ? d : (T)1), ljj = (d > (T)0 ? d : (T)1) * inv;
+    if (i == j) {
+      g[j].x = ljj;
+      g[j].y = (T)0;
+    } else if (i > j) {
+      g[j] = cx_scale(g[j], inv);
+    }
 #pragma unroll
-      for (int k = j + 1; k < 16; ++k) {
-        if (k < r) {
-          const T2 lkj = lane_get(g[j], k);
-          if (i >= k) g[k] = cx_sub(g[k], cx_mul(g[j], T2{lkj.x, -lkj.y}));
-        }
-      }
+    for (int k = j + 1; k < RT; ++k) {
+      const T2 lkj = lane_get(g[j], k);
+      if (i >= k) g[k] = cx_sub(g[k], cx_mul(g[j], T2{lkj.x, -lkj.y}));
     }
   }
   return ok;

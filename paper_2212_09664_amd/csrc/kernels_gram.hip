@@ -42,6 +42,21 @@ struct Mma<double> {
 // B[l/16][l%16].  The accumulator differs: register v of lane l holds
 // D[4*(l/16) + v][l%16] for f32 and D[4*v + l/16][l%16] for f64.
 
+// Sum the NW waves' tile (one 16x16 accumulator per wave) into LDS buffer t.
+template <typename T, int NW>
+__device__ __forceinline__ void tile_reduce_n(T* t, const typename Mma<T>::V& acc, int wave, int lane) {
+  for (int w = 0; w < NW; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int idx = Mma<T>::row(lane, v) * 16 + (lane & 15);
+        t[idx] = (w == 0) ? acc[v] : t[idx] + acc[v];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Sum the 4 waves' tile (one 16x16 accumulator per wave) into LDS buffer t.
 template <typename T>
 __device__ __forceinline__ void tile_reduce(T* t, const typename Mma<T>::V& acc, int wave, int lane) {
@@ -336,7 +351,7 @@ struct Cx<double> {
   static constexpr double tiny = 1e-12;
 };
 
-template <typename T>
+template <typename T, int RT>
 __global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
   using C = Cx<T>;
   using T2 = typename C::T2;
@@ -400,38 +415,36 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
     }
   }
   __syncthreads();
-  // the factorization and the two triangular solves: one wave, rows in lanes
+  // the factorization and the two triangular solves: one wave, rows in lanes,
+  // padded to RT with the identity
   if (tid >= 64) return;
   const int i = tid;
-  T2 g[16];
+  T2 g[RT];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) g[m] = (i < r && m < r) ? G[i * 16 + m] : T2{(T)0, (T)0};
+  for (int m = 0; m < RT; ++m)
+    g[m] = (i < r && m < r) ? G[i * 16 + m] : T2{(T)(i == m ? 1 : 0), (T)0};
   double dmax = 0.0;
   for (int m = 0; m < r; ++m) dmax = fmax(dmax, (double)G[m * 16 + m].x);
-  if (!wave_chol<T, T2>(g, r, (T)(C::tiny * dmax))) {
+  if (!wave_chol<T, T2, RT>(g, r, (T)(C::tiny * dmax))) {
     if (i == 0) set_error(a.st, 4 /*ENOTPD*/, k);
     return;
   }
   // L y = h, then L^H b = y; lane i ends with b_i
   T2 sv = (i < r) ? h[i] : T2{(T)0, (T)0};
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    if (j < r) {
-      const T2 yj = C::scale(lane_get(sv, j), (T)1 / lane_get(g[j].x, j));
-      if (i == j) sv = yj;
-      else if (i > j) sv = C::sub(sv, C::mul(g[j], yj));
-    }
+  for (int j = 0; j < RT; ++j) {
+    const T2 yj = C::scale(lane_get(sv, j), (T)1 / lane_get(g[j].x, j));
+    if (i == j) sv = yj;
+    else if (i > j) sv = C::sub(sv, C::mul(g[j], yj));
   }
 #pragma unroll
-  for (int j = 15; j >= 0; --j) {
-    if (j < r) {
-      const T2 bj = C::scale(lane_get(sv, j), (T)1 / lane_get(g[j].x, j));
-      if (i == j) sv = bj;
+  for (int j = RT - 1; j >= 0; --j) {
+    const T2 bj = C::scale(lane_get(sv, j), (T)1 / lane_get(g[j].x, j));
+    if (i == j) sv = bj;
 #pragma unroll
-      for (int m = 0; m < j; ++m) {
-        const T2 ljm = lane_get(g[m], j);  // L[j][m]
-        if (i == m) sv = C::sub(sv, C::cjm(ljm, bj));
-      }
+    for (int m = 0; m < j; ++m) {
+      const T2 ljm = lane_get(g[m], j);  // L[j][m]
+      if (i == m) sv = C::sub(sv, C::cjm(ljm, bj));
     }
   }
   double hb = 0.0;
@@ -507,9 +520,11 @@ hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp
 
 hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s) {
   if (fp64)
-    hipLaunchKernelGGL(k_solve<double>, dim3(q), dim3(SOLVE_NT), 0, s, a);
+    if (a.r <= 8) hipLaunchKernelGGL((k_solve<double, 8>), dim3(q), dim3(SOLVE_NT), 0, s, a);
+    else hipLaunchKernelGGL((k_solve<double, 16>), dim3(q), dim3(SOLVE_NT), 0, s, a);
   else
-    hipLaunchKernelGGL(k_solve<float>, dim3(q), dim3(SOLVE_NT), 0, s, a);
+    if (a.r <= 8) hipLaunchKernelGGL((k_solve<float, 8>), dim3(q), dim3(SOLVE_NT), 0, s, a);
+    else hipLaunchKernelGGL((k_solve<float, 16>), dim3(q), dim3(SOLVE_NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -525,8 +540,8 @@ namespace ag {
 // Output: per block, the upper triangle (i <= j, tri order) of the complex
 // m x m Gram, FP64.
 // ===========================================================================
-template <typename T, int TRM>
-__global__ __launch_bounds__(256) void k_qr_gram_mma(GramColsArgs a) {
+template <typename T, int TRM, int NSM>
+__global__ __launch_bounds__(256 * NSM) void k_qr_gram_mma(GramColsArgs a) {
   using M = Mma<T>;
   constexpr int NT = TRM * (TRM + 1) / 2;
   constexpr int RC = 64;  // rows per chunk staged in LDS
@@ -534,20 +549,22 @@ __global__ __launch_bounds__(256) void k_qr_gram_mma(GramColsArgs a) {
   // land in disjoint quarters of the 64 LDS banks
   constexpr int LDX = (16 * TRM) % 64 == 0 || (16 * TRM) % 64 == 32 ? 16 * TRM + 16 : 16 * TRM;
   constexpr int EM = RC * 8 * TRM / 256;  // complex elements per thread per chunk (m <= 8 TRM)
-  __shared__ T X[RC * LDX];
+  // NSM streams of 4 waves each take interleaved chunks of the block's rows
+  __shared__ T X[NSM][RC * LDX];
   __shared__ T red[NT * 256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sm = wave >> 2, wl = wave & 3, lt = tid & 255;  // stream, its wave, its thread
   const int col = lane & 15, kk = lane >> 4;
   const int m1 = a.m1, m2 = a.m2, m = m1 + m2;
   const long pa = (long)blockIdx.x * a.rows_per_block;
   const long pb = min(a.n, pa + a.rows_per_block);
-  for (int e = tid; e < RC * LDX; e += 256) X[e] = (T)0;  // columns >= 2m stay zero
+  for (int e = tid; e < NSM * RC * LDX; e += 256 * NSM) (&X[0][0])[e] = (T)0;  // columns >= 2m stay zero
   // this thread's elements of a chunk: e < RC*m1 from A, then RC*m2 from B,
   // both contiguous in the pixel-major arrays
   int erow[EM], ecol[EM];
 #pragma unroll
   for (int q = 0; q < EM; ++q) {
-    const int e = tid + 256 * q;
+    const int e = lt + 256 * q;
     if (e < RC * m1) {
       erow[q] = e / m1;
       ecol[q] = e - erow[q] * m1;
@@ -561,7 +578,8 @@ __global__ __launch_bounds__(256) void k_qr_gram_mma(GramColsArgs a) {
     }
   }
   float2 v[EM];
-  // load (and for B, sum over the partial arrays) the chunk at row p0
+  // load (and for B, sum over the partial arrays) the chunk at row p0; rows
+  // at or past pb read as zero
   auto load = [&](long p0) {
     float2 w[EM][4];
 #pragma unroll
@@ -593,26 +611,29 @@ __global__ __launch_bounds__(256) void k_qr_gram_mma(GramColsArgs a) {
   typename M::V acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = M::zero();
-  if (pa < pb) load(pa);
+  load(pa + sm * RC);
   // the state is read once the first chunk's loads are in flight
   if (a.st->err || (a.check_halt && a.st->halt)) return;
-  for (long p0 = pa; p0 < pb; p0 += RC) {
+  // every workgroup-wide step runs the same number of times in both streams
+  for (long base = pa; base < pb; base += NSM * RC) {
+    const long p0 = base + sm * RC;
     __syncthreads();  // the previous chunk's MFMA reads of X are done
+    T* Xs = X[sm];
 #pragma unroll
     for (int q = 0; q < EM; ++q) {
       if (erow[q] < RC) {
         const long p = p0 + erow[q];
-        X[erow[q] * LDX + ecol[q]] = (T)v[q].x;
-        X[erow[q] * LDX + m + ecol[q]] = (T)v[q].y;
+        Xs[erow[q] * LDX + ecol[q]] = (T)v[q].x;
+        Xs[erow[q] * LDX + m + ecol[q]] = (T)v[q].y;
         if (a.write_sum && a.nparts > 1 && ecol[q] >= m1 && p < pb)
           const_cast<float2*>(a.B)[p * m2 + (ecol[q] - m1)] = v[q];
       }
     }
     __syncthreads();
-    if (p0 + RC < pb) load(p0 + RC);  // in flight during this chunk's MFMAs
+    if (base + NSM * RC < pb) load(p0 + NSM * RC);  // in flight during this chunk's MFMAs
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
-      const T* xr = X + (16 * wave + 4 * st + kk) * LDX + col;
+      const T* xr = Xs + (16 * wl + 4 * st + kk) * LDX + col;
       T xv[TRM];
 #pragma unroll
       for (int t = 0; t < TRM; ++t) xv[t] = xr[16 * t];
@@ -626,7 +647,7 @@ __global__ __launch_bounds__(256) void k_qr_gram_mma(GramColsArgs a) {
     }
   }
 #pragma unroll
-  for (int t = 0; t < NT; ++t) tile_reduce<T>(red + t * 256, acc[t], wave, lane);
+  for (int t = 0; t < NT; ++t) tile_reduce_n<T, 4 * NSM>(red + t * 256, acc[t], wave, lane);
   // C(i, j) of the real 2m x 2m Gram from the upper tiles
   auto C = [&](int i, int j) -> double {
     if (i > j) {
@@ -639,12 +660,15 @@ __global__ __launch_bounds__(256) void k_qr_gram_mma(GramColsArgs a) {
     return (double)red[ti * 256 + (i % 16) * 16 + (j % 16)];
   };
   const int nout = m * (m + 1) / 2;
-  for (int o = tid; o < nout; o += 256) {
+  for (int o = tid; o < nout; o += 256 * NSM) {
     int i, j;
     tri_index(o, m, i, j);
     const double re = C(i, j) + C(m + i, m + j);
     const double imv = C(i, m + j) - C(m + i, j);
-    a.part[(long)blockIdx.x * nout + o] = make_double2(re, imv);
+    if constexpr (sizeof(T) == 4)  // an FP32 Gram's partials carry FP32 information
+      reinterpret_cast<float2*>(a.part)[(long)blockIdx.x * nout + o] = make_float2((float)re, (float)imv);
+    else
+      a.part[(long)blockIdx.x * nout + o] = make_double2(re, imv);
   }
 }
 
@@ -653,17 +677,17 @@ hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_
   const dim3 g(nblk);
   if (fp64) {
     switch (trm) {
-      case 1: hipLaunchKernelGGL((k_qr_gram_mma<double, 1>), g, dim3(256), 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_qr_gram_mma<double, 2>), g, dim3(256), 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_qr_gram_mma<double, 3>), g, dim3(256), 0, s, a); break;
-      default: hipLaunchKernelGGL((k_qr_gram_mma<double, 4>), g, dim3(256), 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_qr_gram_mma<double, 1, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_qr_gram_mma<double, 2, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_qr_gram_mma<double, 3, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_qr_gram_mma<double, 4, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
     }
   } else {
     switch (trm) {
-      case 1: hipLaunchKernelGGL((k_qr_gram_mma<float, 1>), g, dim3(256), 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_qr_gram_mma<float, 2>), g, dim3(256), 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_qr_gram_mma<float, 3>), g, dim3(256), 0, s, a); break;
-      default: hipLaunchKernelGGL((k_qr_gram_mma<float, 4>), g, dim3(256), 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_qr_gram_mma<float, 1, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_qr_gram_mma<float, 2, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_qr_gram_mma<float, 3, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_qr_gram_mma<float, 4, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
     }
   }
   return hipGetLastError();
