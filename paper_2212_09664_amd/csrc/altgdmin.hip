@@ -62,7 +62,7 @@ struct altgdmin_ctx {
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
       o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rfac, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
-      o_fcmp, o_planes, o_gwork, o_coilb, o_end;
+      o_fcmp, o_planes, o_gwork, o_coilb, o_yg, o_end;
   size_t T_bytes;
   // timing
   int timed = TK_NONE;
@@ -81,6 +81,11 @@ namespace {
     hipError_t _e = (x);                     \
     if (_e != hipSuccess) return ALTGDMIN_EHIP; \
   } while (0)
+
+// sum over lines of ceil(pairs / 8) <= (pairs + 7 lines) / 8, pairs <= q * width
+long gram_items_bound(const altgdmin_ctx* c) {
+  return ((long)c->p.q * c->width + 7L * c->n_loc) / 8 + 1;
+}
 
 void carve(altgdmin_ctx* c) {
   const altgdmin_params& p = c->p;
@@ -108,6 +113,7 @@ void carve(altgdmin_ctx* c) {
   c->o_gwork = take(sizeof(int4) * ((size_t)c->n_loc * ((q + 7) / 8) + (c->lines ? p.ny + 64 : 0)));
   c->o_planes = take(sizeof(double) * 256);
   c->o_coilb = take(sizeof(float2) * (size_t)n * nc);
+  c->o_yg = take(c->lines ? sizeof(float2) * 8 * (size_t)gram_items_bound(c) * nc * p.nx : 0);
   c->o_pairs = take(sizeof(int2) * (size_t)q * c->width);
   c->o_pairof = take(sizeof(int32_t) * (size_t)q * c->width);
   c->o_unitof = take(sizeof(int32_t) * (size_t)q * c->width);
@@ -257,6 +263,7 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
     GramLinesArgs g{};
     g.W = c->at<float2>(c->o_W);
     g.yu = c->at<float2>(c->o_yh);
+    g.yg = c->at<float2>(c->o_yg);
     g.items = c->at<int4>(c->o_gwork);
     g.pairs = c->at<int2>(c->o_pairs);
     g.loc_ptr = c->at<int32_t>(c->o_locptr);
@@ -676,6 +683,9 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
                          c->at<int2>(c->o_pairs), c->mask, c->at<int32_t>(c->o_locptr), c->n_loc, c->width,
                          p.nc, p.nx,
                          c->lmax, c->at<float2>(c->o_yh), c->st());
+      hipLaunchKernelGGL(k_build_yg, dim3((unsigned)gram_items_bound(c), p.nc), dim3(256), 0, s,
+                         c->at<float2>(c->o_yh), c->at<int4>(c->o_gwork), p.nc, p.nx, c->at<float2>(c->o_yg),
+                         c->st());
       HIPCHK(hipGetLastError());
     }
   }

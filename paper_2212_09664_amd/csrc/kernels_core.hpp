@@ -6,6 +6,7 @@
 #define GRAM_OPT 2    // outputs per thread in the per-line Gram kernels
 #define SOLVE_NT 1024  // threads of the per-frame solve
 #define QR_NSM 2       // QR Gram: streams of 4 waves per workgroup
+#define GRAM_NWG 1     // per-line Gram: groups of 4 waves per workgroup
 #define GCOLS_OPT 9   // outputs per thread in the column-Gram kernel (m <= 128)
 #define GCOLS_NT 1024
 
@@ -28,6 +29,7 @@ struct JacobiScratch {
 struct GramLinesArgs {
   const float2* W;       // [c][u][x][j], ua rows per coil
   const float2* yu;      // per-line data [c][p][x]
+  const float2* yg;      // per work item: [c][x][8 samples]
   const int4* items;     // work items (line, sample tile of 8, first pair, pair count)
   const int2* pairs;
   const int32_t* loc_ptr;
@@ -323,6 +325,7 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s);
 hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
 hipError_t launch_gram_work(const int2* unit_span, int4* items, DevState* st, hipStream_t s);
+__global__ void k_build_yg(const float2* yu, const int4* items, int nc, int nx, float2* yg, const DevState* st);
 hipError_t launch_cnn_pack(const float* Wl, int cin, int cout, int kp, int kpb, float* Wf, float* Wb, hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, int batch, hipStream_t s);
 hipError_t launch_wgrad(const WgradArgs& a, int bands, int batch, int nparam_layer, float* g, float scale,

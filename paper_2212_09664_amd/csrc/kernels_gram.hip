@@ -79,9 +79,9 @@ __device__ __forceinline__ void tile_reduce(T* t, const typename Mma<T>::V& acc,
 // Loads are unconditional (clamped address, then a select) so the MFMA chain
 // is branch-free.  Outputs (FP64): Ppart[g][u][i][j], hpart[g][pair][j].
 // ---------------------------------------------------------------------------
-template <typename T, int TR, int UN, bool WP>
+template <typename T, int TR, int UN, bool WP, int NWG>
 __device__ __forceinline__ void gram_lines_loop(const GramLinesArgs& a, int u, int c0, int c1, int np, int pp,
-                                                bool pok, int lane, int wave,
+                                                bool pok, int lane, int wave, int wg,
                                                 typename Mma<T>::V (&P)[TR][TR], typename Mma<T>::V (&H)[TR]) {
   using M = Mma<T>;
   const int r = a.r, nx = a.nx, col = lane & 15, kk = lane >> 4;
@@ -99,15 +99,17 @@ __device__ __forceinline__ void gram_lines_loop(const GramLinesArgs& a, int u, i
   const int yim = col >> 3;
   const float ymask = pok ? 1.f : 0.f;
   const float* Wf = reinterpret_cast<const float*>(a.W);
-  const float* Yline = reinterpret_cast<const float*>(a.yu);
-  // one flat loop over (coil, block of 16*UN rows x); the next block's
-  // operands are loaded while the current one feeds the matrix cores
+  // the item's data: [c][x][8 samples] complex (zero past the line's count)
+  const float* Yitem = reinterpret_cast<const float*>(a.yg);
+  // one flat loop over (coil, block of 16*UN rows x), the NWG groups of 4
+  // waves taking every NWG-th block; the next block's operands are loaded
+  // while the current one feeds the matrix cores
   constexpr int XB = 16 * UN;
   const int nxb = (nx + XB - 1) / XB;
   const int niter = max(0, c1 - c0) * nxb;
   T av[UN][TR], bv[UN];
   auto load = [&](int c, int x0, T (&A)[UN][TR], T (&Bv)[UN]) {
-    const float* yrow = Yline + 2L * (((long)c * np + pp) * nx) + yim;
+    const float* yrow = Yitem + 16L * ((long)c * nx) + 2 * (col & 7) + yim;
     const long wbase = 2L * (((long)c * a.ua + u) * nx * r);
 #pragma unroll
     for (int q2 = 0; q2 < UN; ++q2) {
@@ -119,19 +121,14 @@ __device__ __forceinline__ void gram_lines_loop(const GramLinesArgs& a, int u, i
 #pragma unroll
       for (int t = 0; t < TR; ++t)
         A[q2][t] = (T)(Wf[wbase + 2L * (r * xc + wj[t]) + wim[t]] * (rm * wmask[t]));
-      Bv[q2] = (T)(yrow[2 * xc] * (rm * ymask));
+      Bv[q2] = (T)(yrow[16 * xc] * (rm * ymask));
     }
   };
-  if (niter > 0) load(c0, 0, av, bv);
-  int cn = c0, xn = 0;
-  for (int it = 0; it < niter; ++it) {
+  if (wg < niter) load(c0 + wg / nxb, (wg % nxb) * XB, av, bv);
+  for (int it = wg; it < niter; it += NWG) {
     T an[UN][TR], bn[UN];
-    xn += XB;
-    if (xn >= nx) {
-      xn = 0;
-      ++cn;
-    }
-    if (it + 1 < niter) load(cn, xn, an, bn);
+    const int itn = it + NWG;
+    if (itn < niter) load(c0 + itn / nxb, (itn % nxb) * XB, an, bn);
 #pragma unroll
     for (int q2 = 0; q2 < UN; ++q2) {
       if constexpr (WP) {
@@ -149,6 +146,21 @@ __device__ __forceinline__ void gram_lines_loop(const GramLinesArgs& a, int u, i
 #pragma unroll
       for (int t = 0; t < TR; ++t) av[q2][t] = an[q2][t];
     }
+  }
+}
+
+// the Gram kernel's data per work item: [item][c][x][8 samples] complex,
+// zero past the line's sample count (consecutive lanes read consecutive
+// floats).  Grid (items bound, nc).
+__global__ void k_build_yg(const float2* yu, const int4* items, int nc, int nx, float2* yg, const DevState* st) {
+  const int w = blockIdx.x, c = blockIdx.y;
+  if (st->err || w >= st->n_gwork) return;
+  const int4 it = items[w];  // (line, tile, first pair, pair count)
+  const float2* src = yu + (long)nc * nx * it.z + (long)c * it.w * nx;  // the line's [c][p][x] block
+  float2* dst = yg + ((long)w * nc + c) * nx * 8;
+  for (int e = threadIdx.x; e < nx * 8; e += blockDim.x) {
+    const int x = e >> 3, p = 8 * it.y + (e & 7);
+    dst[e] = (p < it.w) ? src[(long)p * nx + x] : make_float2(0.f, 0.f);
   }
 }
 
@@ -177,12 +189,12 @@ __global__ __launch_bounds__(1024) void k_gram_work(const int2* unit_span, int4*
   if (tid == 1023) st->n_gwork = s_off[1023];
 }
 
-template <typename T, int TR, int UN>
-__global__ __launch_bounds__(256) void k_gram_lines_mma(GramLinesArgs a) {
+template <typename T, int TR, int UN, int NWG>
+__global__ __launch_bounds__(256 * NWG) void k_gram_lines_mma(GramLinesArgs a) {
   using M = Mma<T>;
   __shared__ T red[(TR * TR + TR) * 256];
   const int g = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wl = wave & 3, wg = wave >> 2;
   // the first item is requested together with the state (the list holds
   // gridDim.x entries at least; one past the count is not used)
   const int4 first = a.items[blockIdx.x];
@@ -200,7 +212,7 @@ __global__ __launch_bounds__(256) void k_gram_lines_mma(GramLinesArgs a) {
   const bool pok = pl < np;
   const int pp = pok ? pl : 0;
   GramLinesArgs al = a;
-  al.yu = a.yu + (long)a.nc * a.nx * p0;  // this line's [c][p][x] block
+  al.yg = a.yg + (long)w * a.nc * a.nx * 8;  // this item's [c][x][8] block
   typename M::V P[TR][TR], H[TR];
 #pragma unroll
   for (int i = 0; i < TR; ++i) {
@@ -209,9 +221,9 @@ __global__ __launch_bounds__(256) void k_gram_lines_mma(GramLinesArgs a) {
     for (int j = 0; j < TR; ++j) P[i][j] = M::zero();
   }
   if (t == 0)
-    gram_lines_loop<T, TR, UN, true>(al, u, c0, c1, np, pp, pok, lane, wave, P, H);
+    gram_lines_loop<T, TR, UN, true, NWG>(al, u, c0, c1, np, pp, pok, lane, wl, wg, P, H);
   else
-    gram_lines_loop<T, TR, UN, false>(al, u, c0, c1, np, pp, pok, lane, wave, P, H);
+    gram_lines_loop<T, TR, UN, false, NWG>(al, u, c0, c1, np, pp, pok, lane, wl, wg, P, H);
   // reduce across the 4 waves and form the complex outputs
   T* Pt = red;                    // TR*TR tiles
   T* Ht = red + TR * TR * 256;    // TR tiles of the h column block
@@ -222,9 +234,9 @@ __global__ __launch_bounds__(256) void k_gram_lines_mma(GramLinesArgs a) {
 #pragma unroll
     for (int i = 0; i < TR; ++i)
 #pragma unroll
-      for (int j = 0; j < TR; ++j) tile_reduce<T>(Pt + (i * TR + j) * 256, P[i][j], wave, lane);
+      for (int j = 0; j < TR; ++j) tile_reduce_n<T, 4 * NWG>(Pt + (i * TR + j) * 256, P[i][j], wave, lane);
     double2* Pout = a.P + ((long)g * a.ua + u) * r * r;
-    for (int e = tid; e < r * r; e += 256) {
+    for (int e = tid; e < r * r; e += 256 * NWG) {
       const int i = e / r, j = e % r;
       const double re = C(Pt, TR, i, j) + C(Pt, TR, r + i, r + j);
       const double im = C(Pt, TR, i, r + j) - C(Pt, TR, r + i, j);
@@ -232,9 +244,9 @@ __global__ __launch_bounds__(256) void k_gram_lines_mma(GramLinesArgs a) {
     }
   }
 #pragma unroll
-  for (int i = 0; i < TR; ++i) tile_reduce<T>(Ht + i * 256, H[i], wave, lane);
+  for (int i = 0; i < TR; ++i) tile_reduce_n<T, 4 * NWG>(Ht + i * 256, H[i], wave, lane);
   const int npt = min(8, np - 8 * t);
-  for (int e = tid; e < npt * r; e += 256) {
+  for (int e = tid; e < npt * r; e += 256 * NWG) {
     const int p = e / r, j = e % r;
     // rows j and r + j of the TR x 1 column of tiles, columns p (Re y) and 8 + p (Im y)
     const double re = C(Ht, 1, j, p) + C(Ht, 1, r + j, 8 + p);
@@ -481,9 +493,9 @@ static void launch_lines_tr(const GramLinesArgs& a, int ny, int ngroups, int ht,
   // sample tiles; a grid-stride loop takes any remainder
   (void)ht;
   const dim3 g(ny + 64, ngroups);
-  if (a.nx >= 128) hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 4>), g, dim3(256), 0, s, a);
-  else if (a.nx >= 64) hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 4>), g, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 1>), g, dim3(256), 0, s, a);
+  constexpr int NWG = GRAM_NWG;
+  if (a.nx >= 64) hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 4, NWG>), g, dim3(256 * NWG), 0, s, a);
+  else hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 1, NWG>), g, dim3(256 * NWG), 0, s, a);
 }
 
 hipError_t launch_gram_work(const int2* unit_span, int4* items, DevState* st, hipStream_t s) {
