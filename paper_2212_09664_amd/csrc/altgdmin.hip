@@ -62,7 +62,7 @@ struct altgdmin_ctx {
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
       o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rfac, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
-      o_fcmp, o_planes, o_gwork, o_coilb, o_yg, o_end;
+      o_fcmp, o_planes, o_gwork, o_coilb, o_yg, o_ysqp, o_end;
   size_t T_bytes;
   // timing
   int timed = TK_NONE;
@@ -121,6 +121,7 @@ void carve(altgdmin_ctx* c) {
   const size_t ysz = sizeof(float2) * (size_t)q * nc * p.m_max;
   c->o_yh = take(c->lines ? ysz : 0);
   c->o_ysq = take(sizeof(double) * q);
+  c->o_ysqp = take(sizeof(double) * q * nc);
   c->o_cost = take(sizeof(double) * q);
   const size_t wsz = sizeof(float2) * (size_t)nc * r * c->ua * p.nx;
   c->o_W = take(wsz);
@@ -662,7 +663,10 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
                      c->at<int32_t>(c->o_unitof), c->st());
   HIPCHK(hipGetLastError());
   if (c->y) {
-    hipLaunchKernelGGL(k_ysq, dim3(p.q), dim3(AG_NT), 0, s, c->y, c->m_k, p.nc, p.m_max, c->at<double>(c->o_ysq));
+    hipLaunchKernelGGL(k_ysq, dim3(p.q, p.nc), dim3(AG_NT), 0, s, c->y, c->m_k, p.nc, p.m_max,
+                       c->at<double>(c->o_ysqp));
+    hipLaunchKernelGGL(k_ysq_sum, dim3(1), dim3(128), 0, s, c->at<double>(c->o_ysqp), p.q, p.nc,
+                       c->at<double>(c->o_ysq));
     hipLaunchKernelGGL(k_init_stats, dim3(1), dim3(1), 0, s, c->at<double>(c->o_ysq), c->m_k, p.q, p.trunc_c,
                        c->st());
     HIPCHK(hipGetLastError());

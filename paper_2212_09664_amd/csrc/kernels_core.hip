@@ -96,19 +96,18 @@ __global__ void k_inv_fill(const int32_t* mask, const int32_t* m_k, int width, i
   unit_of[(long)k * width + e] = loc2unit[loc];
 }
 
-// ||y_k||^2 in FP64, one workgroup per frame
+// ||y_{k,c}||^2 in FP64, one workgroup per (frame k, coil c): part[k * nc + c]
 __global__ __launch_bounds__(AG_NT) void k_ysq(const float2* y, const int32_t* m_k, int nc, int m_max,
-                                               double* ysq_k) {
+                                               double* part) {
   __shared__ double red[AG_NT];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
   const int mk = m_k[k];
+  const float2* yk = y + ((long)k * nc + c) * m_max;
   double s = 0.0;
-  for (int c = 0; c < nc; ++c) {
-    const float2* yk = y + ((long)k * nc + c) * m_max;
-    for (int i = tid; i < mk; i += AG_NT) {
-      float2 v = yk[i];
-      s += (double)v.x * v.x + (double)v.y * v.y;
-    }
+#pragma unroll 8
+  for (int i = tid; i < mk; i += AG_NT) {
+    const float2 v = yk[i];
+    s += (double)v.x * v.x + (double)v.y * v.y;
   }
   red[tid] = s;
   __syncthreads();
@@ -116,7 +115,16 @@ __global__ __launch_bounds__(AG_NT) void k_ysq(const float2* y, const int32_t* m
     if (tid < off) red[tid] += red[tid + off];
     __syncthreads();
   }
-  if (tid == 0) ysq_k[k] = red[0];
+  if (tid == 0) part[(long)k * nc + c] = red[0];
+}
+
+// ||y_k||^2 = sum over coils of the parts, in coil order (one thread per frame)
+__global__ void k_ysq_sum(const double* part, int q, int nc, double* ysq_k) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < q; k += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < nc; ++c) s += part[(long)k * nc + c];
+    ysq_k[k] = s;
+  }
 }
 
 // gamma = trunc_c * sum |y|^2 / (m q), m = max_k m_k; mbar = sum_k m_k / q
@@ -742,54 +750,295 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 // ===========================================================================
 // IN_LDS: matrix and eigenvectors in dynamic LDS (q <= 64; the accesses are
 // then LDS instructions), else in the workspace
-template <int ITEMS, bool IN_LDS>
+// one-wave reductions
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ double2 wave_sum2(double2 v) { return make_double2(wave_sum(v.x), wave_sum(v.y)); }
+
+// number of eigenvalues of the real symmetric tridiagonal (d, e) below x
+// (Sturm count of the LDL^T pivots; tiny pivots are replaced by -pivmin)
+__device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// ===========================================================================
+// spectral initialisation, the q x q eigenproblem: the r largest eigenpairs
+// of the Hermitian X_0^H X_0 by one wave, then V_r Sigma_r^{-1}:
+//  1. Householder reduction M = Q T Q^H, T tridiagonal with complex
+//     off-diagonals e_k; reflectors H_k = I - beta_k v_k v_k^H kept in Vh;
+//  2. a diagonal unitary D makes T real: T = D T_r D^H, off-diagonals |e_k|;
+//  3. the r largest eigenvalues of T_r by multisection on Sturm counts;
+//  4. their eigenvectors by inverse iteration (one lane each, LDL^T without
+//     pivoting, tiny pivots replaced), orthogonalised within clusters;
+//  5. back-transformation Y = Q D Z.
+// IN_LDS: matrix and reflectors in dynamic LDS (q <= 64), else in the workspace.
+// ===========================================================================
+template <bool IN_LDS>
 __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
-  extern __shared__ double2 lds_m[];  // q x q matrix, then q x q eigenvectors (when they fit)
-  __shared__ JacobiScratch js;
-  __shared__ int idx[16];
-  __shared__ double lam_s[16];
-  const int tid = threadIdx.x, NT = blockDim.x, q = a.q, r = a.r;
+  extern __shared__ double2 lds_m[];  // q x q matrix, then q x q reflectors
+  __shared__ double s_d[128], s_ea[128], s_e2[128], s_beta[128];
+  __shared__ double2 s_ec[128], s_ph[128], s_w[128];
+  __shared__ double s_lam[16];
+  const int tid = threadIdx.x, NT = blockDim.x, n = a.q, r = a.r;
   double2* A = IN_LDS ? lds_m : a.V;
-  double2* V = A + q * q;
-  const int nout = q * (q + 1) / 2;
+  double2* Vh = A + n * n;
+  const int nout = n * (n + 1) / 2;
   for (int o = tid; o < nout; o += NT) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int b = 0; b < a.nblk; ++b) s = dadd(s, a.part[(long)b * nout + o]);
+    double2 sum = make_double2(0.0, 0.0);
+    for (int b = 0; b < a.nblk; ++b) sum = dadd(sum, a.part[(long)b * nout + o]);
     int i, j;
-    tri_index(o, q, i, j);
-    A[i * q + j] = s;
-    A[j * q + i] = dconj(s);
+    tri_index(o, n, i, j);
+    if (i == j) sum.y = 0.0;
+    A[i * n + j] = sum;
+    A[j * n + i] = dconj(sum);
   }
   __syncthreads();
-  if (tid < q) A[tid * q + tid].y = 0.0;
-  __syncthreads();
-  jacobi_eig<ITEMS>(A, q, q, V, &js, 60, r);
-  __syncthreads();
-  if (tid == 0) {
-    // top-r eigenvalues, descending
-    for (int j = 0; j < r; ++j) {
-      int best = -1;
-      double bv = -INFINITY;
-      for (int i = 0; i < q; ++i) {
-        bool used = false;
-        for (int m = 0; m < j; ++m) used = used || (idx[m] == i);
-        if (!used && A[i * q + i].x > bv) {
-          bv = A[i * q + i].x;
-          best = i;
+  if (tid >= 64) return;  // one wave from here on
+  const int l = tid;
+  // ---- 1. Householder tridiagonalisation (full Hermitian trailing block kept)
+  for (int k = 0; k + 2 < n; ++k) {
+    const int k1 = k + 1, m = n - k1;
+    double sig = 0.0;
+    for (int i = 1 + l; i < m; i += 64) {
+      const double2 x = A[(k1 + i) * n + k];
+      sig += x.x * x.x + x.y * x.y;
+    }
+    sig = wave_sum(sig);
+    const double2 x0 = A[k1 * n + k];
+    if (sig == 0.0 && x0.y == 0.0) {  // already reduced: H_k = I
+      if (l == 0) {
+        s_beta[k] = 0.0;
+        s_ec[k] = x0;
+      }
+      wave_sync();
+      continue;
+    }
+    const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y), nrm = sqrt(ax0 * ax0 + sig);
+    const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+    const double2 alpha = make_double2(-ph.x * nrm, -ph.y * nrm);
+    const double2 v0 = dsub(x0, alpha);
+    const double beta = 2.0 / (v0.x * v0.x + v0.y * v0.y + sig);
+    for (int i = 1 + l; i < m; i += 64) Vh[(k1 + i) * n + k] = A[(k1 + i) * n + k];
+    if (l == 0) {
+      Vh[k1 * n + k] = v0;
+      s_beta[k] = beta;
+      s_ec[k] = alpha;
+    }
+    wave_sync();
+    // p = beta B v, K = (beta / 2) v^H p, w = p - K v
+    double2 kp = make_double2(0.0, 0.0);
+    auto pmul = [&](int i) -> double2 {  // (beta B v)_i for a row of the trailing block
+      double2 acc = make_double2(0.0, 0.0);
+      if (i < m) {
+        const double2* row = A + (k1 + i) * n + k1;
+        for (int j = 0; j < m; ++j) acc = dadd(acc, dmul(row[j], Vh[(k1 + j) * n + k]));
+        acc = make_double2(beta * acc.x, beta * acc.y);
+        kp = dadd(kp, djmul(Vh[(k1 + i) * n + k], acc));
+      }
+      return acc;
+    };
+    const double2 pa = pmul(l), pb = pmul(l + 64);
+    kp = wave_sum2(kp);
+    const double2 K = make_double2(0.5 * beta * kp.x, 0.5 * beta * kp.y);
+    if (l < m) s_w[l] = dsub(pa, dmul(K, Vh[(k1 + l) * n + k]));
+    if (l + 64 < m) s_w[l + 64] = dsub(pb, dmul(K, Vh[(k1 + l + 64) * n + k]));
+    wave_sync();
+    // B -= v w^H + w v^H
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = l + 64 * h;
+      if (i < m) {
+        const double2 vi = Vh[(k1 + i) * n + k], wi = s_w[i];
+        double2* row = A + (k1 + i) * n + k1;
+        for (int j = 0; j < m; ++j) {
+          const double2 vj = Vh[(k1 + j) * n + k], wj = s_w[j];
+          row[j] = dsub(row[j], dadd(dmul(vi, dconj(wj)), dmul(wi, dconj(vj))));
         }
       }
-      idx[j] = best;
-      lam_s[j] = bv;
     }
-    if (!(lam_s[r - 1] > 1e-14 * lam_s[0]) || !(lam_s[0] > 0.0)) set_error(a.st, 4, -1);
+    wave_sync();
   }
-  __syncthreads();
-  if (a.st->err) return;
-  for (int e = tid; e < q * r; e += NT) {
-    const int k = e / r, j = e % r;
-    const double2 v = V[k * q + idx[j]];
-    const double sc = 1.0 / sqrt(lam_s[j]);
-    a.Vs[k * r + j] = make_float2((float)(v.x * sc), (float)(v.y * sc));
+  // ---- 2. T_r: diagonal, |e_k|, and the phases of D
+  for (int i = l; i < n; i += 64) s_d[i] = A[i * n + i].x;
+  if (l == 0 && n >= 2) s_ec[n - 2] = A[(n - 1) * n + (n - 2)];
+  wave_sync();
+  for (int i = l; i + 1 < n; i += 64) {
+    const double2 e = s_ec[i];
+    const double ae = sqrt(e.x * e.x + e.y * e.y);
+    s_ea[i] = ae;
+    s_e2[i] = ae * ae;
+  }
+  if (l == 0) {
+    double2 ph = make_double2(1.0, 0.0);
+    s_ph[0] = ph;
+    for (int i = 0; i + 1 < n; ++i) {
+      const double2 e = s_ec[i];
+      const double ae = sqrt(e.x * e.x + e.y * e.y);
+      if (ae > 0.0) ph = dmul(ph, make_double2(e.x / ae, e.y / ae));
+      s_ph[i + 1] = ph;
+    }
+  }
+  wave_sync();
+  // Gershgorin interval and scales
+  double glo = INFINITY, ghi = -INFINITY, emax2 = 0.0, scale = 0.0;
+  for (int i = l; i < n; i += 64) {
+    const double rad = (i > 0 ? s_ea[i - 1] : 0.0) + (i + 1 < n ? s_ea[i] : 0.0);
+    glo = fmin(glo, s_d[i] - rad);
+    ghi = fmax(ghi, s_d[i] + rad);
+    scale = fmax(scale, fabs(s_d[i]) + rad);
+    if (i + 1 < n) emax2 = fmax(emax2, s_e2[i]);
+  }
+  glo = wave_min(glo);
+  ghi = wave_max(ghi);
+  scale = fmax(wave_max(scale), 1e-300);
+  emax2 = wave_max(emax2);
+  const double pivmin = 2.3e-308 * fmax(1.0, emax2);
+  {
+    const double wdt = ghi - glo;
+    glo -= 1e-3 * wdt + 1e-300;
+    ghi += 1e-3 * wdt + 1e-300;
+  }
+  // ---- 3. multisection: RL eigenvalue slots of L lanes; slot j -> ascending index n-1-j
+  const int RL = r <= 8 ? 8 : 16, L = 64 / RL, slot = l / L, sub = l % L;
+  const int idx = n - 1 - slot;
+  double lo = glo, hi = ghi;
+  bool done = slot >= r;
+  for (int rnd = 0; rnd < 80; ++rnd) {
+    if (__all(done)) break;
+    const double x = lo + (hi - lo) * (double)(sub + 1) / (double)(L + 1);
+    const int cnt = done ? 0 : sturm_count(s_d, s_e2, n, x, pivmin);
+    double nlo = (!done && cnt <= idx) ? x : -INFINITY;
+    double nhi = (!done && cnt > idx) ? x : INFINITY;
+    for (int off = 1; off < L; off <<= 1) {
+      nlo = fmax(nlo, __shfl_xor(nlo, off));
+      nhi = fmin(nhi, __shfl_xor(nhi, off));
+    }
+    if (!done) {
+      lo = fmax(lo, nlo);
+      hi = fmin(hi, nhi);
+      done = hi - lo <= 4e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+    }
+  }
+  if (slot < r && sub == 0) s_lam[slot] = 0.5 * (lo + hi);
+  wave_sync();
+  // ---- 4. inverse iteration, lane j < r for eigenvalue j; scratch in A's region
+  double* su = reinterpret_cast<double*>(A);  // u pivots [i * r + j]
+  double* sy = su + n * r;                    // right-hand side / solution [i * r + j]
+  if (l < r) {
+    const double lam = s_lam[l], tiny = 1e-14 * scale;
+    for (int i = 0; i < n; ++i) {  // a start vector of its own per lane (golden-ratio sequence)
+      const double t = (double)(i + 1) * (double)(2 * l + 3) * 0.6180339887498949;
+      sy[i * r + l] = 0.5 + (t - floor(t));
+    }
+    for (int it = 0; it < 3; ++it) {
+      double u = s_d[0] - lam, y = sy[l];
+      for (int i = 0; i + 1 < n; ++i) {
+        if (fabs(u) <= tiny) u = tiny;
+        su[i * r + l] = u;
+        sy[i * r + l] = y;
+        const double lm = s_ea[i] / u;
+        u = s_d[i + 1] - lam - lm * s_ea[i];
+        y = sy[(i + 1) * r + l] - lm * y;
+      }
+      if (fabs(u) <= tiny) u = tiny;
+      double xnext = y / u, nrm2 = xnext * xnext;
+      sy[(n - 1) * r + l] = xnext;
+      for (int i = n - 2; i >= 0; --i) {
+        const double xi = (sy[i * r + l] - s_ea[i] * xnext) / su[i * r + l];
+        sy[i * r + l] = xi;
+        nrm2 += xi * xi;
+        xnext = xi;
+      }
+      const double inv = 1.0 / sqrt(nrm2);
+      for (int i = 0; i < n; ++i) sy[i * r + l] *= inv;
+    }
+  }
+  wave_sync();
+  // orthogonalise within clusters of close eigenvalues, twice, in descending order
+  for (int j = 1; j < r; ++j) {
+    bool any = false;
+    for (int jp = 0; jp < j; ++jp) any = any || fabs(s_lam[jp] - s_lam[j]) <= 1e-3 * scale;
+    if (!any) continue;
+    for (int rep = 0; rep < 2; ++rep) {
+      for (int jp = 0; jp < j; ++jp) {
+        if (!(fabs(s_lam[jp] - s_lam[j]) <= 1e-3 * scale)) continue;
+        double dot = 0.0;
+        for (int i = l; i < n; i += 64) dot += sy[i * r + jp] * sy[i * r + j];
+        dot = wave_sum(dot);
+        for (int i = l; i < n; i += 64) sy[i * r + j] -= dot * sy[i * r + jp];
+        wave_sync();
+      }
+    }
+    double nn = 0.0;
+    for (int i = l; i < n; i += 64) nn += sy[i * r + j] * sy[i * r + j];
+    const double inv = 1.0 / sqrt(wave_sum(nn));
+    for (int i = l; i < n; i += 64) sy[i * r + j] *= inv;
+    wave_sync();
+  }
+  // ---- 5. Y = Q D Z, Y [i * r + j] complex over the start of A's region
+  double zr[2][16];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int i = l + 64 * h;
+      zr[h][j] = (i < n && j < r) ? sy[i * r + j] : 0.0;
+    }
+  wave_sync();
+  double2* Y = A;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int i = l + 64 * h;
+      if (i < n && j < r) Y[i * r + j] = make_double2(s_ph[i].x * zr[h][j], s_ph[i].y * zr[h][j]);
+    }
+  wave_sync();
+  // lane = (column j = l % 16, row group g = l / 16: rows i = g mod 4)
+  const int jc = l & 15, g4 = l >> 4;
+  for (int k = n - 3; k >= 0; --k) {
+    const double beta = s_beta[k];
+    if (beta == 0.0) continue;
+    double2 sj = make_double2(0.0, 0.0);
+    if (jc < r)
+      for (int i = k + 1 + g4; i < n; i += 4) sj = dadd(sj, djmul(Vh[i * n + k], Y[i * r + jc]));
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+      sj.x += __shfl_xor(sj.x, off);
+      sj.y += __shfl_xor(sj.y, off);
+    }
+    if (jc < r) {
+      const double2 bs = make_double2(beta * sj.x, beta * sj.y);
+      for (int i = k + 1 + g4; i < n; i += 4) Y[i * r + jc] = dsub(Y[i * r + jc], dmul(Vh[i * n + k], bs));
+    }
+    wave_sync();
+  }
+  const double lam0 = s_lam[0], lamr = s_lam[r - 1];
+  if (!(lamr > 1e-14 * lam0) || !(lam0 > 0.0)) {
+    if (l == 0) set_error(a.st, 4, -1);
+    return;
+  }
+  for (int e = l; e < n * r; e += 64) {
+    const int j = e % r;
+    const double sc = 1.0 / sqrt(s_lam[j]);
+    const double2 v = Y[e];  // Y[k][j] with e = k * r + j
+    a.Vs[e] = make_float2((float)(v.x * sc), (float)(v.y * sc));
   }
 }
 
@@ -868,16 +1117,17 @@ hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s) {
+  if (a.q > 128 || a.r > 16 || a.r > a.q) return hipErrorInvalidValue;
   const size_t lds = a.in_lds ? 2 * (size_t)a.q * a.q * sizeof(double2) : 0;
   if (a.in_lds) {
     if (lds > 48 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_init_eig<1, true>,
+      hipError_t e = hipFuncSetAttribute((const void*)k_init_eig<true>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_init_eig<1, true>), dim3(1), dim3(1024), lds, s, a);
+    hipLaunchKernelGGL((k_init_eig<true>), dim3(1), dim3(1024), lds, s, a);
   } else {
-    hipLaunchKernelGGL((k_init_eig<4, false>), dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL((k_init_eig<false>), dim3(1), dim3(1024), 0, s, a);
   }
   return hipGetLastError();
 }

@@ -302,7 +302,8 @@ __global__ void k_inv_scan(const uint32_t* bitmap, int nw, int n_loc, int32_t* l
 __global__ void k_inv_fill(const int32_t* mask, const int32_t* m_k, int width, int per, const uint32_t* bitmap,
                            int nw, const int32_t* loc_ptr, const int32_t* loc2unit, int2* pairs, int32_t* pair_of,
                            int32_t* unit_of, const DevState* st);
-__global__ void k_ysq(const float2* y, const int32_t* m_k, int nc, int m_max, double* ysq_k);
+__global__ void k_ysq(const float2* y, const int32_t* m_k, int nc, int m_max, double* part);
+__global__ void k_ysq_sum(const double* part, int q, int nc, double* ysq_k);
 __global__ void k_init_stats(const double* ysq_k, const int32_t* m_k, int q, double trunc_c, DevState* st);
 __global__ void k_state_reset(DevState* st, int full);
 __global__ void k_state_set_eta(DevState* st, double eta);

@@ -148,39 +148,44 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
 #pragma unroll
   for (int it = 0; it < IT; ++it) acc[it] = make_float2(0.f, 0.f);
   const int cb = blockIdx.z * a.cgs, ce = min(a.nc, cb + a.cgs);
-  for (int c = cb; c < ce; ++c) {
+  // a coil's sampled rows and its map, loaded one coil ahead so that the
+  // loads overlap the previous coil's transform
+  float2 v[IT], cw[IT];
+  int d[IT];
+  auto fetch = [&](int c) {
     const float2* src = a.src + (long)c * a.src_c_stride + (long)img * a.src_img_stride;
+    const float2* coil = a.coils + (long)c * a.n;
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const int g = tid + j * AG_NT;
+      d[j] = -1;
+      if (g < n_rows * TX) {
+        const int u = g / TX, col = g % TX;
+        d[j] = (full ? u : rows[u]) * TX + col;
+        v[j] = src[(long)u * a.nx + x0 + col];
+      }
+      if (g < N * TX) cw[j] = coil[(long)(g / TX) * a.nx + x0 + g % TX];
+    }
+  };
+  if (cb < ce) fetch(cb);
+  for (int c = cb; c < ce; ++c) {
     if (!full) {
       for (int g = tid; g < N * TX; g += AG_NT) s[g] = make_float2(0.f, 0.f);
       __syncthreads();
     }
-    for (int g0 = 0; g0 < n_rows * TX; g0 += 8 * AG_NT) {
-      float2 v[8];
-      int d[8];
+    float2 cwc[IT];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int g = g0 + tid + j * AG_NT;
-        d[j] = -1;
-        if (g < n_rows * TX) {
-          const int u = g / TX, col = g % TX;
-          d[j] = (full ? u : rows[u]) * TX + col;
-          v[j] = src[(long)u * a.nx + x0 + col];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (d[j] >= 0) s[d[j]] = v[j];
+    for (int j = 0; j < IT; ++j) {
+      if (d[j] >= 0) s[d[j]] = v[j];
+      cwc[j] = cw[j];
     }
     __syncthreads();
+    if (c + 1 < ce) fetch(c + 1);
     fft_lds<N, TX, AG_NT, true>(s, a.tw);
-    const float2* coil = a.coils + (long)c * a.n;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int g = tid + it * AG_NT;
-      if (g < N * TX) {
-        const int y = g / TX, col = g % TX;
-        acc[it] = cadd(acc[it], cjmul(coil[(long)y * a.nx + x0 + col], s[g]));
-      }
+      if (g < N * TX) acc[it] = cadd(acc[it], cjmul(cwc[it], s[g]));
     }
     __syncthreads();
   }
