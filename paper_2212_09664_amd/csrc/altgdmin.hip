@@ -141,7 +141,7 @@ void carve(altgdmin_ctx* c) {
   c->o_qpart = take(sizeof(double2) * qo * c->qr_nblk);
   c->o_rfac = take(sizeof(float2) * r * r);
   c->o_Vs = take(sizeof(float2) * (size_t)q * r);
-  c->o_V = take(sizeof(double2) * 2 * (size_t)q * q);
+  c->o_V = take(sizeof(double2) * 2 * (size_t)q * (q | 1));  // matrix and reflectors, odd row pitch
   // temp: X0 plus the truncated hybrid data (LINES) or a chunk of coil images (INDEX)
   size_t tb = sizeof(float2) * (size_t)n * q;
   if (c->lines)

@@ -769,8 +769,9 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   int cnt = q < 0.0;
+#pragma unroll 8
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
+    q = d[i] - x - e2[i - 1] * rcp_nr(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
@@ -796,17 +797,20 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
   __shared__ double2 s_ec[128], s_ph[128], s_w[128];
   __shared__ double s_lam[16];
   const int tid = threadIdx.x, NT = blockDim.x, n = a.q, r = a.r;
+  // row pitch ld odd: the rows one wave reads together fall in distinct LDS banks
+  const int ld = n | 1;
   double2* A = IN_LDS ? lds_m : a.V;
-  double2* Vh = A + n * n;
+  double2* Vh = A + n * ld;
   const int nout = n * (n + 1) / 2;
   for (int o = tid; o < nout; o += NT) {
     double2 sum = make_double2(0.0, 0.0);
+#pragma unroll 16
     for (int b = 0; b < a.nblk; ++b) sum = dadd(sum, a.part[(long)b * nout + o]);
     int i, j;
     tri_index(o, n, i, j);
     if (i == j) sum.y = 0.0;
-    A[i * n + j] = sum;
-    A[j * n + i] = dconj(sum);
+    A[i * ld + j] = sum;
+    A[j * ld + i] = dconj(sum);
   }
   __syncthreads();
   if (tid >= 64) return;  // one wave from here on
@@ -816,11 +820,11 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     const int k1 = k + 1, m = n - k1;
     double sig = 0.0;
     for (int i = 1 + l; i < m; i += 64) {
-      const double2 x = A[(k1 + i) * n + k];
+      const double2 x = A[(k1 + i) * ld + k];
       sig += x.x * x.x + x.y * x.y;
     }
     sig = wave_sum(sig);
-    const double2 x0 = A[k1 * n + k];
+    const double2 x0 = A[k1 * ld + k];
     if (sig == 0.0 && x0.y == 0.0) {  // already reduced: H_k = I
       if (l == 0) {
         s_beta[k] = 0.0;
@@ -834,9 +838,9 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     const double2 alpha = make_double2(-ph.x * nrm, -ph.y * nrm);
     const double2 v0 = dsub(x0, alpha);
     const double beta = 2.0 / (v0.x * v0.x + v0.y * v0.y + sig);
-    for (int i = 1 + l; i < m; i += 64) Vh[(k1 + i) * n + k] = A[(k1 + i) * n + k];
+    for (int i = 1 + l; i < m; i += 64) Vh[(k1 + i) * ld + k] = A[(k1 + i) * ld + k];
     if (l == 0) {
-      Vh[k1 * n + k] = v0;
+      Vh[k1 * ld + k] = v0;
       s_beta[k] = beta;
       s_ec[k] = alpha;
     }
@@ -846,28 +850,39 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     auto pmul = [&](int i) -> double2 {  // (beta B v)_i for a row of the trailing block
       double2 acc = make_double2(0.0, 0.0);
       if (i < m) {
-        const double2* row = A + (k1 + i) * n + k1;
-        for (int j = 0; j < m; ++j) acc = dadd(acc, dmul(row[j], Vh[(k1 + j) * n + k]));
+        const double2* row = A + (k1 + i) * ld + k1;
+        const double2* vk = Vh + k1 * ld + k;
+        double2 c0 = acc, c1 = acc, c2 = acc, c3 = acc;  // independent chains
+        int j = 0;
+        for (; j + 4 <= m; j += 4) {
+          c0 = dadd(c0, dmul(row[j], vk[j * ld]));
+          c1 = dadd(c1, dmul(row[j + 1], vk[(j + 1) * ld]));
+          c2 = dadd(c2, dmul(row[j + 2], vk[(j + 2) * ld]));
+          c3 = dadd(c3, dmul(row[j + 3], vk[(j + 3) * ld]));
+        }
+        for (; j < m; ++j) c0 = dadd(c0, dmul(row[j], vk[j * ld]));
+        acc = dadd(dadd(c0, c1), dadd(c2, c3));
         acc = make_double2(beta * acc.x, beta * acc.y);
-        kp = dadd(kp, djmul(Vh[(k1 + i) * n + k], acc));
+        kp = dadd(kp, djmul(Vh[(k1 + i) * ld + k], acc));
       }
       return acc;
     };
     const double2 pa = pmul(l), pb = pmul(l + 64);
     kp = wave_sum2(kp);
     const double2 K = make_double2(0.5 * beta * kp.x, 0.5 * beta * kp.y);
-    if (l < m) s_w[l] = dsub(pa, dmul(K, Vh[(k1 + l) * n + k]));
-    if (l + 64 < m) s_w[l + 64] = dsub(pb, dmul(K, Vh[(k1 + l + 64) * n + k]));
+    if (l < m) s_w[l] = dsub(pa, dmul(K, Vh[(k1 + l) * ld + k]));
+    if (l + 64 < m) s_w[l + 64] = dsub(pb, dmul(K, Vh[(k1 + l + 64) * ld + k]));
     wave_sync();
     // B -= v w^H + w v^H
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int i = l + 64 * h;
       if (i < m) {
-        const double2 vi = Vh[(k1 + i) * n + k], wi = s_w[i];
-        double2* row = A + (k1 + i) * n + k1;
+        const double2 vi = Vh[(k1 + i) * ld + k], wi = s_w[i];
+        double2* row = A + (k1 + i) * ld + k1;
+#pragma unroll 8
         for (int j = 0; j < m; ++j) {
-          const double2 vj = Vh[(k1 + j) * n + k], wj = s_w[j];
+          const double2 vj = Vh[(k1 + j) * ld + k], wj = s_w[j];
           row[j] = dsub(row[j], dadd(dmul(vi, dconj(wj)), dmul(wi, dconj(vj))));
         }
       }
@@ -875,8 +890,8 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     wave_sync();
   }
   // ---- 2. T_r: diagonal, |e_k|, and the phases of D
-  for (int i = l; i < n; i += 64) s_d[i] = A[i * n + i].x;
-  if (l == 0 && n >= 2) s_ec[n - 2] = A[(n - 1) * n + (n - 2)];
+  for (int i = l; i < n; i += 64) s_d[i] = A[i * ld + i].x;
+  if (l == 0 && n >= 2) s_ec[n - 2] = A[(n - 1) * ld + (n - 2)];
   wave_sync();
   for (int i = l; i + 1 < n; i += 64) {
     const double2 e = s_ec[i];
@@ -948,19 +963,22 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     }
     for (int it = 0; it < 3; ++it) {
       double u = s_d[0] - lam, y = sy[l];
+#pragma unroll 4
       for (int i = 0; i + 1 < n; ++i) {
         if (fabs(u) <= tiny) u = tiny;
-        su[i * r + l] = u;
+        const double ru = rcp_nr(u);
+        su[i * r + l] = ru;  // 1 / u_i for the backward pass
         sy[i * r + l] = y;
-        const double lm = s_ea[i] / u;
+        const double lm = s_ea[i] * ru;
         u = s_d[i + 1] - lam - lm * s_ea[i];
         y = sy[(i + 1) * r + l] - lm * y;
       }
       if (fabs(u) <= tiny) u = tiny;
       double xnext = y / u, nrm2 = xnext * xnext;
       sy[(n - 1) * r + l] = xnext;
+#pragma unroll 4
       for (int i = n - 2; i >= 0; --i) {
-        const double xi = (sy[i * r + l] - s_ea[i] * xnext) / su[i * r + l];
+        const double xi = (sy[i * r + l] - s_ea[i] * xnext) * su[i * r + l];
         sy[i * r + l] = xi;
         nrm2 += xi * xi;
         xnext = xi;
@@ -1016,8 +1034,10 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     const double beta = s_beta[k];
     if (beta == 0.0) continue;
     double2 sj = make_double2(0.0, 0.0);
-    if (jc < r)
-      for (int i = k + 1 + g4; i < n; i += 4) sj = dadd(sj, djmul(Vh[i * n + k], Y[i * r + jc]));
+    if (jc < r) {
+#pragma unroll 4
+      for (int i = k + 1 + g4; i < n; i += 4) sj = dadd(sj, djmul(Vh[i * ld + k], Y[i * r + jc]));
+    }
 #pragma unroll
     for (int off = 16; off < 64; off <<= 1) {
       sj.x += __shfl_xor(sj.x, off);
@@ -1025,7 +1045,8 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     }
     if (jc < r) {
       const double2 bs = make_double2(beta * sj.x, beta * sj.y);
-      for (int i = k + 1 + g4; i < n; i += 4) Y[i * r + jc] = dsub(Y[i * r + jc], dmul(Vh[i * n + k], bs));
+#pragma unroll 4
+      for (int i = k + 1 + g4; i < n; i += 4) Y[i * r + jc] = dsub(Y[i * r + jc], dmul(Vh[i * ld + k], bs));
     }
     wave_sync();
   }
@@ -1118,7 +1139,7 @@ hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
 
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s) {
   if (a.q > 128 || a.r > 16 || a.r > a.q) return hipErrorInvalidValue;
-  const size_t lds = a.in_lds ? 2 * (size_t)a.q * a.q * sizeof(double2) : 0;
+  const size_t lds = a.in_lds ? 2 * (size_t)a.q * (a.q | 1) * sizeof(double2) : 0;
   if (a.in_lds) {
     if (lds > 48 * 1024) {
       hipError_t e = hipFuncSetAttribute((const void*)k_init_eig<true>,

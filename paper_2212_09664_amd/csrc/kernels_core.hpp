@@ -195,7 +195,7 @@ struct ApplyArgs {
 struct InitEigArgs {
   const double2* part;
   int nblk, q, r;
-  double2* V;            // 2 q x q scratch (global): matrix and eigenvectors when not in LDS
+  double2* V;            // 2 q x (q | 1) scratch (global): matrix and reflectors when not in LDS
   int in_lds;            // matrix and eigenvectors in dynamic LDS (q <= 64)
   float2* Vs;            // q x r out: V_r Sigma_r^{-1}
   DevState* st;
