@@ -642,9 +642,7 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
   double2 g[RT];  // padded to RT with the identity
 #pragma unroll
   for (int m = 0; m < RT; ++m) g[m] = (i < r && m < r) ? gh(i, m) : make_double2(i == m ? 1.0 : 0.0, 0.0);
-  double dmax = (i < r) ? gh(i, i).x : 0.0;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
+  const double dmax = wave_max((i < r) ? gh(i, i).x : 0.0);
   if (!wave_chol<double, double2, RT>(g, r, 1e-14 * dmax)) {
     if (i == 0) {
       set_error(st, 4, -1);
@@ -751,16 +749,6 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 // IN_LDS: matrix and eigenvectors in dynamic LDS (q <= 64; the accesses are
 // then LDS instructions), else in the workspace
 // one-wave reductions
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-  return v;
-}
 __device__ __forceinline__ double2 wave_sum2(double2 v) { return make_double2(wave_sum(v.x), wave_sum(v.y)); }
 
 // number of eigenvalues of the real symmetric tridiagonal (d, e) below x
@@ -940,14 +928,21 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     const int cnt = done ? 0 : sturm_count(s_d, s_e2, n, x, pivmin);
     double nlo = (!done && cnt <= idx) ? x : -INFINITY;
     double nhi = (!done && cnt > idx) ? x : INFINITY;
-    for (int off = 1; off < L; off <<= 1) {
-      nlo = fmax(nlo, __shfl_xor(nlo, off));
-      nhi = fmin(nhi, __shfl_xor(nhi, off));
+    // within the slot's L = 4 or 8 lanes
+    nlo = fmax(nlo, dpp_get<DPP_XOR1>(nlo));
+    nhi = fmin(nhi, dpp_get<DPP_XOR1>(nhi));
+    nlo = fmax(nlo, dpp_get<DPP_XOR2>(nlo));
+    nhi = fmin(nhi, dpp_get<DPP_XOR2>(nhi));
+    if (L == 8) {
+      nlo = fmax(nlo, dpp_get<DPP_HALF_MIRROR>(nlo));
+      nhi = fmin(nhi, dpp_get<DPP_HALF_MIRROR>(nhi));
     }
     if (!done) {
       lo = fmax(lo, nlo);
       hi = fmin(hi, nhi);
-      done = hi - lo <= 4e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+      // an isolating interval of relative width 1e-10 is enough: inverse
+      // iteration converges from it and the Rayleigh quotient refines it
+      done = hi - lo <= 1e-10 * fmax(fabs(lo), fabs(hi)) + 1e-300;
     }
   }
   if (slot < r && sub == 0) s_lam[slot] = 0.5 * (lo + hi);
@@ -986,6 +981,14 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
       const double inv = 1.0 / sqrt(nrm2);
       for (int i = 0; i < n; ++i) sy[i * r + l] *= inv;
     }
+    // the Rayleigh quotient z^T T_r z of the normalised vector
+    double rq = 0.0, zp = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double zi = sy[i * r + l];
+      rq += zi * (s_d[i] * zi + 2.0 * (i > 0 ? s_ea[i - 1] * zp : 0.0));
+      zp = zi;
+    }
+    s_lam[l] = rq;
   }
   wave_sync();
   // orthogonalise within clusters of close eigenvalues, twice, in descending order

@@ -224,11 +224,36 @@ __device__ __forceinline__ float2 lane_get(float2 v, int src) { return make_floa
 __device__ __forceinline__ double2 lane_get(double2 v, int src) {
   return make_double2(lane_get(v.x, src), lane_get(v.y, src));
 }
-// sum over the 64 lanes
+// v from another lane by a DPP move (CTRL: quad_perm / row_ror / row_half_mirror)
+template <int CTRL>
+__device__ __forceinline__ double dpp_get(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+#define DPP_XOR1 0xB1       // quad_perm [1,0,3,2]
+#define DPP_XOR2 0x4E       // quad_perm [2,3,0,1]
+#define DPP_ROR4 0x124      // row_ror:4
+#define DPP_ROR8 0x128      // row_ror:8
+#define DPP_HALF_MIRROR 0x141
+// maximum over the 64 lanes (every lane active)
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_get<DPP_XOR1>(v));
+  v = fmax(v, dpp_get<DPP_XOR2>(v));
+  v = fmax(v, dpp_get<DPP_ROR4>(v));
+  v = fmax(v, dpp_get<DPP_ROR8>(v));
+  return fmax(fmax(lane_get(v, 0), lane_get(v, 16)), fmax(lane_get(v, 32), lane_get(v, 48)));
+}
+__device__ __forceinline__ double wave_min(double v) { return -wave_max(-v); }
+// sum over the 64 lanes (every lane active): sums within rows of 16 by DPP,
+// then the four row sums
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v += dpp_get<DPP_XOR1>(v);
+  v += dpp_get<DPP_XOR2>(v);
+  v += dpp_get<DPP_ROR4>(v);
+  v += dpp_get<DPP_ROR8>(v);
+  return (lane_get(v, 0) + lane_get(v, 16)) + (lane_get(v, 32) + lane_get(v, 48));
 }
 // this wave's LDS writes are seen by its later LDS reads in any lane
 __device__ __forceinline__ void wave_sync() {
