@@ -783,6 +783,7 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
   extern __shared__ double2 lds_m[];  // q x q matrix, then q x q reflectors
   __shared__ double s_d[128], s_ea[128], s_e2[128], s_beta[128];
   __shared__ double2 s_ec[128], s_ph[128], s_w[128];
+  __shared__ double2 s_p[8][128];  // the reflector product's column-slice partials
   __shared__ double s_lam[16];
   const int tid = threadIdx.x, NT = blockDim.x, n = a.q, r = a.r;
   // row pitch ld odd: the rows one wave reads together fall in distinct LDS banks
@@ -801,82 +802,91 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     A[j * ld + i] = dconj(sum);
   }
   __syncthreads();
-  if (tid >= 64) return;  // one wave from here on
-  const int l = tid;
-  // ---- 1. Householder tridiagonalisation (full Hermitian trailing block kept)
+  // ---- 1. Householder tridiagonalisation (full Hermitian trailing block
+  // kept): wave 0 forms each reflector, the workgroup shares the product
+  // p = beta B v (8 column slices) and the rank-2 update of B
+  const int l = tid & 63, wv = tid >> 6;
   for (int k = 0; k + 2 < n; ++k) {
     const int k1 = k + 1, m = n - k1;
-    double sig = 0.0;
-    for (int i = 1 + l; i < m; i += 64) {
-      const double2 x = A[(k1 + i) * ld + k];
-      sig += x.x * x.x + x.y * x.y;
-    }
-    sig = wave_sum(sig);
-    const double2 x0 = A[k1 * ld + k];
-    if (sig == 0.0 && x0.y == 0.0) {  // already reduced: H_k = I
-      if (l == 0) {
-        s_beta[k] = 0.0;
-        s_ec[k] = x0;
+    if (wv == 0) {
+      double sig = 0.0;
+      for (int i = 1 + l; i < m; i += 64) {
+        const double2 x = A[(k1 + i) * ld + k];
+        sig += x.x * x.x + x.y * x.y;
       }
-      wave_sync();
-      continue;
-    }
-    const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y), nrm = sqrt(ax0 * ax0 + sig);
-    const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
-    const double2 alpha = make_double2(-ph.x * nrm, -ph.y * nrm);
-    const double2 v0 = dsub(x0, alpha);
-    const double beta = 2.0 / (v0.x * v0.x + v0.y * v0.y + sig);
-    for (int i = 1 + l; i < m; i += 64) Vh[(k1 + i) * ld + k] = A[(k1 + i) * ld + k];
-    if (l == 0) {
-      Vh[k1 * ld + k] = v0;
-      s_beta[k] = beta;
-      s_ec[k] = alpha;
-    }
-    wave_sync();
-    // p = beta B v, K = (beta / 2) v^H p, w = p - K v
-    double2 kp = make_double2(0.0, 0.0);
-    auto pmul = [&](int i) -> double2 {  // (beta B v)_i for a row of the trailing block
-      double2 acc = make_double2(0.0, 0.0);
-      if (i < m) {
-        const double2* row = A + (k1 + i) * ld + k1;
-        const double2* vk = Vh + k1 * ld + k;
-        double2 c0 = acc, c1 = acc, c2 = acc, c3 = acc;  // independent chains
-        int j = 0;
-        for (; j + 4 <= m; j += 4) {
-          c0 = dadd(c0, dmul(row[j], vk[j * ld]));
-          c1 = dadd(c1, dmul(row[j + 1], vk[(j + 1) * ld]));
-          c2 = dadd(c2, dmul(row[j + 2], vk[(j + 2) * ld]));
-          c3 = dadd(c3, dmul(row[j + 3], vk[(j + 3) * ld]));
+      sig = wave_sum(sig);
+      const double2 x0 = A[k1 * ld + k];
+      if (sig == 0.0 && x0.y == 0.0) {  // already reduced: H_k = I
+        if (l == 0) {
+          s_beta[k] = 0.0;
+          s_ec[k] = x0;
         }
-        for (; j < m; ++j) c0 = dadd(c0, dmul(row[j], vk[j * ld]));
-        acc = dadd(dadd(c0, c1), dadd(c2, c3));
-        acc = make_double2(beta * acc.x, beta * acc.y);
-        kp = dadd(kp, djmul(Vh[(k1 + i) * ld + k], acc));
+      } else {
+        const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y), nrm = sqrt(ax0 * ax0 + sig);
+        const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+        const double2 alpha = make_double2(-ph.x * nrm, -ph.y * nrm);
+        const double2 v0 = dsub(x0, alpha);
+        for (int i = 1 + l; i < m; i += 64) Vh[(k1 + i) * ld + k] = A[(k1 + i) * ld + k];
+        if (l == 0) {
+          Vh[k1 * ld + k] = v0;
+          s_beta[k] = 2.0 / (v0.x * v0.x + v0.y * v0.y + sig);
+          s_ec[k] = alpha;
+        }
       }
-      return acc;
-    };
-    const double2 pa = pmul(l), pb = pmul(l + 64);
-    kp = wave_sum2(kp);
-    const double2 K = make_double2(0.5 * beta * kp.x, 0.5 * beta * kp.y);
-    if (l < m) s_w[l] = dsub(pa, dmul(K, Vh[(k1 + l) * ld + k]));
-    if (l + 64 < m) s_w[l + 64] = dsub(pb, dmul(K, Vh[(k1 + l + 64) * ld + k]));
-    wave_sync();
-    // B -= v w^H + w v^H
+    }
+    __syncthreads();
+    const double beta = s_beta[k];
+    if (beta == 0.0) continue;  // the same in every thread
+    // partial products over column slices j = h (mod 8), 8 waves
+    if (wv < 8) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = l + 64 * h;
-      if (i < m) {
-        const double2 vi = Vh[(k1 + i) * ld + k], wi = s_w[i];
-        double2* row = A + (k1 + i) * ld + k1;
-#pragma unroll 8
-        for (int j = 0; j < m; ++j) {
-          const double2 vj = Vh[(k1 + j) * ld + k], wj = s_w[j];
-          row[j] = dsub(row[j], dadd(dmul(vi, dconj(wj)), dmul(wi, dconj(vj))));
+      for (int hh = 0; hh < 2; ++hh) {
+        const int i = l + 64 * hh;
+        if (i < m) {
+          const double2* row = A + (k1 + i) * ld + k1;
+          double2 acc = make_double2(0.0, 0.0);
+          for (int j = wv; j < m; j += 8) acc = dadd(acc, dmul(row[j], Vh[(k1 + j) * ld + k]));
+          s_p[wv][i] = acc;
         }
       }
     }
-    wave_sync();
+    __syncthreads();
+    // p = beta B v, K = (beta / 2) v^H p, w = p - K v (wave 0)
+    if (wv == 0) {
+      double2 pv[2];
+      double2 kp = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int i = l + 64 * hh;
+        double2 acc = make_double2(0.0, 0.0);
+        if (i < m) {
+#pragma unroll
+          for (int h = 0; h < 8; ++h) acc = dadd(acc, s_p[h][i]);
+          acc = make_double2(beta * acc.x, beta * acc.y);
+          kp = dadd(kp, djmul(Vh[(k1 + i) * ld + k], acc));
+        }
+        pv[hh] = acc;
+      }
+      kp = wave_sum2(kp);
+      const double2 K = make_double2(0.5 * beta * kp.x, 0.5 * beta * kp.y);
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int i = l + 64 * hh;
+        if (i < m) s_w[i] = dsub(pv[hh], dmul(K, Vh[(k1 + i) * ld + k]));
+      }
+    }
+    __syncthreads();
+    // B -= v w^H + w v^H, entry by entry over the workgroup
+    for (int e = tid; e < m * m; e += NT) {
+      const int i = e / m, j = e - (e / m) * m;
+      const double2 vi = Vh[(k1 + i) * ld + k], wi = s_w[i];
+      const double2 vj = Vh[(k1 + j) * ld + k], wj = s_w[j];
+      double2* aij = A + (k1 + i) * ld + k1 + j;
+      *aij = dsub(*aij, dadd(dmul(vi, dconj(wj)), dmul(wi, dconj(vj))));
+    }
+    __syncthreads();
   }
+  if (tid >= 64) return;  // one wave from here on
   // ---- 2. T_r: diagonal, |e_k|, and the phases of D
   for (int i = l; i < n; i += 64) s_d[i] = A[i * ld + i].x;
   if (l == 0 && n >= 2) s_ec[n - 2] = A[(n - 1) * ld + (n - 2)];
