@@ -509,7 +509,7 @@ __device__ __forceinline__ float2 rfac_entry(const double2* L, int r, int e) {
 // mode 1: plain CholeskyQR of U (no gradient).
 // ===========================================================================
 template <int RT>
-__global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
+__global__ __launch_bounds__(RT <= 8 ? 1024 : 256) void k_qr_small(QrSmallArgs a) {
   __shared__ double2 UU[256], UG[256], GG[256], Gh[256], Tm[256];
   __shared__ JacobiScratch js;
   __shared__ int s_ok;
@@ -657,18 +657,15 @@ __global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
   // U^H U+ = (U^H U - eta U^H G) R^{-1}: lane i solves x R = row i by forward
   // substitution (R = L^H); SD^2 = r - ||U^H U+||_F^2
   double fro = 0.0;
-  if (i < r) {
-    double2 x[RT];
-#pragma unroll
-    for (int j = 0; j < RT; ++j) {
-      double2 acc = (j < r) ? make_double2(UU[i * 16 + j].x - eta * UG[i * 16 + j].x,
-                                           UU[i * 16 + j].y - eta * UG[i * 16 + j].y)
-                            : make_double2(0.0, 0.0);
-#pragma unroll
+  if (i < r) {  // x in LDS (Tm, free after the first iteration's step size): short code, few registers
+    double2* x = Tm + i * 16;
+    for (int j = 0; j < r; ++j) {
+      double2 acc = make_double2(UU[i * 16 + j].x - eta * UG[i * 16 + j].x, UU[i * 16 + j].y - eta * UG[i * 16 + j].y);
       for (int k = 0; k < j; ++k) acc = dsub(acc, dmul(x[k], dconj(Gh[j * 16 + k])));  // R[k][j] = conj(L[j][k])
       const double rd = 1.0 / Gh[j * 16 + j].x;
-      x[j] = make_double2(acc.x * rd, acc.y * rd);
-      fro += x[j].x * x[j].x + x[j].y * x[j].y;
+      const double2 xj = make_double2(acc.x * rd, acc.y * rd);
+      x[j] = xj;
+      fro += xj.x * xj.x + xj.y * xj.y;
     }
   }
   fro = wave_sum(fro);
@@ -886,193 +883,204 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     }
     __syncthreads();
   }
-  if (tid >= 64) return;  // one wave from here on
-  // ---- 2. T_r: diagonal, |e_k|, and the phases of D
-  for (int i = l; i < n; i += 64) s_d[i] = A[i * ld + i].x;
-  if (l == 0 && n >= 2) s_ec[n - 2] = A[(n - 1) * ld + (n - 2)];
-  wave_sync();
-  for (int i = l; i + 1 < n; i += 64) {
-    const double2 e = s_ec[i];
-    const double ae = sqrt(e.x * e.x + e.y * e.y);
-    s_ea[i] = ae;
-    s_e2[i] = ae * ae;
-  }
-  if (l == 0) {
-    double2 ph = make_double2(1.0, 0.0);
-    s_ph[0] = ph;
-    for (int i = 0; i + 1 < n; ++i) {
+  if (wv == 0) {  // one wave: the tridiagonal eigenproblem
+    // ---- 2. T_r: diagonal, |e_k|, and the phases of D
+    for (int i = l; i < n; i += 64) s_d[i] = A[i * ld + i].x;
+    if (l == 0 && n >= 2) s_ec[n - 2] = A[(n - 1) * ld + (n - 2)];
+    wave_sync();
+    for (int i = l; i + 1 < n; i += 64) {
       const double2 e = s_ec[i];
       const double ae = sqrt(e.x * e.x + e.y * e.y);
-      if (ae > 0.0) ph = dmul(ph, make_double2(e.x / ae, e.y / ae));
-      s_ph[i + 1] = ph;
+      s_ea[i] = ae;
+      s_e2[i] = ae * ae;
     }
-  }
-  wave_sync();
-  // Gershgorin interval and scales
-  double glo = INFINITY, ghi = -INFINITY, emax2 = 0.0, scale = 0.0;
-  for (int i = l; i < n; i += 64) {
-    const double rad = (i > 0 ? s_ea[i - 1] : 0.0) + (i + 1 < n ? s_ea[i] : 0.0);
-    glo = fmin(glo, s_d[i] - rad);
-    ghi = fmax(ghi, s_d[i] + rad);
-    scale = fmax(scale, fabs(s_d[i]) + rad);
-    if (i + 1 < n) emax2 = fmax(emax2, s_e2[i]);
-  }
-  glo = wave_min(glo);
-  ghi = wave_max(ghi);
-  scale = fmax(wave_max(scale), 1e-300);
-  emax2 = wave_max(emax2);
-  const double pivmin = 2.3e-308 * fmax(1.0, emax2);
-  {
-    const double wdt = ghi - glo;
-    glo -= 1e-3 * wdt + 1e-300;
-    ghi += 1e-3 * wdt + 1e-300;
-  }
-  // ---- 3. multisection: RL eigenvalue slots of L lanes; slot j -> ascending index n-1-j
-  const int RL = r <= 8 ? 8 : 16, L = 64 / RL, slot = l / L, sub = l % L;
-  const int idx = n - 1 - slot;
-  double lo = glo, hi = ghi;
-  bool done = slot >= r;
-  for (int rnd = 0; rnd < 80; ++rnd) {
-    if (__all(done)) break;
-    const double x = lo + (hi - lo) * (double)(sub + 1) / (double)(L + 1);
-    const int cnt = done ? 0 : sturm_count(s_d, s_e2, n, x, pivmin);
-    double nlo = (!done && cnt <= idx) ? x : -INFINITY;
-    double nhi = (!done && cnt > idx) ? x : INFINITY;
-    // within the slot's L = 4 or 8 lanes
-    nlo = fmax(nlo, dpp_get<DPP_XOR1>(nlo));
-    nhi = fmin(nhi, dpp_get<DPP_XOR1>(nhi));
-    nlo = fmax(nlo, dpp_get<DPP_XOR2>(nlo));
-    nhi = fmin(nhi, dpp_get<DPP_XOR2>(nhi));
-    if (L == 8) {
-      nlo = fmax(nlo, dpp_get<DPP_HALF_MIRROR>(nlo));
-      nhi = fmin(nhi, dpp_get<DPP_HALF_MIRROR>(nhi));
-    }
-    if (!done) {
-      lo = fmax(lo, nlo);
-      hi = fmin(hi, nhi);
-      // an isolating interval of relative width 1e-10 is enough: inverse
-      // iteration converges from it and the Rayleigh quotient refines it
-      done = hi - lo <= 1e-10 * fmax(fabs(lo), fabs(hi)) + 1e-300;
-    }
-  }
-  if (slot < r && sub == 0) s_lam[slot] = 0.5 * (lo + hi);
-  wave_sync();
-  // ---- 4. inverse iteration, lane j < r for eigenvalue j; scratch in A's region
-  double* su = reinterpret_cast<double*>(A);  // u pivots [i * r + j]
-  double* sy = su + n * r;                    // right-hand side / solution [i * r + j]
-  if (l < r) {
-    const double lam = s_lam[l], tiny = 1e-14 * scale;
-    for (int i = 0; i < n; ++i) {  // a start vector of its own per lane (golden-ratio sequence)
-      const double t = (double)(i + 1) * (double)(2 * l + 3) * 0.6180339887498949;
-      sy[i * r + l] = 0.5 + (t - floor(t));
-    }
-    for (int it = 0; it < 3; ++it) {
-      double u = s_d[0] - lam, y = sy[l];
-#pragma unroll 4
+    if (l == 0) {
+      double2 ph = make_double2(1.0, 0.0);
+      s_ph[0] = ph;
       for (int i = 0; i + 1 < n; ++i) {
+        const double2 e = s_ec[i];
+        const double ae = sqrt(e.x * e.x + e.y * e.y);
+        if (ae > 0.0) ph = dmul(ph, make_double2(e.x / ae, e.y / ae));
+        s_ph[i + 1] = ph;
+      }
+    }
+    wave_sync();
+    // Gershgorin interval and scales
+    double glo = INFINITY, ghi = -INFINITY, emax2 = 0.0, scale = 0.0;
+    for (int i = l; i < n; i += 64) {
+      const double rad = (i > 0 ? s_ea[i - 1] : 0.0) + (i + 1 < n ? s_ea[i] : 0.0);
+      glo = fmin(glo, s_d[i] - rad);
+      ghi = fmax(ghi, s_d[i] + rad);
+      scale = fmax(scale, fabs(s_d[i]) + rad);
+      if (i + 1 < n) emax2 = fmax(emax2, s_e2[i]);
+    }
+    glo = wave_min(glo);
+    ghi = wave_max(ghi);
+    scale = fmax(wave_max(scale), 1e-300);
+    emax2 = wave_max(emax2);
+    const double pivmin = 2.3e-308 * fmax(1.0, emax2);
+    {
+      const double wdt = ghi - glo;
+      glo -= 1e-3 * wdt + 1e-300;
+      ghi += 1e-3 * wdt + 1e-300;
+    }
+    // ---- 3. multisection: RL eigenvalue slots of L lanes; slot j -> ascending index n-1-j
+    const int RL = r <= 8 ? 8 : 16, L = 64 / RL, slot = l / L, sub = l % L;
+    const int idx = n - 1 - slot;
+    double lo = glo, hi = ghi;
+    bool done = slot >= r;
+    for (int rnd = 0; rnd < 80; ++rnd) {
+      if (__all(done)) break;
+      const double x = lo + (hi - lo) * (double)(sub + 1) / (double)(L + 1);
+      const int cnt = done ? 0 : sturm_count(s_d, s_e2, n, x, pivmin);
+      double nlo = (!done && cnt <= idx) ? x : -INFINITY;
+      double nhi = (!done && cnt > idx) ? x : INFINITY;
+      // within the slot's L = 4 or 8 lanes
+      nlo = fmax(nlo, dpp_get<DPP_XOR1>(nlo));
+      nhi = fmin(nhi, dpp_get<DPP_XOR1>(nhi));
+      nlo = fmax(nlo, dpp_get<DPP_XOR2>(nlo));
+      nhi = fmin(nhi, dpp_get<DPP_XOR2>(nhi));
+      if (L == 8) {
+        nlo = fmax(nlo, dpp_get<DPP_HALF_MIRROR>(nlo));
+        nhi = fmin(nhi, dpp_get<DPP_HALF_MIRROR>(nhi));
+      }
+      if (!done) {
+        lo = fmax(lo, nlo);
+        hi = fmin(hi, nhi);
+        // an isolating interval of relative width 1e-10 is enough: inverse
+        // iteration converges from it and the Rayleigh quotient refines it
+        done = hi - lo <= 1e-10 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+      }
+    }
+    if (slot < r && sub == 0) s_lam[slot] = 0.5 * (lo + hi);
+    wave_sync();
+    // ---- 4. inverse iteration, lane j < r for eigenvalue j; scratch in A's region
+    double* su = reinterpret_cast<double*>(A);  // u pivots [i * r + j]
+    double* sy = su + n * r;                    // right-hand side / solution [i * r + j]
+    if (l < r) {
+      const double lam = s_lam[l], tiny = 1e-14 * scale;
+      for (int i = 0; i < n; ++i) {  // a start vector of its own per lane (golden-ratio sequence)
+        const double t = (double)(i + 1) * (double)(2 * l + 3) * 0.6180339887498949;
+        sy[i * r + l] = 0.5 + (t - floor(t));
+      }
+      for (int it = 0; it < 3; ++it) {
+        double u = s_d[0] - lam, y = sy[l];
+  #pragma unroll 4
+        for (int i = 0; i + 1 < n; ++i) {
+          if (fabs(u) <= tiny) u = tiny;
+          const double ru = rcp_nr(u);
+          su[i * r + l] = ru;  // 1 / u_i for the backward pass
+          sy[i * r + l] = y;
+          const double lm = s_ea[i] * ru;
+          u = s_d[i + 1] - lam - lm * s_ea[i];
+          y = sy[(i + 1) * r + l] - lm * y;
+        }
         if (fabs(u) <= tiny) u = tiny;
-        const double ru = rcp_nr(u);
-        su[i * r + l] = ru;  // 1 / u_i for the backward pass
-        sy[i * r + l] = y;
-        const double lm = s_ea[i] * ru;
-        u = s_d[i + 1] - lam - lm * s_ea[i];
-        y = sy[(i + 1) * r + l] - lm * y;
+        double xnext = y / u, nrm2 = xnext * xnext;
+        sy[(n - 1) * r + l] = xnext;
+  #pragma unroll 4
+        for (int i = n - 2; i >= 0; --i) {
+          const double xi = (sy[i * r + l] - s_ea[i] * xnext) * su[i * r + l];
+          sy[i * r + l] = xi;
+          nrm2 += xi * xi;
+          xnext = xi;
+        }
+        const double inv = 1.0 / sqrt(nrm2);
+        for (int i = 0; i < n; ++i) sy[i * r + l] *= inv;
       }
-      if (fabs(u) <= tiny) u = tiny;
-      double xnext = y / u, nrm2 = xnext * xnext;
-      sy[(n - 1) * r + l] = xnext;
-#pragma unroll 4
-      for (int i = n - 2; i >= 0; --i) {
-        const double xi = (sy[i * r + l] - s_ea[i] * xnext) * su[i * r + l];
-        sy[i * r + l] = xi;
-        nrm2 += xi * xi;
-        xnext = xi;
+      // the Rayleigh quotient z^T T_r z of the normalised vector
+      double rq = 0.0, zp = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double zi = sy[i * r + l];
+        rq += zi * (s_d[i] * zi + 2.0 * (i > 0 ? s_ea[i - 1] * zp : 0.0));
+        zp = zi;
       }
-      const double inv = 1.0 / sqrt(nrm2);
-      for (int i = 0; i < n; ++i) sy[i * r + l] *= inv;
+      s_lam[l] = rq;
     }
-    // the Rayleigh quotient z^T T_r z of the normalised vector
-    double rq = 0.0, zp = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double zi = sy[i * r + l];
-      rq += zi * (s_d[i] * zi + 2.0 * (i > 0 ? s_ea[i - 1] * zp : 0.0));
-      zp = zi;
-    }
-    s_lam[l] = rq;
-  }
-  wave_sync();
-  // orthogonalise within clusters of close eigenvalues, twice, in descending order
-  for (int j = 1; j < r; ++j) {
-    bool any = false;
-    for (int jp = 0; jp < j; ++jp) any = any || fabs(s_lam[jp] - s_lam[j]) <= 1e-3 * scale;
-    if (!any) continue;
-    for (int rep = 0; rep < 2; ++rep) {
-      for (int jp = 0; jp < j; ++jp) {
-        if (!(fabs(s_lam[jp] - s_lam[j]) <= 1e-3 * scale)) continue;
-        double dot = 0.0;
-        for (int i = l; i < n; i += 64) dot += sy[i * r + jp] * sy[i * r + j];
-        dot = wave_sum(dot);
-        for (int i = l; i < n; i += 64) sy[i * r + j] -= dot * sy[i * r + jp];
-        wave_sync();
+    wave_sync();
+    // orthogonalise within clusters of close eigenvalues, twice, in descending order
+    for (int j = 1; j < r; ++j) {
+      bool any = false;
+      for (int jp = 0; jp < j; ++jp) any = any || fabs(s_lam[jp] - s_lam[j]) <= 1e-3 * scale;
+      if (!any) continue;
+      for (int rep = 0; rep < 2; ++rep) {
+        for (int jp = 0; jp < j; ++jp) {
+          if (!(fabs(s_lam[jp] - s_lam[j]) <= 1e-3 * scale)) continue;
+          double dot = 0.0;
+          for (int i = l; i < n; i += 64) dot += sy[i * r + jp] * sy[i * r + j];
+          dot = wave_sum(dot);
+          for (int i = l; i < n; i += 64) sy[i * r + j] -= dot * sy[i * r + jp];
+          wave_sync();
+        }
       }
+      double nn = 0.0;
+      for (int i = l; i < n; i += 64) nn += sy[i * r + j] * sy[i * r + j];
+      const double inv = 1.0 / sqrt(wave_sum(nn));
+      for (int i = l; i < n; i += 64) sy[i * r + j] *= inv;
+      wave_sync();
     }
-    double nn = 0.0;
-    for (int i = l; i < n; i += 64) nn += sy[i * r + j] * sy[i * r + j];
-    const double inv = 1.0 / sqrt(wave_sum(nn));
-    for (int i = l; i < n; i += 64) sy[i * r + j] *= inv;
+    // ---- 5. Y = Q D Z, Y [i * r + j] complex over the start of A's region
+    double zr[2][16];
+  #pragma unroll
+    for (int h = 0; h < 2; ++h)
+  #pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int i = l + 64 * h;
+        zr[h][j] = (i < n && j < r) ? sy[i * r + j] : 0.0;
+      }
+    wave_sync();
+    double2* const Y0 = A;
+  #pragma unroll
+    for (int h = 0; h < 2; ++h)
+  #pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int i = l + 64 * h;
+        if (i < n && j < r) Y0[i * r + j] = make_double2(s_ph[i].x * zr[h][j], s_ph[i].y * zr[h][j]);
+      }
     wave_sync();
   }
-  // ---- 5. Y = Q D Z, Y [i * r + j] complex over the start of A's region
-  double zr[2][16];
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int i = l + 64 * h;
-      zr[h][j] = (i < n && j < r) ? sy[i * r + j] : 0.0;
-    }
-  wave_sync();
+  __syncthreads();
+  // back-transformation Y <- H_k Y, k descending, over the workgroup:
+  // thread = (column j = tid % 16, row group g = tid / 16); column sums by
+  // DPP-free shuffles within a wave, then across the 16 waves through LDS
   double2* Y = A;
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int i = l + 64 * h;
-      if (i < n && j < r) Y[i * r + j] = make_double2(s_ph[i].x * zr[h][j], s_ph[i].y * zr[h][j]);
-    }
-  wave_sync();
-  // lane = (column j = l % 16, row group g = l / 16: rows i = g mod 4)
-  const int jc = l & 15, g4 = l >> 4;
+  const int jc = tid & 15, g64 = tid >> 4;
+  double2* s_sj = &s_p[0][0];  // [wave][16] partial sums, then the 16 totals
   for (int k = n - 3; k >= 0; --k) {
     const double beta = s_beta[k];
-    if (beta == 0.0) continue;
+    if (beta == 0.0) continue;  // the same in every thread
     double2 sj = make_double2(0.0, 0.0);
-    if (jc < r) {
-#pragma unroll 4
-      for (int i = k + 1 + g4; i < n; i += 4) sj = dadd(sj, djmul(Vh[i * ld + k], Y[i * r + jc]));
-    }
+    if (jc < r)
+      for (int i = k + 1 + g64; i < n; i += 64) sj = dadd(sj, djmul(Vh[i * ld + k], Y[i * r + jc]));
 #pragma unroll
     for (int off = 16; off < 64; off <<= 1) {
       sj.x += __shfl_xor(sj.x, off);
       sj.y += __shfl_xor(sj.y, off);
     }
-    if (jc < r) {
-      const double2 bs = make_double2(beta * sj.x, beta * sj.y);
-#pragma unroll 4
-      for (int i = k + 1 + g4; i < n; i += 4) Y[i * r + jc] = dsub(Y[i * r + jc], dmul(Vh[i * ld + k], bs));
+    if (l < 16) s_sj[wv * 16 + l] = sj;
+    __syncthreads();
+    if (tid < 16) {
+      double2 t = make_double2(0.0, 0.0);
+      for (int w = 0; w < NT / 64; ++w) t = dadd(t, s_sj[w * 16 + tid]);
+      s_sj[256 + tid] = make_double2(beta * t.x, beta * t.y);
     }
-    wave_sync();
+    __syncthreads();
+    for (int e2 = tid; e2 < (n - k - 1) * r; e2 += NT) {
+      const int i = k + 1 + e2 / r, j = e2 % r;
+      Y[i * r + j] = dsub(Y[i * r + j], dmul(Vh[i * ld + k], s_sj[256 + j]));
+    }
+    __syncthreads();
   }
   const double lam0 = s_lam[0], lamr = s_lam[r - 1];
   if (!(lamr > 1e-14 * lam0) || !(lam0 > 0.0)) {
-    if (l == 0) set_error(a.st, 4, -1);
+    if (tid == 0) set_error(a.st, 4, -1);
     return;
   }
-  for (int e = l; e < n * r; e += 64) {
-    const int j = e % r;
+  for (int e2 = tid; e2 < n * r; e2 += NT) {
+    const int j = e2 % r;
     const double sc = 1.0 / sqrt(s_lam[j]);
-    const double2 v = Y[e];  // Y[k][j] with e = k * r + j
-    a.Vs[e] = make_float2((float)(v.x * sc), (float)(v.y * sc));
+    const double2 v = Y[e2];  // Y[k][j] with e2 = k * r + j
+    a.Vs[e2] = make_float2((float)(v.x * sc), (float)(v.y * sc));
   }
 }
 
@@ -1145,8 +1153,9 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
+  // the 16-row form keeps its one-wave registers with 256 threads
   if (a.r <= 8) hipLaunchKernelGGL(k_qr_small<8>, dim3(1), dim3(1024), 0, s, a);
-  else hipLaunchKernelGGL(k_qr_small<16>, dim3(1), dim3(1024), 0, s, a);
+  else hipLaunchKernelGGL(k_qr_small<16>, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

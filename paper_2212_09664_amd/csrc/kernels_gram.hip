@@ -684,6 +684,7 @@ __global__ __launch_bounds__(256 * NSM) void k_qr_gram_mma(GramColsArgs a) {
   }
 }
 
+// (three or four row tiles keep their accumulators with one stream of 256 threads)
 hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s) {
   const int trm = (2 * (a.m1 + a.m2) + 15) / 16;
   const dim3 g(nblk);
@@ -691,15 +692,15 @@ hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_
     switch (trm) {
       case 1: hipLaunchKernelGGL((k_qr_gram_mma<double, 1, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
       case 2: hipLaunchKernelGGL((k_qr_gram_mma<double, 2, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_qr_gram_mma<double, 3, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
-      default: hipLaunchKernelGGL((k_qr_gram_mma<double, 4, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_qr_gram_mma<double, 3, 1>), g, dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_qr_gram_mma<double, 4, 1>), g, dim3(256), 0, s, a); break;
     }
   } else {
     switch (trm) {
       case 1: hipLaunchKernelGGL((k_qr_gram_mma<float, 1, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
       case 2: hipLaunchKernelGGL((k_qr_gram_mma<float, 2, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_qr_gram_mma<float, 3, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
-      default: hipLaunchKernelGGL((k_qr_gram_mma<float, 4, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_qr_gram_mma<float, 3, 1>), g, dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_qr_gram_mma<float, 4, 1>), g, dim3(256), 0, s, a); break;
     }
   }
   return hipGetLastError();
