@@ -427,7 +427,8 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
 
 // Gram of [U grad] (summing the partial gradients) and the small QR-step
 // work; mode 0 a step, mode 2 only the step size at the first iteration
-hipError_t qr_step_small(altgdmin_ctx* c, int mode, int check_halt) {
+// the QR Gram of [U grad] (summing the adjoint's partial gradients)
+hipError_t qr_step_gram(altgdmin_ctx* c, int check_halt) {
   const altgdmin_params& p = c->p;
   GramColsArgs g{};
   g.A = c->at<float2>(c->o_Ui);
@@ -445,7 +446,11 @@ hipError_t qr_step_small(altgdmin_ctx* c, int mode, int check_halt) {
   tmark(c, TK_QRGRAM);
   hipError_t e = launch_qr_gram(g, c->qr_nblk, c->fp64, c->stream);
   tmark(c, TK_QRGRAM);
-  if (e != hipSuccess) return e;
+  return e;
+}
+
+QrSmallArgs qr_small_args(altgdmin_ctx* c, int mode, int check_halt) {
+  const altgdmin_params& p = c->p;
   QrSmallArgs qa{};
   qa.part = c->at<double2>(c->o_qpart);
   qa.part_f32 = !c->fp64;
@@ -463,9 +468,39 @@ hipError_t qr_step_small(altgdmin_ctx* c, int mode, int check_halt) {
   qa.rfac = c->at<float2>(c->o_rfac);
   qa.st = c->st();
   qa.check_halt = check_halt;
+  return qa;
+}
+
+hipError_t qr_step_small(altgdmin_ctx* c, int mode, int check_halt) {
+  hipError_t e = qr_step_gram(c, check_halt);
+  if (e != hipSuccess) return e;
+  const QrSmallArgs qa = qr_small_args(c, mode, check_halt);
   tmark(c, TK_QRSMALL);
   e = launch_qr_small(qa, c->stream);
   tmark(c, TK_QRSMALL);
+  return e;
+}
+
+// the step and the update fused (rank <= 8): QR Gram, then one kernel that
+// factors and updates, then the commit of its outcome
+hipError_t qr_step_apply(altgdmin_ctx* c, float2* U, float2* U_prev) {
+  const altgdmin_params& p = c->p;
+  hipError_t e = qr_step_gram(c, 1);
+  if (e != hipSuccess) return e;
+  const QrSmallArgs qa = qr_small_args(c, 0, 1);
+  ApplyArgs aa{};
+  aa.U = U;
+  aa.Ui = c->at<float2>(c->o_Ui);
+  aa.G = c->at<float2>(c->o_G);
+  aa.rfac = c->at<float2>(c->o_rfac);
+  aa.U_prev = U_prev;
+  aa.n = c->n;
+  aa.r = p.r;
+  aa.mode = 0;
+  aa.st = c->st();
+  tmark(c, TK_APPLY);
+  e = launch_step_apply(qa, aa, c->stream);
+  tmark(c, TK_APPLY);
   return e;
 }
 
@@ -473,6 +508,7 @@ hipError_t one_iteration(altgdmin_ctx* c, float2* U, float2* U_prev) {
   const altgdmin_params& p = c->p;
   hipError_t e = gradient_pieces(c, 1);
   if (e != hipSuccess) return e;
+  if (p.r <= 8) return qr_step_apply(c, U, U_prev);
   e = qr_step_small(c, 0, 1);
   if (e != hipSuccess) return e;
   ApplyArgs aa{};

@@ -59,9 +59,13 @@ struct DevState {
   double grad_norm;   // ||grad||_F of the last iteration
   double cost_out;    // scratch for altgdmin_cost
   int32_t n_gwork;    // LINES: (line, sample tile) work items of the Gram kernel
-  int32_t pad_i;
-  double pad[5];
+  int32_t step_flags; // the fused QR step's outcome, committed after it (STEP_*)
+  double eta_next;    // the step size it used (committed after it)
+  double pad[4];
 };
+#define STEP_APPLIED 1
+#define STEP_EXIT 2
+#define STEP_CONVERGED 4
 
 // ---------------------------------------------------------------------------
 // in-register DFTs of radix 2, 4, 8, 16

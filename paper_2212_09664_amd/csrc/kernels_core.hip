@@ -156,6 +156,8 @@ __global__ void k_state_reset(DevState* st, int full) {
   st->exited = 0;
   st->converged = 0;
   st->eta = -1.0;
+  st->step_flags = 0;
+  st->eta_next = -1.0;
   st->f = 0.0;
   st->sd = 0.0;
   st->grad_norm = 0.0;
@@ -745,6 +747,223 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 // ===========================================================================
 // IN_LDS: matrix and eigenvectors in dynamic LDS (q <= 64; the accesses are
 // then LDS instructions), else in the workspace
+// ===========================================================================
+// the QR step fused with the update (r <= 8): every workgroup sums the QR
+// Gram partials, takes the step size (Algorithm 2's rule at t = 1, then the
+// stored one), factors Uhat^H Uhat = L L^H in one wave, and solves
+// U+ R = U - eta grad for its 1024 pixels, R = L^H.  Every workgroup computes
+// the same factor from the same partials in the same order.  Workgroup 0
+// also forms SD(U, U+) and the cost; no workgroup writes a state field that
+// another reads during the launch: the outcome (applied, exit rule,
+// stationary start) and the step size go to step_flags / eta_next and are
+// committed by k_step_commit.
+// ===========================================================================
+template <int RT>
+__global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap) {
+  __shared__ double2 UU[256], UG[256], GG[256], Gh[256], Tm[256];
+  __shared__ JacobiScratch js;
+  __shared__ double2 red2[1024];
+  __shared__ float2 Rf[RT * RT];
+  __shared__ int s_ok;
+  __shared__ double s_eta;
+  const int tid = threadIdx.x, r = a.r, wv = tid >> 6, l = tid & 63;
+  DevState* st = a.st;
+  const long n = ap.n, p = (long)blockIdx.x * 1024 + tid, pc = min(p, n - 1);
+  // this pixel's basis row and gradient, requested first (clamped, valid addresses)
+  float2 u0[RT], g0[RT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i) {
+    u0[i] = (i < r) ? ap.U[(long)i * n + pc] : make_float2(0.f, 0.f);
+    g0[i] = (i < r) ? ap.G[pc * r + i] : make_float2(0.f, 0.f);
+  }
+  // the Gram of [U G] from the partials: thread = (output, slice of partials)
+  const int m = 2 * r, nout = m * (m + 1) / 2;
+  const int NS = max(1, 1024 / nout), OW = 1024 / NS;
+  for (int o0 = 0; o0 < nout; o0 += OW) {
+    const int o = o0 + tid % OW, sl = tid / OW;
+    double2 sum = make_double2(0.0, 0.0);
+    if (o < nout && sl < NS) {
+      if (a.part_f32) {
+        const float2* pf = reinterpret_cast<const float2*>(a.part);
+#pragma unroll 8
+        for (int b = sl; b < a.nblk; b += NS) sum = dadd(sum, f2d(pf[(long)b * nout + o]));
+      } else {
+#pragma unroll 8
+        for (int b = sl; b < a.nblk; b += NS) sum = dadd(sum, a.part[(long)b * nout + o]);
+      }
+    }
+    red2[tid] = sum;
+    __syncthreads();
+    if (tid < OW && o < nout) {
+      for (int q2 = 1; q2 < NS; ++q2) sum = dadd(sum, red2[tid + q2 * OW]);
+      int i, j;
+      tri_index(o, m, i, j);
+      if (j < r) {
+        UU[i * 16 + j] = sum;
+        UU[j * 16 + i] = dconj(sum);
+      } else if (i < r) {
+        UG[i * 16 + (j - r)] = sum;
+      } else {
+        GG[(i - r) * 16 + (j - r)] = sum;
+        GG[(j - r) * 16 + (i - r)] = dconj(sum);
+      }
+    }
+    __syncthreads();
+  }
+  // halt and eta are not written during this launch; err only when a factor
+  // fails, which then fails in every workgroup alike.  Thread 0 reads them
+  // once for the whole workgroup.
+  if (tid == 0) {
+    s_ok = !(st->err || (a.check_halt && st->halt));
+    s_eta = st->eta;
+  }
+  __syncthreads();
+  if (!s_ok) return;
+  if (!(s_eta > 0.0)) {  // first iteration: eta = eta_c / ||grad||_2 (with the guard and the cap)
+    for (int e = tid; e < 256; e += 1024) Tm[e] = GG[e];
+    __syncthreads();
+    jacobi_eig<1>(Tm, r, 16, nullptr, &js, 40);
+    __syncthreads();
+    if (tid == 0) {
+      double lam = 0.0;
+      for (int i = 0; i < r; ++i) lam = fmax(lam, Tm[i * 16 + i].x);
+      const double smax = sqrt(lam);
+      if (!(smax > a.guard * st->ysq)) {
+        s_ok = 0;  // stationary start
+        if (blockIdx.x == 0) {
+          st->grad_norm = smax;
+          st->step_flags = STEP_CONVERGED;
+        }
+      } else {
+        s_eta = a.eta_c / smax;
+      }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    if (a.eta_cap_c > 0.0) {  // cap: eta <= c n / (mbar ||B_0||_2^2)
+      for (int e = tid; e < r * r; e += 1024) {
+        const int i = e / r, j = e % r;
+        double2 sum = make_double2(0.0, 0.0);
+        for (int k = 0; k < a.q; ++k)
+          sum = dadd(sum, dmul(f2d(a.B[(long)k * r + i]), dconj(f2d(a.B[(long)k * r + j]))));
+        Tm[i * 16 + j] = sum;
+      }
+      __syncthreads();
+      jacobi_eig<1>(Tm, r, 16, nullptr, &js, 40);
+      __syncthreads();
+      if (tid == 0) {
+        double lam = 0.0;
+        for (int i = 0; i < r; ++i) lam = fmax(lam, Tm[i * 16 + i].x);
+        const double cap = a.eta_cap_c * (double)a.n / (st->mbar * lam);
+        if (cap < s_eta) s_eta = cap;
+      }
+      __syncthreads();
+    }
+  }
+  const double eta = s_eta;
+  if (wv == 0) {  // one wave: the Cholesky factor (rows in lanes, padded with the identity)
+    auto gh = [&](int a_, int b_) -> double2 {  // (Uhat^H Uhat)[a_][b_]
+      const double2 ug = UG[a_ * 16 + b_], gu = dconj(UG[b_ * 16 + a_]);
+      const double2 v = UU[a_ * 16 + b_], g = GG[a_ * 16 + b_];
+      return make_double2(v.x - eta * (ug.x + gu.x) + eta * eta * g.x, v.y - eta * (ug.y + gu.y) + eta * eta * g.y);
+    };
+    double2 g[RT];
+#pragma unroll
+    for (int mm = 0; mm < RT; ++mm) g[mm] = (l < r && mm < r) ? gh(l, mm) : make_double2(l == mm ? 1.0 : 0.0, 0.0);
+    const double dmax = wave_max((l < r) ? gh(l, l).x : 0.0);
+    const bool ok = wave_chol<double, double2, RT>(g, r, 1e-14 * dmax);
+    if (!ok) {
+      if (l == 0) {
+        s_ok = 0;
+        set_error(st, 4, -1);
+      }
+    } else {
+#pragma unroll
+      for (int mm = 0; mm < RT; ++mm)
+        if (l < RT && mm <= l) Gh[l * 16 + mm] = g[mm];
+      wave_sync();
+      for (int e = l; e < r * r; e += 64) Rf[(e / r) * RT + (e % r)] = rfac_entry(Gh, r, e);
+      if (blockIdx.x == 0) {
+        // U^H U+ = (U^H U - eta U^H G) R^{-1}, row by row; SD^2 = r - ||U^H U+||_F^2
+        double fro = 0.0;
+        if (l < r) {
+          double2* x = Tm + l * 16;
+          for (int j = 0; j < r; ++j) {
+            double2 acc =
+                make_double2(UU[l * 16 + j].x - eta * UG[l * 16 + j].x, UU[l * 16 + j].y - eta * UG[l * 16 + j].y);
+            for (int k = 0; k < j; ++k) acc = dsub(acc, dmul(x[k], dconj(Gh[j * 16 + k])));
+            const double rd = 1.0 / Gh[j * 16 + j].x;
+            const double2 xj = make_double2(acc.x * rd, acc.y * rd);
+            x[j] = xj;
+            fro += xj.x * xj.x + xj.y * xj.y;
+          }
+        }
+        fro = wave_sum(fro);
+        double fv = 0.0;  // f = sum_k cost_k
+        for (int k = l; k < a.q; k += 64) fv += a.cost_k[k];
+        fv = wave_sum(fv);
+        if (l == 0) {
+          const double sd2 = fmax(0.0, (double)r - fro);
+          double tr = 0.0;
+          for (int mm = 0; mm < r; ++mm) tr += GG[mm * 16 + mm].x;
+          st->sd = sqrt(sd2);
+          st->grad_norm = sqrt(tr);
+          st->f = fv;
+          st->eta_next = eta;
+          st->step_flags = STEP_APPLIED | ((a.eps_exit > 0.0 && sqrt(sd2 / r) < a.eps_exit) ? STEP_EXIT : 0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (!s_ok || p >= n) return;
+  // U+ R = U - eta grad for this pixel (forward substitution, 1 / R_jj on the diagonal)
+  const float etaf = (float)eta;
+  float2 un[RT];
+#pragma unroll
+  for (int j = 0; j < RT; ++j) {
+    un[j] = make_float2(0.f, 0.f);
+    if (j < r) {
+      if (ap.U_prev) ap.U_prev[(long)j * n + p] = u0[j];
+      float2 sv = make_float2(u0[j].x - etaf * g0[j].x, u0[j].y - etaf * g0[j].y);
+#pragma unroll
+      for (int i = 0; i < j; ++i) sv = csub(sv, cmul(un[i], Rf[i * RT + j]));
+      un[j] = cscale(sv, Rf[j * RT + j].x);
+      ap.U[(long)j * n + p] = un[j];
+      if (ap.Ui) ap.Ui[p * r + j] = un[j];
+    }
+  }
+}
+
+// the fused step's outcome into the state (one thread, after it)
+__global__ void k_step_commit(DevState* st) {
+  if (threadIdx.x != 0) return;
+  const int f = st->step_flags;
+  st->step_flags = 0;
+  st->step_ok = 0;
+  if (st->err) return;
+  if (f & STEP_CONVERGED) {
+    st->converged = 1;
+    st->halt = 1;
+  } else if (f & STEP_APPLIED) {
+    st->eta = st->eta_next;
+    st->t += 1;
+    st->step_ok = 1;
+    if (f & STEP_EXIT) {
+      st->exited = 1;
+      st->halt = 1;
+    }
+  }
+}
+
+hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStream_t s) {
+  if (a.r > 8) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((ap.n + 1023) / 1024));
+  hipLaunchKernelGGL(k_step_apply<8>, g, dim3(1024), 0, s, a, ap);
+  hipLaunchKernelGGL(k_step_commit, dim3(1), dim3(64), 0, s, a.st);
+  return hipGetLastError();
+}
+
 // one-wave reductions
 __device__ __forceinline__ double2 wave_sum2(double2 v) { return make_double2(wave_sum(v.x), wave_sum(v.y)); }
 

@@ -370,5 +370,6 @@ __global__ void k_to_colmajor(const float2* src, int r, long n, float2* dst);
 __global__ void k_to_pixmajor(const float2* src, int r, long n, float2* dst);
 hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s);
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s);
+hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStream_t s);
 
 }  // namespace ag
