@@ -174,6 +174,26 @@ def test_end_to_end_small_ragged(kind):
     assert rel(Xg, ref.X) < 1e-3
 
 
+@pytest.mark.parametrize("r", [8, 12, 16])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "mixed"])
+def test_end_to_end_ranks_around_the_step_kernels(r, precision):
+    """Rank 8 runs the QR step fused with the update; ranks above 8 the
+    separate step (one-wave factor of 16 rows) and update, with the QR Gram
+    of three or four row tiles."""
+    log(f"end-to-end r={r} precision={precision}")
+    p = datagen.make_small(32, 32, 3, 20, r, seed=30 + r, kind="lines", n_lines=12, lowrank=True,
+                           snr_db=40.0, variable_m=True)
+    cs = Case(p)
+    ctx, Xg, ref = _end_to_end(cs, 8, precision=precision)
+    st = ctx.stats()
+    n_gpu, n_ref = M.nmse(Xg, p.zstar), M.nmse(ref.X, p.zstar)
+    log(f"  NMSE gpu {n_gpu:.6e} oracle {n_ref:.6e}; X rel {rel(Xg, ref.X):.2e}; t {st['t']}")
+    assert st["t"] == 8
+    assert abs(n_gpu - n_ref) <= 1e-4
+    assert rel(Xg, ref.X) < 1e-3
+    assert ctx.get_eta() == pytest.approx(ref.eta, rel=1e-4)
+
+
 def test_mixed_precision_end_to_end_gauss64():
     log("end-to-end gauss64 mixed")
     cs = Case(datagen.make("gauss64", 0))
