@@ -83,6 +83,9 @@ namespace {
   } while (0)
 
 // sum over lines of ceil(pairs / 8) <= (pairs + 7 lines) / 8, pairs <= q * width
+// workgroups of the spectral init's X0^H X0 on the matrix cores: 128 rows each, at most 512
+int init_nblk(const altgdmin_ctx* c) { return (int)std::max(1L, std::min(512L, ((long)c->n + 127) / 128)); }
+
 long gram_items_bound(const altgdmin_ctx* c) {
   return ((long)c->p.q * c->width + 7L * c->n_loc) / 8 + 1;
 }
@@ -138,7 +141,9 @@ void carve(altgdmin_ctx* c) {
   c->o_G = take(sizeof(float2) * (size_t)c->adj_parts * n * r);
   const int m_iter = 2 * r;
   const size_t qo = (size_t)std::max(m_iter * (m_iter + 1) / 2, q * (q + 1) / 2);
-  c->o_qpart = take(sizeof(double2) * qo * c->qr_nblk);
+  // QR Gram partials; the spectral init's Gram uses up to init_nblk of them
+  // plus one slot for their sum
+  c->o_qpart = take(sizeof(double2) * qo * (std::max(c->qr_nblk, init_nblk(c)) + 1));
   c->o_rfac = take(sizeof(float2) * r * r);
   c->o_Vs = take(sizeof(float2) * (size_t)q * r);
   c->o_V = take(sizeof(double2) * 2 * (size_t)q * (q | 1));  // matrix and reflectors, odd row pitch
@@ -750,10 +755,26 @@ altgdmin_status altgdmin_init(altgdmin_ctx* c, void* d_U) {
   g.rows_per_block = c->qr_rows;
   g.part = c->at<double2>(c->o_qpart);
   g.st = c->st();
-  HIPCHK(launch_gram_cols(g, c->qr_nblk, true, s));
+  g.nparts = 1;
+  g.a_colmajor = 1;
+  // X0^H X0 in FP64: up to 48 frames on the matrix cores (f64 16x16x4) over
+  // many short workgroups, whose partials a second kernel sums
   InitEigArgs ie{};
-  ie.part = c->at<double2>(c->o_qpart);
-  ie.nblk = c->qr_nblk;
+  if (p.q <= 48) {
+    const int nb = init_nblk(c);
+    g.rows_per_block = ((c->n + nb - 1) / nb + 31) / 32 * 32;
+    const int nbu = (int)((c->n + g.rows_per_block - 1) / g.rows_per_block);
+    HIPCHK(launch_qr_gram(g, nbu, true, s));
+    const int nout = p.q * (p.q + 1) / 2;
+    double2* sum = c->at<double2>(c->o_qpart) + (size_t)nbu * nout;
+    HIPCHK(launch_sum_partials(c->at<double2>(c->o_qpart), nbu, nout, sum, s));
+    ie.part = sum;
+    ie.nblk = 1;
+  } else {
+    HIPCHK(launch_gram_cols(g, c->qr_nblk, true, s));
+    ie.part = c->at<double2>(c->o_qpart);
+    ie.nblk = c->qr_nblk;
+  }
   ie.q = p.q;
   ie.r = p.r;
   ie.V = c->at<double2>(c->o_V);

@@ -163,6 +163,7 @@ struct GramColsArgs {
   int nparts;            // B is the sum of nparts arrays at stride part_stride
   long part_stride;
   int write_sum;         // store the summed B back into part 0
+  int a_colmajor;        // A is column-major n x m1 (else pixel-major [p][j])
   double2* part;         // per workgroup: its partial Gram (the QR Gram of FP32 MFMA stores float2 pairs)
   DevState* st;
   int check_halt;
@@ -371,5 +372,6 @@ __global__ void k_to_pixmajor(const float2* src, int r, long n, float2* dst);
 hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s);
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s);
 hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStream_t s);
+hipError_t launch_sum_partials(const double2* part, int nblk, int nout, double2* out, hipStream_t s);
 
 }  // namespace ag

@@ -556,7 +556,7 @@ template <typename T, int TRM, int NSM>
 __global__ __launch_bounds__(256 * NSM) void k_qr_gram_mma(GramColsArgs a) {
   using M = Mma<T>;
   constexpr int NT = TRM * (TRM + 1) / 2;
-  constexpr int RC = 64;  // rows per chunk staged in LDS
+  constexpr int RC = TRM <= 4 ? 64 : 32;  // rows per chunk staged in LDS (fewer for wide Grams: registers)
   // row pitch of the staged real embedding: the 4 rows one MFMA step reads
   // land in disjoint quarters of the 64 LDS banks
   constexpr int LDX = (16 * TRM) % 64 == 0 || (16 * TRM) % 64 == 32 ? 16 * TRM + 16 : 16 * TRM;
@@ -578,8 +578,13 @@ __global__ __launch_bounds__(256 * NSM) void k_qr_gram_mma(GramColsArgs a) {
   for (int q = 0; q < EM; ++q) {
     const int e = lt + 256 * q;
     if (e < RC * m1) {
-      erow[q] = e / m1;
-      ecol[q] = e - erow[q] * m1;
+      if (a.a_colmajor) {  // consecutive threads on consecutive rows of a column
+        ecol[q] = e / RC;
+        erow[q] = e - ecol[q] * RC;
+      } else {
+        erow[q] = e / m1;
+        ecol[q] = e - erow[q] * m1;
+      }
     } else if (e < RC * m) {
       const int f = e - RC * m1;
       erow[q] = f / m2;
@@ -599,7 +604,7 @@ __global__ __launch_bounds__(256 * NSM) void k_qr_gram_mma(GramColsArgs a) {
       const long p = p0 + erow[q];
       const bool ok = erow[q] < RC && p < pb;
       const bool isb = ecol[q] >= m1;
-      const long off = isb ? p * m2 + (ecol[q] - m1) : p * m1 + ecol[q];
+      const long off = isb ? p * m2 + (ecol[q] - m1) : (a.a_colmajor ? ecol[q] * a.n + p : p * m1 + ecol[q]);
       const float2* src = isb ? a.B : a.A;
 #pragma unroll
       for (int g = 0; g < 4; ++g)
@@ -644,8 +649,8 @@ __global__ __launch_bounds__(256 * NSM) void k_qr_gram_mma(GramColsArgs a) {
     __syncthreads();
     if (base + NSM * RC < pb) load(p0 + NSM * RC);  // in flight during this chunk's MFMAs
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const T* xr = Xs + (16 * wl + 4 * st + kk) * LDX + col;
+    for (int st = 0; st < RC / 16; ++st) {  // each wave takes RC / 4 rows, 4 per MFMA step
+      const T* xr = Xs + ((RC / 4) * wl + 4 * st + kk) * LDX + col;
       T xv[TRM];
 #pragma unroll
       for (int t = 0; t < TRM; ++t) xv[t] = xr[16 * t];
@@ -693,7 +698,11 @@ hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_
       case 1: hipLaunchKernelGGL((k_qr_gram_mma<double, 1, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
       case 2: hipLaunchKernelGGL((k_qr_gram_mma<double, 2, QR_NSM>), g, dim3(256 * QR_NSM), 0, s, a); break;
       case 3: hipLaunchKernelGGL((k_qr_gram_mma<double, 3, 1>), g, dim3(256), 0, s, a); break;
-      default: hipLaunchKernelGGL((k_qr_gram_mma<double, 4, 1>), g, dim3(256), 0, s, a); break;
+      case 4: hipLaunchKernelGGL((k_qr_gram_mma<double, 4, 1>), g, dim3(256), 0, s, a); break;
+      // wider Grams (the spectral init's q columns, up to 48)
+      case 5: hipLaunchKernelGGL((k_qr_gram_mma<double, 5, 1>), g, dim3(256), 0, s, a); break;
+      case 6: hipLaunchKernelGGL((k_qr_gram_mma<double, 6, 1>), g, dim3(256), 0, s, a); break;
+      default: return hipErrorInvalidValue;
     }
   } else {
     switch (trm) {
@@ -703,6 +712,31 @@ hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_
       default: hipLaunchKernelGGL((k_qr_gram_mma<float, 4, 1>), g, dim3(256), 0, s, a); break;
     }
   }
+  return hipGetLastError();
+}
+
+// sum over nblk partials of nout FP64 entries, in workgroup-slice order:
+// workgroup = 16 outputs x 16 slices of the partials, LDS tree over slices
+__global__ __launch_bounds__(256) void k_sum_partials(const double2* part, int nblk, int nout, double2* out) {
+  __shared__ double2 red[256];
+  const int tid = threadIdx.x, ol = tid & 15, sl = tid >> 4;
+  const int o = blockIdx.x * 16 + ol;
+  double2 acc = make_double2(0.0, 0.0);
+  if (o < nout) {
+#pragma unroll 16
+    for (int b = sl; b < nblk; b += 16) acc = dadd(acc, part[(long)b * nout + o]);
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int off = 128; off >= 16; off >>= 1) {
+    if (tid < off) red[tid] = dadd(red[tid], red[tid + off]);
+    __syncthreads();
+  }
+  if (tid < 16 && o < nout) out[o] = red[tid];
+}
+
+hipError_t launch_sum_partials(const double2* part, int nblk, int nout, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3((nout + 15) / 16), dim3(256), 0, s, part, nblk, nout, out);
   return hipGetLastError();
 }
 
