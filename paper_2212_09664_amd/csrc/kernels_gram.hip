@@ -57,6 +57,27 @@ __device__ __forceinline__ void tile_reduce_n(T* t, const typename Mma<T>::V& ac
   }
 }
 
+// Sum NTL tiles over the NW waves (one 16x16 accumulator per tile and wave)
+// into out[tile * 256 + entry] with two barriers: every wave writes its tiles
+// to scratch (NW * NTL * 256 values), then the workgroup adds them up in
+// wave order (the order of tile_reduce_n, so the sums are the same).
+template <typename T, int NW, int NTL>
+__device__ __forceinline__ void tiles_reduce_par(T* out, T* scratch, const typename Mma<T>::V (&acc)[NTL], int wave,
+                                                 int lane) {
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) scratch[(wave * NTL + t) * 256 + Mma<T>::row(lane, v) * 16 + (lane & 15)] = acc[t][v];
+  __syncthreads();
+  for (int e = threadIdx.x; e < NTL * 256; e += blockDim.x) {
+    T sum = scratch[e];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) sum += scratch[w * NTL * 256 + e];
+    out[e] = sum;
+  }
+  __syncthreads();
+}
+
 // Sum the 4 waves' tile (one 16x16 accumulator per wave) into LDS buffer t.
 template <typename T>
 __device__ __forceinline__ void tile_reduce(T* t, const typename Mma<T>::V& acc, int wave, int lane) {
@@ -230,11 +251,17 @@ __global__ __launch_bounds__(256 * NWG) void k_gram_lines_mma(GramLinesArgs a) {
   auto C = [&](const T* base, int ntile_cols, int i, int j) -> double {
     return (double)base[((i / 16) * ntile_cols + (j / 16)) * 256 + (i % 16) * 16 + (j % 16)];
   };
-  if (t == 0) {
+  constexpr int NTP = TR * TR + TR;
+  __shared__ T scr[4 * NWG * NTP * 256];
+  if (t == 0) {  // the P tiles and the h tiles together (red holds P, then h)
+    typename M::V all[NTP];
 #pragma unroll
-    for (int i = 0; i < TR; ++i)
+    for (int i = 0; i < TR; ++i) {
+      all[TR * TR + i] = H[i];
 #pragma unroll
-      for (int j = 0; j < TR; ++j) tile_reduce_n<T, 4 * NWG>(Pt + (i * TR + j) * 256, P[i][j], wave, lane);
+      for (int j = 0; j < TR; ++j) all[i * TR + j] = P[i][j];
+    }
+    tiles_reduce_par<T, 4 * NWG, NTP>(red, scr, all, wave, lane);
     double2* Pout = a.P + ((long)g * a.ua + u) * r * r;
     for (int e = tid; e < r * r; e += 256 * NWG) {
       const int i = e / r, j = e % r;
@@ -242,9 +269,9 @@ __global__ __launch_bounds__(256 * NWG) void k_gram_lines_mma(GramLinesArgs a) {
       const double im = C(Pt, TR, i, r + j) - C(Pt, TR, r + i, j);
       Pout[e] = make_double2(re, im);
     }
+  } else {
+    tiles_reduce_par<T, 4 * NWG, TR>(Ht, scr, H, wave, lane);
   }
-#pragma unroll
-  for (int i = 0; i < TR; ++i) tile_reduce_n<T, 4 * NWG>(Ht + i * 256, H[i], wave, lane);
   const int npt = min(8, np - 8 * t);
   for (int e = tid; e < npt * r; e += 256 * NWG) {
     const int p = e / r, j = e % r;
@@ -663,8 +690,13 @@ __global__ __launch_bounds__(256 * NSM) void k_qr_gram_mma(GramColsArgs a) {
         }
     }
   }
+  if constexpr (4 * NSM * NT * 256 * sizeof(T) <= 48 * 1024) {
+    __shared__ T scr[4 * NSM * NT * 256];
+    tiles_reduce_par<T, 4 * NSM, NT>(red, scr, acc, wave, lane);
+  } else {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) tile_reduce_n<T, 4 * NSM>(red + t * 256, acc[t], wave, lane);
+    for (int t = 0; t < NT; ++t) tile_reduce_n<T, 4 * NSM>(red + t * 256, acc[t], wave, lane);
+  }
   // C(i, j) of the real 2m x 2m Gram from the upper tiles
   auto C = [&](int i, int j) -> double {
     if (i > j) {
