@@ -78,20 +78,6 @@ __device__ __forceinline__ void tiles_reduce_par(T* out, T* scratch, const typen
   __syncthreads();
 }
 
-// Sum the 4 waves' tile (one 16x16 accumulator per wave) into LDS buffer t.
-template <typename T>
-__device__ __forceinline__ void tile_reduce(T* t, const typename Mma<T>::V& acc, int wave, int lane) {
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int idx = Mma<T>::row(lane, v) * 16 + (lane & 15);
-        t[idx] = (w == 0) ? acc[v] : t[idx] + acc[v];
-      }
-    }
-    __syncthreads();
-  }
-}
 
 // ---------------------------------------------------------------------------
 // 1D Cartesian: one workgroup (4 waves) per (sampled line u, tile t of 8 of
@@ -342,11 +328,17 @@ __global__ __launch_bounds__(256) void k_gram_index_mma(GramIndexArgs a) {
   }
   T* Pt = red;
   T* Ht = red + TR * TR * 256;
+  {  // the P tiles, then the h tiles
+    constexpr int NTP = TR * TR + TR;
+    __shared__ T scr[4 * NTP * 256];
+    typename M::V all[NTP];
 #pragma unroll
-  for (int i = 0; i < TR; ++i) {
+    for (int i = 0; i < TR; ++i) {
+      all[TR * TR + i] = H[i];
 #pragma unroll
-    for (int j = 0; j < TR; ++j) tile_reduce<T>(Pt + (i * TR + j) * 256, P[i][j], wave, lane);
-    tile_reduce<T>(Ht + i * 256, H[i], wave, lane);
+      for (int j = 0; j < TR; ++j) all[i * TR + j] = P[i][j];
+    }
+    tiles_reduce_par<T, 4, NTP>(red, scr, all, wave, lane);
   }
   auto C = [&](const T* base, int ntile_cols, int i, int j) -> double {
     return (double)base[((i / 16) * ntile_cols + (j / 16)) * 256 + (i % 16) * 16 + (j % 16)];
