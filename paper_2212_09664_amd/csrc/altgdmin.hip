@@ -487,12 +487,13 @@ hipError_t qr_step_small(altgdmin_ctx* c, int mode, int check_halt) {
 }
 
 // the step and the update fused (rank <= 8): QR Gram, then one kernel that
-// factors and updates, then the commit of its outcome
+// factors and updates, then (exit rule on) the commit of its outcome
 hipError_t qr_step_apply(altgdmin_ctx* c, float2* U, float2* U_prev) {
   const altgdmin_params& p = c->p;
   hipError_t e = qr_step_gram(c, 1);
   if (e != hipSuccess) return e;
-  const QrSmallArgs qa = qr_small_args(c, 0, 1);
+  QrSmallArgs qa = qr_small_args(c, 0, 1);
+  qa.commit_direct = !(p.eps_exit > 0.0);
   ApplyArgs aa{};
   aa.U = U;
   aa.Ui = c->at<float2>(c->o_Ui);

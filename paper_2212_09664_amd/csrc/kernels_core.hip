@@ -753,10 +753,14 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 // stored one), factors Uhat^H Uhat = L L^H in one wave, and solves
 // U+ R = U - eta grad for its 1024 pixels, R = L^H.  Every workgroup computes
 // the same factor from the same partials in the same order.  Workgroup 0
-// also forms SD(U, U+) and the cost; no workgroup writes a state field that
-// another reads during the launch: the outcome (applied, exit rule,
-// stationary start) and the step size go to step_flags / eta_next and are
-// committed by k_step_commit.
+// also forms SD(U, U+) and the cost.  With the exit rule on, the outcome
+// (applied, exit rule, stationary start) and the step size go to step_flags /
+// eta_next and are committed by k_step_commit, because a halt written during
+// the launch would stop workgroups that have not yet updated their pixels.
+// With it off (commit_direct), workgroup 0 commits t and eta itself: t is
+// read by no workgroup, and a workgroup that reads the new eta instead of the
+// unset one gets the value it would have computed (the same rule on the same
+// partials, bitwise); the stationary start halts every workgroup alike.
 // ===========================================================================
 template <int RT>
 __global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap) {
@@ -814,8 +818,8 @@ __global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap
   // fails, which then fails in every workgroup alike.  Thread 0 reads them
   // once for the whole workgroup.
   if (tid == 0) {
-    s_ok = !(st->err || (a.check_halt && st->halt));
-    s_eta = st->eta;
+    s_ok = !(st->err || (a.check_halt && __hip_atomic_load(&st->halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+    s_eta = __hip_atomic_load(&st->eta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   if (!s_ok) return;
@@ -832,7 +836,12 @@ __global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap
         s_ok = 0;  // stationary start
         if (blockIdx.x == 0) {
           st->grad_norm = smax;
-          st->step_flags = STEP_CONVERGED;
+          if (a.commit_direct) {
+            st->converged = 1;
+            __hip_atomic_store(&st->halt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            st->step_flags = STEP_CONVERGED;
+          }
         }
       } else {
         s_eta = a.eta_c / smax;
@@ -909,8 +918,14 @@ __global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap
           st->sd = sqrt(sd2);
           st->grad_norm = sqrt(tr);
           st->f = fv;
-          st->eta_next = eta;
-          st->step_flags = STEP_APPLIED | ((a.eps_exit > 0.0 && sqrt(sd2 / r) < a.eps_exit) ? STEP_EXIT : 0);
+          if (a.commit_direct) {
+            __hip_atomic_store(&st->eta, eta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st->t += 1;
+            st->step_ok = 1;
+          } else {
+            st->eta_next = eta;
+            st->step_flags = STEP_APPLIED | ((a.eps_exit > 0.0 && sqrt(sd2 / r) < a.eps_exit) ? STEP_EXIT : 0);
+          }
         }
       }
     }
@@ -960,7 +975,7 @@ hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStrea
   if (a.r > 8) return hipErrorInvalidValue;
   const dim3 g((unsigned)((ap.n + 1023) / 1024));
   hipLaunchKernelGGL(k_step_apply<8>, g, dim3(1024), 0, s, a, ap);
-  hipLaunchKernelGGL(k_step_commit, dim3(1), dim3(64), 0, s, a.st);
+  if (!a.commit_direct) hipLaunchKernelGGL(k_step_commit, dim3(1), dim3(64), 0, s, a.st);
   return hipGetLastError();
 }
 

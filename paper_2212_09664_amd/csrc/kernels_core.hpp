@@ -180,6 +180,7 @@ struct QrSmallArgs {
   float2* rfac;          // R = L^H (Uhat^H Uhat = L L^H), row-major r x r, upper, 1 / R_jj on the diagonal
   DevState* st;
   int check_halt;
+  int commit_direct;     // fused step only: workgroup 0 commits t and eta itself (the exit rule is off)
 };
 
 struct ApplyArgs {

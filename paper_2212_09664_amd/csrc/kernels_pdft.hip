@@ -14,7 +14,9 @@
 // the product keeps hi*hi + hi*lo + lo*hi.  The data operand is scaled by a
 // power of two per workgroup (and per coil) so that its largest entry sits
 // near 2^14, which keeps both halves in fp16's normal range.  DFT entries
-// come from an LDS table of (cos, sin) hi/lo pairs indexed by (ky*y) mod N.
+// come from two LDS tables (part 0: cos, part 1: the signed sin), one word
+// per entry holding its fp16 hi and lo halves, indexed by (ky*y) mod N; the
+// hi and lo fragments are two byte permutations of eight such words.
 //
 // MFMA lane layout (16x16x32 f16, gfx950): lane l holds A[l%16][8(l/16)+e]
 // and B[8(l/16)+e][l%16], e = 0..7; the result register v holds
@@ -25,10 +27,6 @@ namespace ag {
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-
-struct alignas(8) TwHL {
-  _Float16 ch, cl, sh, sl;  // cos and sin of 2 pi t / N, hi and lo
-};
 
 __device__ __forceinline__ void split_hl(float v, _Float16& h, _Float16& l) {
   h = (_Float16)v;
@@ -54,14 +52,52 @@ __device__ __forceinline__ float block_max(float v, float* red) {
   return m;
 }
 
-__device__ __forceinline__ void load_twiddles(TwHL* tw8, const float2* tw, int N) {
+// one DFT entry as a word: fp16 hi in the low half, fp16 lo in the high half
+__device__ __forceinline__ uint32_t pack_hl(float v) {
+  _Float16 h, l;
+  split_hl(v, h, l);
+  return (uint32_t)__builtin_bit_cast(uint16_t, h) | ((uint32_t)__builtin_bit_cast(uint16_t, l) << 16);
+}
+
+// the two halves of the contraction index: part 0 carries cos(2 pi t / N),
+// part 1 carries psign * sin(2 pi t / N)
+__device__ __forceinline__ void load_tables(uint32_t* t0, uint32_t* t1, const float2* tw, int N, float psign) {
   for (int t = threadIdx.x; t < N; t += blockDim.x) {
     const float2 w = tw[t];  // exp(-2 pi i t / N) = (cos, -sin)
-    TwHL e;
-    split_hl(w.x, e.ch, e.cl);
-    split_hl(-w.y, e.sh, e.sl);
-    tw8[t] = e;
+    t0[t] = pack_hl(w.x);
+    t1[t] = pack_hl(-psign * w.y);
   }
+}
+
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+
+// LDS of both kernels, tables first: their byte offsets then fit the
+// 16-bit immediate offset of an LDS read, so a lookup needs no base add
+template <int N>
+struct alignas(16) PdftLds {
+  uint32_t tw0[N], tw1[N];
+  int s_ky[N];
+  float red[4];
+  _Float16 D[4 * 32 * (N + 8)];
+};
+
+// eight table words -> the hi and lo A fragments (element e from word e).
+// v_perm_b32 picks bytes of the pair {S0, S1} (selector 0-3: S1, 4-7: S0):
+// hi dword k = low halves of words 2k, 2k+1; lo dword k = their high halves
+__device__ __forceinline__ void frag_hl(const uint32_t (&w)[8], h8& ah, h8& al) {
+  u4v h, l;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    h[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x05040100u);
+    l[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x07060302u);
+  }
+  ah = __builtin_bit_cast(h8, h);
+  al = __builtin_bit_cast(h8, l);
+}
+
+// the table word at byte offset b (a multiple of 4 below 4N)
+__device__ __forceinline__ uint32_t tword(const uint32_t* tb, uint32_t b) {
+  return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(tb) + b);
 }
 
 // B fragments for the four 16-column output tiles of a 32-column block:
@@ -105,16 +141,18 @@ __global__ __launch_bounds__(256) void k_pdft_fwd(PdftArgs a) {
   constexpr int LDK = N + 8;               // padded k stride of the staged operand
   constexpr int RT_W = (N / 16 + 3) / 4;   // row tiles per wave at most
   constexpr int EPT = N * 32 / 256;        // staged elements per thread
-  __shared__ TwHL tw8[N];
-  __shared__ _Float16 D[4 * 32 * LDK];
-  __shared__ int s_ky[N];
-  __shared__ float red[4];
+  __shared__ PdftLds<N> L;
+  uint32_t* tw0 = L.tw0;
+  uint32_t* tw1 = L.tw1;
+  _Float16* D = L.D;
+  int* s_ky = L.s_ky;
+  float* red = L.red;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (a.st->err || (a.check_halt && a.st->halt)) return;
   const int nu = a.st->n_units;
   const int c = blockIdx.y, r = a.r, ncols = a.nx * r;
   const int col0 = blockIdx.x * 32;
-  load_twiddles(tw8, a.tw, N);
+  load_tables(tw0, tw1, a.tw, N, -1.f);  // part 1: Im of exp(-i theta) = -sin
   for (int u = tid; u < nu; u += 256) s_ky[u] = a.unit_loc[u];
   // V = s_c o U on this block's 32 columns, all y
   float2 v[EPT];
@@ -147,33 +185,40 @@ __global__ __launch_bounds__(256) void k_pdft_fwd(PdftArgs a) {
   for (int s = 0; s < RT_W; ++s)
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[s][t] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < 2 * N; k0 += 32) {
-    const bool part1 = k0 >= N;
-    const int yb = (k0 & (N - 1)) + 8 * (lane >> 4);  // this lane's 8 consecutive y
-    h8 bh[4], bl[4];
-    b_frags(D, LDK, yb, part1, lane, bh, bl);
+  // this lane's row of each of its row tiles: ky in bytes of the table
+  // (rows past nu take ky = 0; their outputs are not stored, and a row of
+  // the product depends on its own A row only)
+  uint32_t ky4[RT_W];
 #pragma unroll
-    for (int s = 0; s < RT_W; ++s) {
-      const int rt = wave + 4 * s;
-      if (rt < nrt) {
-        const int u = 16 * rt + (lane & 15);
-        const int ky = (u < nu) ? s_ky[u] : 0;
-        const bool ok = u < nu;
-        h8 ah, al;
+  for (int s = 0; s < RT_W; ++s) {
+    const int u = 16 * (wave + 4 * s) + (lane & 15);
+    ky4[s] = (u < nu) ? 4u * (uint32_t)s_ky[u] : 0u;
+  }
+  auto kloop = [&](const uint32_t* tb, bool part1) {
+    for (int y0 = 0; y0 < N; y0 += 32) {
+      const int yb = y0 + 8 * (lane >> 4);  // this lane's 8 consecutive y
+      h8 bh[4], bl[4];
+      b_frags(D, LDK, yb, part1, lane, bh, bl);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const TwHL w = tw8[(ky * (yb + e)) & (N - 1)];
-          // part 0: cos; part 1: Im of exp(-i theta) = -sin
-          _Float16 h = part1 ? (_Float16)(-w.sh) : w.ch;
-          _Float16 l = part1 ? (_Float16)(-w.sl) : w.cl;
-          ah[e] = ok ? h : (_Float16)0.f;
-          al[e] = ok ? l : (_Float16)0.f;
+      for (int s = 0; s < RT_W; ++s) {
+        if (wave + 4 * s < nrt) {
+          uint32_t w[8];
+          uint32_t b = __umul24(ky4[s], (uint32_t)yb);  // 4 ky y, reduced mod 4N per entry
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            w[e] = tword(tb, b & (4u * N - 4u));
+            b += ky4[s];
+          }
+          h8 ah, al;
+          frag_hl(w, ah, al);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[s][t] = mma3(ah, al, bh[t], bl[t], acc[s][t]);
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[s][t] = mma3(ah, al, bh[t], bl[t], acc[s][t]);
       }
     }
-  }
+  };
+  kloop(tw0, false);
+  kloop(tw1, true);
   const float out_scale = a.scale / sig;
   float2* Wc = a.W + (long)c * a.ua * ncols;
 #pragma unroll
@@ -205,18 +250,21 @@ __global__ __launch_bounds__(256) void k_pdft_adj(PdftArgs a) {
   constexpr int LDK = N + 8;
   constexpr int RT_W = (N / 16 + 3) / 4;
   constexpr int EPT = N * 32 / 256;
-  __shared__ TwHL tw8[N];
-  __shared__ _Float16 D[4 * 32 * LDK];
-  __shared__ int s_ky[N];
-  __shared__ float red[4];
+  __shared__ PdftLds<N> L;
+  uint32_t* tw0 = L.tw0;
+  uint32_t* tw1 = L.tw1;
+  _Float16* D = L.D;
+  int* s_ky = L.s_ky;
+  float* red = L.red;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (a.st->err || (a.check_halt && a.st->halt)) return;
   const int nu = a.st->n_units;
   const int LP = (nu + 31) & ~31;
   const int r = a.r, ncols = a.nx * r;
   const int col0 = blockIdx.x * 32;
-  load_twiddles(tw8, a.tw, N);
-  for (int u = tid; u < N; u += 256) s_ky[u] = (u < nu) ? a.unit_loc[u] : 0;
+  load_tables(tw0, tw1, a.tw, N, 1.f);  // part 1: Im of exp(+i theta) = +sin
+  // ky in bytes of the table; rows past nu take ky = 0 (their K rows are zero)
+  for (int u = tid; u < N; u += 256) s_ky[u] = (u < nu) ? 4 * a.unit_loc[u] : 0;
   f4 gre[RT_W][2], gim[RT_W][2];
 #pragma unroll
   for (int s = 0; s < RT_W; ++s)
@@ -254,29 +302,46 @@ __global__ __launch_bounds__(256) void k_pdft_adj(PdftArgs a) {
     for (int s = 0; s < RT_W; ++s)
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[s][t] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < 2 * LP; k0 += 32) {
-      const bool part1 = k0 >= LP;
-      const int ub = (part1 ? k0 - LP : k0) + 8 * (lane >> 4);  // this lane's 8 consecutive u
-      h8 bh[4], bl[4];
-      b_frags(D, LDK, ub, part1, lane, bh, bl);
+    auto kloop = [&](const uint32_t* tb, bool part1) {
+      for (int u0 = 0; u0 < LP; u0 += 32) {
+        const int ub = u0 + 8 * (lane >> 4);  // this lane's 8 consecutive u
+        h8 bh[4], bl[4];
+        b_frags(D, LDK, ub, part1, lane, bh, bl);
+        const int4 ka = *reinterpret_cast<const int4*>(s_ky + ub);
+        const int4 kb = *reinterpret_cast<const int4*>(s_ky + ub + 4);
+        const uint32_t k4[8] = {(uint32_t)ka.x, (uint32_t)ka.y, (uint32_t)ka.z, (uint32_t)ka.w,
+                                (uint32_t)kb.x, (uint32_t)kb.y, (uint32_t)kb.z, (uint32_t)kb.w};
+        // 4 ky y for this lane's row of row tile s: y = y0 + 64 s
+        // (the increments are hidden from the optimiser, which would
+        // otherwise fold the sums back into a 32-bit multiply per tile)
+        const uint32_t y0 = 16 * wave + (lane & 15);
+        uint32_t pk[8], inc[8];
 #pragma unroll
-      for (int s = 0; s < RT_W; ++s) {
-        const int rt = wave + 4 * s;
-        if (16 * rt < N) {
-          const int y = 16 * rt + (lane & 15);
-          h8 ah, al;
+        for (int e = 0; e < 8; ++e) {
+          pk[e] = k4[e] * y0;
+          inc[e] = k4[e] << 6;
+          asm volatile("" : "+v"(inc[e]));
+        }
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const TwHL w = tw8[(s_ky[ub + e] * y) & (N - 1)];
-            // part 0: cos; part 1: Im of exp(+i theta) = +sin
-            ah[e] = part1 ? w.sh : w.ch;
-            al[e] = part1 ? w.sl : w.cl;
+        for (int s = 0; s < RT_W; ++s) {
+          if (s > 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) pk[e] += inc[e];
           }
+          if (16 * (wave + 4 * s) < N) {
+            uint32_t w[8];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) acc[s][t] = mma3(ah, al, bh[t], bl[t], acc[s][t]);
+            for (int e = 0; e < 8; ++e) w[e] = tword(tb, pk[e] & (4u * N - 4u));
+            h8 ah, al;
+            frag_hl(w, ah, al);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[s][t] = mma3(ah, al, bh[t], bl[t], acc[s][t]);
+          }
         }
       }
-    }
+    };
+    kloop(tw0, false);
+    kloop(tw1, true);
     // conj(s_c) o T_c into the partial gradient
     const float inv = 1.f / sig;
     const float2* coil = a.coils + (long)c * a.n;
