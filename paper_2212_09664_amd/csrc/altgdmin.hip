@@ -62,7 +62,7 @@ struct altgdmin_ctx {
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
       o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rfac, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
-      o_fcmp, o_planes, o_gwork, o_coilb, o_yg, o_ysqp, o_end;
+      o_fcmp, o_planes, o_gwork, o_lineord, o_coilb, o_yg, o_ysqp, o_end;
   size_t T_bytes;
   // timing
   int timed = TK_NONE;
@@ -114,6 +114,7 @@ void carve(altgdmin_ctx* c) {
   // Gram work list: at most ceil(q/8) items per line, and at least one entry per
   // workgroup of the Gram launch (ny + 64 of them)
   c->o_gwork = take(sizeof(int4) * ((size_t)c->n_loc * ((q + 7) / 8) + (c->lines ? p.ny + 64 : 0)));
+  c->o_lineord = take(sizeof(int4) * (size_t)c->n_loc);  // the fold's line order, most pairs first
   c->o_planes = take(sizeof(double) * 256);
   c->o_coilb = take(sizeof(float2) * (size_t)n * nc);
   c->o_yg = take(c->lines ? sizeof(float2) * 8 * (size_t)gram_items_bound(c) * nc * p.nx : 0);
@@ -386,6 +387,7 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   // fold the residual over frames
   FoldArgs fa{};
   fa.unit_span = c->at<int2>(c->o_unitspan);
+  fa.line_order = c->at<int4>(c->o_lineord);
   fa.bcp = c->at<float2>(c->o_bcp);
   fa.W = c->at<float2>(c->o_W);
   fa.yu = c->at<float2>(c->o_yh);
@@ -407,7 +409,7 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   fa.check_halt = check_halt;
   tmark(c, TK_FOLD);
   if (c->lines) {
-    e = launch_fold2(fa, true, p.ny, p.nc, c->stream);
+    e = launch_fold2(fa, true, p.nc, p.ny, c->stream);
   } else {
     e = launch_fold2(fa, false, (int)((c->n + AG_NT - 1) / AG_NT), p.nc, c->stream);
   }
@@ -698,7 +700,9 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
   hipLaunchKernelGGL(k_inv_scan, dim3(1), dim3(1024), 0, s, c->at<uint32_t>(c->o_bitmap), c->nw, c->n_loc,
                      c->at<int32_t>(c->o_locptr), c->at<int32_t>(c->o_loc2unit), c->at<int32_t>(c->o_unitloc),
                      c->at<int2>(c->o_unitspan), c->st());
-  if (c->lines) HIPCHK(launch_gram_work(c->at<int2>(c->o_unitspan), c->at<int4>(c->o_gwork), c->st(), s));
+  if (c->lines)
+    HIPCHK(launch_gram_work(c->at<int2>(c->o_unitspan), c->at<int4>(c->o_gwork), c->at<int4>(c->o_lineord),
+                            c->n_loc, c->st(), s));
   hipLaunchKernelGGL(k_inv_fill, dim3((c->width + 255) / 256, p.q), dim3(256), 0, s, c->mask, c->m_k,
                      c->width, c->per, c->at<uint32_t>(c->o_bitmap), c->nw, c->at<int32_t>(c->o_locptr),
                      c->at<int32_t>(c->o_loc2unit), c->at<int2>(c->o_pairs), c->at<int32_t>(c->o_pairof),

@@ -224,7 +224,11 @@ __global__ void k_build_yu(const float2* yh, const int2* pairs, const int32_t* m
 template <int RT>
 __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
   __shared__ float2 bc[128 * RT];  // conj(b_p) of the line's pairs (at most q <= 128)
-  const int u = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  // grid (coils, rows): the lines with the most pairs first; the record of
+  // a row position past the sampled lines names an unsampled row below n_loc,
+  // so u is in range before it is checked
+  const int4 lrec = a.line_order[blockIdx.y];
+  const int u = lrec.x, c = blockIdx.x, tid = threadIdx.x;
   const int r = a.r, nx = a.nx;
   const bool vec = (r & 1) == 0;
   float2 w[RT];
@@ -242,13 +246,12 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
       for (int i = 0; i < RT; ++i) w[i] = (i < r) ? src[i] : make_float2(0.f, 0.f);
     }
   };
-  // the first chunk's W rows and the line's span are requested before the
-  // state is read (every address is valid either way), so that the latencies
-  // overlap; the span is used only once the line is known to be sampled
-  const int2 span = a.unit_span[u];
+  // the first chunk's W rows are requested before the state is read (every
+  // address is valid either way), so that the latencies overlap; the span is
+  // used only once the line is known to be sampled
   load_w(0);
   if (a.st->err || (a.check_halt && a.st->halt) || u >= a.st->n_units) return;
-  const int p0 = span.x, np = span.y;
+  const int p0 = lrec.y, np = lrec.z;
   const float2* Yc = a.yu + (long)a.nc * nx * p0 + (long)c * np * nx;  // this line and coil, [p][x]
   float2 ya[8], yb[8];
   auto load_y = [&](int x0, int pb, float2 (&yv)[8]) {

@@ -139,6 +139,7 @@ struct LossArgs {
 
 struct FoldArgs {
   const int2* unit_span;  // LINES: per sampled line, its first pair and pair count
+  const int4* line_order;  // LINES: per fold row position (line u, first pair, pair count, 0), most pairs first; n_loc entries
   const float2* bcp;      // LINES: conj(b_k) of every pair, in pair order (written by the solve)
   const float2* W;
   const float2* yu;      // LINES: per-line data [c][p][x]
@@ -352,7 +353,8 @@ __global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* 
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s);
 hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
-hipError_t launch_gram_work(const int2* unit_span, int4* items, DevState* st, hipStream_t s);
+hipError_t launch_gram_work(const int2* unit_span, int4* items, int4* line_order, int n_loc, DevState* st,
+                            hipStream_t s);
 __global__ void k_build_yg(const float2* yu, const int4* items, int nc, int nx, float2* yg, const DevState* st);
 hipError_t launch_cnn_pack(const float* Wl, int cin, int cout, int kp, int kpb, float* Wf, float* Wb, hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, int batch, hipStream_t s);

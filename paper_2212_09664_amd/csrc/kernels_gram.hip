@@ -172,9 +172,14 @@ __global__ void k_build_yg(const float2* yu, const int4* items, int nc, int nx, 
 }
 
 // the Gram kernel's work items (line u, sample tile t), one block of 1024
-// threads at setup: every sampled line contributes ceil(np_u / 8) items
-__global__ __launch_bounds__(1024) void k_gram_work(const int2* unit_span, int4* items, DevState* st) {
+// threads at setup: every sampled line contributes ceil(np_u / 8) items.
+// Also the fold's dispatch order: the sampled lines by pair count, largest
+// first (ties by index), then the unsampled rows in order, so that the
+// longest fold workgroups start first instead of ending the launch.
+__global__ __launch_bounds__(1024) void k_gram_work(const int2* unit_span, int4* items, int4* line_order,
+                                                    int n_loc, DevState* st) {
   __shared__ int s_off[1024];
+  __shared__ int s_np[1024];
   const int tid = threadIdx.x, nu = st->n_units;
   int cnt = 0;
   const int per = (nu + 1023) / 1024;
@@ -194,6 +199,20 @@ __global__ __launch_bounds__(1024) void k_gram_work(const int2* unit_span, int4*
     for (int t = 0; t < nt; ++t) items[o++] = make_int4(u, t, sp.x, sp.y);
   }
   if (tid == 1023) st->n_gwork = s_off[1023];
+  if (nu <= 1024) {
+    if (tid < nu) s_np[tid] = unit_span[tid].y;
+    __syncthreads();
+    if (tid < nu) {
+      const int m = s_np[tid];
+      int rk = 0;
+      for (int v = 0; v < nu; ++v) rk += (s_np[v] > m) || (s_np[v] == m && v < tid);
+      const int2 sp = unit_span[tid];
+      line_order[rk] = make_int4(tid, sp.x, sp.y, 0);
+    }
+    for (int u = nu + tid; u < n_loc; u += 1024) line_order[u] = make_int4(u, 0, 0, 0);
+  } else {
+    for (int u = tid; u < n_loc; u += 1024) line_order[u] = make_int4(u, u < nu ? unit_span[u].x : 0, u < nu ? unit_span[u].y : 0, 0);
+  }
 }
 
 template <typename T, int TR, int UN, int NWG>
@@ -517,8 +536,9 @@ static void launch_lines_tr(const GramLinesArgs& a, int ny, int ngroups, int ht,
   else hipLaunchKernelGGL((k_gram_lines_mma<T, TR, 1, NWG>), g, dim3(256 * NWG), 0, s, a);
 }
 
-hipError_t launch_gram_work(const int2* unit_span, int4* items, DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram_work, dim3(1), dim3(1024), 0, s, unit_span, items, st);
+hipError_t launch_gram_work(const int2* unit_span, int4* items, int4* line_order, int n_loc, DevState* st,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_work, dim3(1), dim3(1024), 0, s, unit_span, items, line_order, n_loc, st);
   return hipGetLastError();
 }
 
