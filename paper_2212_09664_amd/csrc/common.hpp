@@ -25,6 +25,18 @@ __device__ __forceinline__ float2 cmulj(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+// acc + a * b and acc + a * conj(b) as two fused multiply-adds per part
+// (cadd(acc, cmul(a, b)) costs six instructions: the sum is rounded apart)
+__device__ __forceinline__ float2 cfma(float2 acc, float2 a, float2 b) {
+  return make_float2(fmaf(-a.y, b.y, fmaf(a.x, b.x, acc.x)), fmaf(a.y, b.x, fmaf(a.x, b.y, acc.y)));
+}
+__device__ __forceinline__ float2 cfmaj(float2 acc, float2 a, float2 b) {
+  return make_float2(fmaf(a.y, b.y, fmaf(a.x, b.x, acc.x)), fmaf(-a.x, b.y, fmaf(a.y, b.x, acc.y)));
+}
+// acc + conj(a) * b
+__device__ __forceinline__ float2 cjfma(float2 acc, float2 a, float2 b) {
+  return make_float2(fmaf(a.y, b.y, fmaf(a.x, b.x, acc.x)), fmaf(-a.y, b.x, fmaf(a.x, b.y, acc.y)));
+}
 
 __device__ __forceinline__ double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }

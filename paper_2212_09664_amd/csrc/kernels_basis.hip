@@ -155,7 +155,7 @@ __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
 #pragma unroll
         for (int q = 0; q < RL; ++q) {
           const float2 cw = cp[(PL_ONE<N>() ? q : q * (N / RL)) * txx];
-          acc[it][q] = cadd(acc[it][q], cjmul(cw, vo[it][q]));
+          acc[it][q] = cjfma(acc[it][q], cw, vo[it][q]);
         }
       }
     }
@@ -271,9 +271,9 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
     const float2* bp = bc + p * RT;
     float2 res = make_float2(-yv.x, -yv.y);
 #pragma unroll
-    for (int i = 0; i < RT; ++i) res = cadd(res, cmulj(w[i], bp[i]));
+    for (int i = 0; i < RT; ++i) res = cfmaj(res, w[i], bp[i]);
 #pragma unroll
-    for (int j = 0; j < RT; ++j) kk[j] = cadd(kk[j], cmul(res, bp[j]));
+    for (int j = 0; j < RT; ++j) kk[j] = cfma(kk[j], res, bp[j]);
   };
   for (int x0 = 0; x0 < nx; x0 += AG_NT) {
     if (x0 > 0) {
@@ -334,11 +334,11 @@ __global__ __launch_bounds__(AG_NT) void k_fold_index2(FoldArgs a) {
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       bb[i] = (i < r) ? b[i] : make_float2(0.f, 0.f);
-      res = cadd(res, cmul(w[i], bb[i]));
+      res = cfma(res, w[i], bb[i]);
     }
     res = csub(res, a.y[((long)ke.x * a.nc + c) * a.m_max + ke.y]);
 #pragma unroll
-    for (int j = 0; j < RT; ++j) kk[j] = cadd(kk[j], cmulj(res, bb[j]));
+    for (int j = 0; j < RT; ++j) kk[j] = cfmaj(kk[j], res, bb[j]);
   }
 #pragma unroll
   for (int j = 0; j < RT; ++j)
