@@ -261,6 +261,37 @@ def cpu_baseline(iters: int, seed: int, T: int):
     return dict(value=T / step_s, init_s=t1 - t0, loop_s=t2 - t1, iters=iters, cores=O.WORKERS)
 
 
+def bandwidth_probe():
+    """Rates of torch's own copy, sum and fill kernels (HIP events, 20
+    launches after 3 warm-up ones) at sizes around a loop kernel's bytes: what
+    a plain streaming kernel reaches with the data resident in the last-level
+    cache (up to ~200 MB) and from HBM (larger)."""
+    import torch
+    def per_launch_us(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+    rows = []
+    for mb in (41, 64, 114, 256, 1024):
+        a = torch.randn(mb * 2**20 // 4, device="cuda:0")
+        b = torch.empty_like(a)
+        nbytes = mb * 2**20
+        us_c = per_launch_us(lambda: b.copy_(a))
+        us_r = per_launch_us(lambda: a.sum())
+        us_w = per_launch_us(lambda: b.fill_(1.0))
+        rows.append({"MiB": mb, "copy_GBps": round(2 * nbytes / us_c / 1e3), "read_GBps": round(nbytes / us_r / 1e3),
+                     "write_GBps": round(nbytes / us_w / 1e3)})
+        del a, b
+    print(json.dumps({"bandwidth_probe": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +309,8 @@ def main():
                     help="the headline figure is cine256; the others are for comparisons")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (scale reference for HBM byte counters)")
+    ap.add_argument("--bandwidth-probe", action="store_true",
+                    help="only time plain device copies, reads and writes of several sizes (practical ceilings)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -295,6 +328,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 5}), flush=True)
+        return
+    if args.bandwidth_probe:
+        bandwidth_probe()
         return
     global WORKLOAD
     WORKLOAD = args.workload
