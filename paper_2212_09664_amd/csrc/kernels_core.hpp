@@ -7,6 +7,8 @@
 #define SOLVE_NT 1024  // threads of the per-frame solve
 #define QR_NSM 2       // QR Gram: streams of 4 waves per workgroup
 #define GRAM_NWG 1     // per-line Gram: groups of 4 waves per workgroup
+#define GRAM_DS32 2    // per-line Gram, FP32: steps whose loads are issued together
+#define GRAM_DS64 4    // the same for FP64
 #define GCOLS_OPT 9   // outputs per thread in the column-Gram kernel (m <= 128)
 #define GCOLS_NT 1024
 

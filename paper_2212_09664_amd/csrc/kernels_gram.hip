@@ -135,7 +135,6 @@ __device__ __forceinline__ void gram_lines_loop(const GramLinesArgs& a, int u, i
   // wave-uniform base per step and a fixed per-lane offset, no masks (the
   // item's data is already zero past the line's count); a mask applied to a
   // loaded value would make the load wait at once
-  // (FP64 operands only: measured, the batched FP32 loads ran no faster)
   const bool fast = (nx % XB) == 0 && 2 * r == 16 * TR;
   const float* Wline = Wf + 2L * ((long)u * nx * r);  // line u of coil 0
   const long CS = 2L * a.ua * nx * r;                 // coil stride of W, floats
@@ -153,14 +152,14 @@ __device__ __forceinline__ void gram_lines_loop(const GramLinesArgs& a, int u, i
       Bv[q2] = (T)yp[256 * q2 + ly];
     }
   };
-  if constexpr (sizeof(T) == 8) {
+  {
     if (fast) {
       // the loads of DS steps are issued together, then their products run
       // (a step past the end loads a valid block of the last coil and skips
       // its products), so a workgroup waits for memory once per DS steps.
       // The group index is wave-uniform: in a scalar register, the step
-      // counters and base addresses are scalar too.
-      constexpr int DS = 8;
+      // counters and base addresses are scalar too.  DS measured per type.
+      constexpr int DS = sizeof(T) == 8 ? GRAM_DS64 : GRAM_DS32;
       const int wgu = __builtin_amdgcn_readfirstlane(wg);
       int ci = wgu / nxb, xb = wgu % nxb;  // (coil, row block) of the next step to load
       for (int it0 = wgu; it0 < niter; it0 += DS * NWG) {
