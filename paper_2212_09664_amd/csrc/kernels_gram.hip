@@ -695,35 +695,27 @@ __global__ __launch_bounds__(256 * NSM) void k_qr_gram_mma(GramColsArgs a) {
       ecol[q] = 0;
     }
   }
-  float2 v[EM];
-  // load (and for B, sum over the partial arrays) the chunk at row p0; rows
-  // at or past pb read as zero
+  // the chunk at row p0: every load issued unconditionally from a clamped,
+  // valid address into w (an A element loads its one entry four times, from
+  // the cache), and the masks and the sum over B's partial arrays applied
+  // only when the chunk is staged, so that the loads stay in flight during
+  // the previous chunk's matrix-core work
+  // (the arguments in registers: a per-lane choice between two argument
+  // fields would otherwise be a load from the argument block)
+  const float2* const pA = a.A;
+  const float2* const pB = a.B;
+  const long pstride = a.part_stride, ncol = a.n;
+  const int nparts = a.nparts, colmaj = a.a_colmajor;
+  float2 w[EM][4];
   auto load = [&](long p0) {
-    float2 w[EM][4];
 #pragma unroll
     for (int q = 0; q < EM; ++q) {
-      const long p = p0 + erow[q];
-      const bool ok = erow[q] < RC && p < pb;
+      const long p = min(p0 + min(erow[q], RC - 1), pb - 1);
       const bool isb = ecol[q] >= m1;
-      const long off = isb ? p * m2 + (ecol[q] - m1) : (a.a_colmajor ? ecol[q] * a.n + p : p * m1 + ecol[q]);
-      const float2* src = isb ? a.B : a.A;
+      const long off = isb ? p * m2 + (ecol[q] - m1) : (colmaj ? ecol[q] * ncol + p : p * m1 + ecol[q]);
+      const float2* src = isb ? pB : pA;
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
-        w[q][g] = (ok && (g == 0 || (isb && g < a.nparts))) ? src[g * a.part_stride + off] : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int q = 0; q < EM; ++q) v[q] = cadd(cadd(w[q][0], w[q][1]), cadd(w[q][2], w[q][3]));
-    for (int g0 = 4; g0 < a.nparts; g0 += 4) {  // more than four partial arrays
-#pragma unroll
-      for (int q = 0; q < EM; ++q) {
-        const long p = p0 + erow[q];
-        if (erow[q] < RC && p < pb && ecol[q] >= m1) {
-          const long off = p * m2 + (ecol[q] - m1);
-#pragma unroll
-          for (int g = 0; g < 4; ++g)
-            if (g0 + g < a.nparts) v[q] = cadd(v[q], a.B[(g0 + g) * a.part_stride + off]);
-        }
-      }
+      for (int g = 0; g < 4; ++g) w[q][g] = src[(isb ? min(g, nparts - 1) : 0) * pstride + off];
     }
   };
   typename M::V acc[NT];
@@ -739,12 +731,22 @@ __global__ __launch_bounds__(256 * NSM) void k_qr_gram_mma(GramColsArgs a) {
     T* Xs = X[sm];
 #pragma unroll
     for (int q = 0; q < EM; ++q) {
+      // element q (zero for rows at or past pb): the A entry, or the sum
+      // over B's partial arrays, in the order (0 + 1) + (2 + 3) + 4 + ...
+      const long p = p0 + erow[q];
+      const bool ok = erow[q] < RC && p < pb;
+      const bool isb = ecol[q] >= m1;
+      const float2 z = make_float2(0.f, 0.f);
+      float2 v = cadd(cadd(w[q][0], (isb && nparts > 1) ? w[q][1] : z),
+                      cadd((isb && nparts > 2) ? w[q][2] : z, (isb && nparts > 3) ? w[q][3] : z));
+      if (ok && isb)
+        for (int g0 = 4; g0 < nparts; ++g0)  // more than four partial arrays
+          v = cadd(v, pB[g0 * pstride + p * m2 + (ecol[q] - m1)]);
+      if (!ok) v = z;
       if (erow[q] < RC) {
-        const long p = p0 + erow[q];
-        Xs[erow[q] * LDX + ecol[q]] = (T)v[q].x;
-        Xs[erow[q] * LDX + m + ecol[q]] = (T)v[q].y;
-        if (a.write_sum && a.nparts > 1 && ecol[q] >= m1 && p < pb)
-          const_cast<float2*>(a.B)[p * m2 + (ecol[q] - m1)] = v[q];
+        Xs[erow[q] * LDX + ecol[q]] = (T)v.x;
+        Xs[erow[q] * LDX + m + ecol[q]] = (T)v.y;
+        if (a.write_sum && nparts > 1 && isb && p < pb) const_cast<float2*>(pB)[p * m2 + (ecol[q] - m1)] = v;
       }
     }
     __syncthreads();
