@@ -486,6 +486,9 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
   if (a.st->err || (a.check_halt && a.st->halt)) return;
   const int E = r * r + r;  // G entries then h entries
   if (a.kind == 0) {
+    const double2* const Pp = a.P;
+    const double2* const Hp = a.hp;
+    const long ua = a.ua, npairs = a.npairs;
     // sum over coil groups and the frame's lines; thread = (entry, slice of lines)
     const int L = mk / a.nx;
     __syncthreads();
@@ -494,14 +497,26 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
       const int e = e0 + tid % SW;
       const int sl = tid / SW;
       double2 s = make_double2(0.0, 0.0);
-      if (e < E && sl < NS) {
-        const int items = a.ngroups * L;
-#pragma unroll 8
-        for (int it = sl; it < items; it += NS) {
+      const int items = a.ngroups * L;
+      if (e < E && sl < NS && items > 0) {
+        // the first MI items' loads issued together from clamped, valid
+        // indices (the argument pointers in registers: a per-lane choice of
+        // argument field would be a load), then summed in item order
+        constexpr int MI = 8;
+        const bool isP = e < r * r;
+        const double2* const src = isP ? Pp : Hp;
+        double2 vv[MI];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          const int it = min(sl + i * NS, items - 1), gg = it / L, l = it - gg * L;
+          vv[i] = src[isP ? ((long)gg * ua + s_mk[l]) * r * r + e : ((long)gg * npairs + s_po[l]) * r + (e - r * r)];
+        }
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+          if (sl + i * NS < items) s = dadd(s, vv[i]);
+        for (int it = sl + MI * NS; it < items; it += NS) {
           const int gg = it / L, l = it - gg * L;
-          const double2 v = (e < r * r) ? a.P[((long)gg * a.ua + s_mk[l]) * r * r + e]
-                                        : a.hp[((long)gg * a.npairs + s_po[l]) * r + (e - r * r)];
-          s = dadd(s, v);
+          s = dadd(s, src[isP ? ((long)gg * ua + s_mk[l]) * r * r + e : ((long)gg * npairs + s_po[l]) * r + (e - r * r)]);
         }
       }
       part[tid] = s;
