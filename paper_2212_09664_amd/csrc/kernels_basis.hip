@@ -38,42 +38,48 @@ __global__ __launch_bounds__(AG_NT) void k_basis_fwd(BasisArgs a) {
   const int tid = threadIdx.x;
   const int txx = a.txx, r = a.r, ctr = txx * r;
   const int x0 = blockIdx.x * txx;
-  for (int e = tid; e < N; e += AG_NT) {
-    s_tw[e] = a.tw[e];
-    const int u = a.row_unit ? a.row_unit[e] : e;
-    s_ro[e] = u >= 0 ? u * a.nx * r : -1;
-  }
+  // the U tile and the first coil's values are requested first, then the
+  // tables (both loads before either store), then the state: one round trip
+  // (loads from clamped, valid addresses, not under a branch; elements out
+  // of the tile are zeroed where U and the coil values are multiplied)
+  bool okg[IT0];
   float2 uv[IT0][R0];
 #pragma unroll
-  for (int it = 0; it < IT0; ++it)
+  for (int it = 0; it < IT0; ++it) {
+    const int g0 = tid + it * AG_NT;
+    okg[it] = GM::in_ok(g0) && (g0 % CT) < ctr;
+    const int g = okg[it] ? g0 : 0, col = g % CT;
 #pragma unroll
-    for (int q = 0; q < R0; ++q) {
-      const int g = tid + it * AG_NT, col = g % CT, y = GM::in_row(g, q);
-      uv[it][q] = (GM::in_ok(g) && col < ctr) ? a.U[((long)y * a.nx + x0) * r + col] : make_float2(0.f, 0.f);
-    }
-  // the state is read once the first loads are in flight (their addresses are valid either way)
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
-  __syncthreads();
+    for (int q = 0; q < R0; ++q) uv[it][q] = a.U[((long)GM::in_row(g, q) * a.nx + x0) * r + col];
+  }
   const int cb = blockIdx.y * a.cgs, ce = min(a.nc, cb + a.cgs);
   float2 cv[IT0][R0];
   auto fetch = [&](int c) {
     const float2* coil = a.coils + (long)c * a.n;
 #pragma unroll
     for (int it = 0; it < IT0; ++it) {
-      const int g = tid + it * AG_NT, col = g % CT;
-      const bool ok = GM::in_ok(g) && col < ctr;
+      const int g = okg[it] ? tid + it * AG_NT : 0, col = g % CT;
       const float2* cp = coil + (long)blockIdx.x * N * txx + (g / CT) * txx + col / r;  // [x/txx][y][x%txx]
 #pragma unroll
-      for (int q = 0; q < R0; ++q) cv[it][q] = ok ? cp[q * (N / R0) * txx] : make_float2(0.f, 0.f);
+      for (int q = 0; q < R0; ++q) cv[it][q] = cp[q * (N / R0) * txx];
     }
   };
   if (cb < ce) fetch(cb);
+  for (int e = tid; e < N; e += AG_NT) {
+    const float2 t = a.tw[e];
+    const int u = a.row_unit ? a.row_unit[e] : e;
+    s_tw[e] = t;
+    s_ro[e] = u >= 0 ? u * a.nx * r : -1;
+  }
+  // the state is read once the first loads are in flight (their addresses are valid either way)
+  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  __syncthreads();
   for (int c = cb; c < ce; ++c) {
     float2 v0[IT0][R0], vo[ITL][RL];
 #pragma unroll
     for (int it = 0; it < IT0; ++it)
 #pragma unroll
-      for (int q = 0; q < R0; ++q) v0[it][q] = cmul(cv[it][q], uv[it][q]);
+      for (int q = 0; q < R0; ++q) v0[it][q] = okg[it] ? cmul(cv[it][q], uv[it][q]) : make_float2(0.f, 0.f);
     if (c + 1 < ce) fetch(c + 1);
     fft_regs<N, CT, AG_NT, false>(v0, vo, s, s_tw);
     float2* dst = a.W + (long)c * a.ua * a.nx * r + x0 * r;
@@ -107,10 +113,10 @@ __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
   const int tid = threadIdx.x;
   const int txx = a.txx, r = a.r, ctr = txx * r;
   const int x0 = blockIdx.x * txx;
-  for (int e = tid; e < N; e += AG_NT) {
-    float2 w = a.tw[e];
-    s_tw[e] = make_float2(w.x, -w.y);
+  for (int e = tid; e < N; e += AG_NT) {  // both loads before either store: one round trip
+    const float2 w = a.tw[e];
     const int u = a.row_unit ? a.row_unit[e] : e;
+    s_tw[e] = make_float2(w.x, -w.y);
     s_ro[e] = u >= 0 ? u * a.nx * r : -1;
   }
   __syncthreads();
