@@ -835,16 +835,15 @@ altgdmin_status altgdmin_init_warm(altgdmin_ctx* c, const void* d_M, void* d_U, 
   HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
   HIPCHK(gradient_pieces(c, 0));
   HIPCHK(qr_step_small(c, 2, 0));
+  // the gradient pass's solve left the spectral basis's per-frame costs:
+  // their sum is the spectral side of the comparison below
+  double* f = c->at<double>(c->o_fcmp);
+  hipLaunchKernelGGL(k_cost_total, dim3(1), dim3(1), 0, s, c->at<double>(c->o_cost), p.q, f, c->st());
   float2* Uc = c->at<float2>(c->o_Uc);
   hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, static_cast<const float2*>(d_M), Uc, (long)c->n * p.r);
   HIPCHK(hipGetLastError());
   HIPCHK(cholqr(c, Uc));
   HIPCHK(cholqr(c, Uc));
-  double* f = c->at<double>(c->o_fcmp);
-  HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
-  HIPCHK(fwd_transform(c, 0));
-  HIPCHK(gram_solve(c, 0));
-  hipLaunchKernelGGL(k_cost_total, dim3(1), dim3(1), 0, s, c->at<double>(c->o_cost), p.q, f, c->st());
   HIPCHK(to_pixmajor(c, Uc));
   HIPCHK(fwd_transform(c, 0));
   HIPCHK(gram_solve(c, 0));

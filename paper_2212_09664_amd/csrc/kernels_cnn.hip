@@ -80,29 +80,52 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
   const int nct = (a.cout + 15) >> 4;
   f4v acc[2] = {f4v{0.f, 0.f, 0.f, 0.f}, f4v{0.f, 0.f, 0.f, 0.f}};
   for (int c0 = 0; c0 < a.cin; c0 += CV_CH) {
-    const int nch = min(CV_CH, a.cin - c0);
+    // channels staged up to a multiple of 16 (the rest zero), so that the
+    // matrix-core loop below has no predicate and both output tiles are
+    // always computed (a second tile past cout is never stored): a branch
+    // in the loop would move the accumulators out of the matrix registers
+    // around every instruction
+    const int nch = min(CV_CH, a.cin - c0), nch4 = (nch + 15) & ~15;  // CV_CH is a multiple of 16
     __syncthreads();
-    for (int e = tid; e < nch * (CV_T + 2) * (CV_T + 2); e += 256) {
+    for (int e = tid; e < nch4 * (CV_T + 2) * (CV_T + 2); e += 256) {
       const int ci = e / ((CV_T + 2) * (CV_T + 2)), rem = e % ((CV_T + 2) * (CV_T + 2));
       const int rr = rem / (CV_T + 2), cc = rem % (CV_T + 2);
       const int gy = ty0 + rr - 1, gx = tx0 + cc - 1;
       float v = 0.f;
-      if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = Xb[(long)(c0 + ci) * plane + (long)gy * a.W + gx];
+      if (ci < nch && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = Xb[(long)(c0 + ci) * plane + (long)gy * a.W + gx];
       xs[ci][rr][cc] = v;
     }
-    for (int e = tid; e < 9 * nch * 32; e += 256) {
-      const int tap = e / (nch * 32), rem = e % (nch * 32), ci = rem / 32, co = rem % 32;
-      wsm[tap][ci][co] = a.Wp[((long)tap * a.cin + c0 + ci) * 32 + co];
+    // weights per tap as float4 rows (a tap's nch x 32 block is contiguous)
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const float4* wsrc = reinterpret_cast<const float4*>(a.Wp + ((long)tap * a.cin + c0) * 32);
+      for (int e = tid; e < nch4 * 8; e += 256) {
+        const float4 w4 = (e < nch * 8) ? wsrc[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float* d = &wsm[tap][e >> 3][4 * (e & 7)];
+        d[0] = w4.x;
+        d[1] = w4.y;
+        d[2] = w4.z;
+        d[3] = w4.w;
+      }
     }
     __syncthreads();
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap % 3;
-      for (int ci0 = 0; ci0 < nch; ci0 += 4) {
-        const int ci = ci0 + kq;
-        const bool ok = ci < nch;
-        const float bv = ok ? xs[ci][py + dy][px + dx] : 0.f;
-        acc[0] = mfma4(ok ? wsm[tap][ci][pl] : 0.f, bv, acc[0]);
-        if (nct > 1) acc[1] = mfma4(ok ? wsm[tap][ci][16 + pl] : 0.f, bv, acc[1]);
+      for (int ci0 = 0; ci0 < nch4; ci0 += 16) {  // four steps of 4 channels: their LDS reads first
+        float bv[4], w0[4], w1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ci = ci0 + 4 * u + kq;
+          bv[u] = xs[ci][py + dy][px + dx];
+          w0[u] = wsm[tap][ci][pl];
+          w1[u] = wsm[tap][ci][16 + pl];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc[0] = mfma4(w0[u], bv[u], acc[0]);
+          acc[1] = mfma4(w1[u], bv[u], acc[1]);
+        }
       }
     }
   }
