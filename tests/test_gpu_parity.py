@@ -222,3 +222,53 @@ def test_gradient_with_rank_below_the_register_tile(r):
     t1 = np.linalg.norm(AG.gradient(cs.op, U, Bref, np.zeros_like(cs.y)))
     t2 = np.linalg.norm(AG.gradient(cs.op, np.zeros_like(U), Bref, cs.y))
     assert np.linalg.norm(G - Gref) / max(t1, t2) < 1e-5
+
+
+@pytest.mark.parametrize("r", [4, 8])
+def test_exit_rule_matches_oracle(r):
+    """Algorithm 2's exit rule SD(U, U+)/sqrt(r) < 0.01 (with the exit rule
+    on, the fused step's outcome goes through the commit kernel): the GPU
+    stops at the oracle's iteration and returns the same X = U_{t-1} B_t.
+    The seed is one where every SD of the oracle's run lies at least 1 %
+    from the threshold (checked here), far beyond the GPU's error on SD."""
+    log(f"exit rule r={r}")
+    eps = 0.01
+    p = datagen.make_small(32, 32, 3, 20, r, seed=43, kind="lines", n_lines=12, lowrank=True, snr_db=40.0,
+                           variable_m=True)
+    cs = Case(p)
+    ref = AG.run(cs.op, cs.y, AG.Params(r=r, eps_exit=eps), record=True)
+    sd = np.array(ref.history["sd"]) / np.sqrt(r)
+    assert ref.history["exit_at"] == ref.iters and ref.iters < 70
+    assert np.min(np.abs(sd - eps)) > 0.01 * eps
+    ctx = cs.gpu_ctx(eps_exit=eps)
+    U = ctx.init()
+    Uprev = torch.empty_like(U)
+    B, done = ctx.iterate(70, U, U_prev=Uprev, sync=True)
+    st = ctx.stats()
+    Xg = from_gpu_U(Uprev) @ from_gpu_B(B)
+    log(f"  iterations gpu {done} oracle {ref.iters}; X rel {rel(Xg, ref.X):.2e}; sd/sqrt(r) gpu {st['sd'] / np.sqrt(r):.6f}")
+    assert done == ref.iters and st["t"] == ref.iters and st["exited"] == 1
+    assert st["sd"] / np.sqrt(r) == pytest.approx(sd[-1], rel=1e-3)
+    assert rel(Xg, ref.X) < 1e-3
+
+
+def test_step_commit_paths_agree():
+    """Rank <= 8 runs the QR step fused with the update.  With the exit rule
+    off, workgroup 0 commits t and eta itself; with it on, a one-thread
+    kernel commits them after the step.  A threshold that never fires must
+    leave the whole trajectory bitwise unchanged."""
+    log("commit paths")
+    p = datagen.make_small(32, 32, 3, 20, 8, seed=44, kind="lines", n_lines=12, lowrank=True, snr_db=40.0,
+                           variable_m=True)
+    cs = Case(p)
+    out = []
+    for eps in (0.0, 1e-30):
+        ctx = cs.gpu_ctx(eps_exit=eps)
+        U = ctx.init()
+        B, done = ctx.iterate(10, U, sync=True)
+        out.append((U.clone(), B.clone(), done, ctx.get_eta(), ctx.stats()))
+    (Ua, Ba, da, ea, sa), (Ub, Bb, db, eb, sb) = out
+    assert da == db == 10 and sa["t"] == sb["t"] == 10
+    assert sa["exited"] == 0 and sb["exited"] == 0
+    assert torch.equal(Ua, Ub) and torch.equal(Ba, Bb)
+    assert ea == eb and sa["f"] == sb["f"] and sa["sd"] == sb["sd"]
