@@ -62,7 +62,7 @@ struct altgdmin_ctx {
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
       o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rfac, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
-      o_fcmp, o_planes, o_gwork, o_lineord, o_coilb, o_yg, o_ysqp, o_end;
+      o_fcmp, o_planes, o_gwork, o_lineord, o_coilb, o_yg, o_ysqp, o_stsrc, o_end;
   size_t T_bytes;
   // timing
   int timed = TK_NONE;
@@ -146,6 +146,7 @@ void carve(altgdmin_ctx* c) {
   // plus one slot for their sum
   c->o_qpart = take(sizeof(double2) * qo * (std::max(c->qr_nblk, init_nblk(c)) + 1));
   c->o_rfac = take(sizeof(float2) * r * r);
+  c->o_stsrc = take(sizeof(double2) * 193);  // deferred statistics of the fused step
   c->o_Vs = take(sizeof(float2) * (size_t)q * r);
   c->o_V = take(sizeof(double2) * 2 * (size_t)q * (q | 1));  // matrix and reflectors, odd row pitch
   // temp: X0 plus the truncated hybrid data (LINES) or a chunk of coil images (INDEX)
@@ -496,6 +497,7 @@ hipError_t qr_step_apply(altgdmin_ctx* c, float2* U, float2* U_prev) {
   if (e != hipSuccess) return e;
   QrSmallArgs qa = qr_small_args(c, 0, 1);
   qa.commit_direct = !(p.eps_exit > 0.0);
+  qa.stats_src = c->at<double2>(c->o_stsrc);
   ApplyArgs aa{};
   aa.U = U;
   aa.Ui = c->at<float2>(c->o_Ui);
@@ -1004,6 +1006,8 @@ altgdmin_status altgdmin_get_stats(altgdmin_ctx* c, altgdmin_stats* out) {
   if (!c || !out) return ALTGDMIN_EINVAL;
   if (!c->bound) return ALTGDMIN_ESTATE;
   DevState h;
+  HIPCHK(launch_stats_finish(c->st(), c->at<double2>(c->o_stsrc), c->at<double>(c->o_cost), c->p.q, c->p.r,
+                             c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpy(&h, c->st(), sizeof(DevState), hipMemcpyDeviceToHost));
   out->t = h.t;

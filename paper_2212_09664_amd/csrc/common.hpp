@@ -73,7 +73,9 @@ struct DevState {
   int32_t n_gwork;    // LINES: (line, sample tile) work items of the Gram kernel
   int32_t step_flags; // the fused QR step's outcome, committed after it (STEP_*)
   double eta_next;    // the step size it used (committed after it)
-  double pad[4];
+  int32_t stats_pending;  // 1: f, sd and grad_norm of the last step wait in the statistics inputs
+  int32_t pad_i;
+  double pad[3];
 };
 #define STEP_APPLIED 1
 #define STEP_EXIT 2

@@ -161,6 +161,7 @@ __global__ void k_state_reset(DevState* st, int full) {
   st->f = 0.0;
   st->sd = 0.0;
   st->grad_norm = 0.0;
+  st->stats_pending = 0;
 }
 
 __global__ void k_state_set_eta(DevState* st, double eta) {
@@ -747,6 +748,28 @@ __global__ __launch_bounds__(AG_NT) void k_apply(ApplyArgs a) {
 // ===========================================================================
 // IN_LDS: matrix and eigenvectors in dynamic LDS (q <= 64; the accesses are
 // then LDS instructions), else in the workspace
+// ||U^H U+||_F^2 = ||(U^H U - eta U^H G) R^{-1}||_F^2, lanes l < r taking
+// row l by forward substitution with R = L^H (L in Gh, rows of stride 16;
+// x is a row scratch of stride 16); the caller sums over the wave.  The
+// fused step and the deferred statistics both use it, so that SD is the
+// same number either way.
+__device__ __forceinline__ double sd_row_sum(const double2* UU, const double2* UG, const double2* Gh, double2* Tm,
+                                             double eta, int r, int l) {
+  double fro = 0.0;
+  if (l < r) {
+    double2* x = Tm + l * 16;
+    for (int j = 0; j < r; ++j) {
+      double2 acc = make_double2(UU[l * 16 + j].x - eta * UG[l * 16 + j].x, UU[l * 16 + j].y - eta * UG[l * 16 + j].y);
+      for (int k = 0; k < j; ++k) acc = dsub(acc, dmul(x[k], dconj(Gh[j * 16 + k])));
+      const double rd = 1.0 / Gh[j * 16 + j].x;
+      const double2 xj = make_double2(acc.x * rd, acc.y * rd);
+      x[j] = xj;
+      fro += xj.x * xj.x + xj.y * xj.y;
+    }
+  }
+  return fro;
+}
+
 // ===========================================================================
 // the QR step fused with the update (r <= 8): every workgroup sums the QR
 // Gram partials, takes the step size (Algorithm 2's rule at t = 1, then the
@@ -893,36 +916,38 @@ __global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap
       wave_sync();
       for (int e = l; e < r * r; e += 64) Rf[(e / r) * RT + (e % r)] = rfac_entry(Gh, r, e);
       if (blockIdx.x == 0) {
-        // U^H U+ = (U^H U - eta U^H G) R^{-1}, row by row; SD^2 = r - ||U^H U+||_F^2
-        double fro = 0.0;
-        if (l < r) {
-          double2* x = Tm + l * 16;
-          for (int j = 0; j < r; ++j) {
-            double2 acc =
-                make_double2(UU[l * 16 + j].x - eta * UG[l * 16 + j].x, UU[l * 16 + j].y - eta * UG[l * 16 + j].y);
-            for (int k = 0; k < j; ++k) acc = dsub(acc, dmul(x[k], dconj(Gh[j * 16 + k])));
-            const double rd = 1.0 / Gh[j * 16 + j].x;
-            const double2 xj = make_double2(acc.x * rd, acc.y * rd);
-            x[j] = xj;
-            fro += xj.x * xj.x + xj.y * xj.y;
+        if (a.commit_direct) {
+          // exit rule off: SD, f and ||grad|| are only reported; their r x r
+          // inputs are stored and k_stats_finish forms them when asked
+          for (int e = l; e < 64; e += 64) {
+            const int i = e >> 3, j = e & 7;
+            a.stats_src[e] = UU[i * 16 + j];
+            a.stats_src[64 + e] = UG[i * 16 + j];
+            a.stats_src[128 + e] = Gh[i * 16 + j];
           }
-        }
-        fro = wave_sum(fro);
-        double fv = 0.0;  // f = sum_k cost_k
-        for (int k = l; k < a.q; k += 64) fv += a.cost_k[k];
-        fv = wave_sum(fv);
-        if (l == 0) {
-          const double sd2 = fmax(0.0, (double)r - fro);
-          double tr = 0.0;
-          for (int mm = 0; mm < r; ++mm) tr += GG[mm * 16 + mm].x;
-          st->sd = sqrt(sd2);
-          st->grad_norm = sqrt(tr);
-          st->f = fv;
-          if (a.commit_direct) {
+          if (l == 0) {
+            double tr = 0.0;
+            for (int mm = 0; mm < r; ++mm) tr += GG[mm * 16 + mm].x;
+            a.stats_src[192] = make_double2(eta, tr);
+            st->stats_pending = 1;
             __hip_atomic_store(&st->eta, eta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             st->t += 1;
             st->step_ok = 1;
-          } else {
+          }
+        } else {
+          // SD^2 = r - ||U^H U+||_F^2 decides the exit rule
+          const double fro = wave_sum(sd_row_sum(UU, UG, Gh, Tm, eta, r, l));
+          double fv = 0.0;  // f = sum_k cost_k
+          for (int k = l; k < a.q; k += 64) fv += a.cost_k[k];
+          fv = wave_sum(fv);
+          if (l == 0) {
+            const double sd2 = fmax(0.0, (double)r - fro);
+            double tr = 0.0;
+            for (int mm = 0; mm < r; ++mm) tr += GG[mm * 16 + mm].x;
+            st->sd = sqrt(sd2);
+            st->grad_norm = sqrt(tr);
+            st->f = fv;
+            st->stats_pending = 0;
             st->eta_next = eta;
             st->step_flags = STEP_APPLIED | ((a.eps_exit > 0.0 && sqrt(sd2 / r) < a.eps_exit) ? STEP_EXIT : 0);
           }
@@ -969,6 +994,39 @@ __global__ void k_step_commit(DevState* st) {
       st->halt = 1;
     }
   }
+}
+
+// the statistics the fused step left pending (exit rule off): SD, f and
+// ||grad||_F of the last applied step, from its r x r inputs and the
+// per-frame costs (no solve has run since), with the fused step's own code
+__global__ __launch_bounds__(64) void k_stats_finish(DevState* st, const double2* src, const double* cost_k, int q,
+                                                     int r) {
+  __shared__ double2 UU[256], UG[256], Gh[256], Tm[256];
+  const int l = threadIdx.x;
+  if (!st->stats_pending) return;
+  for (int e = l; e < 64; e += 64) {
+    const int i = e >> 3, j = e & 7;
+    UU[i * 16 + j] = src[e];
+    UG[i * 16 + j] = src[64 + e];
+    Gh[i * 16 + j] = src[128 + e];
+  }
+  const double2 et = src[192];
+  wave_sync();
+  const double fro = wave_sum(sd_row_sum(UU, UG, Gh, Tm, et.x, r, l));
+  double fv = 0.0;
+  for (int k = l; k < q; k += 64) fv += cost_k[k];
+  fv = wave_sum(fv);
+  if (l == 0) {
+    st->sd = sqrt(fmax(0.0, (double)r - fro));
+    st->grad_norm = sqrt(et.y);
+    st->f = fv;
+    st->stats_pending = 0;
+  }
+}
+
+hipError_t launch_stats_finish(DevState* st, const double2* src, const double* cost_k, int q, int r, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_finish, dim3(1), dim3(64), 0, s, st, src, cost_k, q, r);
+  return hipGetLastError();
 }
 
 hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStream_t s) {

@@ -184,6 +184,7 @@ struct QrSmallArgs {
   DevState* st;
   int check_halt;
   int commit_direct;     // fused step only: workgroup 0 commits t and eta itself (the exit rule is off)
+  double2* stats_src;    // fused step with commit_direct: the r x r inputs of the deferred statistics (193 entries)
 };
 
 struct ApplyArgs {
@@ -377,6 +378,7 @@ __global__ void k_to_pixmajor(const float2* src, int r, long n, float2* dst);
 hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s);
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s);
 hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStream_t s);
+hipError_t launch_stats_finish(DevState* st, const double2* src, const double* cost_k, int q, int r, hipStream_t s);
 hipError_t launch_sum_partials(const double2* part, int nblk, int nout, double2* out, hipStream_t s);
 
 }  // namespace ag
