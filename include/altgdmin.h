@@ -204,7 +204,9 @@ altgdmin_status altgdmin_gradient(altgdmin_ctx* ctx, const void* d_U, void* d_B,
 altgdmin_status altgdmin_apply_A(altgdmin_ctx* ctx, const void* d_X, void* d_Y);
 altgdmin_status altgdmin_apply_AH(altgdmin_ctx* ctx, const void* d_Y, void* d_X);
 
-/* Statistics of the last iteration (synchronises). */
+/* Statistics of the last iteration (synchronises).  When the exit rule is
+ * off, the loop only stores the r x r inputs of f, sd and grad_norm; this
+ * call forms them first (one small kernel on the context's stream). */
 altgdmin_status altgdmin_get_stats(altgdmin_ctx* ctx, altgdmin_stats* stats);
 
 /* The device error flag, if any (synchronises).  *frame receives the frame

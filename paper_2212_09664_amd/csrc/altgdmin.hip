@@ -279,10 +279,8 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
     g.nc = p.nc;
     g.r = p.r;
     g.nx = p.nx;
-    g.lmax = c->lmax;
     g.ua = c->ua;
     g.cg = c->gram_cg;
-    g.nx_shift = __builtin_ctz((unsigned)p.nx);
     g.npairs = (long)p.q * c->width;
     g.P = c->at<double2>(c->o_P);
     g.hp = c->at<double2>(c->o_hp);
@@ -315,7 +313,6 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
   s.hp = c->at<double2>(c->o_hp);
   s.mask = c->mask;
   s.m_k = c->m_k;
-  s.loc2unit = c->at<int32_t>(c->o_loc2unit);
   s.pair_of = c->at<int32_t>(c->o_pairof);
   s.unit_of = c->at<int32_t>(c->o_unitof);
   s.width = c->width;
@@ -387,7 +384,6 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   if (e != hipSuccess) return e;
   // fold the residual over frames
   FoldArgs fa{};
-  fa.unit_span = c->at<int2>(c->o_unitspan);
   fa.line_order = c->at<int4>(c->o_lineord);
   fa.bcp = c->at<float2>(c->o_bcp);
   fa.W = c->at<float2>(c->o_W);
@@ -396,13 +392,10 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   fa.B = c->at<float2>(c->o_B);
   fa.pairs = c->at<int2>(c->o_pairs);
   fa.loc_ptr = c->at<int32_t>(c->o_locptr);
-  fa.unit_loc = c->at<int32_t>(c->o_unitloc);
   fa.nc = p.nc;
   fa.r = p.r;
   fa.nx = p.nx;
-  fa.lmax = c->lmax;
   fa.ua = c->ua;
-  fa.cg = 1;
   fa.n = c->n;
   fa.m_max = p.m_max;
   fa.K = c->at<float2>(c->o_K);

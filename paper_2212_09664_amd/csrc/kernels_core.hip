@@ -775,15 +775,17 @@ __device__ __forceinline__ double sd_row_sum(const double2* UU, const double2* U
 // Gram partials, takes the step size (Algorithm 2's rule at t = 1, then the
 // stored one), factors Uhat^H Uhat = L L^H in one wave, and solves
 // U+ R = U - eta grad for its 1024 pixels, R = L^H.  Every workgroup computes
-// the same factor from the same partials in the same order.  Workgroup 0
-// also forms SD(U, U+) and the cost.  With the exit rule on, the outcome
+// the same factor from the same partials in the same order.  With the exit
+// rule on, workgroup 0 also forms SD(U, U+) and the cost, and the outcome
 // (applied, exit rule, stationary start) and the step size go to step_flags /
 // eta_next and are committed by k_step_commit, because a halt written during
 // the launch would stop workgroups that have not yet updated their pixels.
 // With it off (commit_direct), workgroup 0 commits t and eta itself: t is
 // read by no workgroup, and a workgroup that reads the new eta instead of the
 // unset one gets the value it would have computed (the same rule on the same
-// partials, bitwise); the stationary start halts every workgroup alike.
+// partials, bitwise); the stationary start halts every workgroup alike.  SD,
+// the cost and ||grad|| are then only reported: their r x r inputs are
+// stored and k_stats_finish forms them on request.
 // ===========================================================================
 template <int RT>
 __global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap) {

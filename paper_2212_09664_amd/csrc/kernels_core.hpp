@@ -36,9 +36,8 @@ struct GramLinesArgs {
   const int2* pairs;
   const int32_t* loc_ptr;
   const int32_t* unit_loc;
-  int nc, r, nx, lmax, ua;
+  int nc, r, nx, ua;
   int cg;                // coils per workgroup (coil group)
-  int nx_shift;          // log2(nx)
   long npairs;           // allocated pairs per group in hp
   double2* P;            // [g][u][r][r]
   double2* hp;           // [g][pair][r]
@@ -63,7 +62,6 @@ struct SolveArgs {
   const double2* hp;
   const int32_t* mask;
   const int32_t* m_k;
-  const int32_t* loc2unit;
   const int32_t* pair_of;
   const int32_t* unit_of;    // LINES: sampled-line index of (frame k, line l)
   int width, nx, r, kind, nchunks;
@@ -140,18 +138,15 @@ struct LossArgs {
 };
 
 struct FoldArgs {
-  const int2* unit_span;  // LINES: per sampled line, its first pair and pair count
   const int4* line_order;  // LINES: per fold row position (line u, first pair, pair count, 0), most pairs first; n_loc entries
   const float2* bcp;      // LINES: conj(b_k) of every pair, in pair order (written by the solve)
   const float2* W;
   const float2* yu;      // LINES: per-line data [c][p][x]
-  const float2* yh;      // LINES: hybrid data
   const float2* y;       // INDEX: measurements
   const float2* B;
   const int2* pairs;
   const int32_t* loc_ptr;
-  const int32_t* unit_loc;
-  int nc, r, nx, lmax, ua, cg, n, m_max;
+  int nc, r, nx, ua, n, m_max;
   float2* K;
   DevState* st;
   int check_halt;
