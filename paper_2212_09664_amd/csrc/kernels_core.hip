@@ -770,11 +770,68 @@ __device__ __forceinline__ double sd_row_sum(const double2* UU, const double2* U
   return fro;
 }
 
+// ---------------------------------------------------------------------------
+// tot[o] = sum over the nblk QR Gram partials (FP32 pairs when f32, else
+// FP64) of nout complex entries, in FP64.  Thread = (16-byte unit of a
+// partial, slice): slice sl sums partials sl, sl + NS, sl + 2 NS, ... in
+// that order, with PL loads in flight (issued from clamped, valid addresses
+// before any is used), and the slices are then added in order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void unit_add(double2& a0, double2&, const double2 w) { a0 = dadd(a0, w); }
+__device__ __forceinline__ void unit_add(double2& a0, double2&, const float2 w) { a0 = dadd(a0, f2d(w)); }
+__device__ __forceinline__ void unit_add(double2& a0, double2& a1, const float4 w) {
+  a0 = dadd(a0, make_double2(w.x, w.y));
+  a1 = dadd(a1, make_double2(w.z, w.w));
+}
+
+template <int PL, typename L>
+__device__ __forceinline__ void slice_sum(const L* src, int nblk, int nunit, int u, int sl, int NS, double2& a0,
+                                          double2& a1) {
+  for (int b0 = sl; b0 < nblk; b0 += NS * PL) {
+    L w[PL];
+#pragma unroll
+    for (int k = 0; k < PL; ++k) w[k] = src[(long)min(b0 + k * NS, nblk - 1) * nunit + u];
+#pragma unroll
+    for (int k = 0; k < PL; ++k)
+      if (b0 + k * NS < nblk) unit_add(a0, a1, w[k]);
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void partials_sum(const double2* part, int f32, int nblk, int nout, double2* tot) {
+  constexpr int PL = NT >= 1024 ? 8 : 16;  // (registers: 1024 threads leave at most 128 per lane)
+  __shared__ double2 s_sum[2][NT];
+  const int tid = threadIdx.x;
+  const int per = (f32 && (nout & 1) == 0) ? 2 : 1;  // outputs per load
+  const int nunit = nout / per, NS = max(1, NT / nunit), OW = NT / NS;
+  for (int u0 = 0; u0 < nunit; u0 += OW) {
+    const int u = u0 + tid % OW, sl = tid / OW, uc = min(u, nunit - 1);
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0;
+    if (sl < NS) {
+      if (!f32) slice_sum<PL>(part, nblk, nunit, uc, sl, NS, a0, a1);
+      else if (per == 2) slice_sum<PL>(reinterpret_cast<const float4*>(part), nblk, nunit, uc, sl, NS, a0, a1);
+      else slice_sum<PL>(reinterpret_cast<const float2*>(part), nblk, nunit, uc, sl, NS, a0, a1);
+    }
+    s_sum[0][tid] = a0;
+    s_sum[1][tid] = a1;
+    __syncthreads();
+    if (sl == 0 && u < nunit) {
+      for (int q = 1; q < NS; ++q) {
+        a0 = dadd(a0, s_sum[0][tid + q * OW]);
+        a1 = dadd(a1, s_sum[1][tid + q * OW]);
+      }
+      tot[u * per] = a0;
+      if (per == 2) tot[u * per + 1] = a1;
+    }
+    __syncthreads();
+  }
+}
+
 // ===========================================================================
 // the QR step fused with the update (r <= 8): every workgroup sums the QR
 // Gram partials, takes the step size (Algorithm 2's rule at t = 1, then the
 // stored one), factors Uhat^H Uhat = L L^H in one wave, and solves
-// U+ R = U - eta grad for its 1024 pixels, R = L^H.  Every workgroup computes
+// U+ R = U - eta grad for its NT pixels, R = L^H.  Every workgroup computes
 // the same factor from the same partials in the same order.  With the exit
 // rule on, workgroup 0 also forms SD(U, U+) and the cost, and the outcome
 // (applied, exit rule, stationary start) and the step size go to step_flags /
@@ -787,58 +844,51 @@ __device__ __forceinline__ double sd_row_sum(const double2* UU, const double2* U
 // the cost and ||grad|| are then only reported: their r x r inputs are
 // stored and k_stats_finish forms them on request.
 // ===========================================================================
-template <int RT>
-__global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap) {
+template <int RT, int NT>
+__global__ __launch_bounds__(NT) void k_step_apply(QrSmallArgs a, ApplyArgs ap) {
   __shared__ double2 UU[256], UG[256], GG[256], Gh[256], Tm[256];
   __shared__ JacobiScratch js;
-  __shared__ double2 red2[1024];
+  __shared__ double2 tot[RT * (2 * RT + 1)];  // the summed Gram's upper triangle (m = 2 r <= 2 RT)
   __shared__ float2 Rf[RT * RT];
   __shared__ int s_ok;
   __shared__ double s_eta;
   const int tid = threadIdx.x, r = a.r, wv = tid >> 6, l = tid & 63;
   DevState* st = a.st;
-  const long n = ap.n, p = (long)blockIdx.x * 1024 + tid, pc = min(p, n - 1);
+  const long n = ap.n, p = (long)blockIdx.x * NT + tid, pc = min(p, n - 1);
   // this pixel's basis row and gradient, requested first (clamped, valid addresses)
   float2 u0[RT], g0[RT];
 #pragma unroll
-  for (int i = 0; i < RT; ++i) {
-    u0[i] = (i < r) ? ap.U[(long)i * n + pc] : make_float2(0.f, 0.f);
-    g0[i] = (i < r) ? ap.G[pc * r + i] : make_float2(0.f, 0.f);
+  for (int i = 0; i < RT; ++i) u0[i] = (i < r) ? ap.U[(long)i * n + pc] : make_float2(0.f, 0.f);
+  if (r == RT) {  // the pixel-major gradient row as 16-byte loads
+    const float4* gs = reinterpret_cast<const float4*>(ap.G + pc * RT);
+#pragma unroll
+    for (int h = 0; h < RT / 2; ++h) {
+      const float4 w = gs[h];
+      g0[2 * h] = make_float2(w.x, w.y);
+      g0[2 * h + 1] = make_float2(w.z, w.w);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RT; ++i) g0[i] = (i < r) ? ap.G[pc * r + i] : make_float2(0.f, 0.f);
   }
-  // the Gram of [U G] from the partials: thread = (output, slice of partials)
+  // the Gram of [U G] from the partials
   const int m = 2 * r, nout = m * (m + 1) / 2;
-  const int NS = max(1, 1024 / nout), OW = 1024 / NS;
-  for (int o0 = 0; o0 < nout; o0 += OW) {
-    const int o = o0 + tid % OW, sl = tid / OW;
-    double2 sum = make_double2(0.0, 0.0);
-    if (o < nout && sl < NS) {
-      if (a.part_f32) {
-        const float2* pf = reinterpret_cast<const float2*>(a.part);
-#pragma unroll 8
-        for (int b = sl; b < a.nblk; b += NS) sum = dadd(sum, f2d(pf[(long)b * nout + o]));
-      } else {
-#pragma unroll 8
-        for (int b = sl; b < a.nblk; b += NS) sum = dadd(sum, a.part[(long)b * nout + o]);
-      }
+  partials_sum<NT>(a.part, a.part_f32, a.nblk, nout, tot);
+  for (int o = tid; o < nout; o += NT) {
+    int i, j;
+    tri_index(o, m, i, j);
+    const double2 sum = tot[o];
+    if (j < r) {
+      UU[i * 16 + j] = sum;
+      UU[j * 16 + i] = dconj(sum);
+    } else if (i < r) {
+      UG[i * 16 + (j - r)] = sum;
+    } else {
+      GG[(i - r) * 16 + (j - r)] = sum;
+      GG[(j - r) * 16 + (i - r)] = dconj(sum);
     }
-    red2[tid] = sum;
-    __syncthreads();
-    if (tid < OW && o < nout) {
-      for (int q2 = 1; q2 < NS; ++q2) sum = dadd(sum, red2[tid + q2 * OW]);
-      int i, j;
-      tri_index(o, m, i, j);
-      if (j < r) {
-        UU[i * 16 + j] = sum;
-        UU[j * 16 + i] = dconj(sum);
-      } else if (i < r) {
-        UG[i * 16 + (j - r)] = sum;
-      } else {
-        GG[(i - r) * 16 + (j - r)] = sum;
-        GG[(j - r) * 16 + (i - r)] = dconj(sum);
-      }
-    }
-    __syncthreads();
   }
+  __syncthreads();
   // halt and eta are not written during this launch; err only when a factor
   // fails, which then fails in every workgroup alike.  Thread 0 reads them
   // once for the whole workgroup.
@@ -849,7 +899,7 @@ __global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap
   __syncthreads();
   if (!s_ok) return;
   if (!(s_eta > 0.0)) {  // first iteration: eta = eta_c / ||grad||_2 (with the guard and the cap)
-    for (int e = tid; e < 256; e += 1024) Tm[e] = GG[e];
+    for (int e = tid; e < 256; e += NT) Tm[e] = GG[e];
     __syncthreads();
     jacobi_eig<1>(Tm, r, 16, nullptr, &js, 40);
     __syncthreads();
@@ -875,7 +925,7 @@ __global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap
     __syncthreads();
     if (!s_ok) return;
     if (a.eta_cap_c > 0.0) {  // cap: eta <= c n / (mbar ||B_0||_2^2)
-      for (int e = tid; e < r * r; e += 1024) {
+      for (int e = tid; e < r * r; e += NT) {
         const int i = e / r, j = e % r;
         double2 sum = make_double2(0.0, 0.0);
         for (int k = 0; k < a.q; ++k)
@@ -972,8 +1022,13 @@ __global__ __launch_bounds__(1024) void k_step_apply(QrSmallArgs a, ApplyArgs ap
       for (int i = 0; i < j; ++i) sv = csub(sv, cmul(un[i], Rf[i * RT + j]));
       un[j] = cscale(sv, Rf[j * RT + j].x);
       ap.U[(long)j * n + p] = un[j];
-      if (ap.Ui) ap.Ui[p * r + j] = un[j];
+      if (ap.Ui && r != RT) ap.Ui[p * r + j] = un[j];
     }
+  }
+  if (ap.Ui && r == RT) {  // the pixel-major row as 16-byte stores
+    float4* dst = reinterpret_cast<float4*>(ap.Ui + p * RT);
+#pragma unroll
+    for (int h = 0; h < RT / 2; ++h) dst[h] = make_float4(un[2 * h].x, un[2 * h].y, un[2 * h + 1].x, un[2 * h + 1].y);
   }
 }
 
@@ -1033,8 +1088,13 @@ hipError_t launch_stats_finish(DevState* st, const double2* src, const double* c
 
 hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStream_t s) {
   if (a.r > 8) return hipErrorInvalidValue;
-  const dim3 g((unsigned)((ap.n + 1023) / 1024));
-  hipLaunchKernelGGL(k_step_apply<8>, g, dim3(1024), 0, s, a, ap);
+  // pixels per workgroup: 256 spread the update's stores over every compute
+  // unit; FP64 partials (twice the bytes per entry) keep 1024, so that each
+  // thread sums fewer of them
+  if (a.part_f32)
+    hipLaunchKernelGGL((k_step_apply<8, 256>), dim3((unsigned)((ap.n + 255) / 256)), dim3(256), 0, s, a, ap);
+  else
+    hipLaunchKernelGGL((k_step_apply<8, 1024>), dim3((unsigned)((ap.n + 1023) / 1024)), dim3(1024), 0, s, a, ap);
   if (!a.commit_direct) hipLaunchKernelGGL(k_step_commit, dim3(1), dim3(64), 0, s, a.st);
   return hipGetLastError();
 }
