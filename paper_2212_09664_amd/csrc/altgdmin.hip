@@ -61,7 +61,7 @@ struct altgdmin_ctx {
   int bound = 0, initialized = 0;
   // workspace carve
   size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
-      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_rfac, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
+      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_qtot, o_rfac, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
       o_fcmp, o_planes, o_gwork, o_lineord, o_coilb, o_yg, o_ysqp, o_stsrc, o_end;
   size_t T_bytes;
   // timing
@@ -145,6 +145,7 @@ void carve(altgdmin_ctx* c) {
   // QR Gram partials; the spectral init's Gram uses up to init_nblk of them
   // plus one slot for their sum
   c->o_qpart = take(sizeof(double2) * qo * (std::max(c->qr_nblk, init_nblk(c)) + 1));
+  c->o_qtot = take(sizeof(double2) * m_iter * (m_iter + 1) / 2);  // their sum (the fused step)
   c->o_rfac = take(sizeof(float2) * r * r);
   c->o_stsrc = take(sizeof(double2) * 193);  // deferred statistics of the fused step
   c->o_Vs = take(sizeof(float2) * (size_t)q * r);
@@ -489,6 +490,13 @@ hipError_t qr_step_apply(altgdmin_ctx* c, float2* U, float2* U_prev) {
   hipError_t e = qr_step_gram(c, 1);
   if (e != hipSuccess) return e;
   QrSmallArgs qa = qr_small_args(c, 0, 1);
+  tmark(c, TK_APPLY);
+  const int nout = p.r * (2 * p.r + 1);
+  e = launch_partials_total(qa.part, qa.part_f32, qa.nblk, nout, c->at<double2>(c->o_qtot), c->stream);
+  if (e != hipSuccess) return e;
+  qa.part = c->at<double2>(c->o_qtot);  // the partials summed (FP64)
+  qa.part_f32 = 0;
+  qa.nblk = 1;
   qa.commit_direct = !(p.eps_exit > 0.0);
   qa.stats_src = c->at<double2>(c->o_stsrc);
   ApplyArgs aa{};
@@ -501,7 +509,6 @@ hipError_t qr_step_apply(altgdmin_ctx* c, float2* U, float2* U_prev) {
   aa.r = p.r;
   aa.mode = 0;
   aa.st = c->st();
-  tmark(c, TK_APPLY);
   e = launch_step_apply(qa, aa, c->stream);
   tmark(c, TK_APPLY);
   return e;
@@ -653,7 +660,7 @@ altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** ou
     c->adj_cgs = (p.nc + parts - 1) / parts;
     c->adj_parts = (p.nc + c->adj_cgs - 1) / c->adj_cgs;
   }
-  c->qr_nblk = std::max(1, std::min(128, c->n / 512));
+  c->qr_nblk = std::max(1, std::min(256, c->n / 256));
   c->qr_rows = ((long)c->n + c->qr_nblk - 1) / c->qr_nblk;
   c->qr_rows = (c->qr_rows + 127) / 128 * 128;
   c->qr_nblk = (int)((c->n + c->qr_rows - 1) / c->qr_rows);

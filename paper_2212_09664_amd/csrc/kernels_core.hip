@@ -772,10 +772,11 @@ __device__ __forceinline__ double sd_row_sum(const double2* UU, const double2* U
 
 // ---------------------------------------------------------------------------
 // tot[o] = sum over the nblk QR Gram partials (FP32 pairs when f32, else
-// FP64) of nout complex entries, in FP64.  Thread = (16-byte unit of a
-// partial, slice): slice sl sums partials sl, sl + NS, sl + 2 NS, ... in
-// that order, with PL loads in flight (issued from clamped, valid addresses
-// before any is used), and the slices are then added in order.
+// FP64) of nout complex entries, in FP64; workgroup wg of nwg takes a range
+// of the 16-byte units (one or two entries).  Thread = (unit, slice): slice
+// sl sums partials sl, sl + NS, sl + 2 NS, ... in that order, with PL loads
+// in flight (issued from clamped, valid addresses before any is used), and
+// the slices are then added in order.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void unit_add(double2& a0, double2&, const double2 w) { a0 = dadd(a0, w); }
 __device__ __forceinline__ void unit_add(double2& a0, double2&, const float2 w) { a0 = dadd(a0, f2d(w)); }
@@ -798,14 +799,17 @@ __device__ __forceinline__ void slice_sum(const L* src, int nblk, int nunit, int
 }
 
 template <int NT>
-__device__ __forceinline__ void partials_sum(const double2* part, int f32, int nblk, int nout, double2* tot) {
+__device__ __forceinline__ void partials_sum(const double2* part, int f32, int nblk, int nout, double2* tot, int wg,
+                                             int nwg) {
   constexpr int PL = NT >= 1024 ? 8 : 16;  // (registers: 1024 threads leave at most 128 per lane)
   __shared__ double2 s_sum[2][NT];
   const int tid = threadIdx.x;
   const int per = (f32 && (nout & 1) == 0) ? 2 : 1;  // outputs per load
-  const int nunit = nout / per, NS = max(1, NT / nunit), OW = NT / NS;
-  for (int u0 = 0; u0 < nunit; u0 += OW) {
-    const int u = u0 + tid % OW, sl = tid / OW, uc = min(u, nunit - 1);
+  const int nunit = nout / per, cu = (nunit + nwg - 1) / nwg, ub = wg * cu, ue = min(nunit, ub + cu);
+  const int nu = max(0, ue - ub);
+  const int NS = max(1, min(32, NT / max(nu, 1))), OW = NT / NS;  // (at most 32 slices: their sum is serial)
+  for (int u0 = 0; u0 < nu; u0 += OW) {
+    const int u = ub + u0 + tid % OW, sl = tid / OW, uc = min(u, ue - 1);
     double2 a0 = make_double2(0.0, 0.0), a1 = a0;
     if (sl < NS) {
       if (!f32) slice_sum<PL>(part, nblk, nunit, uc, sl, NS, a0, a1);
@@ -815,7 +819,7 @@ __device__ __forceinline__ void partials_sum(const double2* part, int f32, int n
     s_sum[0][tid] = a0;
     s_sum[1][tid] = a1;
     __syncthreads();
-    if (sl == 0 && u < nunit) {
+    if (sl == 0 && u < ue) {
       for (int q = 1; q < NS; ++q) {
         a0 = dadd(a0, s_sum[0][tid + q * OW]);
         a1 = dadd(a1, s_sum[1][tid + q * OW]);
@@ -873,7 +877,7 @@ __global__ __launch_bounds__(NT) void k_step_apply(QrSmallArgs a, ApplyArgs ap) 
   }
   // the Gram of [U G] from the partials
   const int m = 2 * r, nout = m * (m + 1) / 2;
-  partials_sum<NT>(a.part, a.part_f32, a.nblk, nout, tot);
+  partials_sum<NT>(a.part, a.part_f32, a.nblk, nout, tot, 0, 1);
   for (int o = tid; o < nout; o += NT) {
     int i, j;
     tri_index(o, m, i, j);
@@ -1086,12 +1090,28 @@ hipError_t launch_stats_finish(DevState* st, const double2* src, const double* c
   return hipGetLastError();
 }
 
+// the QR Gram partials summed once for the fused step: workgroups of 256
+// threads, each over a few 16-byte units, so that one round of loads covers
+// its partials
+__global__ __launch_bounds__(256) void k_partials_total(const double2* part, int f32, int nblk, int nout,
+                                                        double2* total) {
+  partials_sum<256>(part, f32, nblk, nout, total, blockIdx.x, gridDim.x);
+}
+
+hipError_t launch_partials_total(const double2* part, int f32, int nblk, int nout, double2* total, hipStream_t s) {
+  const int per = (f32 && (nout & 1) == 0) ? 2 : 1, nunit = nout / per;
+  // 8 units per workgroup: 32 slices of 16 loads in flight cover 512 partials
+  const int nwg = (nunit + 7) / 8;
+  hipLaunchKernelGGL(k_partials_total, dim3(nwg), dim3(256), 0, s, part, f32, nblk, nout, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStream_t s) {
   if (a.r > 8) return hipErrorInvalidValue;
   // pixels per workgroup: 256 spread the update's stores over every compute
-  // unit; FP64 partials (twice the bytes per entry) keep 1024, so that each
-  // thread sums fewer of them
-  if (a.part_f32)
+  // unit; many FP64 partials (twice the bytes per entry) keep 1024, so that
+  // each thread sums fewer of them
+  if (a.part_f32 || a.nblk == 1)
     hipLaunchKernelGGL((k_step_apply<8, 256>), dim3((unsigned)((ap.n + 255) / 256)), dim3(256), 0, s, a, ap);
   else
     hipLaunchKernelGGL((k_step_apply<8, 1024>), dim3((unsigned)((ap.n + 1023) / 1024)), dim3(1024), 0, s, a, ap);

@@ -372,6 +372,7 @@ __global__ void k_to_colmajor(const float2* src, int r, long n, float2* dst);
 __global__ void k_to_pixmajor(const float2* src, int r, long n, float2* dst);
 hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s);
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s);
+hipError_t launch_partials_total(const double2* part, int f32, int nblk, int nout, double2* total, hipStream_t s);
 hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStream_t s);
 hipError_t launch_stats_finish(DevState* st, const double2* src, const double* cost_k, int q, int r, hipStream_t s);
 hipError_t launch_sum_partials(const double2* part, int nblk, int nout, double2* out, hipStream_t s);
