@@ -877,11 +877,12 @@ __global__ __launch_bounds__(NT) void k_step_apply(QrSmallArgs a, ApplyArgs ap) 
   }
   // the Gram of [U G] from the partials
   const int m = 2 * r, nout = m * (m + 1) / 2;
-  partials_sum<NT>(a.part, a.part_f32, a.nblk, nout, tot, 0, 1);
+  const bool summed = a.nblk == 1 && !a.part_f32;  // the FP64 sum itself
+  if (!summed) partials_sum<NT>(a.part, a.part_f32, a.nblk, nout, tot, 0, 1);
   for (int o = tid; o < nout; o += NT) {
     int i, j;
     tri_index(o, m, i, j);
-    const double2 sum = tot[o];
+    const double2 sum = summed ? a.part[o] : tot[o];
     if (j < r) {
       UU[i * 16 + j] = sum;
       UU[j * 16 + i] = dconj(sum);
