@@ -859,7 +859,12 @@ __global__ __launch_bounds__(NT) void k_step_apply(QrSmallArgs a, ApplyArgs ap) 
   const int tid = threadIdx.x, r = a.r, wv = tid >> 6, l = tid & 63;
   DevState* st = a.st;
   const long n = ap.n, p = (long)blockIdx.x * NT + tid, pc = min(p, n - 1);
-  // this pixel's basis row and gradient, requested first (clamped, valid addresses)
+  // the state, then this pixel's basis row and gradient, requested first
+  // (clamped, valid addresses); the state's loads are in every thread, so
+  // that no branch waits on them
+  const int err0 = st->err;
+  const int halt0 = __hip_atomic_load(&st->halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double eta0 = __hip_atomic_load(&st->eta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   float2 u0[RT], g0[RT];
 #pragma unroll
   for (int i = 0; i < RT; ++i) u0[i] = (i < r) ? ap.U[(long)i * n + pc] : make_float2(0.f, 0.f);
@@ -894,12 +899,12 @@ __global__ __launch_bounds__(NT) void k_step_apply(QrSmallArgs a, ApplyArgs ap) 
     }
   }
   __syncthreads();
-  // halt and eta are not written during this launch; err only when a factor
-  // fails, which then fails in every workgroup alike.  Thread 0 reads them
-  // once for the whole workgroup.
+  // err is written during this launch only when a factor fails, which then
+  // fails in every workgroup alike; halt and eta only by workgroup 0, with
+  // the values every workgroup derives itself (see above)
   if (tid == 0) {
-    s_ok = !(st->err || (a.check_halt && __hip_atomic_load(&st->halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-    s_eta = __hip_atomic_load(&st->eta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_ok = !(err0 || (a.check_halt && halt0));
+    s_eta = eta0;
   }
   __syncthreads();
   if (!s_ok) return;
