@@ -77,6 +77,12 @@ struct DevState {
   int32_t pad_i;
   double pad[3];
 };
+// the loop's stop test: err and halt both requested before either is tested
+// (a short-circuit test waits for one load before issuing the other)
+__device__ __forceinline__ bool halted(const DevState* st, int check_halt) {
+  const int e = st->err, h = st->halt;
+  return (e | (h & -(check_halt != 0))) != 0;
+}
 #define STEP_APPLIED 1
 #define STEP_EXIT 2
 #define STEP_CONVERGED 4

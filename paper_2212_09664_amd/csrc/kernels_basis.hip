@@ -72,7 +72,7 @@ __global__ __launch_bounds__(AG_NT) void k_basis_fwd(BasisArgs a) {
     s_ro[e] = u >= 0 ? u * a.nx * r : -1;
   }
   // the state is read once the first loads are in flight (their addresses are valid either way)
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   __syncthreads();
   for (int c = cb; c < ce; ++c) {
     float2 v0[IT0][R0], vo[ITL][RL];
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
   };
   if (cb < ce) fetch(cb);
   // the state is read once the first loads are in flight (their addresses are valid either way)
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   for (int c = cb; c < ce; ++c) {
     float2 v0[IT0][R0], vo[ITL][RL];
 #pragma unroll
@@ -188,7 +188,7 @@ template <int N, int CT, bool INV>
 __global__ __launch_bounds__(AG_NT) void k_basis_rows(BasisArgs a) {
   __shared__ float2 s[N * CT];
   const int tid = threadIdx.x, r = a.r;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   float2* row = (INV ? a.K : a.W) + (long)blockIdx.x * N * r;
   for (int g = tid; g < N * CT; g += AG_NT) {
     const int x = g / CT, j = g % CT;
@@ -256,7 +256,8 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
   // address is valid either way), so that the latencies overlap; the span is
   // used only once the line is known to be sampled
   load_w(0);
-  if (a.st->err || (a.check_halt && a.st->halt) || u >= a.st->n_units) return;
+  const int nu_ = a.st->n_units;  // requested with the stop test's loads
+  if (halted(a.st, a.check_halt) || u >= nu_) return;
   const int p0 = lrec.y, np = lrec.z;
   const float2* Yc = a.yu + (long)a.nc * nx * p0 + (long)c * np * nx;  // this line and coil, [p][x]
   float2 ya[8], yb[8];
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
 template <int RT>
 __global__ __launch_bounds__(AG_NT) void k_fold_index2(FoldArgs a) {
   const int loc = blockIdx.x * AG_NT + threadIdx.x, c = blockIdx.y;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   if (loc >= a.n) return;
   const int r = a.r;
   const long base = ((long)c * a.n + loc) * r;

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(GCOLS_NT) void k_gram_cols(GramColsArgs a) {
   using A2 = Acc2<ACC>;
   __shared__ float2 Xs[64 * 64];
   const int tid = threadIdx.x, blk = blockIdx.x;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   const int m = a.m1 + a.m2;  // <= 128
   const int nout = m * (m + 1) / 2;
   const int RC = m <= 64 ? 64 : 32;  // rows staged per chunk

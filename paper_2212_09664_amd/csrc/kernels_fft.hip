@@ -35,7 +35,7 @@ __global__ __launch_bounds__(AG_NT) void k_rows(RowArgs a) {
   __shared__ float2 s[N * TR];
   const int tid = threadIdx.x;
   const long rho0 = (long)blockIdx.x * TR;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   const double gamma = a.trunc ? a.st->gamma : 0.0;
   for (int g = tid; g < N * TR; g += AG_NT) {
     const int t = g / N, e = g % N;
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(AG_NT) void k_cols_fwd(ColFwdArgs a) {
   __shared__ float2 s[N * TX];
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * TX, img = blockIdx.y, c = blockIdx.z;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   const float2* src = a.src + (long)img * a.src_img_stride;
   const float2* coil = a.coils + (long)c * a.n;
   {
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
   constexpr int IT = (N * TX + AG_NT - 1) / AG_NT;
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * TX, img = blockIdx.y;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   int n_rows;
   const int32_t* rows = nullptr;
   if (a.m_k_rows) {

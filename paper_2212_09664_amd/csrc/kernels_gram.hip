@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256 * NWG) void k_gram_lines_mma(GramLinesArgs a) {
   // the first item is requested together with the state (the list holds
   // gridDim.x entries at least; one past the count is not used)
   const int4 first = a.items[blockIdx.x];
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   const int nwork = a.st->n_gwork;
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
   if (w > blockIdx.x) __syncthreads();  // the previous item's LDS reductions are complete
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(256) void k_gram_index_mma(GramIndexArgs a) {
   __shared__ T red[(TR * TR + TR) * 256];
   const int k = blockIdx.y, ch = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   const int r = a.r, col = lane & 15, kk = lane >> 4;
   const int mk = a.m_k[k];
   const int i0 = ch * a.chunk, i1 = min(mk, i0 + a.chunk);
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
       s_po[l] = a.pair_of[(long)k * a.width + l];
     }
   }
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   const int E = r * r + r;  // G entries then h entries
   if (a.kind == 0) {
     const double2* const Pp = a.P;
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(256 * NSM) void k_qr_gram_mma(GramColsArgs a) {
   for (int t = 0; t < NT; ++t) acc[t] = M::zero();
   load(pa + sm * RC);
   // the state is read once the first chunk's loads are in flight
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   // every workgroup-wide step runs the same number of times in both streams
   for (long base = pa; base < pb; base += NSM * RC) {
     const long p0 = base + sm * RC;

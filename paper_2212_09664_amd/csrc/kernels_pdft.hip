@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_pdft_fwd(PdftArgs a) {
   int* s_ky = L.s_ky;
   float* red = L.red;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   const int nu = a.st->n_units;
   const int c = blockIdx.y, r = a.r, ncols = a.nx * r;
   const int col0 = blockIdx.x * 32;
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_pdft_adj(PdftArgs a) {
   int* s_ky = L.s_ky;
   float* red = L.red;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (a.st->err || (a.check_halt && a.st->halt)) return;
+  if (halted(a.st, a.check_halt)) return;
   const int nu = a.st->n_units;
   const int LP = (nu + 31) & ~31;
   const int r = a.r, ncols = a.nx * r;
