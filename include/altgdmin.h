@@ -171,6 +171,18 @@ altgdmin_status altgdmin_cnn_input(altgdmin_ctx* ctx, float* d_in);
  * learned guess was kept, 0 otherwise.  Resets t. */
 altgdmin_status altgdmin_init_warm(altgdmin_ctx* ctx, const void* d_M, void* d_U, int32_t* d_choice);
 
+/* altgdmin_init_warm with the fallback basis supplied instead of computed:
+ * d_Ufb (device, n x r, column-major complex64, orthonormal; typically the
+ * output of altgdmin_init on this context) takes the place of the spectral
+ * initialisation (Algorithm 2's U_0), and d_U (out, may equal d_Ufb)
+ * receives the lower-cost of it and QR(d_M), d_choice as above.  Splitting
+ * the warm start this way lets the network's forward pass that produces
+ * d_M run on another stream while altgdmin_init runs on the context's; the
+ * caller orders d_M's producer before this call.  Errors: EINVAL for a NULL
+ * context, guess or basis; ESTATE before altgdmin_set_problem.  Resets t. */
+altgdmin_status altgdmin_init_warm_from(altgdmin_ctx* ctx, const void* d_M, const void* d_Ufb, void* d_U,
+                                        int32_t* d_choice);
+
 /* n_iter iterations of the alternating loop (Algorithm 2), continuing from
  * d_U (in/out, n x r orthonormal).  d_B (out, r x q) receives B_T computed
  * from U_{T-1}; d_U_prev (out, may be NULL) receives U_{T-1}, so that

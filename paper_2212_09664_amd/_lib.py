@@ -79,6 +79,7 @@ def load_library():
         "altgdmin_destroy": ([vp], None),
         "altgdmin_cnn_input": ([vp, vp], i32),
         "altgdmin_init_warm": ([vp, vp, vp, vp], i32),
+        "altgdmin_init_warm_from": ([vp, vp, vp, vp, vp], i32),
         "wsinit_create": ([i32, i32, i32, i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
         "wsinit_param_count": ([vp, ctypes.POINTER(ctypes.c_int64)], i32),
         "wsinit_workspace_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], i32),
@@ -188,6 +189,14 @@ class AltGDmin:
         int32, optional) receives 1 if M's basis was kept."""
         U = self._new(self.p.r, self.n) if U is None else U
         self._check(self._L.altgdmin_init_warm(self._h, _ptr(M), _ptr(U), _ptr(choice)), "init_warm")
+        return U
+
+    def init_warm_from(self, M, U_fb, U=None, choice=None):
+        """init_warm with the fallback basis U_fb given (e.g. from init on this
+        context) instead of computed; U may be U_fb."""
+        U = self._new(self.p.r, self.n) if U is None else U
+        self._check(self._L.altgdmin_init_warm_from(self._h, _ptr(M), _ptr(U_fb), _ptr(U), _ptr(choice)),
+                    "init_warm_from")
         return U
 
     def iterate(self, n_iter, U, B=None, U_prev=None, sync=False):

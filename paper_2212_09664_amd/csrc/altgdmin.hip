@@ -824,13 +824,11 @@ altgdmin_status altgdmin_cnn_input(altgdmin_ctx* c, float* d_in) {
   return ALTGDMIN_OK;
 }
 
-altgdmin_status altgdmin_init_warm(altgdmin_ctx* c, const void* d_M, void* d_U, int32_t* d_choice) {
-  if (!c || !d_M || !d_U) return ALTGDMIN_EINVAL;
-  if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
+// the learned guess d_M against the fallback basis already in d_U: the step
+// size at the fallback, the cost of each, the lower-cost one into d_U
+static altgdmin_status warm_combine(altgdmin_ctx* c, const void* d_M, void* d_U, int32_t* d_choice) {
   const altgdmin_params& p = c->p;
   hipStream_t s = c->stream;
-  const altgdmin_status st = altgdmin_init(c, d_U);
-  if (st != ALTGDMIN_OK) return st;
   // the step size of Algorithm 2 (first-iteration rule) at the spectral basis:
   // a good learned basis has a much smaller first gradient, and the rule
   // evaluated there would overshoot
@@ -855,6 +853,26 @@ altgdmin_status altgdmin_init_warm(altgdmin_ctx* c, const void* d_M, void* d_U, 
   HIPCHK(hipGetLastError());
   c->initialized = 1;
   return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_init_warm(altgdmin_ctx* c, const void* d_M, void* d_U, int32_t* d_choice) {
+  if (!c || !d_M || !d_U) return ALTGDMIN_EINVAL;
+  if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
+  const altgdmin_status st = altgdmin_init(c, d_U);
+  if (st != ALTGDMIN_OK) return st;
+  return warm_combine(c, d_M, d_U, d_choice);
+}
+
+altgdmin_status altgdmin_init_warm_from(altgdmin_ctx* c, const void* d_M, const void* d_Ufb, void* d_U,
+                                        int32_t* d_choice) {
+  if (!c || !d_M || !d_Ufb || !d_U) return ALTGDMIN_EINVAL;
+  if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, c->stream, c->st(), 0);
+  if (d_Ufb != d_U)
+    hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, c->stream, static_cast<const float2*>(d_Ufb),
+                       static_cast<float2*>(d_U), (long)c->n * c->p.r);
+  HIPCHK(hipGetLastError());
+  return warm_combine(c, d_M, d_U, d_choice);
 }
 
 altgdmin_status altgdmin_iterate(altgdmin_ctx* c, int32_t n_iter, void* d_U, void* d_B, void* d_U_prev,

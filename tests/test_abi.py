@@ -25,7 +25,7 @@ def test_header_declares_the_boundary():
     names = declared()
     for must in ("altgdmin_init", "altgdmin_iterate", "altgdmin_apply_A", "altgdmin_apply_AH",
                  "altgdmin_create", "altgdmin_set_problem", "altgdmin_destroy", "altgdmin_cnn_input",
-                 "altgdmin_init_warm", "wsinit_create", "wsinit_forward", "wsinit_loss_backward",
+                 "altgdmin_init_warm", "altgdmin_init_warm_from", "wsinit_create", "wsinit_forward", "wsinit_loss_backward",
                  "wsinit_adam_step"):
         assert must in names
 

@@ -131,3 +131,30 @@ def test_warm_init_keeps_the_lower_cost_basis():
     ctx.init_warm(to_gpu_U(Ugood))
     ctx.iterate(1, to_gpu_U(Ugood), sync=True)
     assert ctx.get_eta() == pytest.approx(eta_plain, rel=1e-6)
+
+
+def test_warm_init_from_a_given_fallback_matches_init_warm():
+    """altgdmin_init_warm_from, given the basis altgdmin_init computed, gives
+    bitwise the basis, the choice and the next iterates of altgdmin_init_warm,
+    for a kept and for a rejected guess, into a new buffer or in place."""
+    p = datagen.make_small(32, 32, 3, 10, 2, seed=8, kind="lines", n_lines=8, lowrank=True, snr_db=40.0)
+    cs = Case(p)
+    ctx = cs.gpu_ctx()
+    rng = np.random.default_rng(9)
+    Ugood, _ = np.linalg.qr(p.zstar @ datagen.crandn(rng, p.q, p.r))
+    for M, kept in ((Ugood @ datagen.crandn(rng, p.r, p.r), 1), (datagen.crandn(rng, p.n, p.r), 0)):
+        Mg = to_gpu_U(M)
+        c0 = torch.full((1,), -1, dtype=torch.int32, device="cuda:0")
+        U0 = ctx.init_warm(Mg, choice=c0)
+        B0 = ctx.iterate(2, U0)
+        torch.cuda.synchronize()
+        assert int(c0.item()) == kept
+        for in_place in (False, True):
+            Ufb = ctx.init()
+            c1 = torch.full((1,), -1, dtype=torch.int32, device="cuda:0")
+            U1 = ctx.init_warm_from(Mg, Ufb, U=Ufb if in_place else None, choice=c1)
+            B1 = ctx.iterate(2, U1)
+            torch.cuda.synchronize()
+            log(f"  kept {kept} in_place {in_place}: choice {int(c1.item())}")
+            assert int(c1.item()) == kept
+            assert torch.equal(U1, U0) and torch.equal(B1, B0)
