@@ -801,7 +801,8 @@ __device__ __forceinline__ void slice_sum(const L* src, int nblk, int nunit, int
 template <int NT>
 __device__ __forceinline__ void partials_sum(const double2* part, int f32, int nblk, int nout, double2* tot, int wg,
                                              int nwg) {
-  constexpr int PL = NT >= 1024 ? 8 : 16;  // (registers: 1024 threads leave at most 128 per lane)
+  constexpr int PL = 16;
+  static_assert(NT <= 256, "16 loads of 16 bytes in flight per thread need more than 1024-thread workgroups allow");
   __shared__ double2 s_sum[2][NT];
   const int tid = threadIdx.x;
   const int per = (f32 && (nout & 1) == 0) ? 2 : 1;  // outputs per load
@@ -1114,13 +1115,8 @@ hipError_t launch_partials_total(const double2* part, int f32, int nblk, int nou
 
 hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStream_t s) {
   if (a.r > 8) return hipErrorInvalidValue;
-  // pixels per workgroup: 256 spread the update's stores over every compute
-  // unit; many FP64 partials (twice the bytes per entry) keep 1024, so that
-  // each thread sums fewer of them
-  if (a.part_f32 || a.nblk == 1)
-    hipLaunchKernelGGL((k_step_apply<8, 256>), dim3((unsigned)((ap.n + 255) / 256)), dim3(256), 0, s, a, ap);
-  else
-    hipLaunchKernelGGL((k_step_apply<8, 1024>), dim3((unsigned)((ap.n + 1023) / 1024)), dim3(1024), 0, s, a, ap);
+  // 256 pixels per workgroup: the update's stores spread over every compute unit
+  hipLaunchKernelGGL((k_step_apply<8, 256>), dim3((unsigned)((ap.n + 255) / 256)), dim3(256), 0, s, a, ap);
   if (!a.commit_direct) hipLaunchKernelGGL(k_step_commit, dim3(1), dim3(64), 0, s, a.st);
   return hipGetLastError();
 }
