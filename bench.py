@@ -1,29 +1,40 @@
-"""altGDmin throughput on one MI355X, with a roofline figure and the FP64
-CPU oracle timed beside it.
+"""altGDmin throughput on one MI355X, with a roofline figure, the three forms
+(plain, learned warm start, mixed precision + warm start) timed to the same
+NMSE on the same inputs, and the FP64 CPU oracle timed beside it.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form plain|mixed]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form all|plain|mixed|warm|mixed_warm]
+                    [--workload cine256|radial128|cine256r16|cine128|gauss64]
 
-Workload: the 256x256, 12-coil, 40-frame cine-like sequence (motion-ellipse
-phantom, ring coils, 1D Cartesian variable-density mask at acceleration 8
-with 8 centre lines redrawn per frame, 30 dB noise), rank 8, 70 iterations.
+Workload (default): the 256x256, 12-coil, 40-frame cine-like sequence
+(motion-ellipse phantom, ring coils, 1D Cartesian variable-density mask at
+acceleration 8 with 8 centre lines redrawn per frame, 30 dB noise), rank 8,
+70 iterations.
 
 One step is a whole reconstruction: bind the problem (per-line inverse DFT
 along kx of y, index tables, ||y_k||^2), truncated spectral initialisation,
-then 70 altGDmin iterations.  value = iterations per second over the timed
-steps (whole job, inputs already resident in HBM).  Also reported: the loop
-alone (iterate only) and the time to NMSE <= 2e-2 (events after setup, after
-init and after every iteration; NMSE evaluated off the clock on a replay of
-the same deterministic run).
+then the workload's iterations.  value = iterations per second of the plain
+FP32 form over the timed steps (whole job, inputs already resident in HBM).
 
-The roofline figure is for the most expensive kernel class of the loop,
-timed with HIP events on the library's stream during the timed steps;
-its algorithmic bytes per launch are stated in ALG_BYTES below.
+Also reported:
+* the loop alone (iterate only), and per form the time to NMSE <= 2e-2:
+  HIP events after setup, after init and after every iteration (median over
+  10 replays); NMSE evaluated off the clock on a replay of the same
+  deterministic run; the ratio of each form's time to the plain form's;
+* roofline: the unit of work is one altGDmin iteration.  Its algorithmic
+  bytes B_alg = 8 (2 Nc M + 2 Nc n + 5 n r) (y', coils and U read before and
+  after the per-frame solve, the new U written, complex64) and flops F (the
+  2 Nc r shared transforms, the per-line Grams, rhs, fold and residual
+  contractions, the coil products and the QR Gram) are divided by the
+  measured time of one iteration; the bound is whichever of B_alg / 8 TB/s
+  and F / 157.3 TFLOP/s is larger.  The loop's most expensive kernel class
+  is reported beside it with its own operand bytes.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -32,37 +43,83 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "cine256"
 WORKLOAD_TEXT = {
     "cine256": "cine256: 256x256 complex images, 12 ring coils, 40 frames, rank 8, "
                "1D Cartesian variable-density mask R=8 (8 centre lines, redrawn per frame), "
                "motion-ellipse phantom + 1% sparse residual, 30 dB noise, 70 iterations",
+    "radial128": "radial128: 128x128, 8 ring coils, 100 frames, rank 10, 16 golden-angle spokes per frame "
+                 "rasterised onto the grid, gamma-variate perfusion phantom, 25 dB noise, 50 iterations",
     "cine256r16": "cine256r16: 256x256, 16 ring coils, 64 frames, rank 16, 1D Cartesian variable-density "
                   "mask R=12 (8 centre lines), motion-ellipse phantom, 30 dB noise, 70 iterations",
     "cine128": "cine128: 128x128, 8 ring coils, 48 frames, rank 6, 1D Cartesian variable-density mask R=8, "
                "motion-ellipse phantom, 30 dB noise, 70 iterations",
+    "gauss64": "gauss64: 64x64, 4 corner coils, 16 frames, rank 4, exact rank-4 Gaussian sequence, "
+               "4 centre + 12 uniform lines per frame, noise-free, 20 iterations",
 }
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+NMSE_TARGET = 2e-2
 
 
-def alg_bytes(kernel: str, nx, ny, nc, q, r, n_u, M_total) -> float:
-    """Algorithmic bytes of one launch of a kernel class (complex64 = 8 B):
-    every operand the kernel must read or write, once.
-      n_u: distinct sampled phase-encode lines; M_total: sum_k m_k."""
-    n = nx * ny
-    W = nc * r * n_u * nx          # W or K: coil-weighted basis, sampled lines only
+# ---------------------------------------------------------------------------
+# the unit of work: one iteration
+# ---------------------------------------------------------------------------
+def iteration_bytes(prob) -> float:
+    """B_alg of one iteration (complex64 = 8 B): y' (Nc M samples), the coil
+    maps (Nc n) and U (n r) are read in both phases of the iteration (before
+    and after the per-frame solve, which needs all of A_k U first), the new U
+    is written (n r), and the QR reads U and the step twice more (2 n r)."""
+    n, nc, r = prob.n, prob.nc, prob.r
+    M = int(prob.m_k().sum())
+    return 8.0 * (2 * nc * M + 2 * nc * n + 5 * n * r)
+
+
+def iteration_flops(prob) -> float:
+    """Flops of one iteration: 5 N log2 N per length-N complex FFT, 8 per
+    complex multiply-add, Hermitian Grams counted once per pair.
+
+    1D Cartesian (hybrid ky, x form): 2 Nc r transforms along y for every x
+    column; per sampled line the Gram of Nc nx rows (r(r+1)/2 pairs), the rhs
+    and the residual term of the fold (r per sample each), and the fold's
+    W S_u product (r^2 per row of W).  General masks: 2 Nc r full 2D
+    transforms; per sample the Gram pair products, rhs, residual and fold
+    (r(r+1)/2 + 3 r).  Both: the coil products (2 Nc r n) and the Gram of
+    [U grad] (2r(2r+1)/2 n)."""
+    n, nc, r, nx, ny = prob.n, prob.nc, prob.r, prob.nx, prob.ny
+    M = int(prob.m_k().sum())
+    pairs = r * (r + 1) // 2
+    if prob.kind == "lines":
+        n_u = len(np.unique(np.concatenate(prob.masks)))
+        fft = 2 * nc * r * 5 * n * np.log2(ny)
+        contr = 8 * (n_u * nc * nx * pairs + 2 * nc * M * r + n_u * nc * nx * r * r)
+    else:
+        fft = 2 * nc * r * 5 * n * np.log2(n)
+        contr = 8 * nc * M * (pairs + 3 * r)
+    other = 8 * (2 * nc * r * n) + 8 * (2 * r * (2 * r + 1) // 2) * n
+    return float(fft + contr + other)
+
+
+def kernel_operand_bytes(kernel: str, prob) -> float:
+    """Operand bytes of one launch of a loop kernel class (each operand it
+    must read or write once, complex64), for the per-kernel view."""
+    n, nc, r, nx = prob.n, prob.nc, prob.r, prob.nx
+    M = int(prob.m_k().sum())
+    if prob.kind == "lines":
+        n_u = len(np.unique(np.concatenate(prob.masks)))
+        W = nc * r * n_u * nx
+    else:
+        W = nc * r * n
     table = {
-        "fwd_transform": n * r + nc * n + W,          # read U, coils; write W
-        "gram_rhs": W + nc * M_total,                 # read W, y'
-        "fold": 2 * W + nc * M_total,                 # read W, y'; write K
-        "adj_transform": W + nc * n + n * r,          # read K, coils; write grad
-        "qr_gram": 2 * n * r,                         # read U, grad
-        "apply_qr": 3 * n * r,                        # read U, grad; write U
+        "fwd_transform": n * r + nc * n + W,
+        "gram_rhs": W + nc * M,
+        "fold": 2 * W + nc * M,
+        "adj_transform": W + nc * n + n * r,
+        "qr_gram": 2 * n * r,
+        "apply_qr": 3 * n * r,
     }
     return 8.0 * table[kernel]
 
 
-# kernel classes of one iteration that have an algorithmic-bytes figure
 LOOP_KERNELS = ("fwd_transform", "gram_rhs", "fold", "adj_transform", "qr_gram", "apply_qr")
 
 
@@ -78,195 +135,270 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of a kernel class from the committed FETCH_SIZE /
-    WRITE_SIZE summary (copy-calibrated), or None when the summary is absent
-    or was taken on different kernel sources."""
-    path = os.path.join(ROOT, "profiles", "altgdmin_cine256_hbm_counters.txt")
+def measured_traffic(workload: str):
+    """HBM bytes per launch of each loop kernel class from the committed
+    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when the
+    summary is absent or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"altgdmin_{workload}_hbm_counters.txt")
     if not os.path.exists(path):
         return None
     want = kernel_source_hash()
+    out = {}
     with open(path) as fh:
         for line in fh:
             f = line.split()
-            if len(f) == 5 and f[0] == "traffic" and f[1] == kernel and f[3] == "hash":
-                return float(f[2]) if f[4] == want else None
-    return None
+            if len(f) == 5 and f[0] == "traffic" and f[3] == "hash":
+                if f[4] != want:
+                    return None
+                out[f[1]] = float(f[2])
+    return out or None
 
 
-def make_inputs(seed: int):
-    import datagen
-    return datagen.make(WORKLOAD, seed)
-
-
-def gpu_problem(prob, form: str):
+# ---------------------------------------------------------------------------
+# GPU side
+# ---------------------------------------------------------------------------
+def gpu_inputs(prob):
+    """Inputs resident on the device; measurements synthesised with the
+    library's own forward operator plus the seeded noise (R18)."""
     import torch
     import paper_2212_09664_amd as ag
     dev = torch.device("cuda:0")
     m_k = prob.m_k()
     m_max = int(m_k.max())
-    precision = ag.MIXED if form in ("mixed", "mixed_warm") else ag.FP32
     kind = ag.MASK_LINES if prob.kind == "lines" else ag.MASK_INDEX
-    ctx = ag.AltGDmin(prob.nx, prob.ny, prob.nc, prob.q, prob.r, m_max, kind, precision,
-                      t_max=prob.t_iters)
+    ctx = ag.AltGDmin(prob.nx, prob.ny, prob.nc, prob.q, prob.r, m_max, kind, ag.FP32, t_max=prob.t_iters)
     coils = torch.from_numpy(prob.coils.astype(np.complex64)).to(dev)
     mask = torch.from_numpy(prob.mask_array()).to(dev)
     mk = torch.from_numpy(m_k).to(dev)
-    # measurements synthesised on the GPU with the library's forward operator
     ctx.set_problem(coils, mask, mk, None)
     zstar = torch.from_numpy(np.ascontiguousarray(prob.zstar.T.astype(np.complex64))).to(dev)
     y_clean = ctx.apply_A(zstar)
-    w = torch.from_numpy(prob.noise.astype(np.complex64)).to(dev)
-    valid = (torch.arange(m_max, device=dev)[None, None, :] < mk[:, None, None])
-    n_samp = int(valid.sum().item()) * prob.nc
-    sigma = torch.sqrt(torch.sum(torch.abs(y_clean.to(torch.complex128)) ** 2) /
-                       (n_samp * 10.0 ** (prob.snr_db / 10.0)))
-    y = torch.where(valid, y_clean + sigma.to(torch.float32) * w, torch.zeros_like(y_clean))
+    t = dict(coils=coils, mask=mask, m_k=mk, zstar=zstar)
+    if prob.snr_db is None:
+        y = y_clean
+    else:
+        w = torch.from_numpy(prob.noise.astype(np.complex64)).to(dev)
+        valid = (torch.arange(m_max, device=dev)[None, None, :] < mk[:, None, None])
+        n_samp = int(valid.sum().item()) * prob.nc
+        sigma = torch.sqrt(torch.sum(torch.abs(y_clean.to(torch.complex128)) ** 2) /
+                           (n_samp * 10.0 ** (prob.snr_db / 10.0)))
+        y = torch.where(valid, y_clean + sigma.to(torch.float32) * w, torch.zeros_like(y_clean))
+    t["y"] = y.contiguous()
     torch.cuda.synchronize()
-    return ctx, dict(coils=coils, mask=mask, m_k=mk, y=y.contiguous(), zstar=zstar)
+    del ctx
+    return t
 
 
-def nmse_gpu(U_prev, B, zstar, zz):
-    """||U B - Z*||_F^2 / ||Z*||_F^2 with X_k = U b_k (U: r x n rows, B: q x r)."""
-    import torch
-    X = B.to(torch.complex128) @ U_prev.to(torch.complex128)  # (q, n)
-    return float(torch.sum(torch.abs(X - zstar.to(torch.complex128)) ** 2).item() / zz)
+class Form:
+    """One form of the method on the shared inputs: its context, its
+    initialisation (spectral, or learned with the spectral fallback) and its
+    precision."""
 
-
-def run_gpu(args):
-    import torch
-    import datagen  # noqa: F401
-    prob = make_inputs(args.seed)
-    T = prob.t_iters
-    ctx, t = gpu_problem(prob, args.form)
-    stream = ctx.stream
-    U = torch.empty(prob.r, prob.n, dtype=torch.complex64, device="cuda:0")
-    B = torch.empty(prob.q, prob.r, dtype=torch.complex64, device="cuda:0")
-
-    warm = None
-    if args.form in ("warm", "mixed_warm"):
-        wpath = os.path.join(ROOT, "paper_2212_09664_amd", "weights", f"wsinit_{WORKLOAD}.npy")
-        if not os.path.exists(wpath):
-            print(f"no trained warm-start weights for {WORKLOAD} ({wpath})", file=sys.stderr)
-            sys.exit(1)
+    def __init__(self, prob, t, form: str, workload: str):
+        import torch
         import paper_2212_09664_amd as ag
-        params = torch.from_numpy(np.load(wpath)).to("cuda:0")
-        net = ag.WsInit(prob.nx, prob.ny, prob.q, prob.r, width=32, batch=1, stream=stream)
-        xbuf = torch.empty(1, 2 * prob.q, prob.ny, prob.nx, dtype=torch.float32, device="cuda:0")
-        warm = (net, params, xbuf)
+        self.prob, self.t, self.form = prob, t, form
+        m_max = int(prob.m_k().max())
+        precision = ag.MIXED if form in ("mixed", "mixed_warm") else ag.FP32
+        kind = ag.MASK_LINES if prob.kind == "lines" else ag.MASK_INDEX
+        self.ctx = ag.AltGDmin(prob.nx, prob.ny, prob.nc, prob.q, prob.r, m_max, kind, precision,
+                               t_max=prob.t_iters)
+        self.ws = torch.empty(self.ctx.workspace_bytes + 256, dtype=torch.uint8, device="cuda:0")
+        self.bind()
+        self.stream = self.ctx.stream
+        self.U = torch.empty(prob.r, prob.n, dtype=torch.complex64, device="cuda:0")
+        self.B = torch.empty(prob.q, prob.r, dtype=torch.complex64, device="cuda:0")
+        self.warm = None
+        if form in ("warm", "mixed_warm"):
+            wpath = os.path.join(ROOT, "paper_2212_09664_amd", "weights", f"wsinit_{workload}.npy")
+            if not os.path.exists(wpath):
+                raise FileNotFoundError(f"no trained warm-start weights for {workload} ({wpath})")
+            params = torch.from_numpy(np.load(wpath)).to("cuda:0")
+            net = ag.WsInit(prob.nx, prob.ny, prob.q, prob.r, width=32, batch=1, stream=self.stream)
+            xbuf = torch.empty(1, 2 * prob.q, prob.ny, prob.nx, dtype=torch.float32, device="cuda:0")
+            self.warm = (net, params, xbuf)
 
-    def initialise():
-        if warm is None:
-            ctx.init(U)
+    def bind(self):
+        t = self.t
+        self.ctx.set_problem(t["coils"], t["mask"], t["m_k"], t["y"], workspace=self.ws)
+
+    def initialise(self):
+        if self.warm is None:
+            self.ctx.init(self.U)
         else:
-            net, params, xbuf = warm
-            ctx.cnn_input(xbuf[0])
+            net, params, xbuf = self.warm
+            self.ctx.cnn_input(xbuf[0])
             M = net.forward(params, xbuf)
-            ctx.init_warm(M[0], U)
+            self.ctx.init_warm(M[0], self.U)
 
-    def step():
-        ctx.set_problem(t["coils"], t["mask"], t["m_k"], t["y"], workspace=ctx._keep[4])
-        initialise()
-        ctx.iterate(T, U, B)
+    def step(self, T):
+        self.bind()
+        self.initialise()
+        self.ctx.iterate(T, self.U, self.B)
 
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        kernel = args.kernel
-        if kernel == "auto":
-            # the loop's dominant kernel class: total event time per class over one step
-            tot = {}
-            for name in LOOP_KERNELS:
-                ctx.set_timing(name)
-                step()
+    def time_to_nmse(self, T, replays=10, warmups=3):
+        """Run A (events after setup, init and every iteration; median of the
+        replays) and run B (NMSE after every iteration, off the clock)."""
+        import torch
+        s = self.stream
+        zs = self.t["zstar"].to(torch.complex128)
+        zz = float(torch.sum(torch.abs(zs) ** 2).item())
+        with torch.cuda.stream(s):
+            # run B: the deterministic trajectory's NMSE
+            self.bind()
+            self.initialise()
+            Up = torch.empty_like(self.U)
+            nm = []
+            for _ in range(T):
+                self.ctx.iterate(1, self.U, self.B, U_prev=Up)
+                X = self.B.to(torch.complex128) @ Up.to(torch.complex128)
+                nm.append(float(torch.sum(torch.abs(X - zs) ** 2).item()) / zz)
+            hit = next((i for i, v in enumerate(nm) if v <= NMSE_TARGET), None)
+            stamps = []
+            for rep in range(warmups + replays):
+                evs = [torch.cuda.Event(enable_timing=True) for _ in range(T + 3)]
                 torch.cuda.synchronize()
-                kn, nl, ms = ctx.kernel_time()
-                tot[name] = ms
-            ctx.set_timing("none")
-            kernel = max(tot, key=tot.get)
-        ctx.set_timing(kernel)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                evs[0].record(s)
+                self.bind()
+                evs[1].record(s)
+                self.initialise()
+                evs[2].record(s)
+                for i in range(T):
+                    self.ctx.iterate(1, self.U, self.B)
+                    evs[3 + i].record(s)
+                torch.cuda.synchronize()
+                if rep >= warmups:
+                    stamps.append([evs[0].elapsed_time(e) for e in evs[1:]])
+        med = [statistics.median(col) for col in zip(*stamps)]
+        return dict(nmse=nm, hit=hit, ttn_ms=(med[2 + hit] if hit is not None else None),
+                    iters=(hit + 1 if hit is not None else None), setup_ms=med[0], init_ms=med[1] - med[0],
+                    nmse_final=nm[-1])
+
+    def loop_ms(self, T, reps=10):
+        """Median over replays of the event time of iterate(T) alone."""
+        import torch
+        s = self.stream
+        out = []
+        with torch.cuda.stream(s):
+            for _ in range(reps):
+                self.bind()
+                self.initialise()
+                torch.cuda.synchronize()
+                l0, l1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                l0.record(s)
+                self.ctx.iterate(T, self.U, self.B)
+                l1.record(s)
+                torch.cuda.synchronize()
+                out.append(l0.elapsed_time(l1))
+        return statistics.median(out)
+
+
+def headline(prob, t, args, workload):
+    """The plain form's whole-step throughput, its loop, its dominant kernel
+    class and its time to target."""
+    import torch
+    T = prob.t_iters
+    f = Form(prob, t, "plain", workload)
+    s = f.stream
+    with torch.cuda.stream(s):
+        for _ in range(args.warmup):
+            f.step(T)
         torch.cuda.synchronize()
-        ev0.record(stream)
+        # the loop's dominant kernel class: total event time per class over one step
+        tot = {}
+        for name in LOOP_KERNELS:
+            f.ctx.set_timing(name)
+            f.step(T)
+            torch.cuda.synchronize()
+            _, _, ms = f.ctx.kernel_time()
+            tot[name] = ms
+        f.ctx.set_timing("none")
+        kernel = max(tot, key=tot.get)
+        # the timed steps; an event pair around each step's loop gives the
+        # iteration time inside the timed region
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        loop_evs = []
+        torch.cuda.synchronize()
+        ev0.record(s)
         for _ in range(args.steps):
-            step()
-        ev1.record(stream)
+            f.bind()
+            f.initialise()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            f.ctx.iterate(T, f.U, f.B)
+            b.record(s)
+            loop_evs.append((a, b))
+        ev1.record(s)
         torch.cuda.synchronize()
         total_ms = ev0.elapsed_time(ev1)
-        kname, klaunch, kms = ctx.kernel_time()
-        ctx.set_timing("none")
-        # the loop alone
-        ctx.set_problem(t["coils"], t["mask"], t["m_k"], t["y"], workspace=ctx._keep[4])
-        initialise()
-        torch.cuda.synchronize()
-        l0, l1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        l0.record(stream)
-        ctx.iterate(T, U, B)
-        l1.record(stream)
-        torch.cuda.synchronize()
-        loop_ms = l0.elapsed_time(l1)
-        # time to NMSE <= 2e-2: run A with events, run B with NMSE off the clock
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(T + 3)]
-        torch.cuda.synchronize()
-        evs[0].record(stream)
-        ctx.set_problem(t["coils"], t["mask"], t["m_k"], t["y"], workspace=ctx._keep[4])
-        evs[1].record(stream)
-        initialise()
-        evs[2].record(stream)
-        for i in range(T):
-            ctx.iterate(1, U, B)
-            evs[3 + i].record(stream)
-        torch.cuda.synchronize()
-        stamps = [evs[0].elapsed_time(e) for e in evs[1:]]
-        zz = float(torch.sum(torch.abs(t["zstar"].to(torch.complex128)) ** 2).item())
-        ctx.set_problem(t["coils"], t["mask"], t["m_k"], t["y"], workspace=ctx._keep[4])
-        initialise()
-        Up = torch.empty_like(U)
-        nm = []
-        for i in range(T):
-            ctx.iterate(1, U, B, U_prev=Up)
-            torch.cuda.synchronize()
-            nm.append(nmse_gpu(Up, B, t["zstar"], zz))
-    hit = next((i for i, v in enumerate(nm) if v <= 2e-2), None)
-    ttn = stamps[2 + hit] if hit is not None else None
-    lines = np.unique(np.concatenate(prob.masks))
-    kb = alg_bytes(kname, prob.nx, prob.ny, prob.nc, prob.q, prob.r, len(lines), int(prob.m_k().sum()))
-    kavg_ms = kms / max(klaunch, 1)
-    achieved = kb / (kavg_ms * 1e-3) / 1e9
-    return dict(
-        prob=prob, total_ms=total_ms, loop_ms=loop_ms, T=T, nmse=nm, ttn_ms=ttn, ttn_iters=(hit + 1 if hit is not None else None),
-        setup_ms=stamps[0], init_ms=stamps[1] - stamps[0], kname=kname, klaunch=klaunch, kavg_ms=kavg_ms,
-        kbytes=kb, achieved=achieved)
+        loop = statistics.median(a.elapsed_time(b) for a, b in loop_evs)
+        # the dominant class alone, with events around each of its launches
+        f.ctx.set_timing(kernel)
+        for _ in range(args.steps):
+            f.step(T)
+        kname, klaunch, kms = f.ctx.kernel_time()
+        f.ctx.set_timing("none")
+    ttn = f.time_to_nmse(T)
+    return dict(total_ms=total_ms, loop_ms=loop, T=T, kname=kname, klaunch=klaunch,
+                kavg_ms=kms / max(klaunch, 1), class_ms_per_step=tot, ttn=ttn)
 
 
-def cpu_baseline(iters: int, seed: int, T: int):
+def other_form(prob, t, form, workload):
+    T = prob.t_iters
+    f = Form(prob, t, form, workload)
+    return dict(loop_ms=f.loop_ms(T), ttn=f.time_to_nmse(T))
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle
+# ---------------------------------------------------------------------------
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, reps: int = 3):
     """The FP64 oracle (literal Algorithm 2) on the same workload and seed:
-    the truncated spectral initialisation plus `iters` iterations, timed on
-    this host.  Scaled to the GPU figure's unit: one step is the
-    initialisation plus T iterations, so value = T / (init + T * loop/iters)."""
+    the truncated spectral initialisation once, then `reps` single
+    iterations from the spectral basis, each timed; the median iteration time
+    scales the sample to one step of init + T iterations,
+    value = T / (init + T * median)."""
     import datagen
     from oracle import altgdmin as AG
     from oracle import operators as O
-    prob = make_inputs(seed)
     op = O.from_problem(prob)
     Y = datagen.add_noise(op.apply_A(prob.zstar), prob.noise, op.m_k, prob.snr_db)
     t0 = time.perf_counter()
     Ytr, _, _ = AG.truncation(op, Y, 36.0)
     U0 = AG.spectral_init(AG.backprojection(op, Ytr), prob.r)
-    t1 = time.perf_counter()
-    AG.run(op, Y, AG.Params(r=prob.r), U0=U0, t_fixed=iters, record=False)
-    t2 = time.perf_counter()
-    step_s = (t1 - t0) + T * (t2 - t1) / iters
-    return dict(value=T / step_s, init_s=t1 - t0, loop_s=t2 - t1, iters=iters, cores=O.WORKERS)
+    t_init = time.perf_counter() - t0
+    its = []
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        AG.run(op, Y, AG.Params(r=prob.r), U0=U0, t_fixed=1, record=False)
+        its.append(time.perf_counter() - t1)
+    med = statistics.median(its)
+    T = prob.t_iters
+    return dict(value=T / (t_init + T * med), init_s=t_init, iter_s=its, median_iter_s=med, cores=O.WORKERS,
+                cpu=cpu_model(), T=T)
 
 
+# ---------------------------------------------------------------------------
+# probes
+# ---------------------------------------------------------------------------
 def bandwidth_probe():
     """Rates of torch's own copy, sum and fill kernels (HIP events, 20
     launches after 3 warm-up ones) at sizes around a loop kernel's bytes: what
     a plain streaming kernel reaches with the data resident in the last-level
     cache (up to ~200 MB) and from HBM (larger)."""
     import torch
+
     def per_launch_us(fn, reps=20):
         for _ in range(3):
             fn()
@@ -292,18 +424,19 @@ def bandwidth_probe():
     print(json.dumps({"bandwidth_probe": rows}), flush=True)
 
 
+def r4(v):
+    return None if v is None else round(float(v), 4)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", choices=["plain", "mixed", "warm", "mixed_warm"], default="plain",
-                    help="plain FP32; mixed (FP16 hi+lo MFMA ky transforms, FP64 Grams); warm / mixed_warm: "
-                         "learned initial basis with the spectral fallback")
-    ap.add_argument("--kernel", default="auto",
-                    help="kernel class timed for the roofline figure (auto: the loop's most expensive)")
+    ap.add_argument("--form", choices=["all", "plain", "mixed", "warm", "mixed_warm"], default="all",
+                    help="all (default): the plain form's throughput plus the time to NMSE <= 2e-2 of every "
+                         "form on the same inputs; a single form: only that form's figures")
     ap.add_argument("--seed", type=int, default=1001)
-    ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=sorted(WORKLOAD_TEXT), default="cine256",
                     help="the headline figure is cine256; the others are for comparisons")
@@ -332,12 +465,72 @@ def main():
     if args.bandwidth_probe:
         bandwidth_probe()
         return
-    global WORKLOAD
-    WORKLOAD = args.workload
-    g = run_gpu(args)
-    prob = g["prob"]
-    iters = args.steps * g["T"]
-    value = iters / (g["total_ms"] * 1e-3)
+    import datagen
+    workload = args.workload
+    prob = datagen.make(workload, args.seed)
+    t = gpu_inputs(prob)
+    T = prob.t_iters
+    forms = {}
+    if args.form in ("all", "plain"):
+        g = headline(prob, t, args, workload)
+        forms["plain"] = dict(loop_ms=g["loop_ms"], ttn=g["ttn"])
+        print(f"# plain: {args.steps} steps {g['total_ms']:.2f} ms, loop {g['loop_ms']:.3f} ms", flush=True)
+    else:
+        g = None
+    extra = ["warm", "mixed", "mixed_warm"] if args.form == "all" else ([args.form] if args.form != "plain" else [])
+    for form in extra:
+        try:
+            forms[form] = other_form(prob, t, form, workload)
+            print(f"# {form}: loop {forms[form]['loop_ms']:.3f} ms", flush=True)
+        except FileNotFoundError as e:
+            print(f"# {form}: skipped ({e})", flush=True)
+    plain_ttn = forms.get("plain", {}).get("ttn", {}).get("ttn_ms")
+    form_rows = {}
+    for name, fr in forms.items():
+        tt = fr["ttn"]
+        form_rows[name] = {
+            "loop_iter_per_s": round(T / (fr["loop_ms"] * 1e-3), 2),
+            "time_to_nmse_ms": r4(tt["ttn_ms"]), "iters_to_nmse": tt["iters"],
+            "init_ms": r4(tt["init_ms"]), "setup_ms": r4(tt["setup_ms"]),
+            "nmse_final": tt["nmse_final"],
+            "ttn_vs_plain": (None if (plain_ttn is None or tt["ttn_ms"] is None) else round(tt["ttn_ms"] / plain_ttn, 4)),
+        }
+    head = g if g is not None else None
+    main_form = "plain" if head is not None else extra[0]
+    iter_ms = forms[main_form]["loop_ms"] / T
+    b_alg = iteration_bytes(prob)
+    flops = iteration_flops(prob)
+    t_hbm = b_alg / (HBM_PEAK_GBS * 1e9)
+    t_alu = flops / (FP32_PEAK_TFLOPS * 1e12)
+    achieved_gbs = b_alg / (iter_ms * 1e-3) / 1e9
+    achieved_tf = flops / (iter_ms * 1e-3) / 1e12
+    traffic = measured_traffic(workload) if main_form == "plain" else None
+    if t_hbm >= t_alu:
+        roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tf / FP32_PEAK_TFLOPS, 4)}
+    roof.update({
+        "traffic": (round(sum(traffic[k] for k in LOOP_KERNELS if k in traffic)) if traffic else None),
+        "unit_of_work": "one altGDmin iteration (the loop's kernels, summed)",
+        "alg_bytes_per_iter": b_alg, "flops_per_iter": flops, "iter_ms": round(iter_ms, 5),
+        "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "fp32_frac": round(achieved_tf / FP32_PEAK_TFLOPS, 4),
+    })
+    if head is not None:
+        kb = kernel_operand_bytes(head["kname"], prob)
+        kach = kb / (head["kavg_ms"] * 1e-3) / 1e9
+        roof["dominant_kernel"] = {
+            "kernel": head["kname"], "operand_bytes_per_launch": kb, "avg_launch_ms": round(head["kavg_ms"], 5),
+            "launches": head["klaunch"], "achieved": round(kach, 1), "unit": "GB/s",
+            "frac": round(kach / HBM_PEAK_GBS, 4),
+            "traffic": (traffic.get(head["kname"]) if traffic else None),
+        }
+        value = args.steps * T / (head["total_ms"] * 1e-3)
+        ms_step = head["total_ms"] / args.steps
+    else:
+        value = T / (forms[main_form]["loop_ms"] * 1e-3)
+        ms_step = forms[main_form]["loop_ms"]
     out = {
         "metric": "altGDmin iter/s + time-to-NMSE<=2e-2 at 256^2 x 12 coils x 40 frames vs plain",
         "value": round(value, 2),
@@ -345,43 +538,33 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(g["total_ms"] / args.steps, 4),
+        "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.form in ("plain", "warm") else "f32+f16x2+f64",
+        "dtype": "f32" if main_form in ("plain", "warm") else "f32+f16x2+f64",
         "data": "synthetic",
         "config": {
-            "workload": WORKLOAD_TEXT[WORKLOAD],
-            "form": args.form,
-            "step": f"bind + spectral init + {g['T']} iterations",
+            "workload": WORKLOAD_TEXT[workload],
+            "form": main_form,
+            "step": f"bind + spectral init + {T} iterations",
         },
-        "loop_iter_per_s": round(g["T"] / (g["loop_ms"] * 1e-3), 2),
-        "time_to_nmse_ms": None if g["ttn_ms"] is None else round(g["ttn_ms"], 4),
-        "iters_to_nmse": g["ttn_iters"],
-        "nmse_final": g["nmse"][-1],
-        "setup_ms": round(g["setup_ms"], 4),
-        "init_ms": round(g["init_ms"], 4),
-        "roofline": {
-            "kernel": g["kname"],
-            "bound": "hbm",
-            "achieved": round(g["achieved"], 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(g["achieved"] / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(g["kname"]),
-            "alg_bytes_per_launch": g["kbytes"],
-            "avg_launch_ms": round(g["kavg_ms"], 5),
-            "launches": g["klaunch"],
-        },
+        "loop_iter_per_s": form_rows[main_form]["loop_iter_per_s"],
+        "time_to_nmse_ms": form_rows[main_form]["time_to_nmse_ms"],
+        "iters_to_nmse": form_rows[main_form]["iters_to_nmse"],
+        "nmse_final": form_rows[main_form]["nmse_final"],
+        "forms": form_rows,
+        "roofline": roof,
     }
     if not args.no_cpu:
-        cb = cpu_baseline(args.cpu_iters, args.seed, g["T"])
+        cb = cpu_baseline(prob)
         out["cpu_baseline"] = {
             "value": round(cb["value"], 4), "unit": "iter/s", "cores": cb["cores"], "kind": "oracle",
-            "sample": f"FP64 NumPy/SciPy oracle, literal Algorithm 2, same workload and seed: spectral init "
-                      f"({cb['init_s']:.1f} s) + {cb['iters']} iterations ({cb['loop_s']:.1f} s), scaled to one "
-                      f"step of init + {g['T']} iterations",
+            "cpu": cb["cpu"],
+            "sample": f"FP64 NumPy/SciPy oracle (literal Algorithm 2) on the same workload and seed: the spectral "
+                      f"init once ({cb['init_s']:.1f} s) and 3 single iterations "
+                      f"({', '.join(f'{v:.2f}' for v in cb['iter_s'])} s; median {cb['median_iter_s']:.2f} s), "
+                      f"scaled to one step of init + {cb['T']} iterations",
         }
     print(json.dumps(out), flush=True)
 

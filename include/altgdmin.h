@@ -120,6 +120,8 @@ typedef struct {
   double grad_norm;     /* ||grad_t||_F                                    */
   double eta;           /* step size in use                                */
   double gamma;         /* truncation threshold gamma (init)               */
+  int32_t n_trunc;      /* samples (over every frame and coil) zeroed by the
+                           truncation of the last altgdmin_init            */
 } altgdmin_stats;
 
 typedef struct altgdmin_ctx altgdmin_ctx;
@@ -166,9 +168,13 @@ altgdmin_status altgdmin_cnn_input(altgdmin_ctx* ctx, float* d_in);
  * strictly lower cost is written to d_U.  The step size is set by
  * Algorithm 2's first-iteration rule at the spectral basis (the rule at a
  * good learned basis, whose gradient is small, would overshoot), so with
- * the fallback the run is exactly the plain one.  No host synchronisation:
- * if d_choice is not NULL, the device int it points to receives 1 when the
- * learned guess was kept, 0 otherwise.  Resets t. */
+ * the fallback the run is exactly the plain one.  A guess that cannot be
+ * scored (its Gram, or a frame's Gram of A_k QR(M), is not positive
+ * definite, or a value is not finite: e.g. an all-zero or NaN network
+ * output) counts as infinitely costly: the spectral basis is kept and no
+ * error is left set.  No host synchronisation: if d_choice is not NULL, the
+ * device int it points to receives 1 when the learned guess was kept, 0
+ * otherwise.  Resets t. */
 altgdmin_status altgdmin_init_warm(altgdmin_ctx* ctx, const void* d_M, void* d_U, int32_t* d_choice);
 
 /* altgdmin_init_warm with the fallback basis supplied instead of computed:
@@ -191,7 +197,8 @@ altgdmin_status altgdmin_init_warm_from(altgdmin_ctx* ctx, const void* d_M, cons
  * n_iter <= 0 means t_max.  With eps_exit > 0 the loop stops on the device
  * when the exit rule fires (the remaining launches do nothing).
  * h_iters_done (host, may be NULL) receives the number of iterations done by
- * this call; passing it synchronises the stream. */
+ * this call; passing it synchronises the stream (before the call's work, to
+ * read the starting count, and after it). */
 altgdmin_status altgdmin_iterate(altgdmin_ctx* ctx, int32_t n_iter, void* d_U, void* d_B,
                                  void* d_U_prev, int32_t* h_iters_done);
 

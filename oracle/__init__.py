@@ -20,9 +20,12 @@ paper's order and notation:
 * ``variants``   -- FP64 restatements of the algebra the GPU path uses
   (hybrid ky/x form, folded gradient, Gram + Cholesky LS), checked against
   the literal forms;
-* ``metrics``    -- subspace distance, NMSE and the scale-invariant N-S-MSE.
+* ``metrics``    -- subspace distance, NMSE and the scale-invariant N-S-MSE;
+* ``mri``        -- the steps around the loop (Algorithm 1: the mean image by
+  CGLS and the residuals; Algorithm 2's automatic rank; Algorithm 3: MEC-1
+  and MEC-2) and the tracking drivers of Sec. IV (Algorithms 4 and 5).
 
 Each function cites the passage it follows.  Readings chosen where the paper
 is silent or ambiguous are stated at the function that applies them.
 """
-from . import operators, altgdmin, variants, metrics  # noqa: F401
+from . import operators, altgdmin, variants, metrics, mri  # noqa: F401

@@ -36,7 +36,6 @@ class Params:
     eta_c: float = 0.14        # eta = eta_c / ||grad_0||
     eta_cap_c: float = 0.0     # > 0: cap eta by eta_cap_c * n / (mbar ||B_0||^2)
     eps_exit: float = 0.0      # > 0: exit when SD(U, U+)/sqrt(r) < eps_exit (paper: 0.01)
-    eta_norm: str = "spectral"  # which norm of grad_0 sets eta ('spectral' or 'fro')
 
 
 @dataclass
@@ -78,6 +77,16 @@ def truncation(op: Operator, Y: np.ndarray, trunc_c: float):
     valid = np.broadcast_to(valid, Y.shape)
     removed = np.count_nonzero(valid & ~keep) / max(np.count_nonzero(valid), 1)
     return np.where(keep, Y, 0.0), gamma, removed
+
+
+def truncation_count(op: Operator, Y: np.ndarray, trunc_c: float) -> int:
+    """The number of valid samples (every frame and coil) that the
+    truncation of Algorithm 2 zeroes."""
+    if trunc_c <= 0:
+        return 0
+    _, gamma, _ = truncation(op, Y, trunc_c)
+    valid = np.arange(Y.shape[2])[None, None, :] < op.m_k[:, None, None]
+    return int(np.count_nonzero(np.broadcast_to(valid, Y.shape) & (np.abs(Y) > np.sqrt(gamma))))
 
 
 def backprojection(op: Operator, Ytrnc: np.ndarray) -> np.ndarray:
@@ -141,18 +150,24 @@ def gradient(op: Operator, U: np.ndarray, B: np.ndarray, Y: np.ndarray, FU=None)
     return G
 
 
-def step_size(grad0: np.ndarray, eta_c: float, norm: str = "spectral") -> float:
+def step_size(grad0: np.ndarray, eta_c: float) -> float:
     """eta = eta_c / ||grad_U f(U_0, B_0)|| (Algorithm 2, Sec. III-B).
 
     The paper's norm without subscript is the induced l2 (spectral) norm.
     """
-    if norm == "spectral":
-        g = np.linalg.norm(grad0, 2)
-    elif norm == "fro":
-        g = np.linalg.norm(grad0)
-    else:
-        raise ValueError(norm)
-    return eta_c / g
+    return eta_c / np.linalg.norm(grad0, 2)
+
+
+def step_size_cap(op, B0: np.ndarray, cap_c: float) -> float:
+    """The conservative step size eta = c / (m ||U_0 B_0||^2) of Sec. III-B
+    (parameter setting), used only as an upper bound on Algorithm 2's eta.
+
+    Reading: with a unitary F and sum_c |s_c|^2 = 1, E[A_k^H A_k] = (m_k/n) I,
+    so the paper's m (for unnormalised Gaussian A_k) becomes mbar/n here;
+    ||U_0 B_0||_2 = ||B_0||_2 for an orthonormal U_0 (spectral norm).
+    """
+    mbar = float(np.sum(op.m_k)) / op.q
+    return cap_c * op.n / (mbar * float(np.linalg.norm(B0, 2)) ** 2)
 
 
 def qr_project(Uhat: np.ndarray) -> np.ndarray:
@@ -203,11 +218,10 @@ def run(op: Operator, Y: np.ndarray, params: Params, U0: Optional[np.ndarray] = 
                 hist["converged_at_start"] = True
                 iters = 0
                 break
-            eta = step_size(G, params.eta_c, params.eta_norm)
+            eta = step_size(G, params.eta_c)
             if params.eta_cap_c > 0:
-                mbar = float(np.sum(op.m_k)) / op.q
-                cap = params.eta_cap_c * op.n / (mbar * float(np.linalg.norm(B, 2)) ** 2)
-                hist["eta_capped"] = cap < eta
+                cap = step_size_cap(op, B, params.eta_cap_c)
+                hist["eta_capped"] = bool(cap < eta)
                 eta = min(eta, cap)
         Uplus = qr_project(U - eta * G)
         sd = metrics.subspace_distance(U, Uplus)

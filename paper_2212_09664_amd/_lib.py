@@ -28,7 +28,7 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int32), ("exited", ctypes.c_int32), ("f", ctypes.c_double),
                 ("sd", ctypes.c_double), ("grad_norm", ctypes.c_double), ("eta", ctypes.c_double),
-                ("gamma", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("n_trunc", ctypes.c_int32)]
 
 
 class AltGDminError(RuntimeError):

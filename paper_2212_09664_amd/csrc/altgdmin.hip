@@ -110,7 +110,7 @@ void carve(altgdmin_ctx* c) {
   c->o_unitspan = take(sizeof(int2) * (size_t)c->n_loc);
   c->o_bcp = take(sizeof(float2) * (size_t)q * c->width * r);
   c->o_Uc = take(sizeof(float2) * (size_t)n * r);
-  c->o_fcmp = take(sizeof(double) * 2);
+  c->o_fcmp = take(sizeof(double) * 4);  // the two costs compared, then the error snapshot
   // Gram work list: at most ceil(q/8) items per line, and at least one entry per
   // workgroup of the Gram launch (ny + 64 of them)
   c->o_gwork = take(sizeof(int4) * ((size_t)c->n_loc * ((q + 7) / 8) + (c->lines ? p.ny + 64 : 0)));
@@ -553,6 +553,7 @@ hipError_t adjoint_op(altgdmin_ctx* c, const float2* Y, float2* X, int trunc, in
     ra.lmax = c->lmax;
     ra.scale = (float)(1.0 / sqrt((double)p.nx));
     ra.trunc = trunc;
+    ra.trunc_count = trunc ? &c->st()->n_trunc : nullptr;
     ra.st = c->st();
     e = launch_rows(p.nx, ra, true, c->stream);
     if (e != hipSuccess) return e;
@@ -580,7 +581,8 @@ hipError_t adjoint_op(altgdmin_ctx* c, const float2* Y, float2* X, int trunc, in
     const long nimg = (long)kc * p.nc * c->n;
     hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, c->stream, T, nimg);
     hipLaunchKernelGGL(k_scatter, dim3((p.m_max + 255) / 256, kc, p.nc), dim3(256), 0, c->stream, Y, c->mask,
-                       c->m_k, p.m_max, p.nc, k0, T, (long)c->n, (long)p.nc * c->n, c->st(), trunc);
+                       c->m_k, p.m_max, p.nc, k0, T, (long)c->n, (long)p.nc * c->n, c->st(), trunc,
+                       trunc ? &c->st()->n_trunc : nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     RowArgs ra{};
@@ -839,6 +841,9 @@ static altgdmin_status warm_combine(altgdmin_ctx* c, const void* d_M, void* d_U,
   // their sum is the spectral side of the comparison below
   double* f = c->at<double>(c->o_fcmp);
   hipLaunchKernelGGL(k_cost_total, dim3(1), dim3(1), 0, s, c->at<double>(c->o_cost), p.q, f, c->st());
+  // an error raised from here on comes from scoring the guess alone
+  int32_t* snap = reinterpret_cast<int32_t*>(f + 2);
+  hipLaunchKernelGGL(k_err_snapshot, dim3(1), dim3(1), 0, s, c->st(), snap);
   float2* Uc = c->at<float2>(c->o_Uc);
   hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, static_cast<const float2*>(d_M), Uc, (long)c->n * p.r);
   HIPCHK(hipGetLastError());
@@ -848,8 +853,9 @@ static altgdmin_status warm_combine(altgdmin_ctx* c, const void* d_M, void* d_U,
   HIPCHK(fwd_transform(c, 0));
   HIPCHK(gram_solve(c, 0));
   hipLaunchKernelGGL(k_cost_total, dim3(1), dim3(1), 0, s, c->at<double>(c->o_cost), p.q, f + 1, c->st());
-  hipLaunchKernelGGL(k_pick_init, dim3(256), dim3(256), 0, s, f, Uc, static_cast<float2*>(d_U), (long)c->n * p.r,
-                     d_choice, c->st());
+  hipLaunchKernelGGL(k_pick_init, dim3(256), dim3(256), 0, s, f, snap, Uc, static_cast<float2*>(d_U),
+                     (long)c->n * p.r, d_choice, c->st());
+  hipLaunchKernelGGL(k_err_restore, dim3(1), dim3(1), 0, s, snap, c->st());
   HIPCHK(hipGetLastError());
   c->initialized = 1;
   return ALTGDMIN_OK;
@@ -882,7 +888,11 @@ altgdmin_status altgdmin_iterate(altgdmin_ctx* c, int32_t n_iter, void* d_U, voi
   const altgdmin_params& p = c->p;
   if (n_iter <= 0) n_iter = p.t_max;
   int32_t t0 = 0;
-  if (h_iters_done) HIPCHK(hipMemcpy(&t0, &c->st()->t, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (h_iters_done) {
+    // the count before this call's iterations: earlier work on the stream first
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(&t0, &c->st()->t, sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
   HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
   for (int t = 0; t < n_iter; ++t)
     HIPCHK(one_iteration(c, static_cast<float2*>(d_U), static_cast<float2*>(d_U_prev)));
@@ -921,6 +931,9 @@ altgdmin_status altgdmin_set_eta(altgdmin_ctx* c, double eta) {
 altgdmin_status altgdmin_cost(altgdmin_ctx* c, const void* d_U, double* d_f) {
   if (!c || !d_U || !d_f) return ALTGDMIN_EINVAL;
   if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
+  // the last iteration's statistics read cost_k, which the solve below overwrites
+  HIPCHK(launch_stats_finish(c->st(), c->at<double2>(c->o_stsrc), c->at<double>(c->o_cost), c->p.q, c->p.r,
+                             c->stream));
   HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
   HIPCHK(fwd_transform(c, 0));
   HIPCHK(gram_solve(c, 0));
@@ -933,6 +946,7 @@ altgdmin_status altgdmin_gradient(altgdmin_ctx* c, const void* d_U, void* d_B, v
   if (!c || !d_U) return ALTGDMIN_EINVAL;
   if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
   const altgdmin_params& p = c->p;
+  HIPCHK(launch_stats_finish(c->st(), c->at<double2>(c->o_stsrc), c->at<double>(c->o_cost), p.q, p.r, c->stream));
   HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
   HIPCHK(gradient_pieces(c, 0));
   if (c->adj_parts > 1)
@@ -1035,6 +1049,7 @@ altgdmin_status altgdmin_get_stats(altgdmin_ctx* c, altgdmin_stats* out) {
   out->grad_norm = h.grad_norm;
   out->eta = h.eta;
   out->gamma = h.gamma;
+  out->n_trunc = h.n_trunc;
   return ALTGDMIN_OK;
 }
 

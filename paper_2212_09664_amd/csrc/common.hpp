@@ -74,7 +74,7 @@ struct DevState {
   int32_t step_flags; // the fused QR step's outcome, committed after it (STEP_*)
   double eta_next;    // the step size it used (committed after it)
   int32_t stats_pending;  // 1: f, sd and grad_norm of the last step wait in the statistics inputs
-  int32_t pad_i;
+  int32_t n_trunc;    // samples zeroed by the truncation of the last initialisation
   double pad[3];
 };
 // the loop's stop test: err and halt both requested before either is tested

@@ -17,6 +17,7 @@ struct RowArgs {
   int trunc;           // zero samples with |v|^2 > gamma before the transform
   int check_halt;
   const DevState* st;
+  int32_t* trunc_count;  // non-null with trunc: receives the number of samples zeroed
 };
 
 __device__ __forceinline__ bool row_valid(const RowArgs& a, long rho, int N) {
@@ -79,7 +80,7 @@ __global__ void k_gather(const float2* img, long img_stride_c, long img_stride_k
                          const int32_t* m_k, int m_max, int nc, int k0, float2* y, const DevState* st);
 __global__ void k_scatter(const float2* y, const int32_t* mask, const int32_t* m_k, int m_max, int nc,
                           int k0, float2* img, long img_stride_c, long img_stride_k, const DevState* st,
-                          int trunc);
+                          int trunc, int32_t* trunc_count);
 __global__ void k_zero(float2* p, long n);
 
 }  // namespace ag

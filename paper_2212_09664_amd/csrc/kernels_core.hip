@@ -162,6 +162,7 @@ __global__ void k_state_reset(DevState* st, int full) {
   st->sd = 0.0;
   st->grad_norm = 0.0;
   st->stats_pending = 0;
+  st->n_trunc = 0;
 }
 
 __global__ void k_state_set_eta(DevState* st, double eta) {
@@ -1486,13 +1487,32 @@ __global__ __launch_bounds__(AG_NT) void k_x_times_v(const float2* X, const floa
 
 // keep the learned U (src) only if its cost f[1] is strictly below the
 // spectral one f[0]; a non-finite learned cost keeps the spectral U
-__global__ void k_pick_init(const double* f, const float2* src, float2* dst, long n, int32_t* choice,
-                            const DevState* st) {
-  if (st->err) return;
-  const bool take = f[1] < f[0];
+// The error flag as it stood before the learned guess was scored.
+__global__ void k_err_snapshot(const DevState* st, int32_t* snap) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *snap = st->err;
+}
+
+// Keep the learned basis (src) only if its cost f[1] is strictly below the
+// fallback's f[0].  A guess whose scoring raised an error (a Gram of the
+// guess or of A_k U that is not positive definite, a non-finite value) counts
+// as infinitely costly: the fallback stays.  An error that was already set
+// before the guess was scored (snap) is left for the caller.
+__global__ void k_pick_init(const double* f, const int32_t* snap, const float2* src, float2* dst, long n,
+                            int32_t* choice, const DevState* st) {
+  if (*snap) return;
+  const bool take = st->err == 0 && f[1] < f[0];
   if (choice && blockIdx.x == 0 && threadIdx.x == 0) *choice = take ? 1 : 0;
   if (!take) return;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+// After k_pick_init: an error raised only by the rejected guess is cleared.
+__global__ void k_err_restore(const int32_t* snap, DevState* st) {
+  if (threadIdx.x != 0 || *snap) return;
+  if (st->err) {
+    st->err = 0;
+    st->err_frame = -1;
+  }
 }
 
 __global__ void k_copy(const float2* src, float2* dst, long n) {

@@ -335,8 +335,10 @@ __global__ void k_state_reset(DevState* st, int full);
 __global__ void k_state_set_eta(DevState* st, double eta);
 __global__ void k_x_times_v(const float2* X, const float2* Vs, int n, int q, int r, float2* U,
                             const DevState* st);
-__global__ void k_pick_init(const double* f, const float2* src, float2* dst, long n, int32_t* choice,
-                            const DevState* st);
+__global__ void k_err_snapshot(const DevState* st, int32_t* snap);
+__global__ void k_pick_init(const double* f, const int32_t* snap, const float2* src, float2* dst, long n,
+                            int32_t* choice, const DevState* st);
+__global__ void k_err_restore(const int32_t* snap, DevState* st);
 __global__ void k_copy(const float2* src, float2* dst, long n);
 __global__ void k_cost_total(const double* cost_k, int q, double* out, DevState* st);
 __global__ void k_init_eig(InitEigArgs a);

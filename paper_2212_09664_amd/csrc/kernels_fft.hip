@@ -37,6 +37,7 @@ __global__ __launch_bounds__(AG_NT) void k_rows(RowArgs a) {
   const long rho0 = (long)blockIdx.x * TR;
   if (halted(a.st, a.check_halt)) return;
   const double gamma = a.trunc ? a.st->gamma : 0.0;
+  int n_cut = 0;
   for (int g = tid; g < N * TR; g += AG_NT) {
     const int t = g / N, e = g % N;
     const long rho = rho0 + t;
@@ -45,11 +46,15 @@ __global__ __launch_bounds__(AG_NT) void k_rows(RowArgs a) {
       v = a.src[rho * N + e];
       if (a.trunc) {
         double m2 = (double)v.x * v.x + (double)v.y * v.y;
-        if (m2 > gamma) v = make_float2(0.f, 0.f);
+        if (m2 > gamma) {
+          v = make_float2(0.f, 0.f);
+          ++n_cut;
+        }
       }
     }
     s[e * TR + t] = v;
   }
+  if (n_cut && a.trunc_count) atomicAdd(a.trunc_count, n_cut);
   __syncthreads();
   fft_lds<N, TR, AG_NT, INV>(s, a.tw);
   for (int g = tid; g < N * TR; g += AG_NT) {
@@ -221,7 +226,7 @@ __global__ void k_gather(const float2* img, long img_stride_c, long img_stride_k
 
 __global__ void k_scatter(const float2* y, const int32_t* mask, const int32_t* m_k, int m_max, int nc,
                           int k0, float2* img, long img_stride_c, long img_stride_k, const DevState* st,
-                          int trunc) {
+                          int trunc, int32_t* trunc_count) {
   if (st->err) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int kk = blockIdx.y, c = blockIdx.z, k = k0 + kk;
@@ -229,7 +234,10 @@ __global__ void k_scatter(const float2* y, const int32_t* mask, const int32_t* m
   float2 v = y[((long)k * nc + c) * m_max + i];
   if (trunc) {
     double m2 = (double)v.x * v.x + (double)v.y * v.y;
-    if (m2 > st->gamma) v = make_float2(0.f, 0.f);
+    if (m2 > st->gamma) {
+      v = make_float2(0.f, 0.f);
+      if (trunc_count) atomicAdd(trunc_count, 1);
+    }
   }
   img[c * img_stride_c + kk * img_stride_k + mask[(long)k * m_max + i]] = v;
 }

@@ -158,3 +158,32 @@ def test_warm_init_from_a_given_fallback_matches_init_warm():
             log(f"  kept {kept} in_place {in_place}: choice {int(c1.item())}")
             assert int(c1.item()) == kept
             assert torch.equal(U1, U0) and torch.equal(B1, B0)
+
+
+@pytest.mark.parametrize("guess", ["zero", "nan"])
+def test_warm_init_falls_back_when_the_guess_cannot_be_scored(guess):
+    """A network output that cannot be scored (all zero: its Gram is
+    singular even with the ridge; NaN: non-finite) counts as infinitely
+    costly: the spectral basis is kept, no error is left set, and the loop
+    then runs exactly as after the plain initialisation."""
+    p = datagen.make_small(32, 32, 3, 10, 2, seed=8, kind="lines", n_lines=8, lowrank=True, snr_db=40.0)
+    cs = Case(p)
+    ctx = cs.gpu_ctx()
+    Uspec = ctx.init()
+    Bspec = ctx.iterate(4, Uspec.clone())
+    torch.cuda.synchronize()
+    Uspec0 = ctx.init()
+    M = torch.zeros(p.r, p.n, dtype=torch.complex64, device="cuda:0")
+    if guess == "nan":
+        M[:] = float("nan")
+    choice = torch.full((1,), -1, dtype=torch.int32, device="cuda:0")
+    U = ctx.init_warm(M, choice=choice)
+    st, frame = ctx.last_error()
+    log(f"  {guess}: choice {int(choice.item())}, status {st}")
+    assert st == 0 and int(choice.item()) == 0
+    assert torch.equal(U, Uspec0)
+    B, done = ctx.iterate(4, U, sync=True)
+    assert done == 4
+    # the step size comes from the warm start's own evaluation of the rule at
+    # the spectral basis (same value up to rounding)
+    assert rel(from_gpu_U(B.T.contiguous()), from_gpu_U(Bspec.T.contiguous())) < 1e-5

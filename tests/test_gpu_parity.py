@@ -111,11 +111,12 @@ def test_spectral_init_matches_oracle():
     s = np.linalg.svd(X0, compute_uv=False)
     Uref = AG.spectral_init(X0, cs.prob.r)
     assert st["gamma"] == pytest.approx(gamma, rel=1e-12)
+    assert st["n_trunc"] == AG.truncation_count(cs.op, cs.y, 36.0)
     assert np.allclose(U0.conj().T @ U0, np.eye(cs.prob.r), atol=2e-6)
     gap = (s[cs.prob.r - 1] - s[cs.prob.r]) / s[0]
     d = proj_dist(U0, Uref)
     log(f"  projector distance {d:.2e}, relative gap {gap:.2e}")
-    assert d < 1e-5 / gap
+    assert d < 1e-6 / gap
 
 
 @pytest.mark.parametrize("cfg", [(32, 32, 3, 8, 3, "lines", 10, True), (32, 32, 3, 8, 3, "index", 400, True),
@@ -134,7 +135,10 @@ def test_spectral_init_small_shapes(cfg):
     s = np.linalg.svd(X0, compute_uv=False)
     Uref = AG.spectral_init(X0, r)
     gap = (s[r - 1] - s[r]) / s[0]
-    assert proj_dist(U0, Uref) < 1e-5 / gap
+    d = proj_dist(U0, Uref)
+    log(f"  projector distance {d:.2e}, relative gap {gap:.2e}, truncated {ctx.stats()['n_trunc']}")
+    assert d < 1e-6 / gap
+    assert ctx.stats()["n_trunc"] == AG.truncation_count(cs.op, cs.y, 36.0)
 
 
 def _end_to_end(cs, T, trunc_c=36.0, precision=0):
@@ -174,12 +178,13 @@ def test_end_to_end_small_ragged(kind):
     assert rel(Xg, ref.X) < 1e-3
 
 
-@pytest.mark.parametrize("r", [8, 12, 16])
+@pytest.mark.parametrize("r", [3, 5, 7, 8, 12, 16])
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "mixed"])
 def test_end_to_end_ranks_around_the_step_kernels(r, precision):
-    """Rank 8 runs the QR step fused with the update; ranks above 8 the
-    separate step (one-wave factor of 16 rows) and update, with the QR Gram
-    of three or four row tiles."""
+    """Ranks up to 8 run the QR step fused with the update (odd ranks take
+    the 8-byte path of the partial-sum kernel and the strided rows of the
+    update); ranks above 8 the separate step (one-wave factor of 16 rows) and
+    update, with the QR Gram of three or four row tiles."""
     log(f"end-to-end r={r} precision={precision}")
     p = datagen.make_small(32, 32, 3, 20, r, seed=30 + r, kind="lines", n_lines=12, lowrank=True,
                            snr_db=40.0, variable_m=True)
@@ -252,13 +257,14 @@ def test_exit_rule_matches_oracle(r):
     assert rel(Xg, ref.X) < 1e-3
 
 
-def test_step_commit_paths_agree():
+@pytest.mark.parametrize("r", [5, 8])
+def test_step_commit_paths_agree(r):
     """Rank <= 8 runs the QR step fused with the update.  With the exit rule
     off, workgroup 0 commits t and eta itself; with it on, a one-thread
     kernel commits them after the step.  A threshold that never fires must
     leave the whole trajectory bitwise unchanged."""
-    log("commit paths")
-    p = datagen.make_small(32, 32, 3, 20, 8, seed=44, kind="lines", n_lines=12, lowrank=True, snr_db=40.0,
+    log(f"commit paths r={r}")
+    p = datagen.make_small(32, 32, 3, 20, r, seed=44, kind="lines", n_lines=12, lowrank=True, snr_db=40.0,
                            variable_m=True)
     cs = Case(p)
     out = []
@@ -272,3 +278,79 @@ def test_step_commit_paths_agree():
     assert sa["exited"] == 0 and sb["exited"] == 0
     assert torch.equal(Ua, Ub) and torch.equal(Ba, Bb)
     assert ea == eb and sa["f"] == sb["f"] and sa["sd"] == sb["sd"]
+
+
+@pytest.mark.parametrize("bind", [True, False], ids=["cap_binds", "cap_loose"])
+def test_step_size_cap_matches_oracle(bind):
+    """The optional step-size cap eta <= c n / (mbar ||B_0||_2^2) (the
+    conservative rule of Sec. III-B): c is chosen from the oracle's own
+    uncapped eta so that the cap binds (half the rule's eta) or not (twice);
+    the GPU's eta and trajectory match the oracle's."""
+    p = datagen.make_small(32, 32, 3, 12, 3, seed=51, kind="lines", n_lines=10, lowrank=True, snr_db=40.0,
+                           variable_m=True)
+    cs = Case(p)
+    T = 6
+    free = AG.run(cs.op, cs.y, AG.Params(r=3), t_fixed=1, record=False)
+    B0 = AG.ls_step(cs.op, free.U0, cs.y)
+    cap1 = AG.step_size_cap(cs.op, B0, 1.0)
+    c = (0.5 if bind else 2.0) * free.eta / cap1
+    ref = AG.run(cs.op, cs.y, AG.Params(r=3, eta_cap_c=c), t_fixed=T, record=True)
+    assert ref.history["eta_capped"] is bind
+    ctx = cs.gpu_ctx(eta_cap_c=c)
+    U = ctx.init()
+    Uprev = torch.empty_like(U)
+    B, done = ctx.iterate(T, U, U_prev=Uprev, sync=True)
+    assert done == T
+    Xg = from_gpu_U(Uprev) @ from_gpu_B(B)
+    eta = ctx.get_eta()
+    log(f"  c {c:.4e}: eta gpu {eta:.6e} oracle {ref.eta:.6e} (uncapped {free.eta:.6e}); X rel {rel(Xg, ref.X):.2e}")
+    assert eta == pytest.approx(ref.eta, rel=1e-4)
+    assert abs(M.nmse(Xg, p.zstar) - M.nmse(ref.X, p.zstar)) <= 1e-4
+    assert rel(Xg, ref.X) < 1e-3
+
+
+def test_statistics_survive_a_later_cost_call():
+    """With the exit rule off the loop defers its statistics; a cost or
+    gradient call in between (which reruns the per-frame solve) must not
+    change what get_stats then reports for the last iteration."""
+    p = datagen.make_small(32, 32, 3, 12, 4, seed=52, kind="lines", n_lines=10, lowrank=True, snr_db=40.0)
+    cs = Case(p)
+    want = None
+    for eps in (1e-30, 0.0):  # commit kernel (statistics formed at once), then deferred
+        ctx = cs.gpu_ctx(eps_exit=eps)
+        U = ctx.init()
+        ctx.iterate(5, U)
+        other = to_gpu_U(np.linalg.qr(datagen.crandn(np.random.default_rng(3), p.n, p.r))[0])
+        ctx.cost(other)
+        ctx.gradient(other)
+        st = ctx.stats()
+        if want is None:
+            want = st
+    log(f"  f {st['f']:.9e} vs {want['f']:.9e}; sd {st['sd']:.6e} vs {want['sd']:.6e}")
+    assert st["t"] == want["t"] == 5
+    assert st["f"] == pytest.approx(want["f"], rel=1e-12)
+    assert st["sd"] == pytest.approx(want["sd"], rel=1e-9)
+    assert st["grad_norm"] == pytest.approx(want["grad_norm"], rel=1e-12)
+
+
+def test_iteration_count_on_a_non_default_stream():
+    """iterate(sync=True) reads the starting iteration count only after the
+    stream's earlier work (init and the previous iterate) has finished."""
+    p = datagen.make_small(64, 64, 4, 16, 4, seed=53, kind="lines", n_lines=16, lowrank=True, snr_db=40.0)
+    cs = Case(p)
+    s = torch.cuda.Stream()
+    import paper_2212_09664_amd as ag
+    ctx = ag.AltGDmin(p.nx, p.ny, p.nc, p.q, p.r, int(cs.y.shape[2]), 0, 0)
+    dev = torch.device("cuda:0")
+    with torch.cuda.stream(s):
+        ctx.set_problem(torch.from_numpy(cs.coils.astype(np.complex64)).to(dev),
+                        torch.from_numpy(cs.mask).to(dev), torch.from_numpy(cs.m_k).to(dev),
+                        torch.from_numpy(cs.y32).to(dev), stream=s)
+        U = ctx.init()
+        counts = []
+        for n in (7, 3, 5):
+            _, done = ctx.iterate(n, U, sync=True)
+            counts.append(done)
+    log(f"  iterations reported {counts}")
+    assert counts == [7, 3, 5]
+    assert ctx.stats()["t"] == 15

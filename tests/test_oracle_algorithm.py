@@ -182,6 +182,43 @@ def test_qr_closed_forms():
     assert M.subspace_distance(U, Uq) ** 2 == pytest.approx(sd2, rel=1e-10)
 
 
+def _cap_example():
+    """2x2 grid, one coil s = 1, two frames, rank 1, warm start
+    U_0 = [1, 1, 1, 1]/2, whose transform is 1 at DC and 0 elsewhere.
+    Frame 1 samples {DC, index 1} with y = [1, 1]; frame 2 samples
+    {DC, index 2} with y = [2, 1].  By hand: A_k U_0 = [1, 0], so b_1 = 1,
+    b_2 = 2, B_0 = [1, 2], ||B_0||_2 = sqrt(5); the residuals are [0, -1]
+    and grad = -(F^H e_1) 1 - (F^H e_2) 2 with F^H e_1 = [1,-1,1,-1]/2
+    (kx = 1) and F^H e_2 = [1,1,-1,-1]/2 (ky = 1): grad = -[3, 1, -1, -3]/2,
+    ||grad||_2 = sqrt(5).  n = 4, mbar = 2."""
+    op = O.Operator(2, 2, np.ones((1, 4)), [np.array([0, 1]), np.array([0, 2])], "dense")
+    Y = np.zeros((2, 1, 2), dtype=np.complex128)
+    Y[0, 0, :] = [1.0, 1.0]
+    Y[1, 0, :] = [2.0, 1.0]
+    return op, Y, np.full((4, 1), 0.5, dtype=np.complex128)
+
+
+@pytest.mark.parametrize("cap_c,eta_hand,capped", [
+    (0.0, 0.14 / math.sqrt(5.0), None),    # no cap: Algorithm 2's rule
+    (0.5, 0.14 / math.sqrt(5.0), False),   # cap c n/(mbar ||B_0||^2) = 0.5*4/(2*5) = 0.2 > 0.0626
+    (0.1, 0.04, True),                     # cap 0.1*4/(2*5) = 0.04 < 0.0626: binds
+])
+def test_step_size_cap_hand_example(cap_c, eta_hand, capped):
+    """The optional step-size cap (the conservative rule of Sec. III-B,
+    parameter setting) on the hand example above, through the whole run."""
+    op, Y, U0 = _cap_example()
+    B = AG.ls_step(op, U0, Y)
+    assert np.allclose(B, [[1.0, 2.0]], atol=1e-14)
+    G = AG.gradient(op, U0, B, Y)
+    assert np.allclose(G[:, 0], -np.array([3, 1, -1, -3]) / 2, atol=1e-14)
+    res = AG.run(op, Y, AG.Params(r=1, trunc_c=0.0, eta_cap_c=cap_c), U0=U0, t_fixed=1)
+    assert res.eta == pytest.approx(eta_hand, rel=1e-14)
+    assert res.history.get("eta_capped") is capped
+    # one step: U_1 = (U_0 - eta grad) / ||U_0 - eta grad||
+    uh = U0[:, 0] + eta_hand * np.array([3, 1, -1, -3]) / 2
+    assert abs(abs(np.vdot(res.U[:, 0], uh / np.linalg.norm(uh))) - 1) < 1e-14
+
+
 def test_subspace_distance_closed_forms():
     rng = np.random.default_rng(0)
     Q, _ = np.linalg.qr(datagen.crandn(rng, 10, 6))
