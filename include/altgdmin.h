@@ -90,7 +90,7 @@ enum { ALTGDMIN_FP32 = 0, ALTGDMIN_MIXED = 1 };
 /* Problem shape and Algorithm 2's constants.
  *  nx, ny      image size; each a power of two in [8, 512].
  *  nc          coils, 1..64.        q   frames, 1..128.
- *  r           rank, 1..16, r <= q.
+ *  r           rank, 1..16.
  *  m_max       padded samples per coil per frame (max_k m_k).
  *  mask_kind   ALTGDMIN_MASK_LINES or ALTGDMIN_MASK_INDEX.
  *  precision   ALTGDMIN_FP32 (every step in FP32) or ALTGDMIN_MIXED (the
@@ -104,11 +104,18 @@ enum { ALTGDMIN_FP32 = 0, ALTGDMIN_MIXED = 1 };
  *  eps_exit    > 0: stop when SD(U, U+)/sqrt(r) < eps_exit (paper: 0.01);
  *              <= 0: run the requested number of iterations.
  *  t_max       iteration cap used by altgdmin_iterate when n_iter <= 0.
+ *  exit_consec the exit rule fires after this many consecutive iterations
+ *              with SD(U, U+)/sqrt(r) < eps_exit (0 or 1: Algorithm 2's rule;
+ *              more: the more robust variant suggested in Sec. VI).
+ *  r may exceed q for a context used only for the LS step, the operators and
+ *  the steps around the loop (e.g. per-frame online tracking); the spectral
+ *  initialisation needs r <= q.
  */
 typedef struct {
   int32_t nx, ny, nc, q, r, m_max, mask_kind, precision;
   double trunc_c, eta_c, eta_cap_c, eps_exit;
   int32_t t_max;
+  int32_t exit_consec;
 } altgdmin_params;
 
 /* Per-iteration statistics of the last completed iteration. */
@@ -214,8 +221,8 @@ altgdmin_status altgdmin_cost(altgdmin_ctx* ctx, const void* d_U, double* d_f);
 /* The LS step and the gradient at a given n x r basis d_U (Algorithm 2):
  * d_B (r x q, may be NULL) receives b_k = (A_k U)^dagger y_k for every frame
  * and d_G (n x r, may be NULL) receives
- * grad = sum_k A_k^H (A_k U b_k - y_k) b_k^H.  Does not change the
- * iteration state (t, eta). */
+ * grad = sum_k A_k^H (A_k U b_k - y_k) b_k^H; with d_G NULL only the LS step
+ * runs.  Does not change the iteration state (t, eta). */
 altgdmin_status altgdmin_gradient(altgdmin_ctx* ctx, const void* d_U, void* d_B, void* d_G);
 
 /* Y = A(X) (eq. Ymat): d_X n x q in, d_Y [q][nc][m_max] out (padding
@@ -243,6 +250,77 @@ altgdmin_status altgdmin_last_error(altgdmin_ctx* ctx, int32_t* frame);
 altgdmin_status altgdmin_set_timing(altgdmin_ctx* ctx, int32_t which);
 altgdmin_status altgdmin_kernel_time(altgdmin_ctx* ctx, const char** name, int32_t* launches,
                                      double* total_ms);
+
+/* ---- the steps around the loop: altGDmin-MRI (Algorithms 1 and 3) -------
+ * These calls use the measurements bound by altgdmin_set_problem and an
+ * auxiliary device workspace d_aux (caller-owned, 256-byte aligned, at least
+ * altgdmin_aux_bytes; its contents need not survive between calls).  Image
+ * sequences are n x q column-major complex64 (X[k*n + p]); residual
+ * measurements use the padded layout of y.  They run on the context's stream
+ * and do not change the iteration state of the loop. */
+altgdmin_status altgdmin_aux_bytes(const altgdmin_ctx* ctx, size_t* bytes);
+
+/* The mean image (Algorithm 1, step 1): zbar = argmin_z sum_k ||y_k - A_k z||^2
+ * by conjugate gradients on the normal equations from z = 0 (the CGLS
+ * iterates; the normal operator sum_k A_k^H A_k is applied as
+ * sum_c conj(s_c) F^H (cnt o F(s_c z)), cnt the number of frames sampling each
+ * k-space location).  Stops after the iteration at which
+ * ||A^H(y - A z)|| <= tol ||A^H y||, or after maxit iterations (paper: 1e-3,
+ * 10).  d_zbar: n complex64 out.  h_iters (host, may be NULL) receives the
+ * iterations done; passing it synchronises.  EINVAL for maxit < 0 or
+ * tol < 0. */
+altgdmin_status altgdmin_mean(altgdmin_ctx* ctx, double tol, int32_t maxit, void* d_zbar, void* d_aux,
+                              int32_t* h_iters);
+
+/* Residual measurements (Algorithm 1, steps 2a and 3a):
+ * d_yres = y - A(zbar 1^T + X), frame by frame, in the padded layout (padding
+ * written as 0).  d_zbar (n) and d_X (n x q) may each be NULL (then taken as
+ * zero).  d_yres must not alias y. */
+altgdmin_status altgdmin_residual(altgdmin_ctx* ctx, const void* d_zbar, const void* d_X, void* d_yres,
+                                  void* d_aux);
+
+/* MEC model 1 (Algorithm 3, altGDmin-MRI1): for every frame, `iters` CGLS
+ * iterations from e = 0 on min_e ||yres_k - A_k e||^2, a frame stopping early
+ * once ||A_k^H(yres_k - A_k e)|| <= tol ||A_k^H yres_k|| (paper: 3
+ * iterations, tol 1e-36).  d_yres: padded residual measurements (padding
+ * ignored); d_E: n x q complex64 out. */
+altgdmin_status altgdmin_mec_cgls(altgdmin_ctx* ctx, const void* d_yres, int32_t iters, double tol, void* d_E,
+                                  void* d_aux);
+
+/* MEC model 2 (Algorithm 3, altGDmin-MRI2): ISTA on the temporal DFT of the
+ * error.  From E_0 = 0, for t = 0, 1, ...: M_t = F_t(E_t + A^H(yres - A(E_t)))
+ * with F_t the unitary DFT along the frames of every pixel;
+ * omega = omega_frac * max|M_0| (paper: 0.001); E_{t+1} =
+ * F_t^-1(SThr_omega(M_t)) with the complex soft threshold s/|s| (|s| - omega)
+ * (0 where |s| <= omega).  Ends after max_iter updates (paper: 10) or after
+ * the update that follows an M_t (t >= 1) with
+ * ||M_t - M_{t-1}||_F / ||M_{t-1}||_F < tol (paper: 0.0025).  d_E: n x q out.
+ * h_iters (may be NULL; synchronises) receives the updates done.  Needs
+ * q <= 128. */
+altgdmin_status altgdmin_mec_ista(altgdmin_ctx* ctx, const void* d_yres, int32_t max_iter, double omega_frac,
+                                  double tol, void* d_E, void* d_aux, int32_t* h_iters);
+
+/* The output of Algorithm 1: d_Z[:, k] = zbar + U b_k + e_k (n x q,
+ * complex64), each term optional: d_U (n x r) and d_B (r x q) together or
+ * neither, d_zbar (n), d_E (n x q).  d_Z may alias d_E. */
+altgdmin_status altgdmin_expand(altgdmin_ctx* ctx, const void* d_U, const void* d_B, const void* d_zbar,
+                                const void* d_E, void* d_Z);
+
+/* The spectrum behind the automatic rank (Algorithm 2, parameter setting):
+ * the r_cap largest eigenvalues of X_0^H X_0 (the squared singular values of
+ * the truncated, scaled back-projection X_0 of the initialisation),
+ * descending, into h_sigma2 (host, r_cap doubles; 1 <= r_cap <= min(16, q)).
+ * Synchronises. */
+altgdmin_status altgdmin_rank_energy(altgdmin_ctx* ctx, int32_t r_cap, double* h_sigma2, void* d_aux);
+
+/* The automatic rank: r_cap = floor(min(n, q, nc min_k m_k) / 10) (at least
+ * 1, at most 16), then the smallest r with
+ * sum_{j<=r} sigma_j^2 >= (b_percent/100) sum_{j<=r_cap} sigma_j^2 (paper:
+ * b = 85).  h_rank (host) receives r, h_rcap (may be NULL) r_cap.
+ * Synchronises.  The result is the rank to create the reconstruction's
+ * context with. */
+altgdmin_status altgdmin_auto_rank(altgdmin_ctx* ctx, double b_percent, int32_t* h_rank, int32_t* h_rcap,
+                                   void* d_aux);
 
 const char* altgdmin_status_string(altgdmin_status s);
 

@@ -36,6 +36,7 @@ class Params:
     eta_c: float = 0.14        # eta = eta_c / ||grad_0||
     eta_cap_c: float = 0.0     # > 0: cap eta by eta_cap_c * n / (mbar ||B_0||^2)
     eps_exit: float = 0.0      # > 0: exit when SD(U, U+)/sqrt(r) < eps_exit (paper: 0.01)
+    exit_consec: int = 1       # exit after this many consecutive small steps (Sec. VI variant: > 1)
 
 
 @dataclass
@@ -206,6 +207,7 @@ def run(op: Operator, Y: np.ndarray, params: Params, U0: Optional[np.ndarray] = 
     T = params.t_max if t_fixed is None else t_fixed
     ysq = float(np.sum(np.abs(Y) ** 2))
     iters = 0
+    run_small = 0
     hist["exit_at"] = None
     for t in range(1, T + 1):
         FU = op.transform_basis(U)
@@ -237,7 +239,10 @@ def run(op: Operator, Y: np.ndarray, params: Params, U0: Optional[np.ndarray] = 
                 hist["sd_star"].append(metrics.subspace_distance(Ustar, Uplus))
         iters = t
         U = Uplus
-        if params.eps_exit > 0 and sd / np.sqrt(r) < params.eps_exit:
+        # exit rule (Algorithm 2); with exit_consec > 1 the variant of Sec. VI
+        # that asks for several consecutive small steps
+        run_small = run_small + 1 if (params.eps_exit > 0 and sd / np.sqrt(r) < params.eps_exit) else 0
+        if params.eps_exit > 0 and run_small >= max(1, params.exit_consec):
             if hist["exit_at"] is None:
                 hist["exit_at"] = t
             if t_fixed is None:

@@ -22,7 +22,7 @@ class Params(ctypes.Structure):
                 ("mask_kind", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("trunc_c", ctypes.c_double), ("eta_c", ctypes.c_double),
                 ("eta_cap_c", ctypes.c_double), ("eps_exit", ctypes.c_double),
-                ("t_max", ctypes.c_int32)]
+                ("t_max", ctypes.c_int32), ("exit_consec", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -78,6 +78,14 @@ def load_library():
         "altgdmin_status_string": ([i32], ctypes.c_char_p),
         "altgdmin_destroy": ([vp], None),
         "altgdmin_cnn_input": ([vp, vp], i32),
+        "altgdmin_aux_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "altgdmin_mean": ([vp, dbl, i32, vp, vp, pi32], i32),
+        "altgdmin_residual": ([vp, vp, vp, vp, vp], i32),
+        "altgdmin_mec_cgls": ([vp, vp, i32, dbl, vp, vp], i32),
+        "altgdmin_mec_ista": ([vp, vp, i32, dbl, dbl, vp, vp, pi32], i32),
+        "altgdmin_rank_energy": ([vp, i32, ctypes.POINTER(dbl), vp], i32),
+        "altgdmin_expand": ([vp, vp, vp, vp, vp, vp], i32),
+        "altgdmin_auto_rank": ([vp, dbl, pi32, pi32, vp], i32),
         "altgdmin_init_warm": ([vp, vp, vp, vp], i32),
         "altgdmin_init_warm_from": ([vp, vp, vp, vp, vp], i32),
         "wsinit_create": ([i32, i32, i32, i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
@@ -110,10 +118,10 @@ class AltGDmin:
     """One reconstruction context (one problem shape, one bound problem)."""
 
     def __init__(self, nx, ny, nc, q, r, m_max, mask_kind=MASK_LINES, precision=FP32, trunc_c=36.0,
-                 eta_c=0.14, eta_cap_c=0.0, eps_exit=0.0, t_max=70):
+                 eta_c=0.14, eta_cap_c=0.0, eps_exit=0.0, t_max=70, exit_consec=1):
         self._L = load_library()
         self.p = Params(nx, ny, nc, q, r, m_max, mask_kind, precision, trunc_c, eta_c, eta_cap_c,
-                        eps_exit, t_max)
+                        eps_exit, t_max, exit_consec)
         self.n = nx * ny
         h = ctypes.c_void_p()
         self._check(self._L.altgdmin_create(ctypes.byref(self.p), ctypes.byref(h)), "create")
@@ -225,6 +233,73 @@ class AltGDmin:
         G = self._new(self.p.r, self.n)
         self._check(self._L.altgdmin_gradient(self._h, _ptr(U), _ptr(B), _ptr(G)), "gradient")
         return B, G
+
+    def ls(self, U, B=None):
+        """B (q, r): the LS coefficients b_k = (A_k U)^dagger y_k at U."""
+        B = self._new(self.p.q, self.p.r) if B is None else B
+        self._check(self._L.altgdmin_gradient(self._h, _ptr(U), _ptr(B), None), "ls")
+        return B
+
+    # --- the steps around the loop (altGDmin-MRI) ----------------------------
+    def aux(self):
+        """The auxiliary workspace of the steps around the loop (allocated
+        once per context, 256-byte aligned)."""
+        if getattr(self, "_aux", None) is None:
+            nb = ctypes.c_size_t()
+            self._check(self._L.altgdmin_aux_bytes(self._h, ctypes.byref(nb)), "aux_bytes")
+            buf = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+            off = (-buf.data_ptr()) % 256
+            self._aux = (buf, buf[off: off + nb.value])
+        return self._aux[1]
+
+    def mean(self, tol=1e-3, maxit=10, zbar=None, sync=False):
+        """The mean image zbar (n,) by CG on the normal equations."""
+        zbar = self._new(self.n) if zbar is None else zbar
+        it = ctypes.c_int32(-1)
+        self._check(self._L.altgdmin_mean(self._h, float(tol), int(maxit), _ptr(zbar), _ptr(self.aux()),
+                                          ctypes.byref(it) if sync else None), "mean")
+        return (zbar, it.value) if sync else zbar
+
+    def residual(self, zbar=None, X=None, out=None):
+        """y - A(zbar 1^T + X) in the padded layout (q, nc, m_max); X is (q, n)."""
+        out = self._new(self.p.q, self.p.nc, self.p.m_max) if out is None else out
+        self._check(self._L.altgdmin_residual(self._h, _ptr(zbar), _ptr(X), _ptr(out), _ptr(self.aux())),
+                    "residual")
+        return out
+
+    def mec_cgls(self, yres, iters=3, tol=1e-36, E=None):
+        """MEC model 1: E (q, n), per-frame CGLS from zero."""
+        E = self._new(self.p.q, self.n) if E is None else E
+        self._check(self._L.altgdmin_mec_cgls(self._h, _ptr(yres), int(iters), float(tol), _ptr(E),
+                                              _ptr(self.aux())), "mec_cgls")
+        return E
+
+    def mec_ista(self, yres, max_iter=10, omega_frac=1e-3, tol=0.0025, E=None, sync=False):
+        """MEC model 2: E (q, n) by ISTA on the temporal DFT."""
+        E = self._new(self.p.q, self.n) if E is None else E
+        it = ctypes.c_int32(-1)
+        self._check(self._L.altgdmin_mec_ista(self._h, _ptr(yres), int(max_iter), float(omega_frac), float(tol),
+                                              _ptr(E), _ptr(self.aux()), ctypes.byref(it) if sync else None),
+                    "mec_ista")
+        return (E, it.value) if sync else E
+
+    def expand(self, U=None, B=None, zbar=None, E=None, Z=None):
+        """Z (q, n): zbar + U b_k + e_k per frame (U (r, n), B (q, r), E (q, n))."""
+        Z = self._new(self.p.q, self.n) if Z is None else Z
+        self._check(self._L.altgdmin_expand(self._h, _ptr(U), _ptr(B), _ptr(zbar), _ptr(E), _ptr(Z)), "expand")
+        return Z
+
+    def rank_energy(self, r_cap):
+        out = (ctypes.c_double * int(r_cap))()
+        self._check(self._L.altgdmin_rank_energy(self._h, int(r_cap), out, _ptr(self.aux())), "rank_energy")
+        return list(out)
+
+    def auto_rank(self, b_percent=85.0):
+        """(r_hat, r_cap) by Algorithm 2's energy rule."""
+        r, cap = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._L.altgdmin_auto_rank(self._h, float(b_percent), ctypes.byref(r), ctypes.byref(cap),
+                                               _ptr(self.aux())), "auto_rank")
+        return r.value, cap.value
 
     def apply_A(self, X, Y=None):
         Y = self._new(self.p.q, self.p.nc, self.p.m_max) if Y is None else Y

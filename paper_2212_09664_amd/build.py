@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaltgdmin.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["kernels_fft.hip", "kernels_core.hip", "kernels_gram.hip", "kernels_basis.hip", "kernels_pdft.hip",
-           "kernels_cnn.hip", "altgdmin.hip", "wsinit.hip"]
+           "kernels_cnn.hip", "kernels_mri.hip", "altgdmin.hip", "mri.hip", "wsinit.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

@@ -7,25 +7,12 @@
 #include <new>
 #include <vector>
 
-#include "../../include/altgdmin.h"
-#include "kernels_core.hpp"
+#include "ctx.hpp"
 
-using namespace ag;
+using ag_host::map_hip;
 
 namespace {
 
-enum TimedKernel {
-  TK_NONE = 0,
-  TK_FWD = 1,
-  TK_GRAM = 2,
-  TK_SOLVE = 3,
-  TK_FOLD = 4,
-  TK_ADJ = 5,
-  TK_QRGRAM = 6,
-  TK_QRSMALL = 7,
-  TK_APPLY = 8,
-  TK_COUNT = 9
-};
 const char* kTimedNames[TK_COUNT] = {"none",  "fwd_transform", "gram_rhs", "solve",     "fold",
                                      "adj_transform", "qr_gram", "qr_small", "apply_qr"};
 
@@ -34,53 +21,9 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 }  // namespace
 
-struct altgdmin_ctx {
-  altgdmin_params p;
-  int n, lines, fp64;
-  int pdft;       // ky transforms as FP16 hi+lo MFMA partial DFTs (mixed form, 1D Cartesian)
-  int width;     // mask row width: lines per frame (LINES) or m_max (INDEX)
-  int lmax;      // LINES: m_max / nx
-  int per;       // samples per mask entry (nx for LINES, 1 for INDEX)
-  int n_loc, nw;
-  int ua;        // rows per (c, j) plane of W / K
-  int nchunks;   // INDEX gram chunks per frame
-  int qr_nblk;
-  long qr_rows;
-  int kc;        // INDEX: frames per chunk of the operator passes
-  int gram_cg, gram_ngroups, gram_chunk;
-  int adj_parts, adj_cgs;  // coil groups of the adjoint transform (partial gradients)
-  int txx;                 // image columns per workgroup in the basis transforms
-  size_t bytes;
-  // bound problem
-  const float2* coils = nullptr;
-  const int32_t* mask = nullptr;
-  const int32_t* m_k = nullptr;
-  const float2* y = nullptr;
-  char* ws = nullptr;
-  hipStream_t stream = nullptr;
-  int bound = 0, initialized = 0;
-  // workspace carve
-  size_t o_st, o_twx, o_twy, o_bitmap, o_locptr, o_loc2unit, o_unitloc, o_pairs, o_pairof, o_yh, o_ysq,
-      o_cost, o_W, o_K, o_P, o_hp, o_B, o_G, o_qpart, o_qtot, o_rfac, o_Vs, o_V, o_T, o_Ui, o_unitof, o_unitspan, o_bcp, o_Uc,
-      o_fcmp, o_planes, o_gwork, o_lineord, o_coilb, o_yg, o_ysqp, o_stsrc, o_end;
-  size_t T_bytes;
-  // timing
-  int timed = TK_NONE;
-  std::vector<hipEvent_t> ev;
-  size_t ev_used = 0;
-
-  template <typename T>
-  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-  DevState* st() const { return at<DevState>(o_st); }
-};
 
 namespace {
 
-#define HIPCHK(x)                            \
-  do {                                       \
-    hipError_t _e = (x);                     \
-    if (_e != hipSuccess) return ALTGDMIN_EHIP; \
-  } while (0)
 
 // sum over lines of ceil(pairs / 8) <= (pairs + 7 lines) / 8, pairs <= q * width
 // workgroups of the spectral init's X0^H X0 on the matrix cores: 128 rows each, at most 512
@@ -166,14 +109,14 @@ altgdmin_status check_params(const altgdmin_params* p) {
   if (!p) return ALTGDMIN_EINVAL;
   if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < 8 || p->ny < 8 || p->nx > 512 || p->ny > 512)
     return ALTGDMIN_EINVAL;
-  if (p->nc < 1 || p->nc > 64 || p->q < 1 || p->q > 128 || p->r < 1 || p->r > 16 || p->r > p->q)
+  if (p->nc < 1 || p->nc > 64 || p->q < 1 || p->q > 128 || p->r < 1 || p->r > 16)
     return ALTGDMIN_EINVAL;
   if (p->mask_kind != ALTGDMIN_MASK_LINES && p->mask_kind != ALTGDMIN_MASK_INDEX) return ALTGDMIN_EINVAL;
   if (p->precision != ALTGDMIN_FP32 && p->precision != ALTGDMIN_MIXED) return ALTGDMIN_EINVAL;
   if (p->m_max < 1 || p->m_max > p->nx * p->ny) return ALTGDMIN_EINVAL;
   if (p->mask_kind == ALTGDMIN_MASK_LINES && (p->m_max % p->nx) != 0) return ALTGDMIN_EINVAL;
   if (!(p->eta_c > 0) || !isfinite(p->eta_c) || !isfinite(p->trunc_c) || !(p->eta_cap_c >= 0) ||
-      !isfinite(p->eps_exit))
+      !isfinite(p->eps_exit) || p->exit_consec < 0)
     return ALTGDMIN_EINVAL;
   if (p->t_max < 1) return ALTGDMIN_EINVAL;
   return ALTGDMIN_OK;
@@ -464,6 +407,7 @@ QrSmallArgs qr_small_args(altgdmin_ctx* c, int mode, int check_halt) {
   qa.eta_c = p.eta_c;
   qa.eta_cap_c = p.eta_cap_c;
   qa.eps_exit = p.eps_exit;
+  qa.exit_consec = p.exit_consec > 1 ? p.exit_consec : 1;
   qa.guard = 1e-6;  // FP32 gradient: below this it is rounding noise
   qa.B = c->at<float2>(c->o_B);
   qa.cost_k = c->at<double>(c->o_cost);
@@ -536,6 +480,16 @@ hipError_t one_iteration(altgdmin_ctx* c, float2* U, float2* U_prev) {
   tmark(c, TK_APPLY);
   return e;
 }
+
+}  // namespace
+
+#define AGCHK(x)                           \
+  do {                                     \
+    hipError_t _e = (x);                   \
+    if (_e != hipSuccess) return _e;       \
+  } while (0)
+
+namespace ag_host {
 
 // X = A^H(Y) scaled per column (back-projection when trunc/scale are set)
 hipError_t adjoint_op(altgdmin_ctx* c, const float2* Y, float2* X, int trunc, int scale_mk) {
@@ -613,9 +567,117 @@ hipError_t adjoint_op(altgdmin_ctx* c, const float2* Y, float2* X, int trunc, in
   return hipSuccess;
 }
 
-altgdmin_status map_hip(hipError_t e) { return e == hipSuccess ? ALTGDMIN_OK : ALTGDMIN_EHIP; }
 
-}  // namespace
+
+hipError_t forward_op(altgdmin_ctx* c, const float2* X, float2* Y) {
+  const altgdmin_params& p = c->p;
+  hipStream_t s = c->stream;
+  if (c->lines) {
+    ColFwdArgs f{};
+    f.src = X;
+    f.src_img_stride = c->n;
+    f.coils = c->coils;
+    f.n = c->n;
+    f.nx = p.nx;
+    f.tw = c->at<float2>(c->o_twy);
+    f.dst = Y;
+    f.dst_c_stride = p.m_max;
+    f.dst_img_stride = (long)p.nc * p.m_max;
+    f.rows = c->mask;
+    f.rows_img_stride = c->width;
+    f.m_k = c->m_k;
+    f.zero_pad_rows = c->lmax;
+    f.scale = (float)(1.0 / sqrt((double)p.ny));
+    f.st = c->st();
+    AGCHK(launch_cols(p.ny, &f, nullptr, p.nx, p.q, p.nc, s));
+    RowArgs ra{};
+    ra.src = ra.dst = Y;
+    ra.tw = c->at<float2>(c->o_twx);
+    ra.nrows = (long)p.q * p.nc * c->lmax;
+    ra.m_k = c->m_k;
+    ra.nc = p.nc;
+    ra.lmax = c->lmax;
+    ra.scale = (float)(1.0 / sqrt((double)p.nx));
+    ra.st = c->st();
+    AGCHK(launch_rows(p.nx, ra, false, s));
+    return hipSuccess;
+  }
+  float2* T = c->at<float2>(c->o_T) + (size_t)c->n * p.q;
+  for (int k0 = 0; k0 < p.q; k0 += c->kc) {
+    const int kc = std::min(c->kc, p.q - k0);
+    ColFwdArgs f{};
+    f.src = X + (size_t)k0 * c->n;
+    f.src_img_stride = c->n;
+    f.coils = c->coils;
+    f.n = c->n;
+    f.nx = p.nx;
+    f.tw = c->at<float2>(c->o_twy);
+    f.dst = T;
+    f.dst_c_stride = c->n;
+    f.dst_img_stride = (long)p.nc * c->n;
+    f.scale = (float)(1.0 / sqrt((double)p.ny));
+    f.st = c->st();
+    AGCHK(launch_cols(p.ny, &f, nullptr, p.nx, kc, p.nc, s));
+    RowArgs ra{};
+    ra.src = ra.dst = T;
+    ra.tw = c->at<float2>(c->o_twx);
+    ra.nrows = (long)kc * p.nc * p.ny;
+    ra.scale = (float)(1.0 / sqrt((double)p.nx));
+    ra.st = c->st();
+    AGCHK(launch_rows(p.nx, ra, false, s));
+    hipLaunchKernelGGL(k_gather, dim3((p.m_max + 255) / 256, kc, p.nc), dim3(256), 0, s, T, (long)c->n,
+                       (long)p.nc * c->n, c->mask, c->m_k, p.m_max, p.nc, k0, Y, c->st());
+    AGCHK(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+
+hipError_t spectral_eig(altgdmin_ctx* c, int r_eig, double* lam_out) {
+  const altgdmin_params& p = c->p;
+  hipStream_t s = c->stream;
+  float2* X0 = c->at<float2>(c->o_T);
+  AGCHK(adjoint_op(c, c->y, X0, p.trunc_c > 0 ? 1 : 0, 1));
+  GramColsArgs g{};
+  g.A = X0;
+  g.m1 = p.q;
+  g.m2 = 0;
+  g.n = c->n;
+  g.rows_per_block = c->qr_rows;
+  g.part = c->at<double2>(c->o_qpart);
+  g.st = c->st();
+  g.nparts = 1;
+  g.a_colmajor = 1;
+  // X0^H X0 in FP64: up to 48 frames on the matrix cores (f64 16x16x4) over
+  // many short workgroups, whose partials a second kernel sums
+  InitEigArgs ie{};
+  if (p.q <= 48) {
+    const int nb = init_nblk(c);
+    g.rows_per_block = ((c->n + nb - 1) / nb + 31) / 32 * 32;
+    const int nbu = (int)((c->n + g.rows_per_block - 1) / g.rows_per_block);
+    AGCHK(launch_qr_gram(g, nbu, true, s));
+    const int nout = p.q * (p.q + 1) / 2;
+    double2* sum = c->at<double2>(c->o_qpart) + (size_t)nbu * nout;
+    AGCHK(launch_sum_partials(c->at<double2>(c->o_qpart), nbu, nout, sum, s));
+    ie.part = sum;
+    ie.nblk = 1;
+  } else {
+    AGCHK(launch_gram_cols(g, c->qr_nblk, true, s));
+    ie.part = c->at<double2>(c->o_qpart);
+    ie.nblk = c->qr_nblk;
+  }
+  ie.q = p.q;
+  ie.r = r_eig;
+  ie.lam_out = lam_out;
+  ie.V = c->at<double2>(c->o_V);
+  ie.in_lds = p.q <= 64;
+  ie.Vs = c->at<float2>(c->o_Vs);
+  ie.st = c->st();
+  AGCHK(launch_init_eig(ie, s));
+  return hipSuccess;
+}
+
+}  // namespace ag_host
 
 extern "C" {
 
@@ -748,49 +810,14 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
 }
 
 altgdmin_status altgdmin_init(altgdmin_ctx* c, void* d_U) {
-  if (!c || !d_U) return ALTGDMIN_EINVAL;
+  if (!c || !d_U || c->p.r > c->p.q) return ALTGDMIN_EINVAL;  // top r of q singular vectors
   if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
   const altgdmin_params& p = c->p;
   hipStream_t s = c->stream;
   float2* U = static_cast<float2*>(d_U);
   hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, c->st(), 0);
+  HIPCHK(ag_host::spectral_eig(c, p.r, nullptr));
   float2* X0 = c->at<float2>(c->o_T);
-  HIPCHK(adjoint_op(c, c->y, X0, p.trunc_c > 0 ? 1 : 0, 1));
-  GramColsArgs g{};
-  g.A = X0;
-  g.m1 = p.q;
-  g.m2 = 0;
-  g.n = c->n;
-  g.rows_per_block = c->qr_rows;
-  g.part = c->at<double2>(c->o_qpart);
-  g.st = c->st();
-  g.nparts = 1;
-  g.a_colmajor = 1;
-  // X0^H X0 in FP64: up to 48 frames on the matrix cores (f64 16x16x4) over
-  // many short workgroups, whose partials a second kernel sums
-  InitEigArgs ie{};
-  if (p.q <= 48) {
-    const int nb = init_nblk(c);
-    g.rows_per_block = ((c->n + nb - 1) / nb + 31) / 32 * 32;
-    const int nbu = (int)((c->n + g.rows_per_block - 1) / g.rows_per_block);
-    HIPCHK(launch_qr_gram(g, nbu, true, s));
-    const int nout = p.q * (p.q + 1) / 2;
-    double2* sum = c->at<double2>(c->o_qpart) + (size_t)nbu * nout;
-    HIPCHK(launch_sum_partials(c->at<double2>(c->o_qpart), nbu, nout, sum, s));
-    ie.part = sum;
-    ie.nblk = 1;
-  } else {
-    HIPCHK(launch_gram_cols(g, c->qr_nblk, true, s));
-    ie.part = c->at<double2>(c->o_qpart);
-    ie.nblk = c->qr_nblk;
-  }
-  ie.q = p.q;
-  ie.r = p.r;
-  ie.V = c->at<double2>(c->o_V);
-  ie.in_lds = p.q <= 64;
-  ie.Vs = c->at<float2>(c->o_Vs);
-  ie.st = c->st();
-  HIPCHK(launch_init_eig(ie, s));
   hipLaunchKernelGGL(k_x_times_v, dim3((c->n + AG_NT - 1) / AG_NT), dim3(AG_NT), 0, s, X0,
                      c->at<float2>(c->o_Vs), c->n, p.q, p.r, U, c->st());
   HIPCHK(hipGetLastError());
@@ -821,7 +848,7 @@ altgdmin_status altgdmin_cnn_input(altgdmin_ctx* c, float* d_in) {
   if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
   const altgdmin_params& p = c->p;
   float2* X = c->at<float2>(c->o_T);
-  HIPCHK(adjoint_op(c, c->y, X, 0, 0));
+  HIPCHK(ag_host::adjoint_op(c, c->y, X, 0, 0));
   HIPCHK(launch_cnn_planes(X, c->n, p.q, c->at<double>(c->o_planes), d_in, c->stream));
   return ALTGDMIN_OK;
 }
@@ -948,6 +975,14 @@ altgdmin_status altgdmin_gradient(altgdmin_ctx* c, const void* d_U, void* d_B, v
   const altgdmin_params& p = c->p;
   HIPCHK(launch_stats_finish(c->st(), c->at<double2>(c->o_stsrc), c->at<double>(c->o_cost), p.q, p.r, c->stream));
   HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
+  if (!d_G) {  // the LS step alone
+    HIPCHK(fwd_transform(c, 0));
+    HIPCHK(gram_solve(c, 0));
+    if (d_B)
+      hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, c->stream, c->at<float2>(c->o_B), static_cast<float2*>(d_B),
+                         (long)p.q * p.r);
+    return map_hip(hipGetLastError());
+  }
   HIPCHK(gradient_pieces(c, 0));
   if (c->adj_parts > 1)
     hipLaunchKernelGGL(k_sum_parts, dim3(1024), dim3(256), 0, c->stream, c->at<float2>(c->o_G),
@@ -964,74 +999,13 @@ altgdmin_status altgdmin_gradient(altgdmin_ctx* c, const void* d_U, void* d_B, v
 altgdmin_status altgdmin_apply_A(altgdmin_ctx* c, const void* d_X, void* d_Y) {
   if (!c || !d_X || !d_Y) return ALTGDMIN_EINVAL;
   if (!c->bound) return ALTGDMIN_ESTATE;
-  const altgdmin_params& p = c->p;
-  const float2* X = static_cast<const float2*>(d_X);
-  float2* Y = static_cast<float2*>(d_Y);
-  hipStream_t s = c->stream;
-  if (c->lines) {
-    ColFwdArgs f{};
-    f.src = X;
-    f.src_img_stride = c->n;
-    f.coils = c->coils;
-    f.n = c->n;
-    f.nx = p.nx;
-    f.tw = c->at<float2>(c->o_twy);
-    f.dst = Y;
-    f.dst_c_stride = p.m_max;
-    f.dst_img_stride = (long)p.nc * p.m_max;
-    f.rows = c->mask;
-    f.rows_img_stride = c->width;
-    f.m_k = c->m_k;
-    f.zero_pad_rows = c->lmax;
-    f.scale = (float)(1.0 / sqrt((double)p.ny));
-    f.st = c->st();
-    HIPCHK(launch_cols(p.ny, &f, nullptr, p.nx, p.q, p.nc, s));
-    RowArgs ra{};
-    ra.src = ra.dst = Y;
-    ra.tw = c->at<float2>(c->o_twx);
-    ra.nrows = (long)p.q * p.nc * c->lmax;
-    ra.m_k = c->m_k;
-    ra.nc = p.nc;
-    ra.lmax = c->lmax;
-    ra.scale = (float)(1.0 / sqrt((double)p.nx));
-    ra.st = c->st();
-    HIPCHK(launch_rows(p.nx, ra, false, s));
-    return ALTGDMIN_OK;
-  }
-  float2* T = c->at<float2>(c->o_T) + (size_t)c->n * p.q;
-  for (int k0 = 0; k0 < p.q; k0 += c->kc) {
-    const int kc = std::min(c->kc, p.q - k0);
-    ColFwdArgs f{};
-    f.src = X + (size_t)k0 * c->n;
-    f.src_img_stride = c->n;
-    f.coils = c->coils;
-    f.n = c->n;
-    f.nx = p.nx;
-    f.tw = c->at<float2>(c->o_twy);
-    f.dst = T;
-    f.dst_c_stride = c->n;
-    f.dst_img_stride = (long)p.nc * c->n;
-    f.scale = (float)(1.0 / sqrt((double)p.ny));
-    f.st = c->st();
-    HIPCHK(launch_cols(p.ny, &f, nullptr, p.nx, kc, p.nc, s));
-    RowArgs ra{};
-    ra.src = ra.dst = T;
-    ra.tw = c->at<float2>(c->o_twx);
-    ra.nrows = (long)kc * p.nc * p.ny;
-    ra.scale = (float)(1.0 / sqrt((double)p.nx));
-    ra.st = c->st();
-    HIPCHK(launch_rows(p.nx, ra, false, s));
-    hipLaunchKernelGGL(k_gather, dim3((p.m_max + 255) / 256, kc, p.nc), dim3(256), 0, s, T, (long)c->n,
-                       (long)p.nc * c->n, c->mask, c->m_k, p.m_max, p.nc, k0, Y, c->st());
-    HIPCHK(hipGetLastError());
-  }
-  return ALTGDMIN_OK;
+  return map_hip(ag_host::forward_op(c, static_cast<const float2*>(d_X), static_cast<float2*>(d_Y)));
 }
 
 altgdmin_status altgdmin_apply_AH(altgdmin_ctx* c, const void* d_Y, void* d_X) {
   if (!c || !d_X || !d_Y) return ALTGDMIN_EINVAL;
   if (!c->bound) return ALTGDMIN_ESTATE;
-  return map_hip(adjoint_op(c, static_cast<const float2*>(d_Y), static_cast<float2*>(d_X), 0, 0));
+  return map_hip(ag_host::adjoint_op(c, static_cast<const float2*>(d_Y), static_cast<float2*>(d_X), 0, 0));
 }
 
 altgdmin_status altgdmin_get_stats(altgdmin_ctx* c, altgdmin_stats* out) {

@@ -75,7 +75,9 @@ struct DevState {
   double eta_next;    // the step size it used (committed after it)
   int32_t stats_pending;  // 1: f, sd and grad_norm of the last step wait in the statistics inputs
   int32_t n_trunc;    // samples zeroed by the truncation of the last initialisation
-  double pad[3];
+  int32_t exit_run;   // consecutive iterations that met the exit test
+  int32_t pad_e;
+  double pad[2];
 };
 // the loop's stop test: err and halt both requested before either is tested
 // (a short-circuit test waits for one load before issuing the other)

@@ -163,6 +163,7 @@ __global__ void k_state_reset(DevState* st, int full) {
   st->grad_norm = 0.0;
   st->stats_pending = 0;
   st->n_trunc = 0;
+  st->exit_run = 0;
 }
 
 __global__ void k_state_set_eta(DevState* st, double eta) {
@@ -687,8 +688,13 @@ __global__ __launch_bounds__(RT <= 8 ? 1024 : 256) void k_qr_small(QrSmallArgs a
     st->t += 1;
     st->step_ok = 1;
     if (a.eps_exit > 0.0 && sqrt(sd2 / r) < a.eps_exit) {
-      st->exited = 1;
-      st->halt = 1;
+      st->exit_run += 1;
+      if (st->exit_run >= a.exit_consec) {
+        st->exited = 1;
+        st->halt = 1;
+      }
+    } else {
+      st->exit_run = 0;
     }
   }
 }
@@ -1045,7 +1051,7 @@ __global__ __launch_bounds__(NT) void k_step_apply(QrSmallArgs a, ApplyArgs ap) 
 }
 
 // the fused step's outcome into the state (one thread, after it)
-__global__ void k_step_commit(DevState* st) {
+__global__ void k_step_commit(DevState* st, int exit_consec) {
   if (threadIdx.x != 0) return;
   const int f = st->step_flags;
   st->step_flags = 0;
@@ -1059,8 +1065,13 @@ __global__ void k_step_commit(DevState* st) {
     st->t += 1;
     st->step_ok = 1;
     if (f & STEP_EXIT) {
-      st->exited = 1;
-      st->halt = 1;
+      st->exit_run += 1;
+      if (st->exit_run >= exit_consec) {
+        st->exited = 1;
+        st->halt = 1;
+      }
+    } else {
+      st->exit_run = 0;
     }
   }
 }
@@ -1118,7 +1129,7 @@ hipError_t launch_step_apply(const QrSmallArgs& a, const ApplyArgs& ap, hipStrea
   if (a.r > 8) return hipErrorInvalidValue;
   // 256 pixels per workgroup: the update's stores spread over every compute unit
   hipLaunchKernelGGL((k_step_apply<8, 256>), dim3((unsigned)((ap.n + 255) / 256)), dim3(256), 0, s, a, ap);
-  if (!a.commit_direct) hipLaunchKernelGGL(k_step_commit, dim3(1), dim3(64), 0, s, a.st);
+  if (!a.commit_direct) hipLaunchKernelGGL(k_step_commit, dim3(1), dim3(64), 0, s, a.st, a.exit_consec);
   return hipGetLastError();
 }
 
@@ -1448,6 +1459,10 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     }
     __syncthreads();
   }
+  if (a.lam_out) {  // only the spectrum was asked for
+    if (tid < r) a.lam_out[tid] = s_lam[tid];
+    return;
+  }
   const double lam0 = s_lam[0], lamr = s_lam[r - 1];
   if (!(lamr > 1e-14 * lam0) || !(lam0 > 0.0)) {
     if (tid == 0) set_error(a.st, 4, -1);
@@ -1487,9 +1502,13 @@ __global__ __launch_bounds__(AG_NT) void k_x_times_v(const float2* X, const floa
 
 // keep the learned U (src) only if its cost f[1] is strictly below the
 // spectral one f[0]; a non-finite learned cost keeps the spectral U
-// The error flag as it stood before the learned guess was scored.
+// The error and halt flags as they stood before the learned guess was scored
+// (raising an error also halts the loop).
 __global__ void k_err_snapshot(const DevState* st, int32_t* snap) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *snap = st->err;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    snap[0] = st->err;
+    snap[1] = st->halt;
+  }
 }
 
 // Keep the learned basis (src) only if its cost f[1] is strictly below the
@@ -1506,12 +1525,14 @@ __global__ void k_pick_init(const double* f, const int32_t* snap, const float2* 
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) dst[i] = src[i];
 }
 
-// After k_pick_init: an error raised only by the rejected guess is cleared.
+// After k_pick_init: an error raised only by the rejected guess is cleared,
+// with the halt it raised.
 __global__ void k_err_restore(const int32_t* snap, DevState* st) {
-  if (threadIdx.x != 0 || *snap) return;
+  if (threadIdx.x != 0 || snap[0]) return;
   if (st->err) {
     st->err = 0;
     st->err_frame = -1;
+    st->halt = snap[1];
   }
 }
 

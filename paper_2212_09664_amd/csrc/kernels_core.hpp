@@ -172,6 +172,7 @@ struct QrSmallArgs {
   int part_f32;
   int nblk, r, mode, n, q;
   double eta_c, eta_cap_c, eps_exit;
+  int exit_consec;  // the exit rule fires after this many consecutive small steps (>= 1)
   double guard;          // stationary start: ||grad_0||_2 <= guard * sum_k ||y_k||^2
   const float2* B;
   const double* cost_k;
@@ -199,6 +200,7 @@ struct InitEigArgs {
   double2* V;            // 2 q x (q | 1) scratch (global): matrix and reflectors when not in LDS
   int in_lds;            // matrix and eigenvectors in dynamic LDS (q <= 64)
   float2* Vs;            // q x r out: V_r Sigma_r^{-1}
+  double* lam_out;       // non-null: the r largest eigenvalues (descending) go here, no eigenvectors
   DevState* st;
 };
 

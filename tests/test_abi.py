@@ -59,12 +59,29 @@ def test_host_only_argument_checks():
     L.altgdmin_destroy(h)
     for bad in (P(48, 64, 4, 16, 4, 1024, 0, 0, 36.0, 0.14, 0.0, 0.0, 70),   # nx not 2^k
                 P(64, 64, 4, 16, 17, 1024, 0, 0, 36.0, 0.14, 0.0, 0.0, 70),  # r > 16
-                P(64, 64, 4, 3, 4, 1024, 0, 0, 36.0, 0.14, 0.0, 0.0, 70),    # r > q
+                P(64, 64, 4, 16, 4, 1024, 0, 0, 36.0, 0.14, 0.0, 0.0, 70, -1),  # exit_consec < 0
                 P(64, 64, 4, 16, 4, 1000, 0, 0, 36.0, 0.14, 0.0, 0.0, 70),   # m_max % nx
                 P(64, 64, 4, 16, 4, 1024, 2, 0, 36.0, 0.14, 0.0, 0.0, 70),   # mask kind
                 P(64, 64, 4, 16, 4, 1024, 0, 0, 36.0, 0.0, 0.0, 0.0, 70)):   # eta_c
         assert L.altgdmin_create(ctypes.byref(bad), ctypes.byref(h)) == 1
     assert L.altgdmin_status_string(4) == b"Gram matrix not positive definite"
+    # r > q is a valid context (LS step, operators, the steps around the loop);
+    # the spectral initialisation refuses it
+    wide = P(64, 64, 4, 1, 4, 1024, 0, 0, 36.0, 0.14, 0.0, 0.0, 70)
+    assert L.altgdmin_create(ctypes.byref(wide), ctypes.byref(h)) == 0
+    assert L.altgdmin_init(h, ctypes.c_void_p(256)) == 1
+    nb = ctypes.c_size_t()
+    assert L.altgdmin_aux_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
+    # the steps around the loop check their arguments before any launch
+    one = ctypes.c_void_p(256)
+    assert L.altgdmin_mean(h, -1.0, 10, one, one, None) == 1          # tol < 0
+    assert L.altgdmin_mean(h, 1e-3, 10, one, ctypes.c_void_p(300), None) == 1  # unaligned aux
+    assert L.altgdmin_mec_cgls(h, one, -1, 0.0, one, one) == 1        # iters < 0
+    assert L.altgdmin_mec_ista(h, one, 10, -1.0, 0.0, one, one, None) == 1
+    assert L.altgdmin_rank_energy(h, 17, (ctypes.c_double * 17)(), one) == 1
+    assert L.altgdmin_expand(h, one, None, None, None, one) == 1       # U without B
+    assert L.altgdmin_mean(h, 1e-3, 10, one, one, None) == 2           # no problem bound yet
+    L.altgdmin_destroy(h)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

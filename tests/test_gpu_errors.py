@@ -21,7 +21,9 @@ def test_bad_parameters_are_rejected_before_launch():
         ag.AltGDmin(48, 64, 2, 4, 2, 48)          # nx not a power of two
     assert e.value.status == 1
     with pytest.raises(ag.AltGDminError):
-        ag.AltGDmin(64, 64, 2, 4, 5, 64)          # r > q
+        ag.AltGDmin(64, 64, 2, 4, 17, 64)         # r > 16
+    with pytest.raises(ag.AltGDminError):
+        ag.AltGDmin(64, 64, 2, 4, 2, 64, exit_consec=-1)
     with pytest.raises(ag.AltGDminError):
         ag.AltGDmin(64, 64, 2, 4, 2, 100)         # lines: m_max not a multiple of nx
     with pytest.raises(ag.AltGDminError):
@@ -98,3 +100,21 @@ def test_full_sampling_without_truncation_is_stationary():
     U = ctx.init()
     B, done = ctx.iterate(5, U, sync=True)
     assert done == 0
+
+
+def test_spectral_init_needs_r_at_most_q():
+    """A context with r > q is valid (LS step, operators, the steps around
+    the loop) but the spectral initialisation (top r of q singular vectors)
+    refuses it before any launch."""
+    p = datagen.make_small(32, 32, 2, 2, 2, seed=1, kind="lines", n_lines=8)
+    cs = Case(p)
+    ctx = ag.AltGDmin(p.nx, p.ny, p.nc, p.q, 4, int(cs.y.shape[2]))
+    dev = torch.device("cuda:0")
+    ctx.set_problem(torch.from_numpy(cs.coils.astype(np.complex64)).to(dev), torch.from_numpy(cs.mask).to(dev),
+                    torch.from_numpy(cs.m_k).to(dev), torch.from_numpy(cs.y32).to(dev))
+    with pytest.raises(ag.AltGDminError) as e:
+        ctx.init()
+    assert e.value.status == 1
+    U, _ = np.linalg.qr(datagen.crandn(np.random.default_rng(0), p.n, 4))
+    B = ctx.ls(torch.from_numpy(np.ascontiguousarray(U.T.astype(np.complex64))).to(dev))
+    assert B.shape == (p.q, 4)

@@ -321,3 +321,21 @@ def test_exit_rule_fires_and_is_recorded():
     sd = np.array(res.history["sd"]) / math.sqrt(r)
     t = res.iters
     assert t < 70 and sd[t - 1] < 0.01 and np.all(sd[: t - 1] >= 0.01)
+
+
+def test_consecutive_exit_variant():
+    """The Sec. VI variant of the exit rule: with exit_consec = c the loop
+    ends at the first t whose last c steps all had SD/sqrt(r) < eps; with
+    c = 1 it is Algorithm 2's rule.  Checked against the recorded SD
+    sequence of a fixed-length run."""
+    nx, ny, nc, q, r = 16, 16, 4, 20, 2
+    p = datagen.make_small(nx, ny, nc, q, r, seed=2, kind="lines", n_lines=8, snr_db=30.0)
+    op = O.from_problem(p)
+    Y = datagen.add_noise(op.apply_A(p.zstar), p.noise, op.m_k, 30.0)
+    eps = 0.01
+    full = AG.run(op, Y, AG.Params(r=r, t_max=70, eps_exit=0.0), t_fixed=70)
+    small = np.array(full.history["sd"]) / math.sqrt(r) < eps
+    for c in (1, 2, 4):
+        want = next(t + 1 for t in range(70) if t + 1 >= c and small[t + 1 - c: t + 1].all())
+        res = AG.run(op, Y, AG.Params(r=r, t_max=70, eps_exit=eps, exit_consec=c))
+        assert res.iters == want and res.history["exit_at"] == want
