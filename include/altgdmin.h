@@ -81,7 +81,8 @@ typedef enum {
   ALTGDMIN_EHIP = 3,        /* a HIP runtime call failed                    */
   ALTGDMIN_ENOTPD = 4,      /* a Gram matrix was not positive definite      */
   ALTGDMIN_ENONFINITE = 5,  /* a NaN or Inf appeared                         */
-  ALTGDMIN_EUNSUPPORTED = 6 /* valid but not supported by this build         */
+  ALTGDMIN_EUNSUPPORTED = 6, /* valid but not supported by this build        */
+  ALTGDMIN_ESCRATCH = 7      /* problem too large for the built-in scratch     */
 } altgdmin_status;
 
 enum { ALTGDMIN_MASK_LINES = 0, ALTGDMIN_MASK_INDEX = 1 };
@@ -271,6 +272,21 @@ altgdmin_status altgdmin_aux_bytes(const altgdmin_ctx* ctx, size_t* bytes);
  * tol < 0. */
 altgdmin_status altgdmin_mean(altgdmin_ctx* ctx, double tol, int32_t maxit, void* d_zbar, void* d_aux,
                               int32_t* h_iters);
+
+/* altgdmin_mean without the auxiliary workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments and result as
+ * altgdmin_mean (bitwise: the same kernels in the same order); its scratch
+ * (three n-vectors, nc*n coil images, reduction partials and scalars) is a
+ * 16 MiB array built into the library, one per GPU, kept until the process
+ * ends.  Problems whose scratch exceeds it (8 (3 + nc) n bytes plus about
+ * 2 KiB; e.g. 256x256 with up to 28 coils) return ALTGDMIN_ESCRATCH before
+ * any launch.  Calls allocate nothing.  Every call on one GPU shares that
+ * GPU's scratch, so calls that overlap on one GPU (two streams, two threads)
+ * race and must be serialised by the caller.  The stream's device must be
+ * the current device. */
+altgdmin_status altgdmin_mean_noalloc(altgdmin_ctx* ctx, double tol, int32_t maxit, void* d_zbar,
+                                      int32_t* h_iters);
 
 /* Residual measurements (Algorithm 1, steps 2a and 3a):
  * d_yres = y - A(zbar 1^T + X), frame by frame, in the padded layout (padding

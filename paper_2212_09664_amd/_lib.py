@@ -13,7 +13,8 @@ TIMED_KERNELS = {"fwd_transform": 1, "gram_rhs": 2, "solve": 3, "fold": 4, "adj_
                  "qr_gram": 6, "qr_small": 7, "apply_qr": 8}
 
 _STATUS = {0: "ok", 1: "invalid argument", 2: "call out of order", 3: "HIP runtime error",
-           4: "Gram matrix not positive definite", 5: "non-finite value", 6: "unsupported configuration"}
+           4: "Gram matrix not positive definite", 5: "non-finite value", 6: "unsupported configuration",
+           7: "problem too large for the built-in scratch"}
 
 
 class Params(ctypes.Structure):
@@ -80,6 +81,7 @@ def load_library():
         "altgdmin_cnn_input": ([vp, vp], i32),
         "altgdmin_aux_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], i32),
         "altgdmin_mean": ([vp, dbl, i32, vp, vp, pi32], i32),
+        "altgdmin_mean_noalloc": ([vp, dbl, i32, vp, pi32], i32),
         "altgdmin_residual": ([vp, vp, vp, vp, vp], i32),
         "altgdmin_mec_cgls": ([vp, vp, i32, dbl, vp, vp], i32),
         "altgdmin_mec_ista": ([vp, vp, i32, dbl, dbl, vp, vp, pi32], i32),
@@ -259,6 +261,14 @@ class AltGDmin:
         self._check(self._L.altgdmin_mean(self._h, float(tol), int(maxit), _ptr(zbar), _ptr(self.aux()),
                                           ctypes.byref(it) if sync else None), "mean")
         return (zbar, it.value) if sync else zbar
+
+    def mean_noalloc(self, zbar, tol=1e-3, maxit=10, sync=False):
+        """The mean image into the caller's zbar (n,), with the library's
+        built-in scratch instead of an auxiliary workspace (allocates nothing)."""
+        it = ctypes.c_int32(-1)
+        self._check(self._L.altgdmin_mean_noalloc(self._h, float(tol), int(maxit), _ptr(zbar),
+                                                  ctypes.byref(it) if sync else None), "mean_noalloc")
+        return it.value if sync else None
 
     def residual(self, zbar=None, X=None, out=None):
         """y - A(zbar 1^T + X) in the padded layout (q, nc, m_max); X is (q, n)."""

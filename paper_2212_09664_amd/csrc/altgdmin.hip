@@ -690,6 +690,7 @@ const char* altgdmin_status_string(altgdmin_status s) {
     case ALTGDMIN_ENOTPD: return "Gram matrix not positive definite";
     case ALTGDMIN_ENONFINITE: return "non-finite value";
     case ALTGDMIN_EUNSUPPORTED: return "unsupported configuration";
+    case ALTGDMIN_ESCRATCH: return "problem too large for the built-in scratch";
   }
   return "unknown status";
 }

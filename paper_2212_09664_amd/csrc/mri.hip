@@ -7,12 +7,20 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "ctx.hpp"
 #include "kernels_mri.hpp"
 
 using ag_host::map_hip;
+
+// The scratch of altgdmin_mean_noalloc (the CG vectors, the normal operator's
+// coil images, the reduction partials and the CG scalars): one copy per GPU,
+// held until the process ends.  Host code uses only the device address that
+// hipGetSymbolAddress returns for the current device, never this name.
+constexpr size_t kMeanScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) char scratch[kMeanScratchBytes];
 
 namespace {
 
@@ -152,6 +160,45 @@ hipError_t mean_seq(altgdmin_ctx* c, double tol, int maxit, float2* x, const Aux
   return hipSuccess;
 }
 
+// ---- the no-allocation variant of the mean image ---------------------------
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the scratch's device address on the current device (looked up once per device)
+altgdmin_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return ALTGDMIN_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ALTGDMIN_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ALTGDMIN_OK;
+}
+
+// the mean image's buffers carved from a base: three n-vectors, the coil
+// images, the partials and the scalars; returns the bytes used
+size_t mean_layout(const altgdmin_ctx* c, char* base, Aux* a) {
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = al256(off + b);
+    return base ? base + o : nullptr;
+  };
+  Aux t{};
+  t.v0 = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)c->n));
+  t.v1 = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)c->n));
+  t.v2 = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)c->n));
+  t.ci = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)c->p.nc * c->n));
+  t.part = reinterpret_cast<double*>(take(sizeof(double) * MRI_NB));
+  t.cg = reinterpret_cast<CgState*>(take(sizeof(CgState)));
+  if (a) *a = t;
+  return off;
+}
+
 // the device error, if any, after a synchronisation
 altgdmin_status sync_status(altgdmin_ctx* c) {
   if (hipStreamSynchronize(c->stream) != hipSuccess) return ALTGDMIN_EHIP;
@@ -176,6 +223,24 @@ altgdmin_status altgdmin_mean(altgdmin_ctx* c, double tol, int32_t maxit, void* 
   if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
   Aux a;
   aux_layout(c, static_cast<char*>(d_aux), &a);
+  HIPCHK(mean_seq(c, tol, maxit, static_cast<float2*>(d_zbar), a));
+  if (h_iters) {
+    const altgdmin_status e = sync_status(c);
+    HIPCHK(hipMemcpy(h_iters, &a.cg->iters, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (e != ALTGDMIN_OK) return e;
+  }
+  return ALTGDMIN_OK;
+}
+
+altgdmin_status altgdmin_mean_noalloc(altgdmin_ctx* c, double tol, int32_t maxit, void* d_zbar, int32_t* h_iters) {
+  if (!c || !d_zbar || maxit < 0 || !(tol >= 0.0) || !isfinite(tol)) return ALTGDMIN_EINVAL;
+  if (mean_layout(c, nullptr, nullptr) > kMeanScratchBytes) return ALTGDMIN_ESCRATCH;
+  if (!c->bound || !c->y) return ALTGDMIN_ESTATE;
+  void* base = nullptr;
+  const altgdmin_status s = scratch_address(&base);
+  if (s != ALTGDMIN_OK) return s;
+  Aux a;
+  mean_layout(c, static_cast<char*>(base), &a);
   HIPCHK(mean_seq(c, tol, maxit, static_cast<float2*>(d_zbar), a));
   if (h_iters) {
     const altgdmin_status e = sync_status(c);

@@ -82,6 +82,12 @@ def test_host_only_argument_checks():
     assert L.altgdmin_expand(h, one, None, None, None, one) == 1       # U without B
     assert L.altgdmin_mean(h, 1e-3, 10, one, one, None) == 2           # no problem bound yet
     L.altgdmin_destroy(h)
+    # the no-allocation mean refuses, before anything else, a problem whose
+    # scratch (8 (3 + nc) n bytes) exceeds its built-in 16 MiB
+    big = P(512, 512, 8, 4, 2, 512 * 8, 0, 0, 36.0, 0.14, 0.0, 0.0, 70)
+    assert L.altgdmin_create(ctypes.byref(big), ctypes.byref(h)) == 0
+    assert L.altgdmin_mean_noalloc(h, 1e-3, 10, one, None) == 7
+    L.altgdmin_destroy(h)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
