@@ -342,6 +342,7 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   fa.ua = c->ua;
   fa.n = c->n;
   fa.m_max = p.m_max;
+  fa.max_pairs = p.q;
   fa.K = c->at<float2>(c->o_K);
   fa.st = c->st();
   fa.check_halt = check_halt;

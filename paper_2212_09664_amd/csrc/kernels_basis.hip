@@ -317,6 +317,201 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines2(FoldArgs a) {
   }
 }
 
+// gradient fold, 1D Cartesian, on the matrix cores: per (line u, coil c)
+//   K(x, :) = sum_{p in u} (W(x, :) . b_p - y_p(x)) conj(b_p)^T
+//           = [W(x, :) | y_1(x) .. y_np(x)] . [S_u ; -conj(b_1)^T ; ...]
+// with S_u = sum_p b_p b_p^H: one complex contraction per row x of length
+// r + np, run as a real one (v_mfma_f32_16x16x4f32) over the contraction
+// index kappa = [Re W_0..RT-1, Im W_0..RT-1, (Re y_p, Im y_p) for every pair]
+// and the 2 RT output columns [Re K_0..RT-1, Im K_0..RT-1]:
+//   Re W_i  -> [ Re S_ij |  Im S_ij ]      Im W_i -> [ -Im S_ij | Re S_ij ]
+//   Re y_p  -> [ -Re b_pj |  Im b_pj ]     Im y_p -> [ -Im b_pj | -Re b_pj ]
+// The B operand (kappa x 2 RT) is built in LDS from the pairs' b; each wave
+// takes 16-row tiles of x, its A operand straight from W and the line data
+// (lane l: row l % 16, contraction slot l / 16), and writes each tile's 16
+// contiguous K rows through LDS.  Accumulation order is fixed.
+template <int RT>
+__global__ __launch_bounds__(AG_NT) void k_fold_lines_mma(FoldArgs a) {
+  typedef float fv4 __attribute__((ext_vector_type(4)));
+  constexpr int NCOL = 2 * RT, NCT = NCOL / 16;
+  constexpr int TW = 4;                   // 16-row tiles per wave, worked together (nx <= 256)
+  constexpr int YB = 4;                   // contraction steps of line data loaded per batch
+  // dynamic LDS sized by the launch for at most a.max_pairs pairs per line:
+  // b_p (not conjugated, zero for j >= r), then the B operand
+  extern __shared__ float2 fold_lds[];
+  float2* bb = fold_lds;
+  float* Bm = reinterpret_cast<float*>(fold_lds + a.max_pairs * RT);
+  __shared__ float spart[4][RT * RT * 2];  // S_u partial sums over four slices of the pairs
+  constexpr int OP = NCOL + 4;            // output-tile row pitch: the 4 row groups of a store fall in distinct banks
+  __shared__ float ot[4][16 * OP];        // one output tile per wave
+  const int4 lrec = a.line_order[blockIdx.y];
+  const int u = lrec.x, c = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, row = lane & 15, kq = lane >> 4;
+  const int r = a.r, nx = a.nx;
+  const int ntile = nx / 16;
+  const int p0 = lrec.y, np = lrec.z;
+  // this wave's W rows, requested first (valid, clamped addresses; the line
+  // is checked once they are in flight): slot kq takes W(x, 4 h + kq)
+  const float2* Wl = a.W + ((long)c * a.ua + u) * nx * r;
+  float2 wv[TW][RT / 4];
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt) {
+    const int t = min(wave + 4 * tt, ntile - 1);
+    const float2* wr = Wl + (t * 16 + row) * r;
+#pragma unroll
+    for (int h = 0; h < RT / 4; ++h) wv[tt][h] = wr[min(4 * h + kq, r - 1)];
+  }
+  const int nu_ = a.st->n_units;
+  if (halted(a.st, a.check_halt) || u >= nu_) return;
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt)
+#pragma unroll
+    for (int h = 0; h < RT / 4; ++h)
+      if (4 * h + kq >= r) wv[tt][h] = make_float2(0.f, 0.f);
+  const float2* Yc = a.yu + (long)a.nc * nx * p0 + (long)c * np * nx;  // this line and coil, [p][x]
+  const int kap = (2 * RT + 2 * np + 3) & ~3;  // contraction length, padded to the MFMA's 4
+  const int nps = (kap - 2 * RT) >> 2;         // steps over the line data: pairs 2s, 2s + 1
+  // the first batch of line data: slot kq of step s takes pair 2 s + kq / 2
+  int toff[TW];
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt) toff[tt] = min(wave + 4 * tt, ntile - 1) * 16 + row;
+  // each slot needs one component: Re for even kq, Im for odd (a per-lane
+  // choice between the two halves of a loaded float2 would become a
+  // runtime-indexed private array)
+  const float* Yf = reinterpret_cast<const float*>(Yc) + (kq & 1);
+  float yv[YB][TW];
+#pragma unroll
+  for (int h = 0; h < YB; ++h) {
+    const int p = min(2 * h + (kq >> 1), np - 1);
+#pragma unroll
+    for (int tt = 0; tt < TW; ++tt) yv[h][tt] = Yf[2 * (p * nx + toff[tt])];
+  }
+  __builtin_amdgcn_sched_barrier(0);  // in flight during the B operand's construction
+  for (int e = tid; e < np * RT; e += AG_NT) {
+    const int p = e / RT, j = e - p * RT;
+    const float2 v = (j < r) ? a.bcp[(long)(p0 + p) * r + j] : make_float2(0.f, 0.f);
+    bb[e] = make_float2(v.x, -v.y);
+  }
+  __syncthreads();
+  // S_u = sum_p b_p b_p^H: entry (i, j) over four slices of the pairs
+  {
+    const int sl = tid / (AG_NT / 4), e0 = tid % (AG_NT / 4);
+    for (int e = e0; e < RT * RT; e += AG_NT / 4) {
+      const int i = e / RT, j = e - i * RT;
+      float sr = 0.f, si = 0.f;
+      for (int p = sl; p < np; p += 4) {
+        const float2 bi = bb[p * RT + i], bj = bb[p * RT + j];
+        sr += bi.x * bj.x + bi.y * bj.y;  // b_i conj(b_j)
+        si += bi.y * bj.x - bi.x * bj.y;
+      }
+      spart[sl][2 * e] = sr;
+      spart[sl][2 * e + 1] = si;
+    }
+  }
+  // the line data's rows of B
+  for (int e = tid; e < (kap - 2 * RT) * RT; e += AG_NT) {
+    const int kk = e / RT, j = e - kk * RT, p = kk >> 1;
+    const float2 b = (p < np) ? bb[p * RT + j] : make_float2(0.f, 0.f);
+    float* br = Bm + (2 * RT + kk) * NCOL;
+    if ((kk & 1) == 0) {
+      br[j] = -b.x;
+      br[RT + j] = b.y;
+    } else {
+      br[j] = -b.y;
+      br[RT + j] = -b.x;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < RT * RT; e += AG_NT) {
+    const int i = e / RT, j = e - i * RT;
+    const float sr = (spart[0][2 * e] + spart[1][2 * e]) + (spart[2][2 * e] + spart[3][2 * e]);
+    const float si = (spart[0][2 * e + 1] + spart[1][2 * e + 1]) + (spart[2][2 * e + 1] + spart[3][2 * e + 1]);
+    Bm[i * NCOL + j] = sr;
+    Bm[i * NCOL + RT + j] = si;
+    Bm[(RT + i) * NCOL + j] = -si;
+    Bm[(RT + i) * NCOL + RT + j] = sr;
+  }
+  __syncthreads();
+  fv4 acc[TW][NCT];
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) acc[tt][ct] = fv4{0.f, 0.f, 0.f, 0.f};
+  // W part: Re W in the first RT / 4 steps, Im W in the next RT / 4
+#pragma unroll
+  for (int h = 0; h < RT / 4; ++h)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const float bre = Bm[(4 * h + kq) * NCOL + ct * 16 + row];
+      const float bim = Bm[(RT + 4 * h + kq) * NCOL + ct * 16 + row];
+#pragma unroll
+      for (int tt = 0; tt < TW; ++tt) {
+        acc[tt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[tt][h].x, bre, acc[tt][ct], 0, 0, 0);
+        acc[tt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[tt][h].y, bim, acc[tt][ct], 0, 0, 0);
+      }
+    }
+  // line-data part: slot kq of step s takes pair 2 s + kq/2, Re (kq even) or
+  // Im; a batch's loads are issued together (the first batch with the W rows)
+  for (int s0 = 0; s0 < nps; s0 += YB) {
+    if (s0 > 0) {
+#pragma unroll
+      for (int h = 0; h < YB; ++h) {
+        const int p = min(2 * (s0 + h) + (kq >> 1), np - 1);
+#pragma unroll
+        for (int tt = 0; tt < TW; ++tt) yv[h][tt] = Yf[2 * (p * nx + toff[tt])];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);  // the batch's loads all issue before the first use
+#pragma unroll
+    for (int h = 0; h < YB; ++h) {
+      if (s0 + h < nps) {
+        const int kk = 2 * RT + 4 * (s0 + h) + kq;
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const float bv = Bm[kk * NCOL + ct * 16 + row];
+#pragma unroll
+          for (int tt = 0; tt < TW; ++tt) {
+            acc[tt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[h][tt], bv, acc[tt][ct], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  // D[4 kq + v][row] of column tile ct -> out[x][n]; then the tile's 16
+  // contiguous rows of r complex values
+  float2* Kl = a.K + ((long)c * a.ua + u) * nx * r;
+  float* out = ot[wave];
+  const bool full = (r == RT);
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt) {
+    const int t = wave + 4 * tt;
+    if (t < ntile) {
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[(4 * kq + v) * OP + ct * 16 + row] = acc[tt][ct][v];
+      // the tile is read back by other lanes of this wave: a wave's LDS
+      // operations execute in order, so only the compiler must keep them so
+      // (a memory fence here would also wait for the wave's global stores)
+      __builtin_amdgcn_wave_barrier();
+      float2* dst = Kl + (long)t * 16 * r;
+      if (full) {  // 16 RT contiguous values, RT / 4 per lane
+#pragma unroll
+        for (int e0 = 0; e0 < 16 * RT; e0 += 64) {
+          const int e = e0 + lane, xr = e / RT, j = e % RT;
+          dst[e] = make_float2(out[xr * OP + j], out[xr * OP + RT + j]);
+        }
+      } else {
+        for (int e = lane; e < 16 * r; e += 64) {
+          const int xr = e / r, j = e - xr * r;
+          dst[e] = make_float2(out[xr * OP + j], out[xr * OP + RT + j]);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();  // read before the next tile overwrites it
+    }
+  }
+}
+
 // gradient fold, general masks: per location and coil,
 //   K_c(loc,:) = sum_{(k,e) at loc} (W_c(loc,:) b_k - y_{k,c}(e)) conj(b_k)
 template <int RT>
@@ -423,7 +618,23 @@ hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int gr
 hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s) {
   const dim3 g(grid_x, grid_y);
   if (lines) {
-    if (a.r <= 4) hipLaunchKernelGGL(k_fold_lines2<4>, g, dim3(AG_NT), 0, s, a);
+    // the matrix-core fold needs whole 16-row tiles of x, at most four per
+    // wave; its LDS holds b_p and the B operand for max_pairs pairs
+    const int rt = a.r <= 8 ? 8 : 16;
+    const size_t lds = sizeof(float2) * a.max_pairs * rt + sizeof(float) * (2 * rt + 2 * a.max_pairs + 4) * 2 * rt;
+    static bool attr_set = false;  // q = 128 at rank 16 needs more than the default 64 KiB
+    if (!attr_set) {
+      hipError_t e1 = hipFuncSetAttribute((const void*)k_fold_lines_mma<8>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+      hipError_t e2 = hipFuncSetAttribute((const void*)k_fold_lines_mma<16>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+      if (e1 != hipSuccess) return e1;
+      if (e2 != hipSuccess) return e2;
+      attr_set = true;
+    }
+    if (a.nx >= 16 && a.nx <= 256 && a.r <= 8) hipLaunchKernelGGL(k_fold_lines_mma<8>, g, dim3(AG_NT), lds, s, a);
+    else if (a.nx >= 16 && a.nx <= 256) hipLaunchKernelGGL(k_fold_lines_mma<16>, g, dim3(AG_NT), lds, s, a);
+    else if (a.r <= 4) hipLaunchKernelGGL(k_fold_lines2<4>, g, dim3(AG_NT), 0, s, a);
     else if (a.r <= 8) hipLaunchKernelGGL(k_fold_lines2<8>, g, dim3(AG_NT), 0, s, a);
     else hipLaunchKernelGGL(k_fold_lines2<16>, g, dim3(AG_NT), 0, s, a);
   } else {

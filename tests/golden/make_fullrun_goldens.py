@@ -32,7 +32,7 @@ from oracle import metrics as M  # noqa: E402
 from oracle import operators as O  # noqa: E402
 
 # workload, seed, fixed iteration count (the workloads' own T)
-RUNS = {"cine256": (1001, 70), "radial128": (0, 50)}
+RUNS = {"cine256": (1001, 70), "radial128": (0, 50), "cine256r16": (0, 70), "cine128": (0, 70)}
 N_SAMPLES = 256
 
 
