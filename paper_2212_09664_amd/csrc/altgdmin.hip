@@ -715,7 +715,7 @@ altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** ou
   c->n_loc = c->lines ? p.ny : c->n;
   c->nw = (p.q + 31) / 32;
   c->ua = p.ny;
-  c->gram_chunk = std::max(64, 2048 / p.nc);
+  c->gram_chunk = std::max(32, 512 / p.nc);
   c->nchunks = (p.m_max + c->gram_chunk - 1) / c->gram_chunk;
   c->gram_cg = std::max(1, std::min(p.nc, 1024 / p.nx));
   c->gram_ngroups = (p.nc + c->gram_cg - 1) / c->gram_cg;
@@ -771,6 +771,7 @@ altgdmin_status altgdmin_set_problem(altgdmin_ctx* c, const void* d_coils, const
   if (c->lines)
     HIPCHK(launch_gram_work(c->at<int2>(c->o_unitspan), c->at<int4>(c->o_gwork), c->at<int4>(c->o_lineord),
                             c->n_loc, c->st(), s));
+
   hipLaunchKernelGGL(k_inv_fill, dim3((c->width + 255) / 256, p.q), dim3(256), 0, s, c->mask, c->m_k,
                      c->width, c->per, c->at<uint32_t>(c->o_bitmap), c->nw, c->at<int32_t>(c->o_locptr),
                      c->at<int32_t>(c->o_loc2unit), c->at<int2>(c->o_pairs), c->at<int32_t>(c->o_pairof),

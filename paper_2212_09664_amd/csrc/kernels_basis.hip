@@ -516,32 +516,51 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines_mma(FoldArgs a) {
 //   K_c(loc,:) = sum_{(k,e) at loc} (W_c(loc,:) b_k - y_{k,c}(e)) conj(b_k)
 template <int RT>
 __global__ __launch_bounds__(AG_NT) void k_fold_index2(FoldArgs a) {
+  // B (every frame's b, q <= 128) staged once per workgroup; a location's
+  // (frame, sample) pairs and their data are loaded in batches of PB, all of
+  // a batch's loads in flight together (the pair counts reach q at the
+  // centre of k-space, where every spoke passes)
+  constexpr int PB = 8;
+  __shared__ float2 sB[128 * RT];
   const int loc = blockIdx.x * AG_NT + threadIdx.x, c = blockIdx.y;
-  if (halted(a.st, a.check_halt)) return;
-  if (loc >= a.n) return;
-  const int r = a.r;
-  const long base = ((long)c * a.n + loc) * r;
+  const int r = a.r, tid = threadIdx.x;
+  for (int e = tid; e < a.max_pairs * RT; e += AG_NT) {
+    const int k = e / RT, j = e - k * RT;
+    sB[e] = (j < r) ? a.B[(long)k * r + j] : make_float2(0.f, 0.f);
+  }
+  const int lc = min(loc, a.n - 1);
+  const long base = ((long)c * a.n + lc) * r;
   float2 w[RT], kk[RT];
 #pragma unroll
   for (int i = 0; i < RT; ++i) {
     w[i] = (i < r) ? a.W[base + i] : make_float2(0.f, 0.f);
     kk[i] = make_float2(0.f, 0.f);
   }
-  const int p0 = a.loc_ptr[loc], p1 = a.loc_ptr[loc + 1];
-  for (int p = p0; p < p1; ++p) {
-    const int2 ke = a.pairs[p];
-    const float2* b = a.B + (long)ke.x * r;
-    float2 bb[RT];
-    float2 res = make_float2(0.f, 0.f);
+  const int p0 = a.loc_ptr[lc], p1 = a.loc_ptr[lc + 1];
+  __syncthreads();
+  if (halted(a.st, a.check_halt)) return;
+  const float2* yc = a.y + (long)c * a.m_max;
+  const long ystride = (long)a.nc * a.m_max;
+  for (int pb = p0; pb < p1; pb += PB) {
+    int2 ke[PB];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-      bb[i] = (i < r) ? b[i] : make_float2(0.f, 0.f);
-      res = cfma(res, w[i], bb[i]);
+    for (int t = 0; t < PB; ++t) ke[t] = a.pairs[min(pb + t, p1 - 1)];
+    float2 yv[PB];
+#pragma unroll
+    for (int t = 0; t < PB; ++t) yv[t] = yc[ke[t].x * ystride + ke[t].y];
+#pragma unroll
+    for (int t = 0; t < PB; ++t) {
+      if (pb + t < p1) {
+        const float2* bb = sB + ke[t].x * RT;
+        float2 res = make_float2(-yv[t].x, -yv[t].y);
+#pragma unroll
+        for (int i = 0; i < RT; ++i) res = cfma(res, w[i], bb[i]);
+#pragma unroll
+        for (int j = 0; j < RT; ++j) kk[j] = cfmaj(kk[j], res, bb[j]);
+      }
     }
-    res = csub(res, a.y[((long)ke.x * a.nc + c) * a.m_max + ke.y]);
-#pragma unroll
-    for (int j = 0; j < RT; ++j) kk[j] = cfmaj(kk[j], res, bb[j]);
   }
+  if (loc >= a.n) return;
 #pragma unroll
   for (int j = 0; j < RT; ++j)
     if (j < r) a.K[base + j] = kk[j];

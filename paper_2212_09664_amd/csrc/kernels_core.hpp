@@ -147,7 +147,7 @@ struct FoldArgs {
   const int2* pairs;
   const int32_t* loc_ptr;
   int nc, r, nx, ua, n, m_max;
-  int max_pairs;         // LINES: at most this many frames sample one line (q)
+  int max_pairs;         // at most this many frames sample one line or location (q)
   float2* K;
   DevState* st;
   int check_halt;

@@ -20,6 +20,9 @@ namespace ag {
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 
+// largest sample chunk of a k_gram_index_mma workgroup (its indices go to LDS)
+constexpr int GRAM_INDEX_MAX_CHUNK = 2048;
+
 template <typename T>
 struct Mma;
 template <>
@@ -384,28 +387,39 @@ __global__ __launch_bounds__(256) void k_gram_index_mma(GramIndexArgs a) {
 #pragma unroll
     for (int j = 0; j < TR; ++j) P[i][j] = M::zero();
   }
+  // the chunk's sample locations staged once, so that the W gathers of a
+  // batch of steps do not wait on their index loads
+  __shared__ int s_loc[GRAM_INDEX_MAX_CHUNK];
+  for (int e = tid; e < ns; e += 256) s_loc[e] = a.mask[(long)k * a.m_max + i0 + e];
+  __syncthreads();
   const float* Wf = reinterpret_cast<const float*>(a.W);
-  for (int rho0 = 4 * wave; rho0 < rows; rho0 += 16) {
-    const int rho = rho0 + kk;
-    const bool rv = rho < rows;
-    const int c = rv ? rho / ns : 0;
-    const int s = rv ? rho % ns : 0;
-    const int loc = rv ? a.mask[(long)k * a.m_max + i0 + s] : 0;
-    T av[TR];
+  const float* yk = reinterpret_cast<const float*>(a.y + (long)k * a.nc * a.m_max + i0) + yim;
+  // batches of UB steps of 4 rows per wave: every load of a batch issued
+  // before its matrix-core work
+  constexpr int UB = 8;
+  for (int rb = 4 * wave; rb < rows; rb += 16 * UB) {
+    T av[UB][TR], bv[UB];
 #pragma unroll
-    for (int t = 0; t < TR; ++t) {
-      T v = (T)0;
-      if (rv && wok[t]) v = (T)Wf[2 * (((long)c * a.n + loc) * r + wj[t]) + wim[t]];
-      av[t] = v;
+    for (int u = 0; u < UB; ++u) {
+      const int rho = rb + 16 * u + kk;
+      const bool rv = rho < rows;
+      const int c = rv ? rho / ns : 0;
+      const int sm = rv ? rho - c * ns : 0;
+      const int loc = s_loc[sm];
+#pragma unroll
+      for (int t = 0; t < TR; ++t)
+        av[u][t] = (rv && wok[t]) ? (T)Wf[2 * (((long)c * a.n + loc) * r + wj[t]) + wim[t]] : (T)0;
+      bv[u] = (rv && ycol) ? (T)yk[2 * ((long)c * a.m_max + sm)] : (T)0;
     }
 #pragma unroll
-    for (int i = 0; i < TR; ++i)
+    for (int u = 0; u < UB; ++u) {
 #pragma unroll
-      for (int j = 0; j < TR; ++j) P[i][j] = M::mma(av[i], av[j], P[i][j]);
-    T bv = (T)0;
-    if (rv && ycol) bv = (T)reinterpret_cast<const float*>(a.y + ((long)k * a.nc + c) * a.m_max + i0 + s)[yim];
+      for (int i = 0; i < TR; ++i)
 #pragma unroll
-    for (int i = 0; i < TR; ++i) H[i] = M::mma(av[i], bv, H[i]);
+        for (int j = 0; j < TR; ++j) P[i][j] = M::mma(av[u][i], av[u][j], P[i][j]);
+#pragma unroll
+      for (int i = 0; i < TR; ++i) H[i] = M::mma(av[u][i], bv[u], H[i]);
+    }
   }
   T* Pt = red;
   T* Ht = red + TR * TR * 256;

@@ -165,10 +165,11 @@ def test_mixed_form_error_table(name):
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-@pytest.mark.parametrize("name", ["cine256", "radial128"])
+@pytest.mark.parametrize("name", ["cine256", "radial128", "cine256r16", "cine128"])
 def test_full_run_matches_oracle(name):
     """The whole reconstruction at the workload's fixed iteration count
-    (cine256: 70, radial128: 50) against the FP64 oracle's run on the same
+    (cine256, cine256r16, cine128: 70; radial128: 50) against the FP64
+    oracle's run on the same
     inputs (stored by tests/golden/make_fullrun_goldens.py, which calls only
     the oracle and the input generator): NMSE after every iteration within
     1e-4, eta within 1e-4 relative, the same gamma and the same truncated
