@@ -16,6 +16,8 @@ then the workload's iterations.  value = iterations per second of the plain
 FP32 form over the timed steps (whole job, inputs already resident in HBM).
 
 Also reported:
+* the steps around the loop (altGDmin-MRI: mean image, residuals, MEC-1,
+  MEC-2, automatic rank), each timed with HIP events on the same inputs;
 * the loop alone (iterate only), and per form the time to NMSE <= 2e-2:
   HIP events after setup, after init and after every iteration (median over
   10 replays); NMSE evaluated off the clock on a replay of the same
@@ -343,6 +345,70 @@ def headline(prob, t, args, workload):
                 kavg_ms=kms / max(klaunch, 1), class_ms_per_step=tot, ttn=ttn)
 
 
+def pipeline_timing(prob, t, reps=5, warmups=2):
+    """The steps around the loop (altGDmin-MRI, Algorithm 1) on the same
+    inputs, each bracketed by HIP events on the library's stream: the mean
+    image (CG, tolerance 1e-3, at most 10 iterations), the first residual,
+    the rebinding of the residual data, the spectral initialisation, the
+    loop, the second residual, MEC-1 (3 CGLS iterations per frame) and MEC-2
+    (ISTA, at most 10 updates), the output assembly, and the automatic-rank
+    spectrum.  Medians over the replays; NMSE of each output off the clock."""
+    import torch
+    import paper_2212_09664_amd as ag
+    T = prob.t_iters
+    m_max = int(prob.m_k().max())
+    kind = ag.MASK_LINES if prob.kind == "lines" else ag.MASK_INDEX
+    ctx = ag.AltGDmin(prob.nx, prob.ny, prob.nc, prob.q, prob.r, m_max, kind, ag.FP32, t_max=T)
+    ws = torch.empty(ctx.workspace_bytes + 256, dtype=torch.uint8, device="cuda:0")
+    names = ["mean", "residual1", "rebind", "init", "loop", "residual2", "mec1", "expand", "mec2", "auto_rank"]
+    times = {k: [] for k in names}
+    s = torch.cuda.current_stream()
+    zs = t["zstar"].to(torch.complex128)
+    zz = float(torch.sum(torch.abs(zs) ** 2).item())
+    nm = {}
+    for rep in range(warmups + reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        ctx.set_problem(t["coils"], t["mask"], t["m_k"], t["y"], workspace=ws)
+        aux = ctx.aux()
+        torch.cuda.synchronize()
+        ev[0].record(s)
+        zbar = ctx.mean(1e-3, 10)
+        ev[1].record(s)
+        yt = ctx.residual(zbar=zbar)
+        ev[2].record(s)
+        ctx.set_problem(t["coils"], t["mask"], t["m_k"], yt, workspace=ws)
+        ev[3].record(s)
+        U = ctx.init()
+        ev[4].record(s)
+        Up = torch.empty_like(U)
+        B = ctx.iterate(T, U, U_prev=Up)
+        ev[5].record(s)
+        X = ctx.expand(Up, B)
+        ytt = ctx.residual(X=X)
+        ev[6].record(s)
+        E1 = ctx.mec_cgls(ytt, 3, 1e-36)
+        ev[7].record(s)
+        Z1 = ctx.expand(Up, B, zbar, E1)
+        ev[8].record(s)
+        E2 = ctx.mec_ista(ytt, 10, 1e-3, 0.0025)
+        ev[9].record(s)
+        ctx.auto_rank(85.0)  # synchronises
+        ev[10].record(s)
+        torch.cuda.synchronize()
+        if rep >= warmups:
+            for i, k in enumerate(names):
+                times[k].append(ev[i].elapsed_time(ev[i + 1]))
+        if rep == 0:
+            Z2 = ctx.expand(Up, B, zbar, E2)
+            for key, Z in (("mri1", Z1), ("mri2", Z2), ("no_mec", ctx.expand(Up, B, zbar))):
+                nm[key] = float(torch.sum(torch.abs(Z.to(torch.complex128) - zs) ** 2).item()) / zz
+    med = {k: round(statistics.median(v), 4) for k, v in times.items()}
+    total1 = sum(med[k] for k in ("mean", "residual1", "rebind", "init", "loop", "residual2", "mec1", "expand"))
+    return {"ms": med, "altgdmin_mri1_ms": round(total1, 4),
+            "altgdmin_mri2_ms": round(total1 - med["mec1"] + med["mec2"], 4),
+            "nmse": {k: v for k, v in nm.items()}}
+
+
 def other_form(prob, t, form, workload):
     T = prob.t_iters
     f = Form(prob, t, form, workload)
@@ -438,6 +504,7 @@ def main():
                          "form on the same inputs; a single form: only that form's figures")
     ap.add_argument("--seed", type=int, default=1001)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true", help="skip the timing of the steps around the loop")
     ap.add_argument("--workload", choices=sorted(WORKLOAD_TEXT), default="cine256",
                     help="the headline figure is cine256; the others are for comparisons")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -556,6 +623,9 @@ def main():
         "forms": form_rows,
         "roofline": roof,
     }
+    if args.form == "all" and not args.no_pipeline:
+        out["pipeline"] = pipeline_timing(prob, t)
+        print(f"# pipeline: {out['pipeline']['ms']}", flush=True)
     if not args.no_cpu:
         cb = cpu_baseline(prob)
         out["cpu_baseline"] = {
