@@ -115,7 +115,7 @@ def kernel_operand_bytes(kernel: str, prob) -> float:
         "fwd_transform": n * r + nc * n + W,
         "gram_rhs": W + nc * M,
         "fold": 2 * W + nc * M,
-        "adj_transform": W + nc * n + n * r,
+        "adj_transform": W + nc * n + 2 * n * r,  # rank <= 8: also reads U for the QR Gram
         "qr_gram": 2 * n * r,
         "apply_qr": 3 * n * r,
     }

@@ -87,7 +87,7 @@ void carve(altgdmin_ctx* c) {
   const size_t qo = (size_t)std::max(m_iter * (m_iter + 1) / 2, q * (q + 1) / 2);
   // QR Gram partials; the spectral init's Gram uses up to init_nblk of them
   // plus one slot for their sum
-  c->o_qpart = take(sizeof(double2) * qo * (std::max(c->qr_nblk, init_nblk(c)) + 1));
+  c->o_qpart = take(sizeof(double2) * qo * (std::max(std::max(c->qr_nblk, init_nblk(c)), p.nx) + 1));
   c->o_qtot = take(sizeof(double2) * m_iter * (m_iter + 1) / 2);  // their sum (the fused step)
   c->o_rfac = take(sizeof(float2) * r * r);
   c->o_stsrc = take(sizeof(double2) * 193);  // deferred statistics of the fused step
@@ -366,7 +366,13 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
     e = launch_basis(3, p.nx, b, p.nc * p.ny, 1, c->stream);
     if (e != hipSuccess) return e;
   }
-  e = launch_basis(1, p.ny, b, p.nx / c->txx, c->adj_parts, c->stream);
+  if (c->adj_qr) {
+    BasisArgs bq = b;
+    bq.qpart = reinterpret_cast<float2*>(c->at<double2>(c->o_qpart));
+    e = launch_adj_qr(p.ny, bq, c->stream);
+  } else {
+    e = launch_basis(1, p.ny, b, p.nx / c->txx, c->adj_parts, c->stream);
+  }
   tmark(c, TK_ADJ);
   return e;
 }
@@ -375,6 +381,7 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
 // work; mode 0 a step, mode 2 only the step size at the first iteration
 // the QR Gram of [U grad] (summing the adjoint's partial gradients)
 hipError_t qr_step_gram(altgdmin_ctx* c, int check_halt) {
+  if (c->adj_qr) return hipSuccess;  // the adjoint transform wrote the block partials
   const altgdmin_params& p = c->p;
   GramColsArgs g{};
   g.A = c->at<float2>(c->o_Ui);
@@ -383,7 +390,7 @@ hipError_t qr_step_gram(altgdmin_ctx* c, int check_halt) {
   g.m2 = p.r;
   g.n = c->n;
   g.rows_per_block = c->qr_rows;
-  g.nparts = c->adj_parts;
+  g.nparts = c->grad_parts;
   g.part_stride = (long)c->n * p.r;
   g.write_sum = 1;
   g.part = c->at<double2>(c->o_qpart);
@@ -400,7 +407,7 @@ QrSmallArgs qr_small_args(altgdmin_ctx* c, int mode, int check_halt) {
   QrSmallArgs qa{};
   qa.part = c->at<double2>(c->o_qpart);
   qa.part_f32 = !c->fp64;
-  qa.nblk = c->qr_nblk;
+  qa.nblk = c->adj_qr ? p.nx : c->qr_nblk;  // one block per image column, or per row block
   qa.r = p.r;
   qa.mode = mode;
   qa.n = c->n;
@@ -726,6 +733,8 @@ altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** ou
     c->adj_cgs = (p.nc + parts - 1) / parts;
     c->adj_parts = (p.nc + c->adj_cgs - 1) / c->adj_cgs;
   }
+  c->adj_qr = !c->fp64 && p.r <= 8 && (p.ny == 64 || p.ny == 128 || p.ny == 256);
+  c->grad_parts = c->adj_qr ? 1 : c->adj_parts;
   c->qr_nblk = std::max(1, std::min(256, c->n / 256));
   c->qr_rows = ((long)c->n + c->qr_nblk - 1) / c->qr_nblk;
   c->qr_rows = (c->qr_rows + 127) / 128 * 128;
@@ -987,9 +996,9 @@ altgdmin_status altgdmin_gradient(altgdmin_ctx* c, const void* d_U, void* d_B, v
     return map_hip(hipGetLastError());
   }
   HIPCHK(gradient_pieces(c, 0));
-  if (c->adj_parts > 1)
+  if (c->grad_parts > 1)
     hipLaunchKernelGGL(k_sum_parts, dim3(1024), dim3(256), 0, c->stream, c->at<float2>(c->o_G),
-                       (long)c->n * p.r, c->adj_parts, c->at<float2>(c->o_G), (long)c->n * p.r);
+                       (long)c->n * p.r, c->grad_parts, c->at<float2>(c->o_G), (long)c->n * p.r);
   if (d_B)
     hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, c->stream, c->at<float2>(c->o_B),
                        static_cast<float2*>(d_B), (long)p.q * p.r);

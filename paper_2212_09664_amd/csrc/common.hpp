@@ -172,7 +172,9 @@ __device__ __forceinline__ void dft_reg(float2* v) {
 
 // ---------------------------------------------------------------------------
 // Stockham autosort FFT of TX columns of length N held in LDS as s[e*TX+col]
-// (column index fastest).  Each pass of radix R reads R points at stride
+// (column index fastest), by NT threads (thread index modulo NT: a
+// workgroup of several groups of NT threads transforms one tile per group,
+// every group reaching the barriers together).  Each pass of radix R reads R points at stride
 // N/R, applies the twiddles exp(-+2 pi i (j mod Ns) r / (Ns R)), does an
 // in-register radix-R DFT and writes them at stride Ns.  tw[t] holds
 // exp(-2 pi i t / N) in float (computed in double).  Unnormalised.
@@ -182,7 +184,7 @@ __device__ __forceinline__ void stockham_pass(float2* s, const float2* __restric
   constexpr int G = TX * (N / R);
   constexpr int IT = (G + NT - 1) / NT;
   float2 v[IT][R];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x % NT;  // a workgroup of several NT-thread groups runs one transform per group
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int g = tid + it * NT;
@@ -283,7 +285,7 @@ __device__ __forceinline__ void fft_regs(float2 (&v0)[IT0_][R0_], float2 (&vo)[I
   static_assert(IT0_ == GM::IT0 && R0_ == GM::R0 && ITL_ == GM::ITL && RL_ == GM::RL,
                 "register tiles do not match the plan");
   constexpr int R0 = GM::R0, RL = GM::RL, P = FftPlan<N>::P;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x % NT;
 #pragma unroll
   for (int it = 0; it < GM::IT0; ++it)
     if (GM::in_ok(tid + it * NT)) dft_reg<R0, INV>(v0[it]);

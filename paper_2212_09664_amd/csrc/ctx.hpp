@@ -37,7 +37,9 @@ struct altgdmin_ctx {
   long qr_rows;
   int kc;        // INDEX: frames per chunk of the operator passes
   int gram_cg, gram_ngroups, gram_chunk;
-  int adj_parts, adj_cgs;  // coil groups of the adjoint transform (partial gradients)
+  int adj_parts, adj_cgs;  // coil groups of the basis transforms (the adjoint's partial gradients)
+  int adj_qr;              // 1: the adjoint sums every coil and forms the QR Gram partials (k_adj_qr)
+  int grad_parts;          // partial gradient arrays the adjoint writes
   int txx;                 // image columns per workgroup in the basis transforms
   size_t bytes;
   // bound problem

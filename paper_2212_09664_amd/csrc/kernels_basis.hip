@@ -16,6 +16,7 @@
 //   adjoint  G(:, j) = sum_c conj(s_c) o F_y^H K_{c,j} (after F_x^H for general
 //            masks), summed over a coil group per workgroup.
 #include "kernels_core.hpp"
+#include "mma.hpp"
 
 namespace ag {
 
@@ -177,6 +178,182 @@ __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
         out[((long)y * a.nx + x0) * r + col] = cscale(acc[it][q], a.scale);
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint + coil combine over every coil + the QR step's Gram partial, one
+// image column x per workgroup (r <= 8, one block of the QR Gram per column):
+// grid nx (consecutive columns on one XCD, which then share the cache lines
+// of K, G and U), 512 threads in two groups of 256.  A transform tile holds
+// ncp = CT / r coils' r columns of K(:, x, :); the two groups transform
+// alternate coil passes into their own accumulators.  Then
+//   G(y, x, :) = scale * sum_c conj(s_c(y, x)) F_y^H K_c(:, x, :)
+// (the groups' and coil slots' terms added in a fixed order) is stored, and
+// the real-embedded Gram [Re U, Re G, Im U, Im G]^T [...] over the column's
+// N pixels is formed on the matrix cores; its complex upper triangle (tri
+// order over the 2r columns [U G], FP32) goes to qpart[blockIdx.x], the
+// block partial that the QR step sums.
+// ---------------------------------------------------------------------------
+template <int N, int CT>
+__global__ __launch_bounds__(512) void k_adj_qr(BasisArgs a) {
+  using GM = FftGeom<N, CT, AG_NT>;
+  constexpr int IT0 = GM::IT0, R0 = GM::R0, ITL = GM::ITL, RL = GM::RL;
+  constexpr int TRM = 2, NTL = 3;  // 2r <= 16 complex columns: a 32 x 32 real Gram, 3 upper tiles
+  constexpr int LDX = 48;          // row pitch of the embedding: a step's 4 rows in disjoint bank quarters
+  constexpr int UE = (N * 8 + 511) / 512;  // U entries per thread (r <= 8)
+  __shared__ float2 s[2][N * CT];
+  __shared__ float X[N * LDX];
+  __shared__ float red[NTL * 256];
+  __shared__ float2 s_tw[N];
+  __shared__ int s_ro[N];  // k-space row -> offset of its K row within a coil, -1 for a zero row
+  constexpr int CMAX = 3072;  // coil values of the column staged in LDS when nc N fits
+  __shared__ float2 s_cw[CMAX];
+  const int tid = threadIdx.x, grp = tid >> 8, lt = tid & 255;
+  const int r = a.r, nx = a.nx, ncp = CT / r, nct = ncp * r, txx = a.txx;
+  const bool cw_lds = a.nc * N <= CMAX;
+  const int b = blockIdx.x;
+  const int x = (nx % 8 == 0) ? (b % 8) * (nx / 8) + b / 8 : b;
+  // the column's basis rows U(y, x, :) for the Gram (pixel-major U), requested first
+  float2 uv[UE];
+#pragma unroll
+  for (int i = 0; i < UE; ++i) {
+    const int e = min(tid + 512 * i, N * r - 1), y = e / r, j = e - y * r;
+    uv[i] = a.U[((long)y * nx + x) * r + j];
+  }
+  for (int e = tid; e < N; e += 512) {
+    const float2 w = a.tw[e];
+    const int u = a.row_unit ? a.row_unit[e] : e;
+    s_tw[e] = make_float2(w.x, -w.y);
+    s_ro[e] = u >= 0 ? u * nx * r : -1;
+  }
+  // the column's coil values s_c(y, x) for every coil: the combine then reads LDS
+  if (cw_lds)
+    for (int e = tid; e < a.nc * N; e += 512) {
+      const int c = e / N, y = e - c * N;
+      s_cw[e] = a.coils[(long)c * a.n + (long)(x / txx) * N * txx + (long)y * txx + (x % txx)];
+    }
+  __syncthreads();
+  const int npass = (a.nc + ncp - 1) / ncp, nround = (npass + 1) / 2;
+  float2 acc[ITL][RL];
+#pragma unroll
+  for (int it = 0; it < ITL; ++it)
+#pragma unroll
+    for (int q = 0; q < RL; ++q) acc[it][q] = make_float2(0.f, 0.f);
+  float2 kv[IT0][R0];
+  auto fetch = [&](int pass) {  // a pass past the last coil gives zeros
+#pragma unroll
+    for (int it = 0; it < IT0; ++it) {
+      const int g = lt + it * AG_NT, col = g % CT, cs = col / r, j = col - cs * r, c = pass * ncp + cs;
+      const bool ok = GM::in_ok(g) && col < nct && c < a.nc;
+      const float2* src = a.K + (long)(ok ? c : 0) * a.ua * nx * r + x * r + j;
+#pragma unroll
+      for (int q = 0; q < R0; ++q) {
+        const int ro = ok ? s_ro[GM::in_row(g, q)] : -1;
+        kv[it][q] = ro >= 0 ? src[ro] : make_float2(0.f, 0.f);
+      }
+    }
+  };
+  fetch(grp);
+  // the state is read once the first loads are in flight; the test is the
+  // same in every thread
+  if (halted(a.st, a.check_halt)) return;
+  for (int rd = 0; rd < nround; ++rd) {  // both groups run every round (and reach every barrier)
+    const int pass = grp + 2 * rd;
+    float2 v0[IT0][R0], vo[ITL][RL];
+#pragma unroll
+    for (int it = 0; it < IT0; ++it)
+#pragma unroll
+      for (int q = 0; q < R0; ++q) v0[it][q] = kv[it][q];
+    if (rd + 1 < nround) fetch(pass + 2);
+    fft_regs<N, CT, AG_NT, true>(v0, vo, s[grp], s_tw);
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int g = lt + it * AG_NT, col = g % CT, cs = col / r, c = pass * ncp + cs;
+      if (GM::out_ok(g) && col < nct && c < a.nc) {
+        if (cw_lds) {
+#pragma unroll
+          for (int q = 0; q < RL; ++q) acc[it][q] = cjfma(acc[it][q], s_cw[c * N + GM::out_row(g, q)], vo[it][q]);
+        } else {
+          const float2* cp = a.coils + (long)c * a.n + (long)(x / txx) * N * txx + (x % txx);
+#pragma unroll
+          for (int q = 0; q < RL; ++q)
+            acc[it][q] = cjfma(acc[it][q], cp[(long)GM::out_row(g, q) * txx], vo[it][q]);
+        }
+      }
+    }
+  }
+  // each group's terms to its tile (free after the last transform's barrier)
+#pragma unroll
+  for (int it = 0; it < ITL; ++it) {
+    const int g = lt + it * AG_NT;
+    if (GM::out_ok(g)) {
+#pragma unroll
+      for (int q = 0; q < RL; ++q) s[grp][GM::out_row(g, q) * CT + g % CT] = acc[it][q];
+    }
+  }
+  __syncthreads();
+  // the column's gradient, stored and embedded with U; embedding columns
+  // from 4r on stay zero
+  const int m = 2 * r;
+  for (int e = tid; e < N * 32; e += 512) {
+    const int y = e >> 5, k = e & 31;
+    if (k >= 2 * m) X[y * LDX + k] = 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < UE; ++i) {
+    const int e = tid + 512 * i;
+    if (e < N * r) {
+      const int y = e / r, j = e - y * r;
+      float2 v = make_float2(0.f, 0.f);
+      for (int h = 0; h < 2; ++h)
+        for (int cs = 0; cs < ncp; ++cs) v = cadd(v, s[h][y * CT + cs * r + j]);
+      v = cscale(v, a.scale);
+      a.G[((long)y * nx + x) * r + j] = v;
+      X[y * LDX + j] = uv[i].x;
+      X[y * LDX + m + j] = uv[i].y;
+      X[y * LDX + r + j] = v.x;
+      X[y * LDX + m + r + j] = v.y;
+    }
+  }
+  __syncthreads();
+  // the Gram on the matrix cores: wave w takes rows [w N/8, (w+1) N/8), 4 per step
+  using M = Mma<float>;
+  const int wave = tid >> 6, lane = tid & 63, mc = lane & 15, kk = lane >> 4;
+  M::V gacc[NTL];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) gacc[t] = M::zero();
+#pragma unroll
+  for (int st = 0; st < N / 32; ++st) {
+    const float* xr = X + ((N / 8) * wave + 4 * st + kk) * LDX + mc;
+    float xv[TRM];
+#pragma unroll
+    for (int t = 0; t < TRM; ++t) xv[t] = xr[16 * t];
+#pragma unroll
+    for (int i = 0; i < TRM; ++i)
+#pragma unroll
+      for (int j = i; j < TRM; ++j) {
+        const int ti = i * TRM - i * (i - 1) / 2 + (j - i);
+        gacc[ti] = M::mma(xv[i], xv[j], gacc[ti]);
+      }
+  }
+  // the transform tiles are free: scratch for the sum over the waves
+  tiles_reduce_par<float, 8, NTL>(red, reinterpret_cast<float*>(&s[0][0]), gacc, wave, lane);
+  auto C = [&](int i, int j) -> float {
+    if (i > j) {
+      const int t = i;
+      i = j;
+      j = t;
+    }
+    const int a_ = i / 16, b_ = j / 16;
+    return red[(a_ * TRM - a_ * (a_ - 1) / 2 + (b_ - a_)) * 256 + (i % 16) * 16 + (j % 16)];
+  };
+  const int nout = m * (m + 1) / 2;
+  float2* qp = a.qpart + (long)b * nout;
+  for (int o = tid; o < nout; o += 512) {
+    int i, j;
+    tri_index(o, m, i, j);
+    qp[o] = make_float2(C(i, j) + C(m + i, m + j), C(i, m + j) - C(m + i, j));
   }
 }
 
@@ -629,6 +806,19 @@ hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int gr
     case 128: launch_basis_n<128>(which, a, grid_x, grid_y, s); break;
     case 256: launch_basis_n<256>(which, a, grid_x, grid_y, s); break;
     case 512: launch_basis_n<512>(which, a, grid_x, grid_y, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// one workgroup per image column; N in {64, 128, 256} and r <= 8
+hipError_t launch_adj_qr(int N, const BasisArgs& a, hipStream_t s) {
+  if (a.r > 8 || !a.qpart) return hipErrorInvalidValue;
+  const dim3 g(a.nx);
+  switch (N) {
+    case 64: hipLaunchKernelGGL((k_adj_qr<64, 64>), g, dim3(512), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_adj_qr<128, 32>), g, dim3(512), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_adj_qr<256, 16>), g, dim3(512), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -92,6 +92,7 @@ struct BasisArgs {
   float scale, scale_x;
   DevState* st;
   int check_halt;
+  float2* qpart;              // k_adj_qr: the column's QR Gram partial (FP32, tri order)
 };
 
 struct PdftArgs {
@@ -355,6 +356,7 @@ hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_
 __global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* dst, long n);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s);
+hipError_t launch_adj_qr(int N, const BasisArgs& a, hipStream_t s);
 hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, hipStream_t s);
 hipError_t launch_gram_work(const int2* unit_span, int4* items, int4* line_order, int n_loc, DevState* st,
                             hipStream_t s);
