@@ -338,6 +338,7 @@ altgdmin_status altgdmin_rank_energy(altgdmin_ctx* ctx, int32_t r_cap, double* h
 altgdmin_status altgdmin_auto_rank(altgdmin_ctx* ctx, double b_percent, int32_t* h_rank, int32_t* h_rcap,
                                    void* d_aux);
 
+/* A static description of status s (one of the altgdmin_status values). */
 const char* altgdmin_status_string(altgdmin_status s);
 
 void altgdmin_destroy(altgdmin_ctx* ctx);
