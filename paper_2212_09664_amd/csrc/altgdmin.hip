@@ -201,7 +201,8 @@ PdftArgs pdft_args(altgdmin_ctx* c, int check_halt) {
 hipError_t fwd_transform(altgdmin_ctx* c, int check_halt) {
   const altgdmin_params& p = c->p;
   if (c->pdft)
-    return launch_pdft(0, p.ny, pdft_args(c, check_halt), (p.nx * p.r + 31) / 32, p.nc, c->stream);
+    return launch_pdft(0, p.ny, pdft_args(c, check_halt), (p.nx * p.r + 31) / 32,
+                       p.ny == 256 ? c->adj_parts : p.nc, c->stream);  // coil groups in the factored form
   const BasisArgs b = basis_args(c, check_halt);
   hipError_t e = launch_basis(0, p.ny, b, p.nx / c->txx, c->adj_parts, c->stream);
   if (e != hipSuccess || c->lines) return e;

@@ -383,6 +383,307 @@ __global__ __launch_bounds__(256) void k_pdft_adj(PdftArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// N = 256 factored as 16 x 16: the same transforms as two dense 16-point DFT
+// stages on the matrix cores with a twiddle between them (w_m = exp(-2 pi i / m)):
+//   forward  (y = 16 y1 + y2, ky = k1 + 16 k2)
+//     A[k1][y2] = w256^(k1 y2) sum_y1 w16^(k1 y1) V[16 y1 + y2],
+//     W[k1 + 16 k2] = sum_y2 w16^(k2 y2) A[k1][y2];
+//   adjoint  (ky = k1 + 16 k2, y = y1 + 16 y2, conjugate exponents)
+//     B[k1][y1] = w256^(-k1 y1) sum_k2 w16^(-k2 y1) K[k1 + 16 k2],
+//     T[y1 + 16 y2] = sum_k1 w16^(-k1 y2) B[k1][y1].
+// Each stage multiplies the fixed 16-point DFT matrix F = C -+ i S (the A
+// operand: [C | +-S] for real outputs against B = [Re; Im], [C | -+S] for
+// imaginary outputs against [Im; Re], its fp16 hi and lo halves in registers)
+// by 16 complex data columns (the B operand).  The data are staged in LDS as
+// fp16 hi and lo planes [comp][hl][n][kappa] (the 16 contraction values of
+// a column n contiguous: one 16-byte read per fragment) after a power-of-two
+// scale that keeps every stage input within 2^14 (inputs at most 2^10; a
+// 16-point stage grows a magnitude at most 16 times).  Products keep
+// hi*hi + hi*lo + lo*hi with FP32 accumulation.  A workgroup of 4 waves
+// takes 16 columns col = x*r + j (the data columns n of every product) and a
+// group of coils; in each stage wave w takes the batches w, w+4, w+8, w+12.
+// ---------------------------------------------------------------------------
+// the A fragments of F (sgn = +1 forward, -1 inverse): lane l holds row
+// m = l%16, contraction entries kappa = 8(l/16) + e (kappa < 16: C[m][kappa],
+// else the signed S[m][kappa - 16])
+__device__ __forceinline__ void dft16_frags(const float2* tw256, float sgn, int lane, h8& re_h, h8& re_l, h8& im_h,
+                                            h8& im_l) {
+  const int m = lane & 15, kb = 8 * (lane >> 4);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int kap = kb + e, k = kap & 15;
+    const float2 w = tw256[16 * ((m * k) & 15)];  // exp(-2 pi i m k / 16) = (C, -S)
+    const float cv = w.x, sv = -w.y;
+    const float vre = kap < 16 ? cv : sgn * sv;
+    const float vim = kap < 16 ? cv : -sgn * sv;
+    _Float16 h, l;
+    split_hl(vre, h, l);
+    re_h[e] = h;
+    re_l[e] = l;
+    split_hl(vim, h, l);
+    im_h[e] = h;
+    im_l[e] = l;
+  }
+}
+
+// plane geometry (halves): a row n holds the 16 contraction values, padded to
+// PR so that the four row groups of a wave's scattered writes fall in
+// different LDS banks; planes (Re hi, Re lo, Im hi, Im lo) follow each other
+template <int PR_>
+struct Planes {
+  static constexpr int PR = PR_, PP = 16 * PR_, PCOL = 4 * PP + 8;  // row, plane, column (padded) strides
+};
+using P1 = Planes<16>;  // staged inputs: whole rows written at once, the column stride padded
+using P2g = Planes<24>; // stage-2 inputs: scattered row writes, the row stride padded
+
+// one stage on the column whose planes start at P: D_re, D_im[v] of lane l
+// hold output row 4(l/16)+v, column l%16
+template <typename G>
+__device__ __forceinline__ void dft16_stage(const _Float16* P, int lane, const h8& re_h, const h8& re_l,
+                                            const h8& im_h, const h8& im_l, f4& d_re, f4& d_im) {
+  constexpr int PR = G::PR, PP = G::PP;
+  const int comp = lane >> 5, n = lane & 15, kb = 8 * ((lane >> 4) & 1);
+  const _Float16* pre = P + comp * 2 * PP + n * PR + kb;        // B_re = [Re; Im]
+  const _Float16* pim = P + (1 - comp) * 2 * PP + n * PR + kb;  // B_im = [Im; Re]
+  const h8 brh = *reinterpret_cast<const h8*>(pre), brl = *reinterpret_cast<const h8*>(pre + PP);
+  const h8 bih = *reinterpret_cast<const h8*>(pim), bil = *reinterpret_cast<const h8*>(pim + PP);
+  d_re = mma3(re_h, re_l, brh, brl, f4{0.f, 0.f, 0.f, 0.f});
+  d_im = mma3(im_h, im_l, bih, bil, f4{0.f, 0.f, 0.f, 0.f});
+}
+
+// four consecutive contraction values k0..k0+3 of row n into the four planes
+// (one 8-byte write per plane; k0 a multiple of 4)
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void put_hl4(_Float16* P, int n, int k0, const float2 (&z)[4]) {
+  constexpr int PR = P2g::PR, PP = P2g::PP;
+  h4 rh, rl, ih, il;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    _Float16 h, l;
+    split_hl(z[q].x, h, l);
+    rh[q] = h;
+    rl[q] = l;
+    split_hl(z[q].y, h, l);
+    ih[q] = h;
+    il[q] = l;
+  }
+  const int o = n * PR + k0;
+  *reinterpret_cast<h4*>(P + o) = rh;
+  *reinterpret_cast<h4*>(P + PP + o) = rl;
+  *reinterpret_cast<h4*>(P + 2 * PP + o) = ih;
+  *reinterpret_cast<h4*>(P + 3 * PP + o) = il;
+}
+
+// 16 contiguous values of one column (kappa = 0..15) into the four planes at row n
+__device__ __forceinline__ void put_row16(_Float16* P, int n, const float2 (&v)[16], float sig) {
+  constexpr int PR = P1::PR, PP = P1::PP;
+  h8 rh[2], rl[2], ih[2], il[2];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    _Float16 h, l;
+    split_hl(v[k].x * sig, h, l);
+    rh[k >> 3][k & 7] = h;
+    rl[k >> 3][k & 7] = l;
+    split_hl(v[k].y * sig, h, l);
+    ih[k >> 3][k & 7] = h;
+    il[k >> 3][k & 7] = l;
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    *reinterpret_cast<h8*>(P + n * PR + 8 * b) = rh[b];
+    *reinterpret_cast<h8*>(P + PP + n * PR + 8 * b) = rl[b];
+    *reinterpret_cast<h8*>(P + 2 * PP + n * PR + 8 * b) = ih[b];
+    *reinterpret_cast<h8*>(P + 3 * PP + n * PR + 8 * b) = il[b];
+  }
+}
+
+// The data of one stage: 16 sets (the batch index of the stage: y2 or k1 in
+// stage 1, k1 or y1 in stage 2), each 16 data columns n = the workgroup's
+// columns.  Stage 1 reads its sets from the staged inputs; its outputs go
+// to registers, then (after a barrier) into the stage-2 sets in the same
+// LDS buffer; stage 2 writes whole runs of the 16 columns per output row.
+constexpr int S1 = P1::PCOL;  // stage-1 set stride (halves)
+constexpr int S2 = P2g::PCOL; // stage-2 set stride: 4 sets apart land 64 bytes apart in the banks
+constexpr int PDFT16_LDS = 16 * (S1 > S2 ? S1 : S2);
+
+// forward: grid (ceil(nx r / 16), coil groups), 256 threads
+__global__ __launch_bounds__(256) void k_pdft16_fwd(PdftArgs a) {
+  constexpr int N = 256;
+  __shared__ float2 s_tw[N];
+  __shared__ int s_ro[N];  // ky -> its row u of W, -1 if not sampled
+  __shared__ float red[4];
+  __shared__ __attribute__((aligned(16))) _Float16 D[PDFT16_LDS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = a.r, ncols = a.nx * r, col0 = blockIdx.x * 16;
+  // staging: this thread's column and y2 (rows y = 16 y1 + y2 of U), requested first
+  const int cl = tid & 15, y2t = tid >> 4, col = col0 + cl;
+  const bool cok = col < ncols;
+  const int colc = cok ? col : 0, x = colc / r;
+  float2 uv[16];
+#pragma unroll
+  for (int y1 = 0; y1 < 16; ++y1) uv[y1] = a.U[(long)(16 * y1 + y2t) * ncols + colc];
+  s_tw[tid] = a.tw[tid];
+  s_ro[tid] = -1;
+  if (halted(a.st, a.check_halt)) return;
+  const int nu = a.st->n_units;
+  __syncthreads();
+  for (int u = tid; u < nu; u += 256) s_ro[a.unit_loc[u]] = u;
+  __syncthreads();
+  h8 fre_h, fre_l, fim_h, fim_l;
+  dft16_frags(s_tw, 1.f, lane, fre_h, fre_l, fim_h, fim_l);
+  const int cb = blockIdx.y * a.cgs, ce = min(a.nc, cb + a.cgs);
+  const int n = lane & 15, g4 = 4 * (lane >> 4);
+  const bool ook = col0 + n < ncols;  // this lane's output column
+  for (int c = cb; c < ce; ++c) {
+    // V = s_c o U on this thread's 16 rows: set y2, row cl
+    // (every load issued from a valid address, then masked: a load under a
+    // branch would wait alone)
+    const float2* coil = a.coils + (long)c * a.n + x;
+    float2 v[16];
+#pragma unroll
+    for (int y1 = 0; y1 < 16; ++y1) v[y1] = coil[(long)(16 * y1 + y2t) * a.nx];
+    float amax = 0.f;
+#pragma unroll
+    for (int y1 = 0; y1 < 16; ++y1) {
+      v[y1] = cok ? cmul(v[y1], uv[y1]) : make_float2(0.f, 0.f);
+      amax = fmaxf(amax, fmaxf(fabsf(v[y1].x), fabsf(v[y1].y)));
+    }
+    // its barriers also retire the previous coil's reads of D
+    const float sig = pow2_scale(block_max(amax, red)) * (1.f / 16.f);
+    put_row16(D + y2t * S1, cl, v, sig);
+    __syncthreads();
+    // stage 1 on sets y2 = 4 wave + q: rows k1 = 4(l/16)+v, then w256^(k1 y2)
+    float2 z[4][4];  // [v][q]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int y2 = 4 * wave + q;
+      f4 dre, dim;
+      dft16_stage<P1>(D + y2 * S1, lane, fre_h, fre_l, fim_h, fim_l, dre, dim);
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) z[vv][q] = cmul(make_float2(dre[vv], dim[vv]), s_tw[((g4 + vv) * y2) & 255]);
+    }
+    __syncthreads();
+    // stage-2 sets k1: row n (column), contraction y2 (this wave's four at once)
+#pragma unroll
+    for (int vv = 0; vv < 4; ++vv) put_hl4(D + (g4 + vv) * S2, n, 4 * wave, z[vv]);
+    __syncthreads();
+    // stage 2 on sets k1 = wave + 4q: rows k2 = 4(l/16)+v, ky = k1 + 16 k2
+    const float os = a.scale / sig;
+    float2* Wc = a.W + (long)c * a.ua * ncols + col0 + n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k1 = wave + 4 * q;
+      f4 dre, dim;
+      dft16_stage<P2g>(D + k1 * S2, lane, fre_h, fre_l, fim_h, fim_l, dre, dim);
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const int u = s_ro[k1 + 16 * (g4 + vv)];
+        if (u >= 0 && ook) Wc[(long)u * ncols] = make_float2(dre[vv] * os, dim[vv] * os);
+      }
+    }
+  }
+}
+
+// adjoint + coil combine: grid (ceil(nx r / 16), coil groups), 256 threads;
+// group g writes its partial gradient to G + g part_stride
+__global__ __launch_bounds__(256) void k_pdft16_adj(PdftArgs a) {
+  constexpr int N = 256;
+  __shared__ float2 s_tw[N];
+  __shared__ int s_ro[N];
+  __shared__ float red[4];
+  __shared__ __attribute__((aligned(16))) _Float16 D[PDFT16_LDS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = a.r, ncols = a.nx * r, col0 = blockIdx.x * 16;
+  const int cl = tid & 15, k1t = tid >> 4, col = col0 + cl;
+  const bool cok = col < ncols;
+  const int colc = cok ? col : 0;
+  s_tw[tid] = a.tw[tid];
+  s_ro[tid] = -1;
+  if (halted(a.st, a.check_halt)) return;
+  const int nu = a.st->n_units;
+  __syncthreads();
+  for (int u = tid; u < nu; u += 256) s_ro[a.unit_loc[u]] = u;
+  __syncthreads();
+  h8 fre_h, fre_l, fim_h, fim_l;
+  dft16_frags(s_tw, -1.f, lane, fre_h, fre_l, fim_h, fim_l);
+  const int n = lane & 15, g4 = 4 * (lane >> 4);
+  const bool ook = col0 + n < ncols;
+  const int xo = min(col0 + n, ncols - 1) / r;  // this lane's output column's image column
+  float2 acc[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int vv = 0; vv < 4; ++vv) acc[q][vv] = make_float2(0.f, 0.f);
+  const int cb = blockIdx.y * a.cgs, ce = min(a.nc, cb + a.cgs);
+  for (int c = cb; c < ce; ++c) {
+    // this thread's 16 rows ky = k1 + 16 k2 of K (zero where not sampled): set k1, row cl
+    // (loads from valid addresses, then masked)
+    const float2* Kc = a.K + (long)c * a.ua * ncols + colc;
+    float2 v[16];
+    bool ok[16];
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) {
+      const int u = s_ro[k1t + 16 * k2];
+      ok[k2] = cok && u >= 0;
+      v[k2] = Kc[(long)max(u, 0) * ncols];
+    }
+    float amax = 0.f;
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) {
+      if (!ok[k2]) v[k2] = make_float2(0.f, 0.f);
+      amax = fmaxf(amax, fmaxf(fabsf(v[k2].x), fabsf(v[k2].y)));
+    }
+    // this lane's coil values at its outputs y = y1 + 16 y2 (y1 = wave + 4q, y2 = 4(l/16)+v)
+    const float2* coil = a.coils + (long)c * a.n + xo;
+    float2 cw[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) cw[q][vv] = coil[(long)(wave + 4 * q + 16 * (g4 + vv)) * a.nx];
+    const float sig = pow2_scale(block_max(amax, red)) * (1.f / 16.f);
+    put_row16(D + k1t * S1, cl, v, sig);
+    __syncthreads();
+    // stage 1 on sets k1 = 4 wave + q: rows y1 = 4(l/16)+v, then w256^(-k1 y1)
+    float2 z[4][4];  // [v][q]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k1 = 4 * wave + q;
+      f4 dre, dim;
+      dft16_stage<P1>(D + k1 * S1, lane, fre_h, fre_l, fim_h, fim_l, dre, dim);
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const float2 w = s_tw[((g4 + vv) * k1) & 255];
+        z[vv][q] = cmul(make_float2(dre[vv], dim[vv]), make_float2(w.x, -w.y));
+      }
+    }
+    __syncthreads();
+    // stage-2 sets y1: row n (column), contraction k1 (this wave's four at once)
+#pragma unroll
+    for (int vv = 0; vv < 4; ++vv) put_hl4(D + (g4 + vv) * S2, n, 4 * wave, z[vv]);
+    __syncthreads();
+    // stage 2 on sets y1 = wave + 4q: rows y2 = 4(l/16)+v; conj(s_c) weighting
+    const float inv = 1.f / sig;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int y1 = wave + 4 * q;
+      f4 dre, dim;
+      dft16_stage<P2g>(D + y1 * S2, lane, fre_h, fre_l, fim_h, fim_l, dre, dim);
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv)
+        acc[q][vv] = cjfma(acc[q][vv], cw[q][vv], make_float2(dre[vv] * inv, dim[vv] * inv));
+    }
+  }
+  if (ook) {
+    float2* out = a.G + (long)blockIdx.y * a.part_stride + col0 + n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv)
+        out[(long)(wave + 4 * q + 16 * (g4 + vv)) * ncols] = cscale(acc[q][vv], a.scale);
+  }
+}
+
 hipError_t launch_pdft(int which, int ny, const PdftArgs& a, int grid_x, int grid_y, hipStream_t s) {
   const dim3 g(grid_x, grid_y), b(256);
 #define AG_PDFT(NN)                                                      \
@@ -390,6 +691,12 @@ hipError_t launch_pdft(int which, int ny, const PdftArgs& a, int grid_x, int gri
     if (which == 0) hipLaunchKernelGGL(k_pdft_fwd<NN>, g, b, 0, s, a);   \
     else hipLaunchKernelGGL(k_pdft_adj<NN>, g, b, 0, s, a);              \
     break;
+  if (ny == 256) {  // the factored form: 16 columns per workgroup
+    const dim3 g16((a.nx * a.r + 15) / 16, grid_y);
+    if (which == 0) hipLaunchKernelGGL(k_pdft16_fwd, g16, b, 0, s, a);
+    else hipLaunchKernelGGL(k_pdft16_adj, g16, b, 0, s, a);
+    return hipGetLastError();
+  }
   switch (ny) {
     AG_PDFT(32)
     AG_PDFT(64)
