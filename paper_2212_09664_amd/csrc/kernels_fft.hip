@@ -154,22 +154,25 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
   for (int it = 0; it < IT; ++it) acc[it] = make_float2(0.f, 0.f);
   const int cb = blockIdx.z * a.cgs, ce = min(a.nc, cb + a.cgs);
   // a coil's sampled rows and its map, loaded one coil ahead so that the
-  // loads overlap the previous coil's transform
+  // loads overlap the previous coil's transform; every load is issued from
+  // a valid (clamped) address and masked afterwards (a load under a branch
+  // would be waited for on its own)
   float2 v[IT], cw[IT];
-  int d[IT];
+  int rv[IT];  // the row table's entries (ky of each sampled row), used once the data are staged
+  // (with every row present the row table is not read: its stand-in is the
+  // coil maps, readable at any u < N, and the value is discarded)
+  const int32_t* const rtab = full ? reinterpret_cast<const int32_t*>(a.coils) : rows;
   auto fetch = [&](int c) {
     const float2* src = a.src + (long)c * a.src_c_stride + (long)img * a.src_img_stride;
     const float2* coil = a.coils + (long)c * a.n;
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
       const int g = tid + j * AG_NT;
-      d[j] = -1;
-      if (g < n_rows * TX) {
-        const int u = g / TX, col = g % TX;
-        d[j] = (full ? u : rows[u]) * TX + col;
-        v[j] = src[(long)u * a.nx + x0 + col];
-      }
-      if (g < N * TX) cw[j] = coil[(long)(g / TX) * a.nx + x0 + g % TX];
+      const int gc = g < n_rows * TX ? g : 0, u = gc / TX, col = gc % TX;
+      rv[j] = rtab[u];
+      v[j] = src[(long)u * a.nx + x0 + col];
+      const int gm = min(g, N * TX - 1);
+      cw[j] = coil[(long)(gm / TX) * a.nx + x0 + gm % TX];
     }
   };
   if (cb < ce) fetch(cb);
@@ -181,7 +184,8 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
     float2 cwc[IT];
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
-      if (d[j] >= 0) s[d[j]] = v[j];
+      const int g = tid + j * AG_NT;
+      if (g < n_rows * TX) s[(full ? g / TX : rv[j]) * TX + g % TX] = v[j];
       cwc[j] = cw[j];
     }
     __syncthreads();
