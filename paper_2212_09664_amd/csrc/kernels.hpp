@@ -67,7 +67,6 @@ struct ColAdjArgs {
   int accumulate;
   int check_halt;
   const DevState* st;
-  int n_img;                  // images in the launch (set by launch_cols)
 };
 
 hipError_t launch_rows(int N, const RowArgs& a, bool inv, hipStream_t st);

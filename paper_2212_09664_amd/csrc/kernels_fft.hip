@@ -128,39 +128,27 @@ __global__ __launch_bounds__(AG_NT) void k_cols_fwd(ColFwdArgs a) {
 // adjoint column transform with the coil combine:
 //   dst_img = scale_img * sum_c conj(s_c) o F_y^H (rows of src_{c,img}
 //             scattered onto their ky, zeros elsewhere).
-// A workgroup transforms TXC image columns of NI images together (tile
-// column col = (image i, column xc), TX = NI TXC): each coil's map tile is
-// loaded once for the NI images.  Grid (nx/TXC, ceil(n_img/NI), coil groups).
+// Grid (nx/TX, n_img).
 // ---------------------------------------------------------------------------
-template <int N, int TXC, int NI>
+template <int N, int TX>
 __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
-  constexpr int TX = TXC * NI;
   __shared__ float2 s[N * TX];
   constexpr int IT = (N * TX + AG_NT - 1) / AG_NT;
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * TXC, img0 = blockIdx.y * NI;
+  const int x0 = blockIdx.x * TX, img = blockIdx.y;
   if (halted(a.st, a.check_halt)) return;
-  // each image's sampled rows (or every row); a slot past the last image
-  // (odd n_img) has no rows, and its row table is the last image's, so that
-  // every table address stays valid
-  const bool full = !(a.m_k_rows || a.n_rows_ptr);
-  int n_rows[NI];
-  const int32_t* rows[NI];
-#pragma unroll
-  for (int i = 0; i < NI; ++i) {
-    const int img = min(img0 + i, a.n_img - 1);
-    const bool real = img0 + i < a.n_img;
-    if (a.m_k_rows) {
-      n_rows[i] = real ? a.m_k_rows[img] / a.nx : 0;
-      rows[i] = a.rows + (long)img * a.rows_img_stride;
-    } else if (a.n_rows_ptr) {
-      n_rows[i] = real ? *a.n_rows_ptr : 0;
-      rows[i] = a.rows;
-    } else {
-      n_rows[i] = real ? N : 0;
-      rows[i] = reinterpret_cast<const int32_t*>(a.coils);  // not read as a table (full)
-    }
+  int n_rows;
+  const int32_t* rows = nullptr;
+  if (a.m_k_rows) {
+    n_rows = a.m_k_rows[img] / a.nx;
+    rows = a.rows + (long)img * a.rows_img_stride;
+  } else if (a.n_rows_ptr) {
+    n_rows = *a.n_rows_ptr;
+    rows = a.rows;
+  } else {
+    n_rows = N;
   }
+  const bool full = (rows == nullptr);
   float2 acc[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) acc[it] = make_float2(0.f, 0.f);
@@ -168,20 +156,23 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
   // a coil's sampled rows and its map, loaded one coil ahead so that the
   // loads overlap the previous coil's transform; every load is issued from
   // a valid (clamped) address and masked afterwards (a load under a branch
-  // would be waited for on its own).  With every row present the row table's
-  // stand-in is the coil maps, readable at any u < N (the value is not used).
+  // would be waited for on its own)
   float2 v[IT], cw[IT];
-  int rv[IT];
+  int rv[IT];  // the row table's entries (ky of each sampled row), used once the data are staged
+  // (with every row present the row table is not read: its stand-in is the
+  // coil maps, readable at any u < N, and the value is discarded)
+  const int32_t* const rtab = full ? reinterpret_cast<const int32_t*>(a.coils) : rows;
   auto fetch = [&](int c) {
+    const float2* src = a.src + (long)c * a.src_c_stride + (long)img * a.src_img_stride;
     const float2* coil = a.coils + (long)c * a.n;
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
-      const int g = min(tid + j * AG_NT, N * TX - 1), u = g / TX, col = g % TX, ii = col / TXC, xc = col % TXC;
-      const int img = min(img0 + ii, a.n_img - 1);
-      const int uc = u < n_rows[ii] ? u : 0;
-      rv[j] = rows[ii][uc];
-      v[j] = a.src[(long)c * a.src_c_stride + (long)img * a.src_img_stride + (long)uc * a.nx + x0 + xc];
-      cw[j] = coil[(long)u * a.nx + x0 + xc];
+      const int g = tid + j * AG_NT;
+      const int gc = g < n_rows * TX ? g : 0, u = gc / TX, col = gc % TX;
+      rv[j] = rtab[u];
+      v[j] = src[(long)u * a.nx + x0 + col];
+      const int gm = min(g, N * TX - 1);
+      cw[j] = coil[(long)(gm / TX) * a.nx + x0 + gm % TX];
     }
   };
   if (cb < ce) fetch(cb);
@@ -193,8 +184,8 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
     float2 cwc[IT];
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
-      const int g = tid + j * AG_NT, u = g / TX, col = g % TX, ii = col / TXC;
-      if (g < N * TX && u < n_rows[ii]) s[(full ? u : rv[j]) * TX + col] = v[j];
+      const int g = tid + j * AG_NT;
+      if (g < n_rows * TX) s[(full ? g / TX : rv[j]) * TX + g % TX] = v[j];
       cwc[j] = cw[j];
     }
     __syncthreads();
@@ -207,19 +198,18 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
     }
     __syncthreads();
   }
+  float sc = a.scale;
+  if (a.m_k_scale) sc *= (float)(1.0 / sqrt((double)a.m_k_scale[img] * a.st->mbar));
+  float2* dst = a.dst + (long)img * a.dst_img_stride + (long)blockIdx.z * a.dst_part_stride;
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int g = tid + it * AG_NT;
     if (g >= N * TX) break;
-    const int y = g / TX, col = g % TX, ii = col / TXC, xc = col % TXC, img = img0 + ii;
-    if (img >= a.n_img) continue;
-    float sc = a.scale;
-    if (a.m_k_scale) sc *= (float)(1.0 / sqrt((double)a.m_k_scale[img] * a.st->mbar));
-    float2* dst = a.dst + (long)img * a.dst_img_stride + (long)blockIdx.z * a.dst_part_stride;
-    const long p = (long)y * a.nx + x0 + xc;
-    float2 vv = cscale(acc[it], sc);
-    if (a.accumulate) vv = cadd(dst[p], vv);
-    dst[p] = vv;
+    const int y = g / TX, col = g % TX;
+    const long p = (long)y * a.nx + x0 + col;
+    float2 v = cscale(acc[it], sc);
+    if (a.accumulate) v = cadd(dst[p], v);
+    dst[p] = v;
   }
 }
 
@@ -308,20 +298,10 @@ static hipError_t launch_cols_tx(const ColFwdArgs* f, const ColAdjArgs* d, int n
     hipLaunchKernelGGL((k_cols_fwd<N, TX>), grid, dim3(AG_NT), 0, st, *f);
   } else {
     const int cgs = d->cgs > 0 ? d->cgs : d->nc;
+    dim3 grid((unsigned)(d->nx / TX), (unsigned)n_img, (unsigned)((d->nc + cgs - 1) / cgs));
     ColAdjArgs dd = *d;
     dd.cgs = cgs;
-    dd.n_img = n_img;
-    // two images per workgroup (each coil map tile read once for both) while
-    // the doubled tile keeps 16 points per thread
-    if constexpr (N * TX <= 2048) {
-      if (n_img >= 2) {
-        dim3 grid((unsigned)(d->nx / TX), (unsigned)((n_img + 1) / 2), (unsigned)((d->nc + cgs - 1) / cgs));
-        hipLaunchKernelGGL((k_cols_adj<N, TX, 2>), grid, dim3(AG_NT), 0, st, dd);
-        return hipGetLastError();
-      }
-    }
-    dim3 grid((unsigned)(d->nx / TX), (unsigned)n_img, (unsigned)((d->nc + cgs - 1) / cgs));
-    hipLaunchKernelGGL((k_cols_adj<N, TX, 1>), grid, dim3(AG_NT), 0, st, dd);
+    hipLaunchKernelGGL((k_cols_adj<N, TX>), grid, dim3(AG_NT), 0, st, dd);
   }
   return hipGetLastError();
 }
