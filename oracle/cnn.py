@@ -19,11 +19,30 @@ Wirtinger gradient is dL/d conj(M) = -(I - P_M) U_tgt U_tgt^H M G^-1, and the
 gradient with respect to the real output channels is (2 Re, 2 Im) of it.
 
 Convolutions are written as explicit im2col matrices (rows ordered
-(input channel, tap row, tap column)) multiplied by the weight matrix.
+(input channel, tap row, tap column)) multiplied by the weight matrix.  With
+operand rounding (rnd = bf16_round) every convolution's two operands (data
+and weights in the forward pass and the input gradient; output gradient and
+data in the weight gradient) are first rounded to bfloat16, the arithmetic
+of a BF16 matrix-core convolution with a wide accumulator; the products and
+sums are then exact up to FP64 rounding.  Biases are not rounded.
 """
 from __future__ import annotations
 
 import numpy as np
+
+
+def bf16_round(x) -> np.ndarray:
+    """x rounded to the nearest bfloat16 (8 significand bits, ties to even),
+    through binary32 (the bfloat16 format is the top half of a binary32
+    word), returned as float64.  Finite inputs only."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    b = f.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _ident(x):
+    return x
 
 
 def layer_channels(cin: int, width: int, cout: int, layers: int = 4):
@@ -83,31 +102,31 @@ def col2im(cols: np.ndarray, C: int, H: int, Wd: int) -> np.ndarray:
     return Xp[:, 1:-1, 1:-1]
 
 
-def conv_forward(X, W, b):
+def conv_forward(X, W, b, rnd=_ident):
     C, H, Wd = X.shape
     co = W.shape[0]
-    return (W.reshape(co, -1) @ im2col(X) + b[:, None]).reshape(co, H, Wd)
+    return (rnd(W).reshape(co, -1) @ im2col(rnd(X)) + b[:, None]).reshape(co, H, Wd)
 
 
-def conv_backward(X, W, dY):
+def conv_backward(X, W, dY, rnd=_ident):
     """Gradients of sum(dY * conv(X, W, b)) with respect to X, W and b."""
     C, H, Wd = X.shape
     co = W.shape[0]
-    d2 = dY.reshape(co, H * Wd)
-    cols = im2col(X)
+    d2 = rnd(dY).reshape(co, H * Wd)
+    cols = im2col(rnd(X))
     dW = (d2 @ cols.T).reshape(W.shape)
     db = d2.sum(axis=1)
-    dX = col2im(W.reshape(co, -1).T @ d2, C, H, Wd)
+    dX = col2im(rnd(W).reshape(co, -1).T @ d2, C, H, Wd)
     return dX, dW, db
 
 
-def forward(params, X, width, cout, layers: int = 4, keep: bool = False):
+def forward(params, X, width, cout, layers: int = 4, keep: bool = False, rnd=_ident):
     """Network output (cout, H, W); with keep, also the layer inputs."""
     wb = unpack(params, X.shape[0], width, cout, layers)
     acts = [X]
     a = X
     for i, (W, b) in enumerate(wb):
-        z = conv_forward(a, W, b)
+        z = conv_forward(a, W, b, rnd)
         a = np.maximum(z, 0.0) if i < layers - 1 else z
         acts.append(a)
     return (a, acts) if keep else a
@@ -141,10 +160,10 @@ def projection_loss(M: np.ndarray, Ut: np.ndarray):
     return L, dMbar
 
 
-def loss_and_grad(params, X, Ut, width, r, layers: int = 4):
+def loss_and_grad(params, X, Ut, width, r, layers: int = 4, rnd=_ident):
     """Loss of one sequence and its gradient with respect to every parameter."""
     cin, H, Wd = X.shape
-    Y, acts = forward(params, X, width, 2 * r, layers, keep=True)
+    Y, acts = forward(params, X, width, 2 * r, layers, keep=True, rnd=rnd)
     L, dMbar = projection_loss(output_to_M(Y), Ut)
     wb = unpack(params, cin, width, 2 * r, layers)
     d = M_grad_to_output(dMbar, H, Wd)
@@ -153,15 +172,15 @@ def loss_and_grad(params, X, Ut, width, r, layers: int = 4):
         W, b = wb[i]
         if i < layers - 1:
             d = d * (acts[i + 1] > 0)  # ReLU of layer i
-        dX, dW, db = conv_backward(acts[i], W, d)
+        dX, dW, db = conv_backward(acts[i], W, d, rnd)
         grads[i] = (dW, db)
         d = dX
     return L, pack(grads)
 
 
-def batch_loss_and_grad(params, Xs, Uts, width, r, layers: int = 4):
+def batch_loss_and_grad(params, Xs, Uts, width, r, layers: int = 4, rnd=_ident):
     """Mean loss and mean gradient over a batch of sequences."""
-    Ls, gs = zip(*[loss_and_grad(params, X, U, width, r, layers) for X, U in zip(Xs, Uts)])
+    Ls, gs = zip(*[loss_and_grad(params, X, U, width, r, layers, rnd) for X, U in zip(Xs, Uts)])
     return float(np.mean(Ls)), np.mean(gs, axis=0)
 
 

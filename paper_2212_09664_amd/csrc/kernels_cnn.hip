@@ -3,8 +3,10 @@
 // 2j + 1 = Im M[:, j]), its projection loss L = r - tr(G^-1 C C^H)
 // (G = M^H M, C = M^H U_tgt), the backward pass and Adam.
 //
-// Convolutions are implicit GEMMs on the matrix cores (v_mfma_f32_16x16x4f32,
-// FP32 operands and accumulation):
+// Convolutions are implicit GEMMs on the matrix cores with BF16 operands and
+// FP32 accumulation (v_mfma_f32_16x16x32_bf16; activations, gradients and
+// the packed weights stay FP32 in memory and are rounded to BF16 as they are
+// staged in LDS):
 //   forward      D[co][px] = sum_kappa Wp[kappa][co] X'[kappa][px],
 //                kappa = tap*cin + ci (tap = 3 ty + tx), plus a bias row;
 //   input grad   the same kernel on dY with the flipped, transposed weights,
@@ -12,20 +14,23 @@
 //   weight grad  D[co][kappa] = sum_px dY[co][px] X'[kappa][px], per band of
 //                image rows, then a deterministic reduction.
 // X'[kappa][px] is the input channel ci shifted by the tap (zero outside the
-// image).  Activations are [b][c][H][W] FP32.  MFMA lane layout: lane l holds
-// A[l%16][l/16] and B[l/16][l%16]; result register v holds D[4(l/16)+v][l%16].
+// image).  Activations are [b][c][H][W] FP32.  MFMA lane layout (16x16x32):
+// lane l holds A[l%16][8(l/16)+e] and B[8(l/16)+e][l%16], e = 0..7; result
+// register v holds D[4(l/16)+v][l%16].
 #include "kernels_core.hpp"
 
 namespace ag {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f4v mfma_bf16(const bf8& a, const bf8& b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-#define CV_T 8    // output tile is CV_T x CV_T pixels
-#define CV_CH 32  // input channels staged per chunk
+#define CV_T 8     // output tile is CV_T x CV_T pixels
+#define CV_CH 32   // input channels staged per chunk (one MFMA contraction)
+#define CV_CHP 40  // BF16 pitch of a staged pixel's / weight row's channels (80 bytes: 16-byte aligned)
 
 // ---------------------------------------------------------------------------
 // pack one layer's weights: forward [kappa][32] (kappa = tap*cin + ci, bias
@@ -64,11 +69,14 @@ __global__ void k_cnn_pack(const float* __restrict__ Wl, int cin, int cout, int 
 // ---------------------------------------------------------------------------
 // convolution as implicit GEMM: grid (tiles of CV_T x CV_T, batch), 256
 // threads; wave w computes tile rows 2w, 2w + 1 (16 pixels) for all output
-// channels (<= 32)
+// channels (<= 32).  Per chunk of 32 input channels the tile's inputs (with
+// the halo) are staged as BF16 [pixel][channel] and the chunk's weights as
+// BF16 [tap][co][channel]: one 16x16x32 product per tap and output tile.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
-  __shared__ float xs[CV_CH][CV_T + 2][CV_T + 3];
-  __shared__ float wsm[9][CV_CH][32];
+  constexpr int NPX = (CV_T + 2) * (CV_T + 2);
+  __shared__ __attribute__((aligned(16))) __bf16 xs[NPX * CV_CHP];
+  __shared__ __attribute__((aligned(16))) __bf16 wsm[9 * 32 * CV_CHP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles_x = a.W / CV_T;
   const int ty0 = (blockIdx.x / tiles_x) * CV_T, tx0 = (blockIdx.x % tiles_x) * CV_T;
@@ -80,64 +88,51 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
   const int nct = (a.cout + 15) >> 4;
   f4v acc[2] = {f4v{0.f, 0.f, 0.f, 0.f}, f4v{0.f, 0.f, 0.f, 0.f}};
   for (int c0 = 0; c0 < a.cin; c0 += CV_CH) {
-    // channels staged up to a multiple of 16 (the rest zero), so that the
-    // matrix-core loop below has no predicate and both output tiles are
-    // always computed (a second tile past cout is never stored): a branch
-    // in the loop would move the accumulators out of the matrix registers
-    // around every instruction
-    const int nch = min(CV_CH, a.cin - c0), nch4 = (nch + 15) & ~15;  // CV_CH is a multiple of 16
+    // channels past cin stage as zeros, so that the matrix-core loop has no
+    // predicate (a second output tile past cout is computed and not stored);
+    // every load comes from a valid address and is masked afterwards
+    const int nch = min(CV_CH, a.cin - c0);
     __syncthreads();
-    for (int e = tid; e < nch4 * (CV_T + 2) * (CV_T + 2); e += 256) {
-      const int ci = e / ((CV_T + 2) * (CV_T + 2)), rem = e % ((CV_T + 2) * (CV_T + 2));
-      const int rr = rem / (CV_T + 2), cc = rem % (CV_T + 2);
+    for (int e = tid; e < NPX * 4; e += 256) {  // (pixel, channel octet)
+      const int pix = e % NPX, j = e / NPX;
+      const int rr = pix / (CV_T + 2), cc = pix % (CV_T + 2);
       const int gy = ty0 + rr - 1, gx = tx0 + cc - 1;
-      float v = 0.f;
-      if (ci < nch && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = Xb[(long)(c0 + ci) * plane + (long)gy * a.W + gx];
-      xs[ci][rr][cc] = v;
-    }
-    // weights per tap as float4 rows (a tap's nch x 32 block is contiguous)
+      const bool in = gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+      const long off = in ? (long)gy * a.W + gx : 0;
+      float f[8];
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const float4* wsrc = reinterpret_cast<const float4*>(a.Wp + ((long)tap * a.cin + c0) * 32);
-      for (int e = tid; e < nch4 * 8; e += 256) {
-        const float4 w4 = (e < nch * 8) ? wsrc[e] : make_float4(0.f, 0.f, 0.f, 0.f);
-        float* d = &wsm[tap][e >> 3][4 * (e & 7)];
-        d[0] = w4.x;
-        d[1] = w4.y;
-        d[2] = w4.z;
-        d[3] = w4.w;
-      }
+      for (int q = 0; q < 8; ++q) f[q] = Xb[(long)(c0 + min(8 * j + q, nch - 1)) * plane + off];
+      bf8 v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (__bf16)((in && 8 * j + q < nch) ? f[q] : 0.f);
+      *reinterpret_cast<bf8*>(&xs[pix * CV_CHP + 8 * j]) = v;
+    }
+    for (int e = tid; e < 9 * 32 * 4; e += 256) {  // (tap, channel octet, co) from the rows [tap*cin + ci][32]
+      const int co = e & 31, j = (e >> 5) & 3, tap = e >> 7;
+      const float* wr = a.Wp + ((long)tap * a.cin + c0) * 32 + co;
+      float f[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) f[q] = wr[(long)min(8 * j + q, nch - 1) * 32];
+      bf8 w;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) w[q] = (__bf16)(8 * j + q < nch ? f[q] : 0.f);
+      *reinterpret_cast<bf8*>(&wsm[(tap * 32 + co) * CV_CHP + 8 * j]) = w;
     }
     __syncthreads();
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap % 3;
-      for (int ci0 = 0; ci0 < nch4; ci0 += 16) {  // four steps of 4 channels: their LDS reads first
-        float bv[4], w0[4], w1[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int ci = ci0 + 4 * u + kq;
-          bv[u] = xs[ci][py + dy][px + dx];
-          w0[u] = wsm[tap][ci][pl];
-          w1[u] = wsm[tap][ci][16 + pl];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          acc[0] = mfma4(w0[u], bv[u], acc[0]);
-          acc[1] = mfma4(w1[u], bv[u], acc[1]);
-        }
-      }
+      const bf8 bv = *reinterpret_cast<const bf8*>(&xs[((py + dy) * (CV_T + 2) + px + dx) * CV_CHP + 8 * kq]);
+      const bf8 w0 = *reinterpret_cast<const bf8*>(&wsm[(tap * 32 + pl) * CV_CHP + 8 * kq]);
+      const bf8 w1 = *reinterpret_cast<const bf8*>(&wsm[(tap * 32 + 16 + pl) * CV_CHP + 8 * kq]);
+      acc[0] = mfma_bf16(w0, bv, acc[0]);
+      acc[1] = mfma_bf16(w1, bv, acc[1]);
     }
-  }
-  if (a.bias) {  // the bias row: input 1 on k = 0
-    const long kb = 9L * a.cin * 32;
-    const float bv = (kq == 0) ? 1.f : 0.f;
-    acc[0] = mfma4(kq == 0 ? a.Wp[kb + pl] : 0.f, bv, acc[0]);
-    if (nct > 1) acc[1] = mfma4(kq == 0 ? a.Wp[kb + 16 + pl] : 0.f, bv, acc[1]);
   }
   const int oy = ty0 + py, ox = tx0 + px;
   float* Yb = a.Y + (long)b * a.cout * plane;
   const float* Mb = a.mask ? a.mask + (long)b * a.cout * plane : nullptr;
+  const long kb = 9L * a.cin * 32;  // the bias row of the packed weights (FP32, added exactly)
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     if (t < nct) {
@@ -146,6 +141,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
         const int co = 16 * t + 4 * kq + v;
         if (co < a.cout) {
           float y = acc[t][v];
+          if (a.bias) y += a.Wp[kb + co];
           if (a.relu) y = fmaxf(y, 0.f);
           const long o = (long)co * plane + (long)oy * a.W + ox;
           if (Mb && !(Mb[o] > 0.f)) y = 0.f;
@@ -159,16 +155,18 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
 // ---------------------------------------------------------------------------
 // weight gradient: grid (row bands, batch, kappa groups), 256 threads.  A
 // band is rows_per_band image rows (whole tiles); the workgroup stages every
-// input channel of a tile (with its halo) and covers WG_KT kappa tiles of 16
-// (8 per wave), writing its partial dWp[kappa][co] to
+// input channel of a tile (with its halo) and the tile's output gradient as
+// BF16 and covers WG_KT kappa tiles of 16 (8 per wave), one 16x16x32 product
+// per 32 pixels, writing its partial dWp[kappa][co] to
 // part + ((b * bands + band) * kp + kappa) * 32 + co.
 // ---------------------------------------------------------------------------
 #define WG_KTW 8            // kappa tiles per wave
 #define WG_KT (4 * WG_KTW)  // kappa tiles per workgroup
 #define XS_STRIDE ((CV_T + 2) * (CV_T + 3))
+#define DS_PITCH (CV_T * CV_T + 8)  // BF16 pitch of a channel's 64 pixels (16-byte aligned rows)
 __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
-  extern __shared__ float xs[];  // [cin][CV_T + 2][CV_T + 3]
-  __shared__ float ds[32][CV_T * CV_T + 1];
+  extern __shared__ __bf16 xsb[];  // [cin][CV_T + 2][CV_T + 3]
+  __shared__ __attribute__((aligned(16))) __bf16 ds[32 * DS_PITCH];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int pl = lane & 15, kq = lane >> 4;
   const int b = blockIdx.y;
@@ -197,6 +195,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
       kci[m] = -2;  // bias: input 1
     }
   }
+  const __bf16 one = (__bf16)1.f, zero = (__bf16)0.f;
   const int row0 = blockIdx.x * a.rows_per_band;
   for (int tr = row0; tr < row0 + a.rows_per_band; tr += CV_T) {
     for (int tc = 0; tc < tiles_x; ++tc) {
@@ -204,27 +203,39 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
       __syncthreads();
       for (int e = tid; e < 32 * CV_T * CV_T; e += 256) {
         const int co = e / (CV_T * CV_T), p = e % (CV_T * CV_T);
-        ds[co][p] = (co < a.cout) ? Db[(long)co * plane + (long)(ty0 + p / CV_T) * a.W + tx0 + p % CV_T] : 0.f;
+        const float d = Db[(long)min(co, a.cout - 1) * plane + (long)(ty0 + p / CV_T) * a.W + tx0 + p % CV_T];
+        ds[co * DS_PITCH + p] = (__bf16)(co < a.cout ? d : 0.f);
       }
       for (int e = tid; e < a.cin * (CV_T + 2) * (CV_T + 2); e += 256) {
         const int ci = e / ((CV_T + 2) * (CV_T + 2)), rem = e % ((CV_T + 2) * (CV_T + 2));
         const int rr = rem / (CV_T + 2), cc = rem % (CV_T + 2);
         const int gy = ty0 + rr - 1, gx = tx0 + cc - 1;
-        float v = 0.f;
-        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = Xb[(long)ci * plane + (long)gy * a.W + gx];
-        xs[ci * XS_STRIDE + rr * (CV_T + 3) + cc] = v;
+        const bool in = gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+        const float v = Xb[(long)ci * plane + (in ? (long)gy * a.W + gx : 0)];
+        xsb[ci * XS_STRIDE + rr * (CV_T + 3) + cc] = (__bf16)(in ? v : 0.f);
       }
       __syncthreads();
-      for (int k0 = 0; k0 < CV_T * CV_T; k0 += 4) {
-        const int p = k0 + kq, pbase = (p / CV_T) * (CV_T + 3) + p % CV_T;
-        const float a0 = ds[pl][p], a1 = ds[16 + pl][p];
+#pragma unroll
+      for (int k0 = 0; k0 < CV_T * CV_T; k0 += 32) {
+        // pixels k0 + 8 kq + e: tile row (k0 / 8 + kq), columns e = 0..7
+        const int prow = k0 / CV_T + kq;
+        const bf8 a0 = *reinterpret_cast<const bf8*>(&ds[pl * DS_PITCH + k0 + 8 * kq]);
+        const bf8 a1 = *reinterpret_cast<const bf8*>(&ds[(16 + pl) * DS_PITCH + k0 + 8 * kq]);
 #pragma unroll
         for (int m = 0; m < WG_KTW; ++m) {
           if (kt0 + wave + 4 * m < nkt) {
             const int ci = kci[m];
-            const float bv = ci >= 0 ? xs[ci * XS_STRIDE + pbase + koff[m]] : (ci == -2 ? 1.f : 0.f);
-            acc[m][0] = mfma4(a0, bv, acc[m][0]);
-            if (nct > 1) acc[m][1] = mfma4(a1, bv, acc[m][1]);
+            bf8 bv;
+            if (ci >= 0) {
+              const __bf16* xr = xsb + ci * XS_STRIDE + prow * (CV_T + 3) + koff[m];
+#pragma unroll
+              for (int q = 0; q < 8; ++q) bv[q] = xr[q];
+            } else {
+#pragma unroll
+              for (int q = 0; q < 8; ++q) bv[q] = (ci == -2) ? one : zero;
+            }
+            acc[m][0] = mfma_bf16(a0, bv, acc[m][0]);
+            if (nct > 1) acc[m][1] = mfma_bf16(a1, bv, acc[m][1]);
           }
         }
       }
@@ -478,7 +489,7 @@ hipError_t launch_conv(const ConvArgs& a, int batch, hipStream_t s) {
 hipError_t launch_wgrad(const WgradArgs& a, int bands, int batch, int nparam_layer, float* g, float scale,
                         hipStream_t s) {
   const int nkt = (9 * a.cin + 1 + 15) / 16;
-  const size_t lds = sizeof(float) * (size_t)a.cin * XS_STRIDE;
+  const size_t lds = sizeof(__bf16) * (size_t)a.cin * XS_STRIDE;
   if (lds > 48 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_conv_wgrad, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);

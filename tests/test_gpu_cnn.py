@@ -38,6 +38,18 @@ def _data(nx, ny, q, r, width, batch, seed):
 
 @pytest.mark.parametrize("cfg", CASES, ids=[f"{c[0]}x{c[1]}_q{c[2]}_w{c[4]}" for c in CASES])
 def test_forward_loss_and_gradients_match_oracle(cfg):
+    """The convolutions run on BF16 matrix-core operands with FP32
+    accumulation.  The reference is the oracle with the same operand rounding
+    (oracle.cnn.bf16_round on both operands of every convolution); what
+    remains is FP32 accumulation and the operands that round to the other
+    bfloat16 neighbour because their FP32 activation differs from the FP64
+    one in the last bits.  Such flips can show far above the FP32 level (a
+    projected loss gradient can be a strongly cancelling sum), so each bound
+    is five times the rounding oracle's own change under a 1e-6 relative
+    perturbation of the input, and at least 1e-4 (output) or 5e-4
+    (gradients, per layer and in total).  The distance to the plain FP64
+    oracle, i.e. the effect of the BF16 operands themselves, is logged and
+    only sanity-bounded (3e-2 output, 0.2 gradient)."""
     nx, ny, q, r, width, batch = cfg
     log(f"cnn {cfg}")
     import paper_2212_09664_amd as ag
@@ -52,23 +64,33 @@ def test_forward_loss_and_gradients_match_oracle(cfg):
     loss, grads = net.loss_backward(pg, xg, ug)
     torch.cuda.synchronize()
     X64, p64, Ut64 = X.astype(np.float64), p.astype(np.float64), Ut.astype(np.complex128)
+    Xp = X64 * (1.0 + 1e-6 * np.random.default_rng(2).standard_normal(X64.shape))
     for b in range(batch):
-        Mref = C.output_to_M(C.forward(p64, X64[b], width, 2 * r))
-        e = rel(Mg[b].T.astype(np.complex128), Mref)
-        log(f"  M[{b}] rel {e:.2e}")
-        assert e < 1e-5
-    Lref, gref = C.batch_loss_and_grad(p64, list(X64), list(Ut64), width, r)
+        Mb16 = C.output_to_M(C.forward(p64, X64[b], width, 2 * r, rnd=C.bf16_round))
+        Mpert = C.output_to_M(C.forward(p64, Xp[b], width, 2 * r, rnd=C.bf16_round))
+        M64 = C.output_to_M(C.forward(p64, X64[b], width, 2 * r))
+        Mgb = Mg[b].T.astype(np.complex128)
+        e, e64, sm = rel(Mgb, Mb16), rel(Mgb, M64), rel(Mpert, Mb16)
+        log(f"  M[{b}] rel {e:.2e} (BF16-operand oracle, flip sensitivity {sm:.2e}), {e64:.2e} (FP64 oracle)")
+        assert e <= max(1e-4, 5 * sm) and e64 < 3e-2
+    Lref, gref = C.batch_loss_and_grad(p64, list(X64), list(Ut64), width, r, rnd=C.bf16_round)
+    L64, g64 = C.batch_loss_and_grad(p64, list(X64), list(Ut64), width, r)
+    _, gpert = C.batch_loss_and_grad(p64, list(Xp), list(Ut64), width, r, rnd=C.bf16_round)
     gl = float(loss.item())
-    eg = rel(grads.cpu().numpy().astype(np.float64), gref)
-    log(f"  loss {gl:.8f} vs {Lref:.8f}; grad rel {eg:.2e}")
-    assert abs(gl - Lref) <= 1e-5 * max(1.0, abs(Lref))
-    assert eg < 1e-4
+    gg = grads.cpu().numpy().astype(np.float64)
+    eg, eg64, sens = rel(gg, gref), rel(gg, g64), rel(gpert, gref)
+    log(f"  loss {gl:.8f} vs {Lref:.8f} (FP64 oracle {L64:.8f}); grad rel {eg:.2e} "
+        f"(flip sensitivity {sens:.2e}), FP64 oracle {eg64:.2e}")
+    assert abs(gl - Lref) <= 1e-4 * max(1.0, abs(Lref))
+    assert eg <= max(5e-4, 5 * sens) and eg64 < 0.2
     # per layer, so that a wrong small layer cannot hide behind a big one
     off = 0
     for ci, co in C.layer_channels(2 * q, width, 2 * r):
         k = co * ci * 9 + co
-        el = rel(grads.cpu().numpy()[off:off + k].astype(np.float64), gref[off:off + k])
-        assert el < 1e-4, (ci, co, el)
+        el = rel(gg[off:off + k], gref[off:off + k])
+        sl = rel(gpert[off:off + k], gref[off:off + k])
+        log(f"    layer {ci}->{co}: rel {el:.2e} (flip sensitivity {sl:.2e})")
+        assert el <= max(5e-4, 5 * sl), (ci, co, el, sl)
         off += k
 
 

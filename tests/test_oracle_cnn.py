@@ -187,3 +187,35 @@ def test_planted_missing_factor_two_fails_finite_differences():
     fd = (L_of(Yr + eps * D) - L_of(Yr - eps * D)) / (2 * eps)
     assert np.isclose(fd, np.sum(C.M_grad_to_output(G, 4, 5).reshape(2 * r, n) * D), rtol=1e-6)
     assert not np.isclose(fd, np.sum(Y.reshape(2 * r, n) * D), rtol=1e-2)
+
+
+def test_bf16_round_hand_values_and_bounds():
+    """bfloat16 keeps 8 significand bits: at 1 the spacing is 2^-7, ties go to
+    the even neighbour; every result has a zero low half in binary32, is a
+    fixed point, and lies within half a spacing (2^-9 relative) of x."""
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -9, 1 + 2.0 ** -7 + 2.0 ** -8, -2.5, np.pi, 0.0])
+    want = np.array([1.0, 1.0, 1 + 2.0 ** -7, 1 + 2.0 ** -6, -2.5, 3.140625, 0.0])
+    assert np.array_equal(C.bf16_round(x), want)
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(10000) * 10.0 ** rng.integers(-20, 20, 10000)
+    z = C.bf16_round(y)
+    assert np.all((z.astype(np.float32).view(np.uint32) & 0xFFFF) == 0)
+    assert np.array_equal(C.bf16_round(z), z)
+    assert np.all(np.abs(z - y) <= 2.0 ** -8 * np.abs(y))
+
+
+def test_rounded_convolution_is_the_convolution_of_rounded_operands():
+    """With operand rounding the forward, the input gradient and the weight
+    gradient are the plain ones evaluated on rounded operands (bias exact)."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((3, 8, 8))
+    W = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    dY = rng.standard_normal((4, 8, 8))
+    R = C.bf16_round
+    assert np.array_equal(C.conv_forward(X, W, b, rnd=R), C.conv_forward(R(X), R(W), b))
+    got = C.conv_backward(X, W, dY, rnd=R)
+    ref = C.conv_backward(R(X), R(W), R(dY))
+    for g, h in zip(got, ref):
+        assert np.array_equal(g, h)
+    assert not np.allclose(C.conv_forward(X, W, b, rnd=R), C.conv_forward(X, W, b), rtol=1e-6)
