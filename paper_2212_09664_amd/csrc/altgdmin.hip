@@ -734,7 +734,7 @@ altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** ou
     c->adj_cgs = (p.nc + parts - 1) / parts;
     c->adj_parts = (p.nc + c->adj_cgs - 1) / c->adj_cgs;
   }
-  c->adj_qr = !c->fp64 && p.r <= 8 && (p.ny == 64 || p.ny == 128 || p.ny == 256);
+  c->adj_qr = !c->fp64 && (p.ny == 64 || p.ny == 128 || p.ny == 256);
   c->grad_parts = c->adj_qr ? 1 : c->adj_parts;
   c->qr_nblk = std::max(1, std::min(256, c->n / 256));
   c->qr_rows = ((long)c->n + c->qr_nblk - 1) / c->qr_nblk;

@@ -183,7 +183,7 @@ __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
 
 // ---------------------------------------------------------------------------
 // adjoint + coil combine over every coil + the QR step's Gram partial, one
-// image column x per workgroup (r <= 8, one block of the QR Gram per column):
+// image column x per workgroup (r <= 16, one block of the QR Gram per column):
 // grid nx (consecutive columns on one XCD, which then share the cache lines
 // of K, G and U), 512 threads in two groups of 256.  A transform tile holds
 // ncp = CT / r coils' r columns of K(:, x, :); the two groups transform
@@ -195,20 +195,29 @@ __global__ __launch_bounds__(AG_NT) void k_basis_adj(BasisArgs a) {
 // order over the 2r columns [U G], FP32) goes to qpart[blockIdx.x], the
 // block partial that the QR step sums.
 // ---------------------------------------------------------------------------
-template <int N, int CT>
+template <int N, int CT, int TRM>
 __global__ __launch_bounds__(512) void k_adj_qr(BasisArgs a) {
   using GM = FftGeom<N, CT, AG_NT>;
   constexpr int IT0 = GM::IT0, R0 = GM::R0, ITL = GM::ITL, RL = GM::RL;
-  constexpr int TRM = 2, NTL = 3;  // 2r <= 16 complex columns: a 32 x 32 real Gram, 3 upper tiles
-  constexpr int LDX = 48;          // row pitch of the embedding: a step's 4 rows in disjoint bank quarters
-  constexpr int UE = (N * 8 + 511) / 512;  // U entries per thread (r <= 8)
-  __shared__ float2 s[2][N * CT];
-  __shared__ float X[N * LDX];
+  // the real embedding of [U G] has 4r <= 16 TRM columns: TRM row tiles, NTL upper tiles
+  constexpr int NTL = TRM * (TRM + 1) / 2, EC = 16 * TRM;
+  // row pitch of the embedding: a step's 4 rows in disjoint bank quarters
+  constexpr int LDX = (EC % 64 == 0 || EC % 64 == 32) ? EC + 16 : EC;
+  constexpr int UE = (N * 4 * TRM + 511) / 512;  // U entries per thread (r <= 4 TRM)
+  constexpr int CMAX = 3072;  // coil values of the column staged in LDS when nc N fits
+  // one LDS block: the two transform tiles, then the embedding X (the staged
+  // coil values share its space: they are done with before X is formed);
+  // after the matrix-core loop both serve as the scratch of the reduction
+  constexpr int S_BYTES = 2 * N * CT * 8;
+  constexpr int XS_BYTES = (N * LDX * 4 > CMAX * 8) ? N * LDX * 4 : CMAX * 8;
+  static_assert(8 * NTL * 256 * 4 <= S_BYTES + XS_BYTES, "reduction scratch");
+  __shared__ __attribute__((aligned(16))) char lds_blk[S_BYTES + XS_BYTES];
+  float2 (*s)[N * CT] = reinterpret_cast<float2 (*)[N * CT]>(lds_blk);
+  float* const X = reinterpret_cast<float*>(lds_blk + S_BYTES);
+  float2* const s_cw = reinterpret_cast<float2*>(lds_blk + S_BYTES);
   __shared__ float red[NTL * 256];
   __shared__ float2 s_tw[N];
   __shared__ int s_ro[N];  // k-space row -> offset of its K row within a coil, -1 for a zero row
-  constexpr int CMAX = 3072;  // coil values of the column staged in LDS when nc N fits
-  __shared__ float2 s_cw[CMAX];
   const int tid = threadIdx.x, grp = tid >> 8, lt = tid & 255;
   const int r = a.r, nx = a.nx, ncp = CT / r, nct = ncp * r, txx = a.txx;
   const bool cw_lds = a.nc * N <= CMAX;
@@ -296,8 +305,8 @@ __global__ __launch_bounds__(512) void k_adj_qr(BasisArgs a) {
   // the column's gradient, stored and embedded with U; embedding columns
   // from 4r on stay zero
   const int m = 2 * r;
-  for (int e = tid; e < N * 32; e += 512) {
-    const int y = e >> 5, k = e & 31;
+  for (int e = tid; e < N * EC; e += 512) {
+    const int y = e / EC, k = e % EC;
     if (k >= 2 * m) X[y * LDX + k] = 0.f;
   }
 #pragma unroll
@@ -337,8 +346,10 @@ __global__ __launch_bounds__(512) void k_adj_qr(BasisArgs a) {
         gacc[ti] = M::mma(xv[i], xv[j], gacc[ti]);
       }
   }
-  // the transform tiles are free: scratch for the sum over the waves
-  tiles_reduce_par<float, 8, NTL>(red, reinterpret_cast<float*>(&s[0][0]), gacc, wave, lane);
+  // once every wave's matrix-core reads of X are done, the whole block is
+  // the scratch for the sum over the waves
+  __syncthreads();
+  tiles_reduce_par<float, 8, NTL>(red, reinterpret_cast<float*>(lds_blk), gacc, wave, lane);
   auto C = [&](int i, int j) -> float {
     if (i > j) {
       const int t = i;
@@ -811,14 +822,24 @@ hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int gr
   return hipGetLastError();
 }
 
-// one workgroup per image column; N in {64, 128, 256} and r <= 8
+template <int N, int CT>
+static void launch_adj_qr_n(const BasisArgs& a, hipStream_t s) {
+  const dim3 g(a.nx), b(512);
+  switch ((4 * a.r + 15) / 16) {  // row tiles of the [U G] embedding
+    case 1: hipLaunchKernelGGL((k_adj_qr<N, CT, 1>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_adj_qr<N, CT, 2>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_adj_qr<N, CT, 3>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_adj_qr<N, CT, 4>), g, b, 0, s, a); break;
+  }
+}
+
+// one workgroup per image column; N in {64, 128, 256} and r <= 16
 hipError_t launch_adj_qr(int N, const BasisArgs& a, hipStream_t s) {
-  if (a.r > 8 || !a.qpart) return hipErrorInvalidValue;
-  const dim3 g(a.nx);
+  if (a.r < 1 || a.r > 16 || !a.qpart) return hipErrorInvalidValue;
   switch (N) {
-    case 64: hipLaunchKernelGGL((k_adj_qr<64, 64>), g, dim3(512), 0, s, a); break;
-    case 128: hipLaunchKernelGGL((k_adj_qr<128, 32>), g, dim3(512), 0, s, a); break;
-    case 256: hipLaunchKernelGGL((k_adj_qr<256, 16>), g, dim3(512), 0, s, a); break;
+    case 64: launch_adj_qr_n<64, 64>(a, s); break;
+    case 128: launch_adj_qr_n<128, 32>(a, s); break;
+    case 256: launch_adj_qr_n<256, 16>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

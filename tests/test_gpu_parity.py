@@ -199,6 +199,24 @@ def test_end_to_end_ranks_around_the_step_kernels(r, precision):
     assert ctx.get_eta() == pytest.approx(ref.eta, rel=1e-4)
 
 
+@pytest.mark.parametrize("ny,r", [(64, 9), (64, 12), (128, 16), (64, 16), (256, 12)])
+def test_end_to_end_fused_adjoint_gram_ranks_above_8(ny, r):
+    """Image columns of 64 and 128 pixels: the adjoint transform also forms
+    the QR Gram of [U grad] per column, here with three and four row tiles
+    of the real embedding (ranks 9 to 16), which the separate QR step then
+    sums over the columns."""
+    log(f"end-to-end fused adjoint Gram ny={ny} r={r}")
+    p = datagen.make_small(32, ny, 3, 20, r, seed=40 + r, kind="lines", n_lines=ny // 3, lowrank=True,
+                           snr_db=40.0, variable_m=True)
+    cs = Case(p)
+    ctx, Xg, ref = _end_to_end(cs, 6)
+    n_gpu, n_ref = M.nmse(Xg, p.zstar), M.nmse(ref.X, p.zstar)
+    log(f"  NMSE gpu {n_gpu:.6e} oracle {n_ref:.6e}; X rel {rel(Xg, ref.X):.2e}")
+    assert abs(n_gpu - n_ref) <= 1e-4
+    assert rel(Xg, ref.X) < 1e-3
+    assert ctx.get_eta() == pytest.approx(ref.eta, rel=1e-4)
+
+
 def test_mixed_precision_end_to_end_gauss64():
     log("end-to-end gauss64 mixed")
     cs = Case(datagen.make("gauss64", 0))
