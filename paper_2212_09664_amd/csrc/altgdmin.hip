@@ -658,13 +658,13 @@ hipError_t spectral_eig(altgdmin_ctx* c, int r_eig, double* lam_out) {
   g.nparts = 1;
   g.a_colmajor = 1;
   // X0^H X0 in FP64: up to 48 frames on the matrix cores (f64 16x16x4) over
-  // many short workgroups, whose partials a second kernel sums
+  // many short workgroups (k_init_gram), whose partials a second kernel sums
   InitEigArgs ie{};
   if (p.q <= 48) {
     const int nb = init_nblk(c);
     g.rows_per_block = ((c->n + nb - 1) / nb + 31) / 32 * 32;
     const int nbu = (int)((c->n + g.rows_per_block - 1) / g.rows_per_block);
-    AGCHK(launch_qr_gram(g, nbu, true, s));
+    AGCHK(launch_init_gram(g, nbu, s));
     const int nout = p.q * (p.q + 1) / 2;
     double2* sum = c->at<double2>(c->o_qpart) + (size_t)nbu * nout;
     AGCHK(launch_sum_partials(c->at<double2>(c->o_qpart), nbu, nout, sum, s));
@@ -831,10 +831,9 @@ altgdmin_status altgdmin_init(altgdmin_ctx* c, void* d_U) {
   hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, c->st(), 0);
   HIPCHK(ag_host::spectral_eig(c, p.r, nullptr));
   float2* X0 = c->at<float2>(c->o_T);
-  hipLaunchKernelGGL(k_x_times_v, dim3((c->n + AG_NT - 1) / AG_NT), dim3(AG_NT), 0, s, X0,
-                     c->at<float2>(c->o_Vs), c->n, p.q, p.r, U, c->st());
-  HIPCHK(hipGetLastError());
-  HIPCHK(cholqr(c, U));
+  HIPCHK(launch_x_times_v(X0, c->at<float2>(c->o_Vs), c->n, p.q, p.r, U, c->st(), s));
+  // X0 V Sigma^-1 is orthonormal up to FP32 rounding (errors grow with
+  // sigma_1 / sigma_r): one CholeskyQR pass restores it
   HIPCHK(cholqr(c, U));
   c->initialized = 1;
   return ALTGDMIN_OK;

@@ -1476,28 +1476,58 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
   }
 }
 
-// U0[:, j] = sum_k X0[:, k] Vs[k][j]
+// U0[:, j] = sum_k X0[:, k] Vs[k][j], one pixel per thread (r <= RT): the
+// frames' values KB at a time in flight, every LDS read of Vs unconditional
+// (a read under a branch would be waited on alone)
+template <int RT>
 __global__ __launch_bounds__(AG_NT) void k_x_times_v(const float2* X, const float2* Vs, int n, int q, int r,
                                                      float2* U, const DevState* st) {
   __shared__ float2 V[128 * 16];
   const int tid = threadIdx.x;
+  const long p = (long)blockIdx.x * AG_NT + tid, pc = min(p, (long)n - 1);
+  // the first frames' values requested before the state and the table (valid, clamped addresses)
+  constexpr int KB = 16;
+  float2 xv[KB];
+#pragma unroll
+  for (int i = 0; i < KB; ++i) xv[i] = X[(long)min(i, q - 1) * n + pc];
   if (st->err) return;
   for (int e = tid; e < q * r; e += AG_NT) V[e] = Vs[e];
   __syncthreads();
-  const long p = (long)blockIdx.x * AG_NT + tid;
-  if (p >= n) return;
-  float2 acc[16];
+  int jc[RT];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc[j] = make_float2(0.f, 0.f);
-  for (int k = 0; k < q; ++k) {
-    const float2 x = X[(long)k * n + p];
+  for (int j = 0; j < RT; ++j) jc[j] = min(j, r - 1);
+  float2 acc[RT];
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (j < r) acc[j] = cadd(acc[j], cmul(x, V[k * r + j]));
+  for (int j = 0; j < RT; ++j) acc[j] = make_float2(0.f, 0.f);
+  for (int k0 = 0; k0 < q; k0 += KB) {
+    float2 xn[KB];
+    const bool more = k0 + KB < q;
+#pragma unroll
+    for (int i = 0; i < KB; ++i) xn[i] = X[(long)min(k0 + KB + i, q - 1) * n + pc];  // the next batch
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      const int k = min(k0 + i, q - 1);
+      const float2 x = (k0 + i < q) ? xv[i] : make_float2(0.f, 0.f);
+      const float2* vk = V + k * r;
+#pragma unroll
+      for (int j = 0; j < RT; ++j) acc[j] = cadd(acc[j], cmul(x, vk[jc[j]]));
+    }
+    if (!more) break;
+#pragma unroll
+    for (int i = 0; i < KB; ++i) xv[i] = xn[i];
   }
+  if (p >= n) return;
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
+  for (int j = 0; j < RT; ++j)
     if (j < r) U[(long)j * n + p] = acc[j];
+}
+
+hipError_t launch_x_times_v(const float2* X, const float2* Vs, int n, int q, int r, float2* U, const DevState* st,
+                            hipStream_t s) {
+  const dim3 g((n + AG_NT - 1) / AG_NT), b(AG_NT);
+  if (r <= 8) hipLaunchKernelGGL(k_x_times_v<8>, g, b, 0, s, X, Vs, n, q, r, U, st);
+  else hipLaunchKernelGGL(k_x_times_v<16>, g, b, 0, s, X, Vs, n, q, r, U, st);
+  return hipGetLastError();
 }
 
 // keep the learned U (src) only if its cost f[1] is strictly below the

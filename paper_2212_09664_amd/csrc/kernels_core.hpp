@@ -337,8 +337,8 @@ __global__ void k_ysq_sum(const double* part, int q, int nc, double* ysq_k);
 __global__ void k_init_stats(const double* ysq_k, const int32_t* m_k, int q, double trunc_c, DevState* st);
 __global__ void k_state_reset(DevState* st, int full);
 __global__ void k_state_set_eta(DevState* st, double eta);
-__global__ void k_x_times_v(const float2* X, const float2* Vs, int n, int q, int r, float2* U,
-                            const DevState* st);
+hipError_t launch_x_times_v(const float2* X, const float2* Vs, int n, int q, int r, float2* U, const DevState* st,
+                            hipStream_t s);  // U = X0 Vs, r <= 16
 __global__ void k_err_snapshot(const DevState* st, int32_t* snap);
 __global__ void k_pick_init(const double* f, const int32_t* snap, const float2* src, float2* dst, long n,
                             int32_t* choice, const DevState* st);
@@ -353,6 +353,7 @@ hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp
 hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s);
 hipError_t launch_gram_cols(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);
 hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);
+hipError_t launch_init_gram(const GramColsArgs& a, int nblk, hipStream_t s);  // X0^H X0, q <= 48
 __global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* dst, long n);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s);

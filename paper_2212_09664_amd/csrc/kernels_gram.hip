@@ -791,6 +791,145 @@ hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_
   return hipGetLastError();
 }
 
+// upper tile ti of a TRM x TRM tile grid (row-major over the upper
+// triangle): its tile row and column
+constexpr int utile_row(int trm, int ti) {
+  int i = 0;
+  while (ti >= trm - i) {
+    ti -= trm - i;
+    ++i;
+  }
+  return i;
+}
+constexpr int utile_col(int trm, int ti) {
+  int i = 0;
+  while (ti >= trm - i) {
+    ti -= trm - i;
+    ++i;
+  }
+  return i + ti;
+}
+
+// one 4-row step of wave W's upper tiles W, W + 4, ... (the tile rows it
+// reads and the accumulator it feeds fixed at compile time)
+template <int TRM, int W, int K = 0>
+__device__ __forceinline__ void init_gram_tiles(const double* xr, typename Mma<double>::V* acc) {
+  constexpr int NTL = TRM * (TRM + 1) / 2, TI = W + 4 * K;
+  if constexpr (TI < NTL) {
+    constexpr int I = utile_row(TRM, TI), J = utile_col(TRM, TI);
+    acc[K] = Mma<double>::mma(xr[16 * I], xr[16 * J], acc[K]);
+    init_gram_tiles<TRM, W, K + 1>(xr, acc);
+  }
+}
+
+template <int TRM, int W, int RC, int LDX>
+__device__ __forceinline__ void init_gram_chunk(const double* X, int kk, int col, typename Mma<double>::V* acc) {
+#pragma unroll
+  for (int st = 0; st < RC / 4; ++st) init_gram_tiles<TRM, W>(X + (4 * st + kk) * LDX + col, acc);
+}
+
+// X0^H X0 of the spectral init (q <= 48 column-major FP32 columns of n
+// pixels) on the f64 matrix cores, one workgroup per block of rows.  A chunk
+// of RC rows is staged in LDS as the real embedding [Re X0 | Im X0] (FP64,
+// odd row pitch: consecutive rows' 8-byte writes fall in distinct banks);
+// wave w owns the upper tiles w, w + 4, ... over all of the chunk's rows, so
+// no sum across waves is needed.  Each chunk's loads are in flight during
+// the previous chunk's matrix-core work.  Output: the block's complex upper
+// triangle (tri order, FP64) at part[blockIdx.x * nout].
+template <int TRM>
+__global__ __launch_bounds__(256) void k_init_gram(GramColsArgs a) {
+  using M = Mma<double>;
+  constexpr int NTL = TRM * (TRM + 1) / 2, TPW = (NTL + 3) / 4;
+  constexpr int RC = 32, LDX = 16 * TRM + 1;
+  constexpr int EM = (RC * 8 * TRM + 255) / 256;  // complex elements per thread per chunk (q <= 8 TRM)
+  constexpr int XW = RC * LDX > NTL * 256 ? RC * LDX : NTL * 256;
+  __shared__ double X[XW];  // the staged chunk, then the tiles
+  const int tid = threadIdx.x, lane = tid & 63, col = lane & 15, kk = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = a.m1;
+  const long n = a.n, pa = (long)blockIdx.x * a.rows_per_block, pb = min(n, pa + a.rows_per_block);
+  const float2* const A = a.A;
+  int erow[EM], ecol[EM];
+#pragma unroll
+  for (int i = 0; i < EM; ++i) {
+    const int e = tid + 256 * i;
+    const bool ok = e < RC * q;
+    ecol[i] = ok ? e / RC : q;  // a column past q: no element
+    erow[i] = ok ? e - (e / RC) * RC : 0;
+  }
+  float2 w[EM];
+  auto load = [&](long p0) {  // valid, clamped addresses; rows past pb are zeroed when staged
+#pragma unroll
+    for (int i = 0; i < EM; ++i) w[i] = A[(long)min(ecol[i], q - 1) * n + min(p0 + erow[i], pb - 1)];
+  };
+  load(pa);
+  for (int e = tid; e < XW; e += 256) X[e] = 0.0;  // columns from 2q on stay zero
+  if (halted(a.st, a.check_halt)) return;
+  M::V acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) acc[t] = M::zero();
+  for (long base = pa; base < pb; base += RC) {
+    __syncthreads();  // the previous chunk's reads (and the zero fill) are done
+#pragma unroll
+    for (int i = 0; i < EM; ++i) {
+      const double re = base + erow[i] < pb ? (double)w[i].x : 0.0;
+      const double im = base + erow[i] < pb ? (double)w[i].y : 0.0;
+      if (ecol[i] < q) {
+        X[erow[i] * LDX + ecol[i]] = re;
+        X[erow[i] * LDX + q + ecol[i]] = im;
+      }
+    }
+    __syncthreads();
+    if (base + RC < pb) load(base + RC);
+    switch (wave) {  // wave-uniform: each branch's tiles fixed at compile time
+      case 0: init_gram_chunk<TRM, 0, RC, LDX>(X, kk, col, acc); break;
+      case 1: init_gram_chunk<TRM, 1, RC, LDX>(X, kk, col, acc); break;
+      case 2: init_gram_chunk<TRM, 2, RC, LDX>(X, kk, col, acc); break;
+      default: init_gram_chunk<TRM, 3, RC, LDX>(X, kk, col, acc); break;
+    }
+  }
+  __syncthreads();  // the last chunk's reads of X are done: X holds the tiles now
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int ti = wave + 4 * k;
+    if (ti < NTL) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[ti * 256 + M::row(lane, v) * 16 + col] = acc[k][v];
+    }
+  }
+  __syncthreads();
+  auto C = [&](int i, int j) -> double {  // entry (i, j) of the real 2q x 2q Gram
+    if (i > j) {
+      const int t = i;
+      i = j;
+      j = t;
+    }
+    const int a_ = i / 16, b_ = j / 16;
+    return X[(a_ * TRM - a_ * (a_ - 1) / 2 + (b_ - a_)) * 256 + (i % 16) * 16 + (j % 16)];
+  };
+  const int nout = q * (q + 1) / 2;
+  double2* out = a.part + (long)blockIdx.x * nout;
+  for (int o = tid; o < nout; o += 256) {
+    int i, j;
+    tri_index(o, q, i, j);
+    out[o] = make_double2(C(i, j) + C(q + i, q + j), C(i, q + j) - C(q + i, j));
+  }
+}
+
+hipError_t launch_init_gram(const GramColsArgs& a, int nblk, hipStream_t s) {
+  if (a.m2 != 0 || !a.a_colmajor || a.m1 < 1 || a.m1 > 48 || a.rows_per_block % 32 != 0) return hipErrorInvalidValue;
+  const dim3 g(nblk), b(256);
+  switch ((2 * a.m1 + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_init_gram<1>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_init_gram<2>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_init_gram<3>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_init_gram<4>), g, b, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_init_gram<5>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_init_gram<6>), g, b, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
 // sum over nblk partials of nout FP64 entries, in workgroup-slice order:
 // workgroup = 16 outputs x 16 slices of the partials, LDS tree over slices
 __global__ __launch_bounds__(256) void k_sum_partials(const double2* part, int nblk, int nout, double2* out) {
