@@ -1151,6 +1151,57 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
   return cnt;
 }
 
+// back-transformation by one wave (q <= 64): Y = Q D Z with Q = H_0 ... H_{n-3},
+// then V_r Sigma_r^{-1} = Y diag(1 / sqrt(lambda_j)) into Vs.  Lane (column
+// j = l % RJ, row group g = l / RJ) keeps rows g, g + G, ... of Y in registers
+// for the whole product: each reflector's column sums are taken over the G
+// lanes of a column by shuffles, with no workgroup barrier.
+template <int RJ, int NR>
+__device__ __forceinline__ void backtransform_wave(const double2* Vh, int ld, const double* s_beta, const double2* s_ph,
+                                                   const double* sy, const double* s_lam, int n, int r, int l,
+                                                   float2* Vs) {
+  constexpr int G = 64 / RJ;
+  const int j = l % RJ, g = l / RJ, jc = min(j, r - 1);
+  double2 y[NR];
+#pragma unroll
+  for (int t = 0; t < NR; ++t) {
+    const int i = g + G * t, ic = min(i, n - 1);
+    const double z = i < n ? sy[ic * r + jc] : 0.0;
+    const double2 ph = s_ph[ic];
+    y[t] = make_double2(ph.x * z, ph.y * z);
+  }
+  for (int k = n - 3; k >= 0; --k) {
+    const double beta = s_beta[k];
+    if (beta == 0.0) continue;  // the same in every lane
+    double2 sj = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+      const int i = g + G * t;
+      const double2 v = Vh[min(i, n - 1) * ld + k];
+      const double2 c = djmul(v, y[t]);
+      if (i > k && i < n) sj = dadd(sj, c);
+    }
+#pragma unroll
+    for (int off = RJ; off < 64; off <<= 1) {
+      sj.x += __shfl_xor(sj.x, off);
+      sj.y += __shfl_xor(sj.y, off);
+    }
+    sj = make_double2(beta * sj.x, beta * sj.y);
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+      const int i = g + G * t;
+      const double2 v = Vh[min(i, n - 1) * ld + k];
+      if (i > k && i < n) y[t] = dsub(y[t], dmul(v, sj));
+    }
+  }
+  const double sc = 1.0 / sqrt(s_lam[jc]);
+#pragma unroll
+  for (int t = 0; t < NR; ++t) {
+    const int i = g + G * t;
+    if (i < n && j < r) Vs[i * r + j] = make_float2((float)(y[t].x * sc), (float)(y[t].y * sc));
+  }
+}
+
 // ===========================================================================
 // spectral initialisation, the q x q eigenproblem: the r largest eigenpairs
 // of the Hermitian X_0^H X_0 by one wave, then V_r Sigma_r^{-1}:
@@ -1407,6 +1458,19 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
       for (int i = l; i < n; i += 64) sy[i * r + j] *= inv;
       wave_sync();
     }
+    if constexpr (IN_LDS) {  // 5. Y = Q D Z by this wave alone, Y in registers
+      if (a.lam_out) {  // only the spectrum was asked for
+        if (l < r) a.lam_out[l] = s_lam[l];
+        return;
+      }
+      if (!(s_lam[r - 1] > 1e-14 * s_lam[0]) || !(s_lam[0] > 0.0)) {
+        if (l == 0) set_error(a.st, 4, -1);
+        return;
+      }
+      if (r <= 8) backtransform_wave<8, 8>(Vh, ld, s_beta, s_ph, sy, s_lam, n, r, l, a.Vs);
+      else backtransform_wave<16, 16>(Vh, ld, s_beta, s_ph, sy, s_lam, n, r, l, a.Vs);
+      return;
+    }
     // ---- 5. Y = Q D Z, Y [i * r + j] complex over the start of A's region
     double zr[2][16];
   #pragma unroll
@@ -1427,8 +1491,9 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
       }
     wave_sync();
   }
+  if constexpr (IN_LDS) return;  // every other wave is done after the reduction
   __syncthreads();
-  // back-transformation Y <- H_k Y, k descending, over the workgroup:
+  // back-transformation Y <- H_k Y, k descending, over the workgroup (q > 64):
   // thread = (column j = tid % 16, row group g = tid / 16); column sums by
   // DPP-free shuffles within a wave, then across the 16 waves through LDS
   double2* Y = A;
