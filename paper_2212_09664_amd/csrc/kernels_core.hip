@@ -1152,20 +1152,24 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
 }
 
 // back-transformation by one wave (q <= 64): Y = Q D Z with Q = H_0 ... H_{n-3},
-// then V_r Sigma_r^{-1} = Y diag(1 / sqrt(lambda_j)) into Vs.  Lane (column
-// j = l % RJ, row group g = l / RJ) keeps rows g, g + G, ... of Y in registers
-// for the whole product: each reflector's column sums are taken over the G
-// lanes of a column by shuffles, with no workgroup barrier.
+// then V_r Sigma_r^{-1} = Y diag(1 / sqrt(lambda_j)) into Vs (r <= RJ).  Lane
+// (column j = l / G, row group g = l % G, G = 64 / RJ) keeps rows g, g + G, ... of Y in
+// registers for the whole product; a reflector's column sums are taken over
+// a column's G adjacent lanes by DPP moves, with no barrier; rows outside the
+// reflector are selected to zero rather than branched around.
 template <int RJ, int NR>
 __device__ __forceinline__ void backtransform_wave(const double2* Vh, int ld, const double* s_beta, const double2* s_ph,
                                                    const double* sy, const double* s_lam, int n, int r, int l,
                                                    float2* Vs) {
   constexpr int G = 64 / RJ;
-  const int j = l % RJ, g = l / RJ, jc = min(j, r - 1);
+  static_assert(G == 4 || G == 8, "column sums over 4 or 8 adjacent lanes");
+  const int j = l / G, g = l % G, jc = min(j, r - 1);
   double2 y[NR];
+  int roff[NR];
 #pragma unroll
   for (int t = 0; t < NR; ++t) {
     const int i = g + G * t, ic = min(i, n - 1);
+    roff[t] = ic * ld;
     const double z = i < n ? sy[ic * r + jc] : 0.0;
     const double2 ph = s_ph[ic];
     y[t] = make_double2(ph.x * z, ph.y * z);
@@ -1173,25 +1177,44 @@ __device__ __forceinline__ void backtransform_wave(const double2* Vh, int ld, co
   for (int k = n - 3; k >= 0; --k) {
     const double beta = s_beta[k];
     if (beta == 0.0) continue;  // the same in every lane
-    double2 sj = make_double2(0.0, 0.0);
+    // the reflector's rows kept in registers when they fit (NR <= 8), else read again for the update
+    constexpr bool KEEP = NR <= 8;
+    double2 v[KEEP ? NR : 1];
+    double sx = 0.0, sy_ = 0.0;
 #pragma unroll
-    for (int t = 0; t < NR; ++t) {
+    for (int t = 0; t < NR; ++t) {  // conj(v) y over the reflector's rows
+      // rows outside it read a valid address whose content is not the
+      // reflector's (possibly not a finite number): selected away, not
+      // multiplied by zero
       const int i = g + G * t;
-      const double2 v = Vh[min(i, n - 1) * ld + k];
-      const double2 c = djmul(v, y[t]);
-      if (i > k && i < n) sj = dadd(sj, c);
+      const double2 vl = Vh[roff[t] + k];
+      const double2 vt = (i > k && i < n) ? vl : make_double2(0.0, 0.0);
+      if constexpr (KEEP) v[t] = vt;
+      sx = fma(vt.x, y[t].x, fma(vt.y, y[t].y, sx));
+      sy_ = fma(vt.x, y[t].y, fma(-vt.y, y[t].x, sy_));
     }
-#pragma unroll
-    for (int off = RJ; off < 64; off <<= 1) {
-      sj.x += __shfl_xor(sj.x, off);
-      sj.y += __shfl_xor(sj.y, off);
+    sx += dpp_get<DPP_XOR1>(sx);
+    sy_ += dpp_get<DPP_XOR1>(sy_);
+    sx += dpp_get<DPP_XOR2>(sx);
+    sy_ += dpp_get<DPP_XOR2>(sy_);
+    if constexpr (G == 8) {
+      sx += dpp_get<DPP_HALF_MIRROR>(sx);
+      sy_ += dpp_get<DPP_HALF_MIRROR>(sy_);
     }
-    sj = make_double2(beta * sj.x, beta * sj.y);
+    sx *= beta;
+    sy_ *= beta;
 #pragma unroll
-    for (int t = 0; t < NR; ++t) {
-      const int i = g + G * t;
-      const double2 v = Vh[min(i, n - 1) * ld + k];
-      if (i > k && i < n) y[t] = dsub(y[t], dmul(v, sj));
+    for (int t = 0; t < NR; ++t) {  // y -= v (beta v^H y), zero outside the reflector
+      double2 vt;
+      if constexpr (KEEP) {
+        vt = v[t];
+      } else {
+        const int i = g + G * t;
+        const double2 vl = Vh[roff[t] + k];
+        vt = (i > k && i < n) ? vl : make_double2(0.0, 0.0);
+      }
+      const double ux = vt.x * sx - vt.y * sy_, uy = vt.x * sy_ + vt.y * sx;
+      y[t] = make_double2(y[t].x - ux, y[t].y - uy);
     }
   }
   const double sc = 1.0 / sqrt(s_lam[jc]);
@@ -1458,7 +1481,7 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
       for (int i = l; i < n; i += 64) sy[i * r + j] *= inv;
       wave_sync();
     }
-    if constexpr (IN_LDS) {  // 5. Y = Q D Z by this wave alone, Y in registers
+    if (IN_LDS && r <= 8) {  // 5. Y = Q D Z by this wave alone, Y in registers
       if (a.lam_out) {  // only the spectrum was asked for
         if (l < r) a.lam_out[l] = s_lam[l];
         return;
@@ -1467,8 +1490,7 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
         if (l == 0) set_error(a.st, 4, -1);
         return;
       }
-      if (r <= 8) backtransform_wave<8, 8>(Vh, ld, s_beta, s_ph, sy, s_lam, n, r, l, a.Vs);
-      else backtransform_wave<16, 16>(Vh, ld, s_beta, s_ph, sy, s_lam, n, r, l, a.Vs);
+      backtransform_wave<8, 8>(Vh, ld, s_beta, s_ph, sy, s_lam, n, r, l, a.Vs);
       return;
     }
     // ---- 5. Y = Q D Z, Y [i * r + j] complex over the start of A's region
@@ -1491,9 +1513,9 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
       }
     wave_sync();
   }
-  if constexpr (IN_LDS) return;  // every other wave is done after the reduction
+  if (IN_LDS && r <= 8) return;  // every other wave is done after the reduction
   __syncthreads();
-  // back-transformation Y <- H_k Y, k descending, over the workgroup (q > 64):
+  // back-transformation Y <- H_k Y, k descending, over the workgroup (q > 64 or r > 8):
   // thread = (column j = tid % 16, row group g = tid / 16); column sums by
   // DPP-free shuffles within a wave, then across the 16 waves through LDS
   double2* Y = A;
