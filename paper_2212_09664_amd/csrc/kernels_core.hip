@@ -1244,6 +1244,7 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
   __shared__ double2 s_ec[128], s_ph[128], s_w[128];
   __shared__ double2 s_p[8][128];  // the reflector product's column-slice partials
   __shared__ double s_lam[16];
+  __shared__ double s_gs[4];  // Gershgorin interval (lo, hi), the scale, the pivot floor
   const int tid = threadIdx.x, NT = blockDim.x, n = a.q, r = a.r;
   // row pitch ld odd: the rows one wave reads together fall in distinct LDS banks
   const int ld = n | 1;
@@ -1380,42 +1381,38 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     ghi = wave_max(ghi);
     scale = fmax(wave_max(scale), 1e-300);
     emax2 = wave_max(emax2);
-    const double pivmin = 2.3e-308 * fmax(1.0, emax2);
-    {
+    if (l == 0) {
       const double wdt = ghi - glo;
-      glo -= 1e-3 * wdt + 1e-300;
-      ghi += 1e-3 * wdt + 1e-300;
+      s_gs[0] = glo - (1e-3 * wdt + 1e-300);
+      s_gs[1] = ghi + (1e-3 * wdt + 1e-300);
+      s_gs[2] = scale;
+      s_gs[3] = 2.3e-308 * fmax(1.0, emax2);  // pivmin
     }
-    // ---- 3. multisection: RL eigenvalue slots of L lanes; slot j -> ascending index n-1-j
-    const int RL = r <= 8 ? 8 : 16, L = 64 / RL, slot = l / L, sub = l % L;
-    const int idx = n - 1 - slot;
-    double lo = glo, hi = ghi;
-    bool done = slot >= r;
+  }
+  __syncthreads();
+  // ---- 3. multisection: wave w < r takes the w-th largest eigenvalue
+  // (ascending index n-1-w), its 64 lanes one Sturm count each per round (a
+  // 65-section of the interval), to an isolating interval of relative width
+  // 1e-10: inverse iteration converges from it and the Rayleigh quotient
+  // refines the value
+  const double scale = s_gs[2];
+  if (wv < r) {
+    const int idx = n - 1 - wv;
+    const double pivmin = s_gs[3];
+    double lo = s_gs[0], hi = s_gs[1];
     for (int rnd = 0; rnd < 80; ++rnd) {
-      if (__all(done)) break;
-      const double x = lo + (hi - lo) * (double)(sub + 1) / (double)(L + 1);
-      const int cnt = done ? 0 : sturm_count(s_d, s_e2, n, x, pivmin);
-      double nlo = (!done && cnt <= idx) ? x : -INFINITY;
-      double nhi = (!done && cnt > idx) ? x : INFINITY;
-      // within the slot's L = 4 or 8 lanes
-      nlo = fmax(nlo, dpp_get<DPP_XOR1>(nlo));
-      nhi = fmin(nhi, dpp_get<DPP_XOR1>(nhi));
-      nlo = fmax(nlo, dpp_get<DPP_XOR2>(nlo));
-      nhi = fmin(nhi, dpp_get<DPP_XOR2>(nhi));
-      if (L == 8) {
-        nlo = fmax(nlo, dpp_get<DPP_HALF_MIRROR>(nlo));
-        nhi = fmin(nhi, dpp_get<DPP_HALF_MIRROR>(nhi));
-      }
-      if (!done) {
-        lo = fmax(lo, nlo);
-        hi = fmin(hi, nhi);
-        // an isolating interval of relative width 1e-10 is enough: inverse
-        // iteration converges from it and the Rayleigh quotient refines it
-        done = hi - lo <= 1e-10 * fmax(fabs(lo), fabs(hi)) + 1e-300;
-      }
+      const double x = lo + (hi - lo) * (double)(l + 1) / 65.0;
+      const int cnt = sturm_count(s_d, s_e2, n, x, pivmin);
+      const double nlo = wave_max(cnt <= idx ? x : -INFINITY);
+      const double nhi = wave_min(cnt > idx ? x : INFINITY);
+      lo = fmax(lo, nlo);
+      hi = fmin(hi, nhi);
+      if (hi - lo <= 1e-10 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;  // the same in every lane
     }
-    if (slot < r && sub == 0) s_lam[slot] = 0.5 * (lo + hi);
-    wave_sync();
+    if (l == 0) s_lam[wv] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  if (wv == 0) {
     // ---- 4. inverse iteration, lane j < r for eigenvalue j; scratch in A's region
     double* su = reinterpret_cast<double*>(A);  // u pivots [i * r + j]
     double* sy = su + n * r;                    // right-hand side / solution [i * r + j]
