@@ -1560,15 +1560,19 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
   }
 }
 
-// U0[:, j] = sum_k X0[:, k] Vs[k][j], one pixel per thread (r <= RT): the
-// frames' values KB at a time in flight, every LDS read of Vs unconditional
-// (a read under a branch would be waited on alone)
+// U0[:, j] = sum_k X0[:, k] Vs[k][j]: a workgroup takes 64 pixels, its four
+// waves the same pixels and a quarter of the r <= RT columns each (the
+// frames' values, loaded by each wave, come from the cache for three of
+// them); the frames' values KB at a time in flight, every LDS read of Vs
+// unconditional (a read under a branch would be waited on alone)
 template <int RT>
 __global__ __launch_bounds__(AG_NT) void k_x_times_v(const float2* X, const float2* Vs, int n, int q, int r,
                                                      float2* U, const DevState* st) {
+  static_assert(AG_NT == 256, "four waves per workgroup");
+  constexpr int CPT = RT / 4;  // columns per thread
   __shared__ float2 V[128 * 16];
-  const int tid = threadIdx.x;
-  const long p = (long)blockIdx.x * AG_NT + tid, pc = min(p, (long)n - 1);
+  const int tid = threadIdx.x, pl = tid & 63, jg = tid >> 6;
+  const long p = (long)blockIdx.x * 64 + pl, pc = min(p, (long)n - 1);
   // the first frames' values requested before the state and the table (valid, clamped addresses)
   constexpr int KB = 16;
   float2 xv[KB];
@@ -1577,12 +1581,12 @@ __global__ __launch_bounds__(AG_NT) void k_x_times_v(const float2* X, const floa
   if (st->err) return;
   for (int e = tid; e < q * r; e += AG_NT) V[e] = Vs[e];
   __syncthreads();
-  int jc[RT];
+  int jc[CPT];
 #pragma unroll
-  for (int j = 0; j < RT; ++j) jc[j] = min(j, r - 1);
-  float2 acc[RT];
+  for (int c = 0; c < CPT; ++c) jc[c] = min(jg * CPT + c, r - 1);
+  float2 acc[CPT];
 #pragma unroll
-  for (int j = 0; j < RT; ++j) acc[j] = make_float2(0.f, 0.f);
+  for (int c = 0; c < CPT; ++c) acc[c] = make_float2(0.f, 0.f);
   for (int k0 = 0; k0 < q; k0 += KB) {
     float2 xn[KB];
     const bool more = k0 + KB < q;
@@ -1594,7 +1598,7 @@ __global__ __launch_bounds__(AG_NT) void k_x_times_v(const float2* X, const floa
       const float2 x = (k0 + i < q) ? xv[i] : make_float2(0.f, 0.f);
       const float2* vk = V + k * r;
 #pragma unroll
-      for (int j = 0; j < RT; ++j) acc[j] = cadd(acc[j], cmul(x, vk[jc[j]]));
+      for (int c = 0; c < CPT; ++c) acc[c] = cadd(acc[c], cmul(x, vk[jc[c]]));
     }
     if (!more) break;
 #pragma unroll
@@ -1602,13 +1606,15 @@ __global__ __launch_bounds__(AG_NT) void k_x_times_v(const float2* X, const floa
   }
   if (p >= n) return;
 #pragma unroll
-  for (int j = 0; j < RT; ++j)
-    if (j < r) U[(long)j * n + p] = acc[j];
+  for (int c = 0; c < CPT; ++c) {
+    const int j = jg * CPT + c;
+    if (j < r) U[(long)j * n + p] = acc[c];
+  }
 }
 
 hipError_t launch_x_times_v(const float2* X, const float2* Vs, int n, int q, int r, float2* U, const DevState* st,
                             hipStream_t s) {
-  const dim3 g((n + AG_NT - 1) / AG_NT), b(AG_NT);
+  const dim3 g((n + 63) / 64), b(AG_NT);
   if (r <= 8) hipLaunchKernelGGL(k_x_times_v<8>, g, b, 0, s, X, Vs, n, q, r, U, st);
   else hipLaunchKernelGGL(k_x_times_v<16>, g, b, 0, s, X, Vs, n, q, r, U, st);
   return hipGetLastError();
