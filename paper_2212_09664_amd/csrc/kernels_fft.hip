@@ -214,6 +214,101 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// the column adjoint with the coil combine for 1D line masks, register-fed:
+// one workgroup per (CT-column tile, image); the image's sampled rows enter
+// the first radix pass straight from registers through an inverse row map in
+// LDS (k-space row -> the image's line holding it, -1 for a zero row), the
+// coil-weighted sum is taken on the last pass's registers, the next coil's
+// rows are loaded during the current transform.  Grid (nx / CT, images).
+// ---------------------------------------------------------------------------
+template <int N, int CT>
+__global__ __launch_bounds__(AG_NT) void k_cols_adj_lines(ColAdjArgs a) {
+  using GM = FftGeom<N, CT, AG_NT>;
+  constexpr int IT0 = GM::IT0, R0 = GM::R0, ITL = GM::ITL, RL = GM::RL;
+  __shared__ float2 s[FftPlan<N>::P > 1 ? N * CT : 1];
+  __shared__ float2 s_tw[N];
+  __shared__ int s_li[N];
+  const int tid = threadIdx.x, x0 = blockIdx.x * CT, img = blockIdx.y;
+  if (halted(a.st, a.check_halt)) return;  // (a mask that failed its checks at bind sets err)
+  const int n_rows = a.m_k_rows[img] / a.nx;
+  const int32_t* rows = a.rows + (long)img * a.rows_img_stride;
+  for (int e = tid; e < N; e += AG_NT) {
+    const float2 w = a.tw[e];
+    s_tw[e] = make_float2(w.x, -w.y);  // the forward table conjugated: the inverse twiddles
+    s_li[e] = -1;
+  }
+  __syncthreads();
+  for (int l = tid; l < n_rows; l += AG_NT) s_li[min(max(rows[l], 0), N - 1)] = l;  // an image's rows are distinct
+  __syncthreads();
+  float2 acc[ITL][RL];
+#pragma unroll
+  for (int it = 0; it < ITL; ++it)
+#pragma unroll
+    for (int q = 0; q < RL; ++q) acc[it][q] = make_float2(0.f, 0.f);
+  int li[IT0][R0];  // this thread's input rows: the line holding each, -1 for a zero row
+#pragma unroll
+  for (int it = 0; it < IT0; ++it)
+#pragma unroll
+    for (int q = 0; q < R0; ++q) {
+      const int g = tid + it * AG_NT;
+      li[it][q] = GM::in_ok(g) ? s_li[GM::in_row(g, q)] : -1;
+    }
+  const float2* const src0 = a.src + (long)img * a.src_img_stride + x0;
+  float2 kv[IT0][R0];
+  auto fetch = [&](int c) {  // valid addresses for every lane; zero rows selected afterwards
+    const float2* src = src0 + (long)c * a.src_c_stride;
+#pragma unroll
+    for (int it = 0; it < IT0; ++it) {
+      const int col = (tid + it * AG_NT) % CT;
+#pragma unroll
+      for (int q = 0; q < R0; ++q) {
+        const float2 v = src[(long)max(li[it][q], 0) * a.nx + col];
+        kv[it][q] = li[it][q] >= 0 ? v : make_float2(0.f, 0.f);
+      }
+    }
+  };
+  fetch(0);
+  for (int c = 0; c < a.nc; ++c) {
+    float2 v0[IT0][R0], vo[ITL][RL];
+#pragma unroll
+    for (int it = 0; it < IT0; ++it)
+#pragma unroll
+      for (int q = 0; q < R0; ++q) v0[it][q] = kv[it][q];
+    if (c + 1 < a.nc) fetch(c + 1);
+    fft_regs<N, CT, AG_NT, true>(v0, vo, s, s_tw);
+    // the coil values at the output rows come from the cache (every image
+    // reads the same maps); loading them one coil ahead cost more in
+    // registers than it saved
+    const float2* coil = a.coils + (long)c * a.n + x0;
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int g = tid + it * AG_NT, col = g % CT;
+      if (GM::out_ok(g)) {
+#pragma unroll
+        for (int q = 0; q < RL; ++q)
+          acc[it][q] = cjfma(acc[it][q], coil[(long)GM::out_row(g, q) * a.nx + col], vo[it][q]);
+      }
+    }
+  }
+  float sc = a.scale;
+  if (a.m_k_scale) sc *= (float)(1.0 / sqrt((double)a.m_k_scale[img] * a.st->mbar));
+  float2* dst = a.dst + (long)img * a.dst_img_stride + x0;
+#pragma unroll
+  for (int it = 0; it < ITL; ++it) {
+    const int g = tid + it * AG_NT, col = g % CT;
+    if (GM::out_ok(g)) {
+#pragma unroll
+      for (int q = 0; q < RL; ++q) {
+        const long p = (long)GM::out_row(g, q) * a.nx + col;
+        float2 v = cscale(acc[it][q], sc);
+        if (a.accumulate) v = cadd(dst[p], v);
+        dst[p] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // general masks: gather the frame's samples from full k-space images, and
 // the adjoint scatter (with optional truncation).
 // ---------------------------------------------------------------------------
@@ -322,6 +417,17 @@ static hipError_t launch_cols_n(const ColFwdArgs* f, const ColAdjArgs* d, int nx
 hipError_t launch_cols(int N, const ColFwdArgs* f, const ColAdjArgs* d, int nx, int n_img, int nc,
                        hipStream_t st) {
   if (n_img <= 0) return hipSuccess;
+  // line masks, every coil in one workgroup: the register-fed transform
+  if (d && d->m_k_rows && (d->cgs <= 0 || d->cgs >= d->nc)) {
+    if (N == 256 && nx % 16 == 0) {
+      hipLaunchKernelGGL((k_cols_adj_lines<256, 16>), dim3(nx / 16, n_img), dim3(AG_NT), 0, st, *d);
+      return hipGetLastError();
+    }
+    if (N == 128 && nx % 32 == 0) {
+      hipLaunchKernelGGL((k_cols_adj_lines<128, 32>), dim3(nx / 32, n_img), dim3(AG_NT), 0, st, *d);
+      return hipGetLastError();
+    }
+  }
   switch (N) {
     case 8: return launch_cols_n<8>(f, d, nx, n_img, nc, st);
     case 16: return launch_cols_n<16>(f, d, nx, n_img, nc, st);
