@@ -1239,17 +1239,21 @@ __device__ __forceinline__ void backtransform_wave(const double2* Vh, int ld, co
 // ===========================================================================
 template <bool IN_LDS>
 __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
-  extern __shared__ double2 lds_m[];  // q x q matrix, then q x q reflectors
+  // q <= 64: the q x q matrix, then the q x q reflectors; 64 < q <= 128: the
+  // matrix's lower triangle packed by rows (row i from i (i + 1) / 2), the
+  // reflectors in global memory (a.V)
+  extern __shared__ double2 lds_m[];
   __shared__ double s_d[128], s_ea[128], s_e2[128], s_beta[128];
-  __shared__ double2 s_ec[128], s_ph[128], s_w[128];
+  __shared__ double2 s_ec[128], s_ph[128], s_w[128], s_v[128];
   __shared__ double2 s_p[8][128];  // the reflector product's column-slice partials
   __shared__ double s_lam[16];
   __shared__ double s_gs[4];  // Gershgorin interval (lo, hi), the scale, the pivot floor
   const int tid = threadIdx.x, NT = blockDim.x, n = a.q, r = a.r;
   // row pitch ld odd: the rows one wave reads together fall in distinct LDS banks
   const int ld = n | 1;
-  double2* A = IN_LDS ? lds_m : a.V;
-  double2* Vh = A + n * ld;
+  double2* A = lds_m;
+  double2* Vh = IN_LDS ? A + n * ld : a.V;
+  auto tri = [](int i) { return (i * (i + 1)) >> 1; };  // packed row offset
   const int nout = n * (n + 1) / 2;
   for (int o = tid; o < nout; o += NT) {
     double2 sum = make_double2(0.0, 0.0);
@@ -1258,98 +1262,196 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
     int i, j;
     tri_index(o, n, i, j);
     if (i == j) sum.y = 0.0;
-    A[i * ld + j] = sum;
-    A[j * ld + i] = dconj(sum);
+    if constexpr (IN_LDS) {
+      A[i * ld + j] = sum;
+      A[j * ld + i] = dconj(sum);
+    } else {
+      A[tri(max(i, j)) + min(i, j)] = i >= j ? sum : dconj(sum);  // the lower entry
+    }
   }
   __syncthreads();
   // ---- 1. Householder tridiagonalisation (full Hermitian trailing block
   // kept): wave 0 forms each reflector, the workgroup shares the product
   // p = beta B v (8 column slices) and the rank-2 update of B
   const int l = tid & 63, wv = tid >> 6;
-  for (int k = 0; k + 2 < n; ++k) {
-    const int k1 = k + 1, m = n - k1;
-    if (wv == 0) {
-      double sig = 0.0;
-      for (int i = 1 + l; i < m; i += 64) {
-        const double2 x = A[(k1 + i) * ld + k];
-        sig += x.x * x.x + x.y * x.y;
-      }
-      sig = wave_sum(sig);
-      const double2 x0 = A[k1 * ld + k];
-      if (sig == 0.0 && x0.y == 0.0) {  // already reduced: H_k = I
-        if (l == 0) {
-          s_beta[k] = 0.0;
-          s_ec[k] = x0;
+  if constexpr (IN_LDS) {
+    for (int k = 0; k + 2 < n; ++k) {
+      const int k1 = k + 1, m = n - k1;
+      if (wv == 0) {
+        double sig = 0.0;
+        for (int i = 1 + l; i < m; i += 64) {
+          const double2 x = A[(k1 + i) * ld + k];
+          sig += x.x * x.x + x.y * x.y;
         }
-      } else {
-        const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y), nrm = sqrt(ax0 * ax0 + sig);
-        const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
-        const double2 alpha = make_double2(-ph.x * nrm, -ph.y * nrm);
-        const double2 v0 = dsub(x0, alpha);
-        for (int i = 1 + l; i < m; i += 64) Vh[(k1 + i) * ld + k] = A[(k1 + i) * ld + k];
-        if (l == 0) {
-          Vh[k1 * ld + k] = v0;
-          s_beta[k] = 2.0 / (v0.x * v0.x + v0.y * v0.y + sig);
-          s_ec[k] = alpha;
+        sig = wave_sum(sig);
+        const double2 x0 = A[k1 * ld + k];
+        if (sig == 0.0 && x0.y == 0.0) {  // already reduced: H_k = I
+          if (l == 0) {
+            s_beta[k] = 0.0;
+            s_ec[k] = x0;
+          }
+        } else {
+          const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y), nrm = sqrt(ax0 * ax0 + sig);
+          const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+          const double2 alpha = make_double2(-ph.x * nrm, -ph.y * nrm);
+          const double2 v0 = dsub(x0, alpha);
+          for (int i = 1 + l; i < m; i += 64) Vh[(k1 + i) * ld + k] = A[(k1 + i) * ld + k];
+          if (l == 0) {
+            Vh[k1 * ld + k] = v0;
+            s_beta[k] = 2.0 / (v0.x * v0.x + v0.y * v0.y + sig);
+            s_ec[k] = alpha;
+          }
         }
       }
-    }
-    __syncthreads();
-    const double beta = s_beta[k];
-    if (beta == 0.0) continue;  // the same in every thread
-    // partial products over column slices j = h (mod 8), 8 waves
-    if (wv < 8) {
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const int i = l + 64 * hh;
-        if (i < m) {
-          const double2* row = A + (k1 + i) * ld + k1;
+      __syncthreads();
+      const double beta = s_beta[k];
+      if (beta == 0.0) continue;  // the same in every thread
+      // partial products over column slices j = h (mod 8), 8 waves
+      if (wv < 8) {
+  #pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int i = l + 64 * hh;
+          if (i < m) {
+            const double2* row = A + (k1 + i) * ld + k1;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int j = wv; j < m; j += 8) acc = dadd(acc, dmul(row[j], Vh[(k1 + j) * ld + k]));
+            s_p[wv][i] = acc;
+          }
+        }
+      }
+      __syncthreads();
+      // p = beta B v, K = (beta / 2) v^H p, w = p - K v (wave 0)
+      if (wv == 0) {
+        double2 pv[2];
+        double2 kp = make_double2(0.0, 0.0);
+  #pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int i = l + 64 * hh;
           double2 acc = make_double2(0.0, 0.0);
-          for (int j = wv; j < m; j += 8) acc = dadd(acc, dmul(row[j], Vh[(k1 + j) * ld + k]));
-          s_p[wv][i] = acc;
+          if (i < m) {
+  #pragma unroll
+            for (int h = 0; h < 8; ++h) acc = dadd(acc, s_p[h][i]);
+            acc = make_double2(beta * acc.x, beta * acc.y);
+            kp = dadd(kp, djmul(Vh[(k1 + i) * ld + k], acc));
+          }
+          pv[hh] = acc;
+        }
+        kp = wave_sum2(kp);
+        const double2 K = make_double2(0.5 * beta * kp.x, 0.5 * beta * kp.y);
+  #pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int i = l + 64 * hh;
+          if (i < m) s_w[i] = dsub(pv[hh], dmul(K, Vh[(k1 + i) * ld + k]));
         }
       }
+      __syncthreads();
+      // B -= v w^H + w v^H, entry by entry over the workgroup
+      for (int e = tid; e < m * m; e += NT) {
+        const int i = e / m, j = e - (e / m) * m;
+        const double2 vi = Vh[(k1 + i) * ld + k], wi = s_w[i];
+        const double2 vj = Vh[(k1 + j) * ld + k], wj = s_w[j];
+        double2* aij = A + (k1 + i) * ld + k1 + j;
+        *aij = dsub(*aij, dadd(dmul(vi, dconj(wj)), dmul(wi, dconj(vj))));
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    // p = beta B v, K = (beta / 2) v^H p, w = p - K v (wave 0)
-    if (wv == 0) {
-      double2 pv[2];
-      double2 kp = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const int i = l + 64 * hh;
-        double2 acc = make_double2(0.0, 0.0);
-        if (i < m) {
-#pragma unroll
-          for (int h = 0; h < 8; ++h) acc = dadd(acc, s_p[h][i]);
-          acc = make_double2(beta * acc.x, beta * acc.y);
-          kp = dadd(kp, djmul(Vh[(k1 + i) * ld + k], acc));
+  } else {
+    // the same steps on the packed lower triangle: B(i, j) of the trailing
+    // block is the stored entry for i >= j and the conjugate of (j, i) above;
+    // the step's reflector is read from LDS (s_v), its global copy kept for
+    // the back-transformation; the rank-2 update touches the lower triangle
+    // only (rows i = w, w + 16, ... by wave, columns by lane)
+    for (int k = 0; k + 2 < n; ++k) {
+      const int k1 = k + 1, m = n - k1;
+      if (wv == 0) {
+        double sig = 0.0;
+        for (int i = 1 + l; i < m; i += 64) {
+          const double2 x = A[tri(k1 + i) + k];
+          sig += x.x * x.x + x.y * x.y;
         }
-        pv[hh] = acc;
+        sig = wave_sum(sig);
+        const double2 x0 = A[tri(k1) + k];
+        if (sig == 0.0 && x0.y == 0.0) {  // already reduced: H_k = I
+          if (l == 0) {
+            s_beta[k] = 0.0;
+            s_ec[k] = x0;
+          }
+        } else {
+          const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y), nrm = sqrt(ax0 * ax0 + sig);
+          const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+          const double2 alpha = make_double2(-ph.x * nrm, -ph.y * nrm);
+          const double2 v0 = dsub(x0, alpha);
+          for (int i = 1 + l; i < m; i += 64) {
+            const double2 x = A[tri(k1 + i) + k];
+            s_v[i] = x;
+            Vh[(k1 + i) * ld + k] = x;
+          }
+          if (l == 0) {
+            s_v[0] = v0;
+            Vh[k1 * ld + k] = v0;
+            s_beta[k] = 2.0 / (v0.x * v0.x + v0.y * v0.y + sig);
+            s_ec[k] = alpha;
+          }
+        }
       }
-      kp = wave_sum2(kp);
-      const double2 K = make_double2(0.5 * beta * kp.x, 0.5 * beta * kp.y);
+      __syncthreads();
+      const double beta = s_beta[k];
+      if (beta == 0.0) continue;  // the same in every thread
+      if (wv < 8) {  // partial products over column slices j = wv (mod 8)
 #pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const int i = l + 64 * hh;
-        if (i < m) s_w[i] = dsub(pv[hh], dmul(K, Vh[(k1 + i) * ld + k]));
+        for (int hh = 0; hh < 2; ++hh) {
+          const int i = l + 64 * hh;
+          if (i < m) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int j = wv; j < m; j += 8) {
+              const double2 bij = i >= j ? A[tri(k1 + i) + k1 + j] : dconj(A[tri(k1 + j) + k1 + i]);
+              acc = dadd(acc, dmul(bij, s_v[j]));
+            }
+            s_p[wv][i] = acc;
+          }
+        }
       }
+      __syncthreads();
+      if (wv == 0) {  // p = beta B v, K = (beta / 2) v^H p, w = p - K v
+        double2 pv[2];
+        double2 kp = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int i = l + 64 * hh;
+          double2 acc = make_double2(0.0, 0.0);
+          if (i < m) {
+#pragma unroll
+            for (int h = 0; h < 8; ++h) acc = dadd(acc, s_p[h][i]);
+            acc = make_double2(beta * acc.x, beta * acc.y);
+            kp = dadd(kp, djmul(s_v[i], acc));
+          }
+          pv[hh] = acc;
+        }
+        kp = wave_sum2(kp);
+        const double2 K = make_double2(0.5 * beta * kp.x, 0.5 * beta * kp.y);
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int i = l + 64 * hh;
+          if (i < m) s_w[i] = dsub(pv[hh], dmul(K, s_v[i]));
+        }
+      }
+      __syncthreads();
+      for (int i = wv; i < m; i += NT / 64) {  // B -= v w^H + w v^H, lower triangle
+        const double2 vi = s_v[i], wi = s_w[i];
+        double2* row = A + tri(k1 + i) + k1;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int j = l + 64 * hh;
+          if (j <= i) row[j] = dsub(row[j], dadd(dmul(vi, dconj(s_w[j])), dmul(wi, dconj(s_v[j]))));
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    // B -= v w^H + w v^H, entry by entry over the workgroup
-    for (int e = tid; e < m * m; e += NT) {
-      const int i = e / m, j = e - (e / m) * m;
-      const double2 vi = Vh[(k1 + i) * ld + k], wi = s_w[i];
-      const double2 vj = Vh[(k1 + j) * ld + k], wj = s_w[j];
-      double2* aij = A + (k1 + i) * ld + k1 + j;
-      *aij = dsub(*aij, dadd(dmul(vi, dconj(wj)), dmul(wi, dconj(vj))));
-    }
-    __syncthreads();
   }
   if (wv == 0) {  // one wave: the tridiagonal eigenproblem
     // ---- 2. T_r: diagonal, |e_k|, and the phases of D
-    for (int i = l; i < n; i += 64) s_d[i] = A[i * ld + i].x;
-    if (l == 0 && n >= 2) s_ec[n - 2] = A[(n - 1) * ld + (n - 2)];
+    for (int i = l; i < n; i += 64) s_d[i] = (IN_LDS ? A[i * ld + i] : A[tri(i) + i]).x;
+    if (l == 0 && n >= 2) s_ec[n - 2] = IN_LDS ? A[(n - 1) * ld + (n - 2)] : A[tri(n - 1) + n - 2];
     wave_sync();
     for (int i = l; i + 1 < n; i += 64) {
       const double2 e = s_ec[i];
@@ -1513,36 +1615,56 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
   if (IN_LDS && r <= 8) return;  // every other wave is done after the reduction
   __syncthreads();
   // back-transformation Y <- H_k Y, k descending, over the workgroup (q > 64 or r > 8):
-  // thread = (column j = tid % 16, row group g = tid / 16); column sums by
-  // DPP-free shuffles within a wave, then across the 16 waves through LDS
+  // thread = (column jc = tid % 16, rows g, g + 64 with g = tid / 16), the same
+  // rows for the column sums and the update, so that a thread only reads the
+  // rows of Y it wrote; the reflector's values at those rows are loaded one
+  // column ahead (they live in global memory for q > 64); column sums by
+  // shuffles within a wave, then across the 16 waves through LDS
   double2* Y = A;
   const int jc = tid & 15, g64 = tid >> 4;
   double2* s_sj = &s_p[0][0];  // [wave][16] partial sums, then the 16 totals
-  for (int k = n - 3; k >= 0; --k) {
-    const double beta = s_beta[k];
-    if (beta == 0.0) continue;  // the same in every thread
-    double2 sj = make_double2(0.0, 0.0);
-    if (jc < r)
-      for (int i = k + 1 + g64; i < n; i += 64) sj = dadd(sj, djmul(Vh[i * ld + k], Y[i * r + jc]));
+  double2 vc[2], vn[2];
+  auto vload = [&](int k, double2 (&dst)[2]) {
 #pragma unroll
-    for (int off = 16; off < 64; off <<= 1) {
-      sj.x += __shfl_xor(sj.x, off);
-      sj.y += __shfl_xor(sj.y, off);
+    for (int h = 0; h < 2; ++h) dst[h] = Vh[min(g64 + 64 * h, n - 1) * ld + max(k, 0)];
+  };
+  vload(n - 3, vc);
+  for (int k = n - 3; k >= 0; --k) {
+    vload(k - 1, vn);
+    const double beta = s_beta[k];
+    if (beta != 0.0) {  // the same in every thread
+      double2 sj = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = g64 + 64 * h;
+        if (jc < r && i > k && i < n) sj = dadd(sj, djmul(vc[h], Y[i * r + jc]));
+      }
+#pragma unroll
+      for (int off = 16; off < 64; off <<= 1) {
+        sj.x += __shfl_xor(sj.x, off);
+        sj.y += __shfl_xor(sj.y, off);
+      }
+      if (l < 16) s_sj[wv * 16 + l] = sj;
+      __syncthreads();
+      if (tid < 16) {
+        double2 t = make_double2(0.0, 0.0);
+        for (int w = 0; w < NT / 64; ++w) t = dadd(t, s_sj[w * 16 + tid]);
+        s_sj[256 + tid] = make_double2(beta * t.x, beta * t.y);
+      }
+      __syncthreads();
+      // (the next step's totals are written after its first barrier, which
+      // every thread reaches only once its update here is done)
+      const double2 sv = s_sj[256 + jc];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = g64 + 64 * h;
+        if (jc < r && i > k && i < n) Y[i * r + jc] = dsub(Y[i * r + jc], dmul(vc[h], sv));
+      }
     }
-    if (l < 16) s_sj[wv * 16 + l] = sj;
-    __syncthreads();
-    if (tid < 16) {
-      double2 t = make_double2(0.0, 0.0);
-      for (int w = 0; w < NT / 64; ++w) t = dadd(t, s_sj[w * 16 + tid]);
-      s_sj[256 + tid] = make_double2(beta * t.x, beta * t.y);
-    }
-    __syncthreads();
-    for (int e2 = tid; e2 < (n - k - 1) * r; e2 += NT) {
-      const int i = k + 1 + e2 / r, j = e2 % r;
-      Y[i * r + j] = dsub(Y[i * r + j], dmul(Vh[i * ld + k], s_sj[256 + j]));
-    }
-    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) vc[h] = vn[h];
   }
+  __syncthreads();  // every row of Y is final before the columns are scaled below
   if (a.lam_out) {  // only the spectrum was asked for
     if (tid < r) a.lam_out[tid] = s_lam[tid];
     return;
@@ -1698,17 +1820,17 @@ hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
 
 hipError_t launch_init_eig(const InitEigArgs& a, hipStream_t s) {
   if (a.q > 128 || a.r > 16 || a.r > a.q) return hipErrorInvalidValue;
-  const size_t lds = a.in_lds ? 2 * (size_t)a.q * (a.q | 1) * sizeof(double2) : 0;
-  if (a.in_lds) {
-    if (lds > 48 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_init_eig<true>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_init_eig<true>), dim3(1), dim3(1024), lds, s, a);
-  } else {
-    hipLaunchKernelGGL((k_init_eig<false>), dim3(1), dim3(1024), 0, s, a);
+  // q <= 64: matrix and reflectors in LDS; else the packed lower triangle
+  // (the reflectors in a.V)
+  const size_t lds = a.in_lds ? 2 * (size_t)a.q * (a.q | 1) * sizeof(double2)
+                              : (size_t)a.q * (a.q + 1) / 2 * sizeof(double2);
+  const void* fn = a.in_lds ? (const void*)k_init_eig<true> : (const void*)k_init_eig<false>;
+  if (lds > 48 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
   }
+  if (a.in_lds) hipLaunchKernelGGL((k_init_eig<true>), dim3(1), dim3(1024), lds, s, a);
+  else hipLaunchKernelGGL((k_init_eig<false>), dim3(1), dim3(1024), lds, s, a);
   return hipGetLastError();
 }
 
