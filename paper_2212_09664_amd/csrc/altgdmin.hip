@@ -657,14 +657,16 @@ hipError_t spectral_eig(altgdmin_ctx* c, int r_eig, double* lam_out) {
   g.st = c->st();
   g.nparts = 1;
   g.a_colmajor = 1;
-  // X0^H X0 in FP64: up to 48 frames on the matrix cores (f64 16x16x4) over
-  // many short workgroups (k_init_gram), whose partials a second kernel sums
+  // X0^H X0 in FP64 on the matrix cores (f64 16x16x4) over many short
+  // workgroups (k_init_gram up to 48 frames, k_init_gram_cx up to 128), whose
+  // partials a second kernel sums
   InitEigArgs ie{};
-  if (p.q <= 48) {
+  if (p.q <= 128) {
     const int nb = init_nblk(c);
     g.rows_per_block = ((c->n + nb - 1) / nb + 31) / 32 * 32;
     const int nbu = (int)((c->n + g.rows_per_block - 1) / g.rows_per_block);
-    AGCHK(launch_init_gram(g, nbu, s));
+    if (p.q <= 48) AGCHK(launch_init_gram(g, nbu, s));
+    else AGCHK(launch_init_gram_cx(g, nbu, s));
     const int nout = p.q * (p.q + 1) / 2;
     double2* sum = c->at<double2>(c->o_qpart) + (size_t)nbu * nout;
     AGCHK(launch_sum_partials(c->at<double2>(c->o_qpart), nbu, nout, sum, s));

@@ -354,6 +354,7 @@ hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s);
 hipError_t launch_gram_cols(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);
 hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);
 hipError_t launch_init_gram(const GramColsArgs& a, int nblk, hipStream_t s);  // X0^H X0, q <= 48
+hipError_t launch_init_gram_cx(const GramColsArgs& a, int nblk, hipStream_t s);  // X0^H X0, 48 < q <= 128
 __global__ void k_sum_parts(const float2* src, long stride, int nparts, float2* dst, long n);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s);

@@ -916,6 +916,129 @@ __global__ __launch_bounds__(256) void k_init_gram(GramColsArgs a) {
   }
 }
 
+// one 4-row step of wave W's complex tiles W, W + 8, ...: tile (a, b) of
+// X0^H X0 is Re = Xr_a^T Xr_b + Xi_a^T Xi_b and Im = Xr_a^T Xi_b - Xi_a^T Xr_b
+// (two accumulators, four matrix-core products per step)
+template <int QT, int W, int K = 0>
+__device__ __forceinline__ void init_gram_cx_tiles(const double* xr, const double* xi,
+                                                   typename Mma<double>::V* acc) {
+  constexpr int NCT = QT * (QT + 1) / 2, TI = W + 8 * K;
+  if constexpr (TI < NCT) {
+    constexpr int I = utile_row(QT, TI), J = utile_col(QT, TI);
+    acc[2 * K] = Mma<double>::mma(xr[16 * I], xr[16 * J], acc[2 * K]);
+    acc[2 * K] = Mma<double>::mma(xi[16 * I], xi[16 * J], acc[2 * K]);
+    acc[2 * K + 1] = Mma<double>::mma(xr[16 * I], xi[16 * J], acc[2 * K + 1]);
+    acc[2 * K + 1] = Mma<double>::mma(-xi[16 * I], xr[16 * J], acc[2 * K + 1]);
+    init_gram_cx_tiles<QT, W, K + 1>(xr, xi, acc);
+  }
+}
+
+template <int QT, int W, int RC, int LDX>
+__device__ __forceinline__ void init_gram_cx_chunk(const double* X, int kk, int col, typename Mma<double>::V* acc) {
+#pragma unroll
+  for (int st = 0; st < RC / 4; ++st) {
+    const double* xr = X + (4 * st + kk) * LDX + col;
+    init_gram_cx_tiles<QT, W>(xr, xr + 16 * QT, acc);
+  }
+}
+
+// X0^H X0 for 48 < q <= 128 columns (QT = ceil(q / 16) complex column
+// tiles): 512 threads, a chunk of RC rows staged as [Re X0 | Im X0] in
+// FP64 (odd pitch), wave w owning the complex upper tiles w, w + 8, ...; each
+// wave writes its tiles' entries of the upper triangle straight to the
+// block's partial (tri order), so no sum across waves is needed.
+template <int QT>
+__global__ __launch_bounds__(512) void k_init_gram_cx(GramColsArgs a) {
+  using M = Mma<double>;
+  constexpr int NCT = QT * (QT + 1) / 2, TPW = (NCT + 7) / 8;
+  constexpr int RC = 32, LDX = 32 * QT + 1;
+  constexpr int EM = (RC * 16 * QT + 511) / 512;  // complex elements per thread per chunk (q <= 16 QT)
+  __shared__ double X[RC * LDX];
+  const int tid = threadIdx.x, lane = tid & 63, col = lane & 15, kk = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = a.m1;
+  const long n = a.n, pa = (long)blockIdx.x * a.rows_per_block, pb = min(n, pa + a.rows_per_block);
+  const float2* const A = a.A;
+  int erow[EM], ecol[EM];
+#pragma unroll
+  for (int i = 0; i < EM; ++i) {
+    const int e = tid + 512 * i;
+    const bool ok = e < RC * q;
+    ecol[i] = ok ? e / RC : q;  // a column past q: no element
+    erow[i] = ok ? e - (e / RC) * RC : 0;
+  }
+  float2 w[EM];
+  auto load = [&](long p0) {
+#pragma unroll
+    for (int i = 0; i < EM; ++i) w[i] = A[(long)min(ecol[i], q - 1) * n + min(p0 + erow[i], pb - 1)];
+  };
+  load(pa);
+  for (int e = tid; e < RC * LDX; e += 512) X[e] = 0.0;  // columns from q on stay zero
+  if (halted(a.st, a.check_halt)) return;
+  M::V acc[2 * TPW];
+#pragma unroll
+  for (int t = 0; t < 2 * TPW; ++t) acc[t] = M::zero();
+  for (long base = pa; base < pb; base += RC) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EM; ++i) {
+      const double re = base + erow[i] < pb ? (double)w[i].x : 0.0;
+      const double im = base + erow[i] < pb ? (double)w[i].y : 0.0;
+      if (ecol[i] < q) {
+        X[erow[i] * LDX + ecol[i]] = re;
+        X[erow[i] * LDX + 16 * QT + ecol[i]] = im;
+      }
+    }
+    __syncthreads();
+    if (base + RC < pb) load(base + RC);
+    switch (wave) {
+      case 0: init_gram_cx_chunk<QT, 0, RC, LDX>(X, kk, col, acc); break;
+      case 1: init_gram_cx_chunk<QT, 1, RC, LDX>(X, kk, col, acc); break;
+      case 2: init_gram_cx_chunk<QT, 2, RC, LDX>(X, kk, col, acc); break;
+      case 3: init_gram_cx_chunk<QT, 3, RC, LDX>(X, kk, col, acc); break;
+      case 4: init_gram_cx_chunk<QT, 4, RC, LDX>(X, kk, col, acc); break;
+      case 5: init_gram_cx_chunk<QT, 5, RC, LDX>(X, kk, col, acc); break;
+      case 6: init_gram_cx_chunk<QT, 6, RC, LDX>(X, kk, col, acc); break;
+      default: init_gram_cx_chunk<QT, 7, RC, LDX>(X, kk, col, acc); break;
+    }
+  }
+  // this wave's tiles to the block's upper triangle: entry (i, j), i <= j < q,
+  // at o = i q - i (i - 1) / 2 + (j - i)
+  const int nout = q * (q + 1) / 2;
+  double2* out = a.part + (long)blockIdx.x * nout;
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int ti = wave + 8 * k;
+    if (ti < NCT) {
+      int ta = 0, rem = ti;
+      while (rem >= QT - ta) {
+        rem -= QT - ta;
+        ++ta;
+      }
+      const int tb = ta + rem;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * ta + M::row(lane, v), j = 16 * tb + col;
+        if (i <= j && j < q) out[i * q - i * (i - 1) / 2 + (j - i)] = make_double2(acc[2 * k][v], acc[2 * k + 1][v]);
+      }
+    }
+  }
+}
+
+hipError_t launch_init_gram_cx(const GramColsArgs& a, int nblk, hipStream_t s) {
+  if (a.m2 != 0 || !a.a_colmajor || a.m1 <= 48 || a.m1 > 128 || a.rows_per_block % 32 != 0)
+    return hipErrorInvalidValue;
+  const dim3 g(nblk), b(512);
+  switch ((a.m1 + 15) / 16) {
+    case 4: hipLaunchKernelGGL((k_init_gram_cx<4>), g, b, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_init_gram_cx<5>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_init_gram_cx<6>), g, b, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_init_gram_cx<7>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_init_gram_cx<8>), g, b, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_init_gram(const GramColsArgs& a, int nblk, hipStream_t s) {
   if (a.m2 != 0 || !a.a_colmajor || a.m1 < 1 || a.m1 > 48 || a.rows_per_block % 32 != 0) return hipErrorInvalidValue;
   const dim3 g(nblk), b(256);
