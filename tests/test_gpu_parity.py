@@ -120,8 +120,15 @@ def test_spectral_init_matches_oracle():
 
 
 @pytest.mark.parametrize("cfg", [(32, 32, 3, 8, 3, "lines", 10, True), (32, 32, 3, 8, 3, "index", 400, True),
-                                 (64, 32, 4, 12, 4, "lines", 12, False)],
-                         ids=["lines32", "index32", "lines64x32"])
+                                 (64, 32, 4, 12, 4, "lines", 12, False),
+                                 # frame counts at the eigen-solver's and the Gram's boundaries:
+                                 # q = 48 / 49 (real-tile / complex-tile Gram), q = 64 with r = 9
+                                 # (matrix in LDS, workgroup back-transformation), q = 65 and 128
+                                 # (packed lower triangle, the largest LDS footprint)
+                                 (32, 32, 2, 48, 6, "lines", 10, True), (32, 32, 2, 49, 6, "lines", 10, True),
+                                 (32, 32, 2, 64, 9, "lines", 10, True), (32, 32, 2, 65, 5, "lines", 10, True),
+                                 (32, 32, 2, 128, 16, "lines", 10, True)],
+                         ids=["lines32", "index32", "lines64x32", "q48", "q49", "q64r9", "q65", "q128r16"])
 def test_spectral_init_small_shapes(cfg):
     log(f"init {cfg}")
     nx, ny, nc, q, r, kind, lm, var = cfg
