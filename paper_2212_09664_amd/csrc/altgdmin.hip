@@ -270,6 +270,7 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
   s.npairs = (long)p.q * c->width;
   s.ysq_k = c->at<double>(c->o_ysq);
   s.B = c->at<float2>(c->o_B);
+  s.B_out = c->b_out;
   s.bcp = c->at<float2>(c->o_bcp);
   s.cost_k = c->at<double>(c->o_cost);
   s.st = c->st();
@@ -935,13 +936,15 @@ altgdmin_status altgdmin_iterate(altgdmin_ctx* c, int32_t n_iter, void* d_U, voi
     HIPCHK(hipMemcpy(&t0, &c->st()->t, sizeof(int32_t), hipMemcpyDeviceToHost));
   }
   HIPCHK(to_pixmajor(c, static_cast<const float2*>(d_U)));
+  // every solve also writes B to the caller's buffer (no copy launch after
+  // the loop; a halt part-way leaves there the last B computed)
+  struct CallScope {  // the caller's buffer is forgotten on every way out
+    altgdmin_ctx* c;
+    ~CallScope() { c->b_out = nullptr; }
+  } scope{c};
+  c->b_out = static_cast<float2*>(d_B);
   for (int t = 0; t < n_iter; ++t)
     HIPCHK(one_iteration(c, static_cast<float2*>(d_U), static_cast<float2*>(d_U_prev)));
-  if (d_B) {
-    hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, c->stream, c->at<float2>(c->o_B),
-                       static_cast<float2*>(d_B), (long)p.q * p.r);
-    HIPCHK(hipGetLastError());
-  }
   if (h_iters_done) {
     int32_t t1 = 0;
     HIPCHK(hipStreamSynchronize(c->stream));

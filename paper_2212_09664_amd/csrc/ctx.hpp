@@ -39,6 +39,9 @@ struct altgdmin_ctx {
   int gram_cg, gram_ngroups, gram_chunk;
   int adj_parts, adj_cgs;  // coil groups of the basis transforms (the adjoint's partial gradients)
   int adj_qr;              // 1: the adjoint sums every coil and forms the QR Gram partials (k_adj_qr)
+  // set by altgdmin_iterate for the duration of one call: the caller's B
+  // buffer, which every solve writes too
+  float2* b_out;
   int grad_parts;          // partial gradient arrays the adjoint writes
   int txx;                 // image columns per workgroup in the basis transforms
   size_t bytes;

@@ -69,6 +69,7 @@ struct SolveArgs {
   long npairs;           // LINES: pairs allocated per group in hp
   const double* ysq_k;
   float2* B;             // r x q
+  float2* B_out;         // non-null: B also written here (the caller's buffer)
   float2* bcp;           // LINES: conj(b_k) per pair, for the gradient fold
   double* cost_k;
   DevState* st;

@@ -534,6 +534,7 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
     hb = (double)hi.x * (double)sv.x + (double)hi.y * (double)sv.y;
     fin = isfinite((double)sv.x) && isfinite((double)sv.y);
     a.B[(long)k * r + i] = make_float2((float)sv.x, (float)sv.y);
+    if (a.B_out) a.B_out[(long)k * r + i] = make_float2((float)sv.x, (float)sv.y);
     z[i] = sv;
   }
   hb = wave_sum(hb);
