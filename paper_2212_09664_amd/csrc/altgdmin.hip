@@ -78,7 +78,7 @@ void carve(altgdmin_ctx* c) {
     c->o_P = take(sizeof(double2) * (size_t)c->gram_ngroups * p.ny * r * r);
     c->o_hp = take(sizeof(double2) * (size_t)c->gram_ngroups * q * c->width * r);
   } else {
-    c->o_P = take(sizeof(double2) * (size_t)q * c->nchunks * (r * r + r));
+    c->o_P = take(sizeof(double2) * (size_t)q * c->nchunks * nc * (r * r + r));
     c->o_hp = take(0);
   }
   c->o_B = take(sizeof(float2) * (size_t)q * r);
@@ -245,11 +245,12 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
     g.n = c->n;
     g.m_max = p.m_max;
     g.chunk = c->gram_chunk;
+    g.nchunks = c->nchunks;
     g.part = c->at<double2>(c->o_P);
     g.st = c->st();
     g.check_halt = check_halt;
     tmark(c, TK_GRAM);
-    e = launch_gram_index(g, c->nchunks, p.q, c->fp64, c->stream);
+    e = launch_gram_index(g, p.q, c->fp64, c->stream);
     tmark(c, TK_GRAM);
   }
   if (e != hipSuccess) return e;
@@ -264,7 +265,7 @@ hipError_t gram_solve(altgdmin_ctx* c, int check_halt) {
   s.nx = p.nx;
   s.r = p.r;
   s.kind = c->lines ? 0 : 1;
-  s.nchunks = c->nchunks;
+  s.nchunks = c->nchunks * p.nc;  // INDEX: partials per frame, one per (chunk, coil)
   s.ngroups = c->gram_ngroups;
   s.ua = c->ua;
   s.npairs = (long)p.q * c->width;
@@ -352,7 +353,7 @@ hipError_t gradient_pieces(altgdmin_ctx* c, int check_halt) {
   if (c->lines) {
     e = launch_fold2(fa, true, p.nc, p.ny, c->stream);
   } else {
-    e = launch_fold2(fa, false, (int)((c->n + AG_NT - 1) / AG_NT), p.nc, c->stream);
+    e = launch_fold2(fa, false, 0, p.nc, c->stream);  // the launcher sizes the grid
   }
   tmark(c, TK_FOLD);
   if (e != hipSuccess) return e;
@@ -726,7 +727,7 @@ altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** ou
   c->n_loc = c->lines ? p.ny : c->n;
   c->nw = (p.q + 31) / 32;
   c->ua = p.ny;
-  c->gram_chunk = std::max(32, 512 / p.nc);
+  c->gram_chunk = GRAM_INDEX_CHUNK;
   c->nchunks = (p.m_max + c->gram_chunk - 1) / c->gram_chunk;
   c->gram_cg = std::max(1, std::min(p.nc, 1024 / p.nx));
   c->gram_ngroups = (p.nc + c->gram_cg - 1) / c->gram_cg;

@@ -702,19 +702,26 @@ __global__ __launch_bounds__(AG_NT) void k_fold_lines_mma(FoldArgs a) {
 
 // gradient fold, general masks: per location and coil,
 //   K_c(loc,:) = sum_{(k,e) at loc} (W_c(loc,:) b_k - y_{k,c}(e)) conj(b_k)
+// FS adjacent lanes share a location and take every FS-th of its (frame,
+// sample) pairs; their partial sums meet by DPP at the end.  The pair counts
+// reach q at the centre of k-space (every spoke passes there) and are a few
+// at the edge, so splitting each location's list shortens the longest chain
+// of dependent loads by FS.
+constexpr int FOLD_FS = 4;  // lanes per location
 template <int RT>
 __global__ __launch_bounds__(AG_NT) void k_fold_index2(FoldArgs a) {
-  // B (every frame's b, q <= 128) staged once per workgroup; a location's
-  // (frame, sample) pairs and their data are loaded in batches of PB, all of
-  // a batch's loads in flight together (the pair counts reach q at the
-  // centre of k-space, where every spoke passes)
-  constexpr int PB = 8;
-  __shared__ float2 sB[128 * RT];
-  const int loc = blockIdx.x * AG_NT + threadIdx.x, c = blockIdx.y;
-  const int r = a.r, tid = threadIdx.x;
+  // B (every frame's b, q <= 128) staged once per workgroup, rows at an odd
+  // stride so that the frames read by the lanes of one instruction fall in
+  // different LDS banks; a lane's pairs and their data are loaded in batches
+  // of PB, all of a batch's loads in flight together
+  constexpr int PB = 8, FS = FOLD_FS, RTP = RT + 1;
+  __shared__ float2 sB[128 * RTP];
+  const int tid = threadIdx.x, sub = tid % FS;
+  const int loc = blockIdx.x * (AG_NT / FS) + tid / FS, c = blockIdx.y;
+  const int r = a.r;
   for (int e = tid; e < a.max_pairs * RT; e += AG_NT) {
     const int k = e / RT, j = e - k * RT;
-    sB[e] = (j < r) ? a.B[(long)k * r + j] : make_float2(0.f, 0.f);
+    sB[k * RTP + j] = (j < r) ? a.B[(long)k * r + j] : make_float2(0.f, 0.f);
   }
   const int lc = min(loc, a.n - 1);
   const long base = ((long)c * a.n + lc) * r;
@@ -729,17 +736,17 @@ __global__ __launch_bounds__(AG_NT) void k_fold_index2(FoldArgs a) {
   if (halted(a.st, a.check_halt)) return;
   const float2* yc = a.y + (long)c * a.m_max;
   const long ystride = (long)a.nc * a.m_max;
-  for (int pb = p0; pb < p1; pb += PB) {
+  for (int pb = p0 + sub; pb < p1; pb += PB * FS) {
     int2 ke[PB];
 #pragma unroll
-    for (int t = 0; t < PB; ++t) ke[t] = a.pairs[min(pb + t, p1 - 1)];
+    for (int t = 0; t < PB; ++t) ke[t] = a.pairs[min(pb + FS * t, p1 - 1)];
     float2 yv[PB];
 #pragma unroll
     for (int t = 0; t < PB; ++t) yv[t] = yc[ke[t].x * ystride + ke[t].y];
 #pragma unroll
     for (int t = 0; t < PB; ++t) {
-      if (pb + t < p1) {
-        const float2* bb = sB + ke[t].x * RT;
+      if (pb + FS * t < p1) {
+        const float2* bb = sB + ke[t].x * RTP;
         float2 res = make_float2(-yv[t].x, -yv[t].y);
 #pragma unroll
         for (int i = 0; i < RT; ++i) res = cfma(res, w[i], bb[i]);
@@ -748,10 +755,20 @@ __global__ __launch_bounds__(AG_NT) void k_fold_index2(FoldArgs a) {
       }
     }
   }
+  // the FS lanes of a location are all active here (they leave the loop
+  // above at different times but reconverge); sum over them, then lane
+  // `sub` stores columns j = sub, sub + FS, ...
+#pragma unroll
+  for (int j = 0; j < RT; ++j) {
+    kk[j].x += dpp_getf<DPP_XOR1>(kk[j].x);
+    kk[j].y += dpp_getf<DPP_XOR1>(kk[j].y);
+    kk[j].x += dpp_getf<DPP_XOR2>(kk[j].x);
+    kk[j].y += dpp_getf<DPP_XOR2>(kk[j].y);
+  }
   if (loc >= a.n) return;
 #pragma unroll
   for (int j = 0; j < RT; ++j)
-    if (j < r) a.K[base + j] = kk[j];
+    if (j < r && j % FS == sub) a.K[base + j] = kk[j];
 }
 
 // column-major (the C ABI's n x r layout) -> pixel-major r columns
@@ -868,9 +885,12 @@ hipError_t launch_fold2(const FoldArgs& a, bool lines, int grid_x, int grid_y, h
     else if (a.r <= 8) hipLaunchKernelGGL(k_fold_lines2<8>, g, dim3(AG_NT), 0, s, a);
     else hipLaunchKernelGGL(k_fold_lines2<16>, g, dim3(AG_NT), 0, s, a);
   } else {
-    if (a.r <= 4) hipLaunchKernelGGL(k_fold_index2<4>, g, dim3(AG_NT), 0, s, a);
-    else if (a.r <= 8) hipLaunchKernelGGL(k_fold_index2<8>, g, dim3(AG_NT), 0, s, a);
-    else hipLaunchKernelGGL(k_fold_index2<16>, g, dim3(AG_NT), 0, s, a);
+    // AG_NT / FOLD_FS locations per workgroup (grid_x is not used here)
+    const dim3 gi((unsigned)((a.n + AG_NT / FOLD_FS - 1) / (AG_NT / FOLD_FS)), grid_y);
+    if (a.r <= 4) hipLaunchKernelGGL(k_fold_index2<4>, gi, dim3(AG_NT), 0, s, a);
+    else if (a.r <= 8) hipLaunchKernelGGL(k_fold_index2<8>, gi, dim3(AG_NT), 0, s, a);
+    else if (a.r <= 12) hipLaunchKernelGGL(k_fold_index2<12>, gi, dim3(AG_NT), 0, s, a);
+    else hipLaunchKernelGGL(k_fold_index2<16>, gi, dim3(AG_NT), 0, s, a);
   }
   return hipGetLastError();
 }

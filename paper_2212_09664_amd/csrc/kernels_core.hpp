@@ -7,6 +7,7 @@
 #define SOLVE_NT 1024  // threads of the per-frame solve
 #define QR_NSM 2       // QR Gram: streams of 4 waves per workgroup
 #define GRAM_NWG 1     // per-line Gram: groups of 4 waves per workgroup
+#define GRAM_INDEX_CHUNK 512  // general masks: samples per Gram workgroup (one coil)
 #define GRAM_DS32 2    // per-line Gram, FP32: steps whose loads are issued together
 #define GRAM_DS64 4    // the same for FP64
 #define GCOLS_OPT 9   // outputs per thread in the column-Gram kernel (m <= 128)
@@ -52,7 +53,8 @@ struct GramIndexArgs {
   const int32_t* m_k;
   int nc, r, n, m_max;
   int chunk;             // samples per workgroup
-  double2* part;         // [k][chunk][r*r + r]
+  int nchunks;           // chunks per frame
+  double2* part;         // [k][chunk][c][r*r + r]
   DevState* st;
   int check_halt;
 };
@@ -238,6 +240,10 @@ __device__ __forceinline__ double dpp_get(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_getf(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
 #define DPP_XOR1 0xB1       // quad_perm [1,0,3,2]
 #define DPP_XOR2 0x4E       // quad_perm [2,3,0,1]
 #define DPP_ROR4 0x124      // row_ror:4
@@ -350,7 +356,7 @@ __global__ void k_init_eig(InitEigArgs a);
 
 hipError_t launch_gram_lines(const GramLinesArgs& a, int ny, int ngroups, int max_pairs, bool fp64,
                              hipStream_t s);
-hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp64, hipStream_t s);
+hipError_t launch_gram_index(const GramIndexArgs& a, int q, bool fp64, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s);
 hipError_t launch_gram_cols(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);
 hipError_t launch_qr_gram(const GramColsArgs& a, int nblk, bool fp64, hipStream_t s);

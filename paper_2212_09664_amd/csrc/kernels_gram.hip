@@ -18,8 +18,6 @@
 
 namespace ag {
 
-// largest sample chunk of a k_gram_index_mma workgroup (its indices go to LDS)
-constexpr int GRAM_INDEX_MAX_CHUNK = 2048;
 
 // ---------------------------------------------------------------------------
 // 1D Cartesian: one workgroup (4 waves) per (sampled line u, tile t of 8 of
@@ -293,98 +291,146 @@ __global__ __launch_bounds__(256 * NWG) void k_gram_lines_mma(GramLinesArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// general masks: one workgroup per (frame k, chunk of its samples); rows of K
-// are (c, sample).  Output part[k][chunk][r*r + r] (G entries, then h).
+// general masks: one workgroup per (frame k, chunk of its samples, coil c);
+// rows of K are the chunk's samples for that coil.  A row of A is the W row
+// as stored, Re W_0, Im W_0, Re W_1, .. (2r floats), then the sample's
+// Re y, Im y (2r + 2 columns, padded to TR tiles of 16), so that one
+// symmetric product A^T A carries the Gram and the right-hand side
+// together; only its upper tiles (ti <= tj) are formed.
+//   Re G_ij = C[2i][2j] + C[2i+1][2j+1],   Im G_ij = C[2i][2j+1] - C[2i+1][2j]
+//   Re h_j  = C[2j][2r] + C[2j+1][2r+1],   Im h_j  = C[2j][2r+1] - C[2j+1][2r]
+// Output part[k][chunk][c][r*r + r] (G entries, then h).
+// Workgroups are dealt to the eight XCDs in turn by their linear index, and
+// the index is laid out so that coil c runs on XCD c % 8: each XCD's L2 then
+// holds the transformed basis of one coil (n r complex values), which every
+// frame sampling a location gathers again.
 // ---------------------------------------------------------------------------
+template <int TR>
+__device__ __forceinline__ constexpr int utile(int ti, int tj) { return ti * TR - ti * (ti - 1) / 2 + (tj - ti); }
+
+constexpr int GRAM_XCDS = 8;
+
 template <typename T, int TR>
 __global__ __launch_bounds__(256) void k_gram_index_mma(GramIndexArgs a) {
   using M = Mma<T>;
-  __shared__ T red[(TR * TR + TR) * 256];
-  const int k = blockIdx.y, ch = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NT = TR * (TR + 1) / 2;
+  // the four waves' tiles, then (in wave 0's place) their sum: each sum
+  // entry is written by the thread that read its four terms
+  __shared__ T scr[4 * NT * 256];
+  T* const red = scr;
+  const int ncg = (a.nc + GRAM_XCDS - 1) / GRAM_XCDS;
+  int bid = blockIdx.x;
+  const int xg = bid % GRAM_XCDS;
+  bid /= GRAM_XCDS;
+  const int c = (bid % ncg) * GRAM_XCDS + xg;
+  bid /= ncg;
+  const int ch = bid % a.nchunks, k = bid / a.nchunks;
+  if (c >= a.nc) return;  // padding of the coil count to a multiple of 8
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (halted(a.st, a.check_halt)) return;
   const int r = a.r, col = lane & 15, kk = lane >> 4;
   const int mk = a.m_k[k];
   const int i0 = ch * a.chunk, i1 = min(mk, i0 + a.chunk);
   const int ns = max(0, i1 - i0);
-  const int rows = ns * a.nc;
-  int wj[TR], wim[TR];
-  bool wok[TR];
+  // batches of 32 samples, batch j taken by wave j % 4; in a batch, lane
+  // row kk of step u (4 rows per matrix-core step) is sample 8 kk + u, so
+  // that a lane's 8 sample locations are adjacent in LDS
+  constexpr int UB = 8;  // a multiple of 4 dividing GRAM_INDEX_CHUNK / 4
+  const int nbat = (ns + 4 * UB - 1) / (4 * UB);
+  typename M::V P[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) P[t] = M::zero();
+  // the chunk's samples staged once: their W row offsets (location x 2r
+  // floats, in bytes), so that the W gathers of a batch of steps do not wait on their
+  // index loads, and their data y; padded to whole batches with location 0
+  // (a valid address) and zero data
+  __shared__ __align__(16) int s_loc[GRAM_INDEX_CHUNK];
+  __shared__ float s_y[2 * GRAM_INDEX_CHUNK];
+  const float2* const yck = a.y + ((long)k * a.nc + c) * a.m_max + i0;
+  for (int e = tid; e < nbat * 4 * UB; e += 256) {
+    const bool ok = e < ns;
+    const int loc = a.mask[(long)k * a.m_max + i0 + min(e, max(ns - 1, 0))];
+    const float2 yv = yck[min(e, max(ns - 1, 0))];
+    s_loc[e] = ok ? loc * 8 * r : 0;
+    s_y[2 * e] = ok ? yv.x : 0.f;
+    s_y[2 * e + 1] = ok ? yv.y : 0.f;
+  }
+  __syncthreads();
+  // every load of a batch is issued before its matrix-core work; each lane
+  // loads from a valid address and padding and rows past the end are zeroed
+  // by a select
+  // (32-bit byte offsets from one base: the loads take the base from
+  // scalar registers and do no 64-bit address arithmetic)
+  const char* const Wc = reinterpret_cast<const char*>(a.W + (long)c * a.n * r);
+  // this lane's column of A in each tile, i = 16 t + col: float i of the W
+  // row (i < 2r), float i - 2r of the y sample (i = 2r, 2r + 1) or padding
+  int wi[TR], yi[TR];
+  bool isy[TR], used[TR];
 #pragma unroll
   for (int t = 0; t < TR; ++t) {
     const int i = 16 * t + col;
-    wok[t] = i < 2 * r;
-    wj[t] = (i < r) ? i : i - r;
-    wim[t] = (i >= r);
+    used[t] = i < 2 * r + 2;
+    isy[t] = used[t] && i >= 2 * r;
+    wi[t] = i < 2 * r ? 4 * i : 0;  // bytes
+    yi[t] = isy[t] ? i - 2 * r : 0;
   }
-  const bool ycol = (col == 0 || col == 8);
-  const int yim = col >> 3;
-  typename M::V P[TR][TR], H[TR];
+  for (int bj = wave; bj < nbat; bj += 4) {
+    const int s0 = 4 * UB * bj + UB * kk;
+    int lw[UB];
 #pragma unroll
-  for (int i = 0; i < TR; ++i) {
-    H[i] = M::zero();
-#pragma unroll
-    for (int j = 0; j < TR; ++j) P[i][j] = M::zero();
-  }
-  // the chunk's sample locations staged once, so that the W gathers of a
-  // batch of steps do not wait on their index loads
-  __shared__ int s_loc[GRAM_INDEX_MAX_CHUNK];
-  for (int e = tid; e < ns; e += 256) s_loc[e] = a.mask[(long)k * a.m_max + i0 + e];
-  __syncthreads();
-  const float* Wf = reinterpret_cast<const float*>(a.W);
-  const float* yk = reinterpret_cast<const float*>(a.y + (long)k * a.nc * a.m_max + i0) + yim;
-  // batches of UB steps of 4 rows per wave: every load of a batch issued
-  // before its matrix-core work
-  constexpr int UB = 8;
-  for (int rb = 4 * wave; rb < rows; rb += 16 * UB) {
-    T av[UB][TR], bv[UB];
+    for (int q4 = 0; q4 < UB / 4; ++q4) {
+      const int4 l = *reinterpret_cast<const int4*>(s_loc + s0 + 4 * q4);
+      lw[4 * q4] = l.x;
+      lw[4 * q4 + 1] = l.y;
+      lw[4 * q4 + 2] = l.z;
+      lw[4 * q4 + 3] = l.w;
+    }
+    float v[UB][TR], yv[UB][TR];
+    bool rv[UB];
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
-      const int rho = rb + 16 * u + kk;
-      const bool rv = rho < rows;
-      const int c = rv ? rho / ns : 0;
-      const int sm = rv ? rho - c * ns : 0;
-      const int loc = s_loc[sm];
+      rv[u] = s0 + u < ns;
 #pragma unroll
-      for (int t = 0; t < TR; ++t)
-        av[u][t] = (rv && wok[t]) ? (T)Wf[2 * (((long)c * a.n + loc) * r + wj[t]) + wim[t]] : (T)0;
-      bv[u] = (rv && ycol) ? (T)yk[2 * ((long)c * a.m_max + sm)] : (T)0;
+      for (int t = 0; t < TR; ++t) {
+        v[u][t] = *reinterpret_cast<const float*>(Wc + (unsigned)(lw[u] + wi[t]));
+        yv[u][t] = s_y[2 * (s0 + u) + yi[t]];
+      }
     }
+    // empty asm statements that take every loaded value, after all the
+    // batch's loads: without them the compiler moves each load under its
+    // select's condition below, where it is then waited for on its own
 #pragma unroll
-    for (int u = 0; u < UB; ++u) {
+    for (int u = 0; u < UB; ++u)
 #pragma unroll
-      for (int i = 0; i < TR; ++i)
+      for (int t = 0; t < TR; ++t) asm volatile("" : "+v"(v[u][t]), "+v"(yv[u][t]));
+    T av[UB][TR];
 #pragma unroll
-        for (int j = 0; j < TR; ++j) P[i][j] = M::mma(av[u][i], av[u][j], P[i][j]);
+    for (int u = 0; u < UB; ++u)
 #pragma unroll
-      for (int i = 0; i < TR; ++i) H[i] = M::mma(av[u][i], bv[u], H[i]);
-    }
+      for (int t = 0; t < TR; ++t) av[u][t] = (rv[u] && used[t]) ? (T)(isy[t] ? yv[u][t] : v[u][t]) : (T)0;
+#pragma unroll
+    for (int u = 0; u < UB; ++u)
+#pragma unroll
+      for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < TR; ++tj) P[utile<TR>(ti, tj)] = M::mma(av[u][ti], av[u][tj], P[utile<TR>(ti, tj)]);
   }
-  T* Pt = red;
-  T* Ht = red + TR * TR * 256;
-  {  // the P tiles, then the h tiles
-    constexpr int NTP = TR * TR + TR;
-    __shared__ T scr[4 * NTP * 256];
-    typename M::V all[NTP];
-#pragma unroll
-    for (int i = 0; i < TR; ++i) {
-      all[TR * TR + i] = H[i];
-#pragma unroll
-      for (int j = 0; j < TR; ++j) all[i * TR + j] = P[i][j];
-    }
-    tiles_reduce_par<T, 4, NTP>(red, scr, all, wave, lane);
-  }
-  auto C = [&](const T* base, int ntile_cols, int i, int j) -> double {
-    return (double)base[((i / 16) * ntile_cols + (j / 16)) * 256 + (i % 16) * 16 + (j % 16)];
+  tiles_reduce_par<T, 4, NT>(red, scr, P, wave, lane);
+  // C[i][j] of the full symmetric product from its upper tiles
+  auto C = [&](int i, int j) -> double {
+    const int ti = i / 16, tj = j / 16;
+    return ti <= tj ? (double)red[utile<TR>(ti, tj) * 256 + (i % 16) * 16 + (j % 16)]
+                    : (double)red[utile<TR>(tj, ti) * 256 + (j % 16) * 16 + (i % 16)];
   };
-  double2* out = a.part + ((long)k * gridDim.x + ch) * (r * r + r);
+  double2* out = a.part + (((long)k * a.nchunks + ch) * a.nc + c) * (r * r + r);
   for (int e = tid; e < r * r + r; e += 256) {
     if (e < r * r) {
       const int i = e / r, j = e % r;
-      out[e] = make_double2(C(Pt, TR, i, j) + C(Pt, TR, r + i, r + j), C(Pt, TR, i, r + j) - C(Pt, TR, r + i, j));
+      out[e] = make_double2(C(2 * i, 2 * j) + C(2 * i + 1, 2 * j + 1), C(2 * i, 2 * j + 1) - C(2 * i + 1, 2 * j));
     } else {
       const int j = e - r * r;
-      out[e] = make_double2(C(Ht, 1, j, 0) + C(Ht, 1, r + j, 8), C(Ht, 1, j, 8) - C(Ht, 1, r + j, 0));
+      out[e] = make_double2(C(2 * j, 2 * r) + C(2 * j + 1, 2 * r + 1), C(2 * j, 2 * r + 1) - C(2 * j + 1, 2 * r));
     }
   }
 }
@@ -485,13 +531,34 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(SolveArgs a) {
       __syncthreads();
     }
   } else {
-    for (int e = tid; e < E; e += SOLVE_NT) {
+    // sum over the frame's partials; thread = (entry, slice of partials)
+    const int NS = max(1, SOLVE_NT / E), SW = SOLVE_NT / NS;
+    const double2* const Pk = a.P + (long)k * a.nchunks * E;
+    for (int e0 = 0; e0 < E; e0 += SW) {
+      const int e = e0 + tid % SW;
+      const int sl = tid / SW;
       double2 s = make_double2(0.0, 0.0);
-      for (int ch = 0; ch < a.nchunks; ++ch) s = dadd(s, a.P[((long)k * a.nchunks + ch) * E + e]);
-      if (e < r * r)
-        G[(e / r) * 16 + (e % r)] = C::from(s);
-      else
-        h[e - r * r] = C::from(s);
+      if (e < E && sl < NS) {
+        constexpr int MI = 4;  // the first MI partials' loads issued together
+        double2 vv[MI];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) vv[i] = Pk[(long)min(sl + i * NS, a.nchunks - 1) * E + e];
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+          if (sl + i * NS < a.nchunks) s = dadd(s, vv[i]);
+        for (int ch = sl + MI * NS; ch < a.nchunks; ch += NS) s = dadd(s, Pk[(long)ch * E + e]);
+      }
+      part[tid] = s;
+      __syncthreads();
+      if (tid < SW && e < E) {
+        double2 t = part[tid];
+        for (int q2 = 1; q2 < NS; ++q2) t = dadd(t, part[tid + q2 * SW]);
+        if (e < r * r)
+          G[(e / r) * 16 + (e % r)] = C::from(t);
+        else
+          h[e - r * r] = C::from(t);
+      }
+      __syncthreads();
     }
   }
   __syncthreads();
@@ -587,15 +654,18 @@ hipError_t launch_gram_lines(const GramLinesArgs& a, int ny, int ngroups, int ma
   return hipGetLastError();
 }
 
-hipError_t launch_gram_index(const GramIndexArgs& a, int nchunks, int q, bool fp64, hipStream_t s) {
-  const int tr = (2 * a.r + 15) / 16;
-  const dim3 g(nchunks, q);
+hipError_t launch_gram_index(const GramIndexArgs& a, int q, bool fp64, hipStream_t s) {
+  const int tr = (2 * a.r + 2 + 15) / 16;  // W's 2r real columns and y's two
+  const int ncg = (a.nc + GRAM_XCDS - 1) / GRAM_XCDS;
+  const dim3 g((unsigned)q * a.nchunks * ncg * GRAM_XCDS);
   if (fp64) {
     if (tr == 1) hipLaunchKernelGGL((k_gram_index_mma<double, 1>), g, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_gram_index_mma<double, 2>), g, dim3(256), 0, s, a);
+    else if (tr == 2) hipLaunchKernelGGL((k_gram_index_mma<double, 2>), g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_gram_index_mma<double, 3>), g, dim3(256), 0, s, a);
   } else {
     if (tr == 1) hipLaunchKernelGGL((k_gram_index_mma<float, 1>), g, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_gram_index_mma<float, 2>), g, dim3(256), 0, s, a);
+    else if (tr == 2) hipLaunchKernelGGL((k_gram_index_mma<float, 2>), g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_gram_index_mma<float, 3>), g, dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
