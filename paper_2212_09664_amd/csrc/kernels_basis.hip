@@ -369,24 +369,54 @@ __global__ __launch_bounds__(512) void k_adj_qr(BasisArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// general masks: the x half of the 2D transform, in place on W or K, one
-// workgroup per (coil, ky) row of nx x r values.
+// general masks: the x half of the 2D transform, in place on W or K.  One
+// workgroup per a.txx consecutive (coil, ky) rows of nx x r values, the
+// rows side by side as the transform's columns (col = row * r + j); the
+// first pass is fed from registers and the last one stays there.
 // ---------------------------------------------------------------------------
 template <int N, int CT, bool INV>
 __global__ __launch_bounds__(AG_NT) void k_basis_rows(BasisArgs a) {
-  __shared__ float2 s[N * CT];
+  using GM = FftGeom<N, CT, AG_NT>;
+  constexpr int IT0 = GM::IT0, R0 = GM::R0, ITL = GM::ITL, RL = GM::RL;
+  __shared__ float2 s[FftPlan<N>::P > 1 ? N * CT : 1];
+  __shared__ float2 s_tw[N];
   const int tid = threadIdx.x, r = a.r;
-  if (halted(a.st, a.check_halt)) return;
-  float2* row = (INV ? a.K : a.W) + (long)blockIdx.x * N * r;
-  for (int g = tid; g < N * CT; g += AG_NT) {
-    const int x = g / CT, j = g % CT;
-    s[g] = (j < r) ? row[(long)x * r + j] : make_float2(0.f, 0.f);
+  const int tyy = a.txx, ctr = tyy * r;
+  const long nrows = (long)a.nc * a.ua;
+  const long row0 = (long)blockIdx.x * tyy;
+  float2* const base = (INV ? a.K : a.W) + row0 * N * r;
+  // loads from clamped, valid addresses (column 0 of the first row), zeroed
+  // outside the tile after the load
+  float2 v0[IT0][R0];
+  bool okg[IT0];
+#pragma unroll
+  for (int it = 0; it < IT0; ++it) {
+    const int g0 = tid + it * AG_NT, col0 = g0 % CT;
+    okg[it] = GM::in_ok(g0) && col0 < ctr && row0 + col0 / r < nrows;
+    const int g = okg[it] ? g0 : 0, col = g % CT, yy = col / r, j = col - yy * r;
+#pragma unroll
+    for (int q = 0; q < R0; ++q) v0[it][q] = base[((long)yy * N + GM::in_row(g, q)) * r + j];
   }
+  for (int e = tid; e < N; e += AG_NT) {
+    const float2 t = a.tw_x[e];
+    s_tw[e] = INV ? make_float2(t.x, -t.y) : t;  // the inverse takes the conjugated table
+  }
+  if (halted(a.st, a.check_halt)) return;
+#pragma unroll
+  for (int it = 0; it < IT0; ++it)
+#pragma unroll
+    for (int q = 0; q < R0; ++q)
+      if (!okg[it]) v0[it][q] = make_float2(0.f, 0.f);
   __syncthreads();
-  fft_lds<N, CT, AG_NT, INV>(s, a.tw_x);
-  for (int g = tid; g < N * CT; g += AG_NT) {
-    const int x = g / CT, j = g % CT;
-    if (j < r) row[(long)x * r + j] = cscale(s[g], a.scale_x);
+  float2 vo[ITL][RL];
+  fft_regs<N, CT, AG_NT, INV>(v0, vo, s, s_tw);
+#pragma unroll
+  for (int it = 0; it < ITL; ++it) {
+    const int g = tid + it * AG_NT, col = g % CT, yy = col / r, j = col - yy * r;
+    if (GM::out_ok(g) && col < ctr && row0 + yy < nrows) {
+#pragma unroll
+      for (int q = 0; q < RL; ++q) base[((long)yy * N + GM::out_row(g, q)) * r + j] = cscale(vo[it][q], a.scale_x);
+    }
   }
 }
 
@@ -821,8 +851,17 @@ static void launch_basis_n(int which, const BasisArgs& a, int grid_x, int grid_y
   const dim3 g(grid_x, grid_y);
   if (which == 0) hipLaunchKernelGGL((k_basis_fwd<N, CT>), g, dim3(AG_NT), 0, s, a);
   else if (which == 1) hipLaunchKernelGGL((k_basis_adj<N, CT>), g, dim3(AG_NT), 0, s, a);
-  else if (which == 2) hipLaunchKernelGGL((k_basis_rows<N, CT, false>), g, dim3(AG_NT), 0, s, a);
-  else hipLaunchKernelGGL((k_basis_rows<N, CT, true>), g, dim3(AG_NT), 0, s, a);
+  else {
+    // the x pass: grid_x (coil, ky) rows, a.txx of them per workgroup side
+    // by side as the transform's columns (at most CT columns)
+    BasisArgs b = a;
+    int tyy = 1;
+    while (2 * tyy * a.r <= CT && grid_x % (2 * tyy) == 0) tyy *= 2;
+    b.txx = tyy;
+    const dim3 gr((unsigned)(grid_x / tyy), grid_y);
+    if (which == 2) hipLaunchKernelGGL((k_basis_rows<N, CT, false>), gr, dim3(AG_NT), 0, s, b);
+    else hipLaunchKernelGGL((k_basis_rows<N, CT, true>), gr, dim3(AG_NT), 0, s, b);
+  }
 }
 
 hipError_t launch_basis(int which, int N, const BasisArgs& a, int grid_x, int grid_y, hipStream_t s) {

@@ -514,7 +514,7 @@ __device__ __forceinline__ float2 rfac_entry(const double2* L, int r, int e) {
 // mode 1: plain CholeskyQR of U (no gradient).
 // ===========================================================================
 template <int RT>
-__global__ __launch_bounds__(RT <= 8 ? 1024 : 256) void k_qr_small(QrSmallArgs a) {
+__global__ __launch_bounds__(1024) void k_qr_small(QrSmallArgs a) {
   __shared__ double2 UU[256], UG[256], GG[256], Gh[256], Tm[256];
   __shared__ JacobiScratch js;
   __shared__ int s_ok;
@@ -1813,8 +1813,9 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s) {
 
 hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
   // the 16-row form keeps its one-wave registers with 256 threads
+  // 1,024 threads: the partial sums at the start take most of its time
   if (a.r <= 8) hipLaunchKernelGGL(k_qr_small<8>, dim3(1), dim3(1024), 0, s, a);
-  else hipLaunchKernelGGL(k_qr_small<16>, dim3(1), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_qr_small<16>, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
