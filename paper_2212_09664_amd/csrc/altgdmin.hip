@@ -744,7 +744,11 @@ altgdmin_status altgdmin_create(const altgdmin_params* params, altgdmin_ctx** ou
   c->qr_rows = ((long)c->n + c->qr_nblk - 1) / c->qr_nblk;
   c->qr_rows = (c->qr_rows + 127) / 128 * 128;
   c->qr_nblk = (int)((c->n + c->qr_rows - 1) / c->qr_rows);
-  c->kc = std::min(p.q, 16);
+  {  // general masks: frames per pass of the operator's per-coil k-space images,
+     // as many as fit 256 MiB (at least 16): fewer, larger launches
+    const double per_frame = 8.0 * p.nc * (double)c->n;
+    c->kc = std::min(p.q, std::max(16, (int)std::min(1e9, (256.0 * 1024 * 1024) / per_frame)));
+  }
   carve(c);
   *out = c;
   return ALTGDMIN_OK;

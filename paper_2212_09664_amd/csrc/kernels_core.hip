@@ -33,49 +33,73 @@ __global__ void k_inv_bitmap(const int32_t* mask, const int32_t* m_k, int width,
   if (old & bit) set_error(st, 1 /*EINVAL: repeated location in a frame*/, k);
 }
 
+// the locations' sample counts and their exclusive prefix sums (pairs per
+// location), and the sampled locations (units) numbered in order; one block
+// of 1024 threads over tiles of 1024 locations, scans within waves by
+// shuffles, a running total across tiles
 __global__ __launch_bounds__(1024) void k_inv_scan(const uint32_t* bitmap, int nw, int n_loc,
                                                    int32_t* loc_ptr, int32_t* loc2unit,
                                                    int32_t* unit_loc, int2* unit_span, DevState* st) {
-  __shared__ int s_cnt[1024], s_un[1024];
-  const int tid = threadIdx.x;
-  const int chunk = (n_loc + 1023) / 1024;
-  const int a = tid * chunk, b = min(n_loc, a + chunk);
-  int cnt = 0, un = 0;
-  for (int l = a; l < b; ++l) {
-    int c = 0;
-    for (int w = 0; w < nw; ++w) c += __popc(bitmap[(long)l * nw + w]);
-    cnt += c;
-    un += (c > 0);
-  }
-  s_cnt[tid] = cnt;
-  s_un[tid] = un;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
-    int vc = (tid >= off) ? s_cnt[tid - off] : 0;
-    int vu = (tid >= off) ? s_un[tid - off] : 0;
-    __syncthreads();
-    s_cnt[tid] += vc;
-    s_un[tid] += vu;
-    __syncthreads();
-  }
-  int pc = s_cnt[tid] - cnt, pu = s_un[tid] - un;
-  for (int l = a; l < b; ++l) {
-    int c = 0;
-    for (int w = 0; w < nw; ++w) c += __popc(bitmap[(long)l * nw + w]);
-    loc_ptr[l] = pc;
-    if (c > 0) {
-      loc2unit[l] = pu;
-      unit_loc[pu] = l;
-      unit_span[pu] = make_int2(pc, c);  // the unit's samples: pairs [pc, pc + c)
-      ++pu;
-    } else {
-      loc2unit[l] = -1;
+  constexpr int LPT = 1;  // locations per thread and tile (4: slower, the loads less coalesced)
+  __shared__ int s_wc[16], s_wu[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int carry_c = 0, carry_u = 0;  // totals of the tiles before this one
+  for (int base = 0; base < n_loc; base += 1024 * LPT) {
+    const int l0 = base + LPT * tid;
+    int cs[LPT], tc = 0, tu = 0;
+#pragma unroll
+    for (int s2 = 0; s2 < LPT; ++s2) {
+      const int l = l0 + s2, lc = min(l, n_loc - 1);
+      int c = 0;
+      for (int w = 0; w < nw; ++w) c += __popc(bitmap[(long)lc * nw + w]);
+      cs[s2] = l < n_loc ? c : 0;
+      tc += cs[s2];
+      tu += cs[s2] > 0;
     }
-    pc += c;
+    int sc = tc, su = tu;  // inclusive scans over the wave
+    for (int off = 1; off < 64; off <<= 1) {
+      const int vc = __shfl_up(sc, off), vu = __shfl_up(su, off);
+      if (lane >= off) {
+        sc += vc;
+        su += vu;
+      }
+    }
+    if (lane == 63) {
+      s_wc[wv] = sc;
+      s_wu[wv] = su;
+    }
+    __syncthreads();
+    int pc = carry_c + sc - tc, pu = carry_u + su - tu;  // exclusive prefixes of this thread's first location
+    for (int w2 = 0; w2 < 16; ++w2) {
+      const int vc = s_wc[w2], vu = s_wu[w2];
+      if (w2 < wv) {
+        pc += vc;
+        pu += vu;
+      }
+      carry_c += vc;
+      carry_u += vu;
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < LPT; ++s2) {
+      const int l = l0 + s2, c = cs[s2];
+      if (l < n_loc) {
+        loc_ptr[l] = pc;
+        if (c > 0) {
+          loc2unit[l] = pu;
+          unit_loc[pu] = l;
+          unit_span[pu] = make_int2(pc, c);  // the unit's samples: pairs [pc, pc + c)
+          ++pu;
+        } else {
+          loc2unit[l] = -1;
+        }
+      }
+      pc += c;
+    }
+    __syncthreads();  // the wave totals are read before the next tile writes them
   }
-  if (tid == 1023) {
-    loc_ptr[n_loc] = s_cnt[1023];
-    st->n_units = s_un[1023];
+  if (tid == 0) {
+    loc_ptr[n_loc] = carry_c;
+    st->n_units = carry_u;
   }
 }
 

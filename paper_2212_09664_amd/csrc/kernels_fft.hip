@@ -343,7 +343,13 @@ __global__ void k_scatter(const float2* y, const int32_t* mask, const int32_t* m
 
 __global__ void k_zero(float2* p, long n) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  long stride = (long)gridDim.x * blockDim.x;
+  const long stride = (long)gridDim.x * blockDim.x;
+  if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {  // 16-byte stores: two values per lane
+    float4* p4 = reinterpret_cast<float4*>(p);
+    for (long j = i; j < n / 2; j += stride) p4[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i == 0 && (n & 1)) p[n - 1] = make_float2(0.f, 0.f);
+    return;
+  }
   for (; i < n; i += stride) p[i] = make_float2(0.f, 0.f);
 }
 
