@@ -67,6 +67,60 @@ __global__ __launch_bounds__(AG_NT) void k_rows(RowArgs a) {
   }
 }
 
+// the same, register-fed (64 <= N <= 256): each thread's rows are loaded straight
+// into the first radix pass (clamped rows, invalid ones zeroed after the
+// load) and the last pass is stored from registers
+template <int N, int TR, bool INV>
+__global__ __launch_bounds__(AG_NT) void k_rows_regs(RowArgs a) {
+  using GM = FftGeom<N, TR, AG_NT>;
+  constexpr int IT0 = GM::IT0, R0 = GM::R0, ITL = GM::ITL, RL = GM::RL;
+  __shared__ float2 s[FftPlan<N>::P > 1 ? N * TR : 1];
+  __shared__ float2 s_tw[N];
+  const int tid = threadIdx.x;
+  const long rho0 = (long)blockIdx.x * TR;
+  float2 v0[IT0][R0];
+  bool okr[IT0];
+#pragma unroll
+  for (int it = 0; it < IT0; ++it) {
+    const int g0 = tid + it * AG_NT, gg = GM::in_ok(g0) ? g0 : 0;
+    const long rho = rho0 + gg % TR, rc = min(rho, a.nrows - 1);
+    okr[it] = GM::in_ok(g0) && rho < a.nrows && row_valid(a, rc, N);
+#pragma unroll
+    for (int q = 0; q < R0; ++q) v0[it][q] = a.src[rc * N + GM::in_row(gg, q)];
+  }
+  for (int e = tid; e < N; e += AG_NT) {
+    const float2 w = a.tw[e];
+    s_tw[e] = INV ? make_float2(w.x, -w.y) : w;  // the inverse takes the conjugated table
+  }
+  if (halted(a.st, a.check_halt)) return;
+  const double gamma = a.trunc ? a.st->gamma : 0.0;
+  int n_cut = 0;
+#pragma unroll
+  for (int it = 0; it < IT0; ++it)
+#pragma unroll
+    for (int q = 0; q < R0; ++q) {
+      const float2 v = v0[it][q];
+      const bool cut = a.trunc && okr[it] && ((double)v.x * v.x + (double)v.y * v.y > gamma);
+      n_cut += cut;
+      if (!okr[it] || cut) v0[it][q] = make_float2(0.f, 0.f);
+    }
+  if (n_cut && a.trunc_count) atomicAdd(a.trunc_count, n_cut);
+  __syncthreads();
+  float2 vo[ITL][RL];
+  fft_regs<N, TR, AG_NT, INV>(v0, vo, s, s_tw);
+#pragma unroll
+  for (int it = 0; it < ITL; ++it) {
+    const int g = tid + it * AG_NT;
+    const long rho = rho0 + g % TR;
+    if (GM::out_ok(g) && rho < a.nrows) {
+      const bool valid = row_valid(a, rho, N);
+#pragma unroll
+      for (int q = 0; q < RL; ++q)
+        a.dst[rho * N + GM::out_row(g, q)] = valid ? cscale(vo[it][q], a.scale) : make_float2(0.f, 0.f);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // forward column transform: dst rows = F_y (s_c o src_img) restricted to a
 // row list.  Grid (nx/TX, n_img, nc).
@@ -215,30 +269,34 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj(ColAdjArgs a) {
 
 // ---------------------------------------------------------------------------
 // the column adjoint with the coil combine for 1D line masks, register-fed:
-// one workgroup per (CT-column tile, image); the image's sampled rows enter
-// the first radix pass straight from registers through an inverse row map in
+// one workgroup per (CT-column tile, image), NG groups of 256 threads, group
+// g transforming coils g, g + NG, ...; the image's sampled rows enter the
+// first radix pass straight from registers through an inverse row map in
 // LDS (k-space row -> the image's line holding it, -1 for a zero row), the
-// coil-weighted sum is taken on the last pass's registers, the next coil's
-// rows are loaded during the current transform.  Grid (nx / CT, images).
+// coil-weighted sum is taken on the last pass's registers and the groups'
+// sums meet in LDS at the end; the next coil's rows are loaded during the
+// current transform.  Grid (nx / CT, images).
 // ---------------------------------------------------------------------------
-template <int N, int CT>
-__global__ __launch_bounds__(AG_NT) void k_cols_adj_lines(ColAdjArgs a) {
+template <int N, int CT, int NG>
+__global__ __launch_bounds__(AG_NT * NG) void k_cols_adj_lines(ColAdjArgs a) {
   using GM = FftGeom<N, CT, AG_NT>;
   constexpr int IT0 = GM::IT0, R0 = GM::R0, ITL = GM::ITL, RL = GM::RL;
-  __shared__ float2 s[FftPlan<N>::P > 1 ? N * CT : 1];
+  static_assert(FftPlan<N>::P > 1, "the groups' sums meet in the transform's LDS tiles");
+  __shared__ float2 s[NG][N * CT];
   __shared__ float2 s_tw[N];
   __shared__ int s_li[N];
-  const int tid = threadIdx.x, x0 = blockIdx.x * CT, img = blockIdx.y;
+  const int tid = threadIdx.x, grp = tid / AG_NT, lt = tid % AG_NT;
+  const int x0 = blockIdx.x * CT, img = blockIdx.y;
   if (halted(a.st, a.check_halt)) return;  // (a mask that failed its checks at bind sets err)
   const int n_rows = a.m_k_rows[img] / a.nx;
   const int32_t* rows = a.rows + (long)img * a.rows_img_stride;
-  for (int e = tid; e < N; e += AG_NT) {
+  for (int e = tid; e < N; e += AG_NT * NG) {
     const float2 w = a.tw[e];
     s_tw[e] = make_float2(w.x, -w.y);  // the forward table conjugated: the inverse twiddles
     s_li[e] = -1;
   }
   __syncthreads();
-  for (int l = tid; l < n_rows; l += AG_NT) s_li[min(max(rows[l], 0), N - 1)] = l;  // an image's rows are distinct
+  for (int l = tid; l < n_rows; l += AG_NT * NG) s_li[min(max(rows[l], 0), N - 1)] = l;  // an image's rows are distinct
   __syncthreads();
   float2 acc[ITL][RL];
 #pragma unroll
@@ -250,16 +308,16 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj_lines(ColAdjArgs a) {
   for (int it = 0; it < IT0; ++it)
 #pragma unroll
     for (int q = 0; q < R0; ++q) {
-      const int g = tid + it * AG_NT;
+      const int g = lt + it * AG_NT;
       li[it][q] = GM::in_ok(g) ? s_li[GM::in_row(g, q)] : -1;
     }
   const float2* const src0 = a.src + (long)img * a.src_img_stride + x0;
   float2 kv[IT0][R0];
   auto fetch = [&](int c) {  // valid addresses for every lane; zero rows selected afterwards
-    const float2* src = src0 + (long)c * a.src_c_stride;
+    const float2* src = src0 + (long)min(c, a.nc - 1) * a.src_c_stride;
 #pragma unroll
     for (int it = 0; it < IT0; ++it) {
-      const int col = (tid + it * AG_NT) % CT;
+      const int col = (lt + it * AG_NT) % CT;
 #pragma unroll
       for (int q = 0; q < R0; ++q) {
         const float2 v = src[(long)max(li[it][q], 0) * a.nx + col];
@@ -267,35 +325,58 @@ __global__ __launch_bounds__(AG_NT) void k_cols_adj_lines(ColAdjArgs a) {
       }
     }
   };
-  fetch(0);
-  for (int c = 0; c < a.nc; ++c) {
+  fetch(grp);
+  // every group runs the same number of rounds (the transforms' barriers are
+  // the workgroup's); a group past the last coil transforms a copy of it and
+  // does not add it
+  for (int c0 = 0; c0 < a.nc; c0 += NG) {
+    const int c = c0 + grp;
     float2 v0[IT0][R0], vo[ITL][RL];
 #pragma unroll
     for (int it = 0; it < IT0; ++it)
 #pragma unroll
       for (int q = 0; q < R0; ++q) v0[it][q] = kv[it][q];
-    if (c + 1 < a.nc) fetch(c + 1);
-    fft_regs<N, CT, AG_NT, true>(v0, vo, s, s_tw);
+    if (c0 + NG < a.nc) fetch(c + NG);
+    fft_regs<N, CT, AG_NT, true>(v0, vo, s[grp], s_tw);
     // the coil values at the output rows come from the cache (every image
     // reads the same maps); loading them one coil ahead cost more in
     // registers than it saved
-    const float2* coil = a.coils + (long)c * a.n + x0;
+    if (c < a.nc) {
+      const float2* coil = a.coils + (long)c * a.n + x0;
 #pragma unroll
-    for (int it = 0; it < ITL; ++it) {
-      const int g = tid + it * AG_NT, col = g % CT;
-      if (GM::out_ok(g)) {
+      for (int it = 0; it < ITL; ++it) {
+        const int g = lt + it * AG_NT, col = g % CT;
+        if (GM::out_ok(g)) {
 #pragma unroll
-        for (int q = 0; q < RL; ++q)
-          acc[it][q] = cjfma(acc[it][q], coil[(long)GM::out_row(g, q) * a.nx + col], vo[it][q]);
+          for (int q = 0; q < RL; ++q)
+            acc[it][q] = cjfma(acc[it][q], coil[(long)GM::out_row(g, q) * a.nx + col], vo[it][q]);
+        }
       }
     }
+  }
+  // the groups' sums: groups 1.. leave theirs in their (now free) LDS tiles
+  if constexpr (NG > 1) {
+    if (grp > 0) {
+#pragma unroll
+      for (int it = 0; it < ITL; ++it)
+#pragma unroll
+        for (int q = 0; q < RL; ++q) s[grp][(it * RL + q) * AG_NT + lt] = acc[it][q];
+    }
+    __syncthreads();
+    if (grp > 0) return;
+#pragma unroll
+    for (int g2 = 1; g2 < NG; ++g2)
+#pragma unroll
+      for (int it = 0; it < ITL; ++it)
+#pragma unroll
+        for (int q = 0; q < RL; ++q) acc[it][q] = cadd(acc[it][q], s[g2][(it * RL + q) * AG_NT + lt]);
   }
   float sc = a.scale;
   if (a.m_k_scale) sc *= (float)(1.0 / sqrt((double)a.m_k_scale[img] * a.st->mbar));
   float2* dst = a.dst + (long)img * a.dst_img_stride + x0;
 #pragma unroll
   for (int it = 0; it < ITL; ++it) {
-    const int g = tid + it * AG_NT, col = g % CT;
+    const int g = lt + it * AG_NT, col = g % CT;
     if (GM::out_ok(g)) {
 #pragma unroll
       for (int q = 0; q < RL; ++q) {
@@ -360,10 +441,17 @@ template <int N>
 static hipError_t launch_rows_n(const RowArgs& a, bool inv, hipStream_t st) {
   constexpr int TR = ColTile<N>::TX;
   dim3 grid((unsigned)((a.nrows + TR - 1) / TR));
-  if (inv)
-    hipLaunchKernelGGL((k_rows<N, TR, true>), grid, dim3(AG_NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_rows<N, TR, false>), grid, dim3(AG_NT), 0, st, a);
+  if constexpr (N >= 64 && N <= 256) {  // the lengths the tests cover
+    if (inv)
+      hipLaunchKernelGGL((k_rows_regs<N, TR, true>), grid, dim3(AG_NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_rows_regs<N, TR, false>), grid, dim3(AG_NT), 0, st, a);
+  } else {
+    if (inv)
+      hipLaunchKernelGGL((k_rows<N, TR, true>), grid, dim3(AG_NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_rows<N, TR, false>), grid, dim3(AG_NT), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -420,17 +508,20 @@ static hipError_t launch_cols_n(const ColFwdArgs* f, const ColAdjArgs* d, int nx
   return hipErrorInvalidValue;
 }
 
+constexpr int COLS_NG = 2;  // coil groups of the line back-projection's workgroup
+
 hipError_t launch_cols(int N, const ColFwdArgs* f, const ColAdjArgs* d, int nx, int n_img, int nc,
                        hipStream_t st) {
   if (n_img <= 0) return hipSuccess;
   // line masks, every coil in one workgroup: the register-fed transform
   if (d && d->m_k_rows && (d->cgs <= 0 || d->cgs >= d->nc)) {
+    // two groups of 256 threads, each over every other coil (four spill)
     if (N == 256 && nx % 16 == 0) {
-      hipLaunchKernelGGL((k_cols_adj_lines<256, 16>), dim3(nx / 16, n_img), dim3(AG_NT), 0, st, *d);
+      hipLaunchKernelGGL((k_cols_adj_lines<256, 16, COLS_NG>), dim3(nx / 16, n_img), dim3(AG_NT * COLS_NG), 0, st, *d);
       return hipGetLastError();
     }
     if (N == 128 && nx % 32 == 0) {
-      hipLaunchKernelGGL((k_cols_adj_lines<128, 32>), dim3(nx / 32, n_img), dim3(AG_NT), 0, st, *d);
+      hipLaunchKernelGGL((k_cols_adj_lines<128, 32, COLS_NG>), dim3(nx / 32, n_img), dim3(AG_NT * COLS_NG), 0, st, *d);
       return hipGetLastError();
     }
   }
