@@ -161,6 +161,40 @@ def _nmse(U_prev, B, zstar, zz):
     return float(torch.sum(torch.abs(X - zstar.to(torch.complex128)) ** 2).item()) / zz
 
 
+def warm_start(ctx, net, params, xbuf, U, M=None, choice=None, side=None):
+    """The learned warm start into U: the network input (2q back-projected
+    planes), the forward pass M = f(planes), then the cost-based pick
+    between the spectral basis and QR(M) (altgdmin_init_warm).
+
+    With `side`, a second stream that `net` was created on, the forward pass
+    runs there beside the spectral initialisation, whose eigen-solver keeps
+    one workgroup busy for most of its time: the spectral basis comes from
+    init on the context's stream, and init_warm_from then scores both
+    exactly as init_warm does.  M (B, r, n) may be given to avoid an
+    allocation per call."""
+    import torch
+    s = ctx.stream
+    if M is None:
+        M = torch.empty(xbuf.shape[0], ctx.p.r, ctx.n, dtype=torch.complex64, device=xbuf.device)
+    ctx.cnn_input(xbuf[0])
+    if side is None:
+        net.forward(params, xbuf, M)
+        ctx.init_warm(M[0], U, choice)
+        return U
+    if net.stream.cuda_stream != side.cuda_stream:
+        raise ValueError("warm_start: the network must run on the side stream")
+    planes_ready = torch.cuda.Event()
+    planes_ready.record(s)
+    side.wait_event(planes_ready)
+    net.forward(params, xbuf, M)
+    guess_ready = torch.cuda.Event()
+    guess_ready.record(side)
+    ctx.init(U)
+    s.wait_event(guess_ready)
+    ctx.init_warm_from(M[0], U, U, choice)
+    return U
+
+
 def time_to_target(ag, torch, ctx, zstar, warm=None, target=2e-2, t_max=70):
     """(iterations, GPU ms, kept-learned flag) to NMSE <= target; the clock
     covers the initialisation (and, for the warm start, the network input
@@ -179,9 +213,7 @@ def time_to_target(ag, torch, ctx, zstar, warm=None, target=2e-2, t_max=70):
         ctx.init(U)
     else:
         net, params, xbuf = warm
-        ctx.cnn_input(xbuf[0])
-        M = net.forward(params, xbuf)
-        ctx.init_warm(M[0], U, choice)
+        warm_start(ctx, net, params, xbuf, U, choice=choice)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
