@@ -516,7 +516,7 @@ def main():
                     help="only time plain device copies, reads and writes of several sizes (practical ceilings)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the method's x-column sharding is a design note, not code).", file=sys.stderr)
         sys.exit(2)
     import torch

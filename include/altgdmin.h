@@ -81,7 +81,7 @@ typedef enum {
   ALTGDMIN_EHIP = 3,        /* a HIP runtime call failed                    */
   ALTGDMIN_ENOTPD = 4,      /* a Gram matrix was not positive definite      */
   ALTGDMIN_ENONFINITE = 5,  /* a NaN or Inf appeared                         */
-  ALTGDMIN_EUNSUPPORTED = 6, /* valid but not supported by this build        */
+  ALTGDMIN_EUNSUPPORTED = 6, /* valid but not supported by this library      */
   ALTGDMIN_ESCRATCH = 7      /* problem too large for the built-in scratch     */
 } altgdmin_status;
 
