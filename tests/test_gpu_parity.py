@@ -206,6 +206,29 @@ def test_end_to_end_ranks_around_the_step_kernels(r, precision):
     assert ctx.get_eta() == pytest.approx(ref.eta, rel=1e-4)
 
 
+@pytest.mark.parametrize("r", [5, 8, 13, 16])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "mixed"])
+def test_end_to_end_general_mask_ranks(r, precision):
+    """General (index) masks at ranks that take each shape of the per-frame
+    Gram (the W row and the sample's y as 2r + 2 real columns in one, two or
+    three 16-column tiles) and of the fold's register tile (8, 16), with two
+    sample chunks per frame (the second ragged) and a coil count below the
+    eight coil slots of the Gram's grid."""
+    log(f"end-to-end general mask r={r} precision={precision}")
+    p = datagen.make_small(64, 32, 3, 20, r, seed=60 + r, kind="index", m=700, lowrank=True,
+                           snr_db=40.0, variable_m=True)
+    cs = Case(p)
+    assert int(max(cs.m_k)) > 512  # two sample chunks of the Gram in the longest frames
+    ctx, Xg, ref = _end_to_end(cs, 8, precision=precision)
+    st = ctx.stats()
+    n_gpu, n_ref = M.nmse(Xg, p.zstar), M.nmse(ref.X, p.zstar)
+    log(f"  NMSE gpu {n_gpu:.6e} oracle {n_ref:.6e}; X rel {rel(Xg, ref.X):.2e}; t {st['t']}")
+    assert st["t"] == 8
+    assert abs(n_gpu - n_ref) <= 1e-4
+    assert rel(Xg, ref.X) < 1e-3
+    assert ctx.get_eta() == pytest.approx(ref.eta, rel=1e-4)
+
+
 @pytest.mark.parametrize("ny,r", [(64, 9), (64, 12), (128, 16), (64, 16), (256, 12)])
 def test_end_to_end_fused_adjoint_gram_ranks_above_8(ny, r):
     """Image columns of 64 and 128 pixels: the adjoint transform also forms
