@@ -1831,14 +1831,16 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s) {
   const dim3 g((unsigned)((a.n + AG_NT - 1) / AG_NT));
   if (a.r <= 4) hipLaunchKernelGGL(k_apply<4>, g, dim3(AG_NT), 0, s, a);
   else if (a.r <= 8) hipLaunchKernelGGL(k_apply<8>, g, dim3(AG_NT), 0, s, a);
+  else if (a.r <= 12) hipLaunchKernelGGL(k_apply<12>, g, dim3(AG_NT), 0, s, a);
   else hipLaunchKernelGGL(k_apply<16>, g, dim3(AG_NT), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_qr_small(const QrSmallArgs& a, hipStream_t s) {
-  // the 16-row form keeps its one-wave registers with 256 threads
-  // 1,024 threads: the partial sums at the start take most of its time
+  // 1,024 threads for the partial sums at the start; the one-wave factor's
+  // rows padded to 8, 12 or 16 with the identity
   if (a.r <= 8) hipLaunchKernelGGL(k_qr_small<8>, dim3(1), dim3(1024), 0, s, a);
+  else if (a.r <= 12) hipLaunchKernelGGL(k_qr_small<12>, dim3(1), dim3(1024), 0, s, a);
   else hipLaunchKernelGGL(k_qr_small<16>, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }

@@ -671,12 +671,16 @@ hipError_t launch_gram_index(const GramIndexArgs& a, int q, bool fp64, hipStream
 }
 
 hipError_t launch_solve(const SolveArgs& a, int q, bool fp64, hipStream_t s) {
-  if (fp64)
+  // the factor's register tile: rows padded to 8, 12 or 16 with the identity
+  if (fp64) {
     if (a.r <= 8) hipLaunchKernelGGL((k_solve<double, 8>), dim3(q), dim3(SOLVE_NT), 0, s, a);
+    else if (a.r <= 12) hipLaunchKernelGGL((k_solve<double, 12>), dim3(q), dim3(SOLVE_NT), 0, s, a);
     else hipLaunchKernelGGL((k_solve<double, 16>), dim3(q), dim3(SOLVE_NT), 0, s, a);
-  else
+  } else {
     if (a.r <= 8) hipLaunchKernelGGL((k_solve<float, 8>), dim3(q), dim3(SOLVE_NT), 0, s, a);
+    else if (a.r <= 12) hipLaunchKernelGGL((k_solve<float, 12>), dim3(q), dim3(SOLVE_NT), 0, s, a);
     else hipLaunchKernelGGL((k_solve<float, 16>), dim3(q), dim3(SOLVE_NT), 0, s, a);
+  }
   return hipGetLastError();
 }
 
