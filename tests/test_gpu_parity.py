@@ -229,6 +229,21 @@ def test_end_to_end_general_mask_ranks(r, precision):
     assert ctx.get_eta() == pytest.approx(ref.eta, rel=1e-4)
 
 
+def test_end_to_end_general_mask_more_coils_than_xcds():
+    """Twelve coils on general masks: the Gram's grid deals coil c to slot
+    c mod 8 of two coil groups (slots 12..15 empty)."""
+    log("end-to-end general mask, 12 coils")
+    p = datagen.make_small(32, 32, 12, 12, 6, seed=71, kind="index", m=600, lowrank=True,
+                           snr_db=40.0, variable_m=True)
+    cs = Case(p)
+    ctx, Xg, ref = _end_to_end(cs, 6)
+    n_gpu, n_ref = M.nmse(Xg, p.zstar), M.nmse(ref.X, p.zstar)
+    log(f"  NMSE gpu {n_gpu:.6e} oracle {n_ref:.6e}; X rel {rel(Xg, ref.X):.2e}")
+    assert abs(n_gpu - n_ref) <= 1e-4
+    assert rel(Xg, ref.X) < 1e-3
+    assert ctx.get_eta() == pytest.approx(ref.eta, rel=1e-4)
+
+
 @pytest.mark.parametrize("ny,r", [(64, 9), (64, 12), (128, 16), (64, 16), (256, 12)])
 def test_end_to_end_fused_adjoint_gram_ranks_above_8(ny, r):
     """Image columns of 64 and 128 pixels: the adjoint transform also forms
