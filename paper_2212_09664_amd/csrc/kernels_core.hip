@@ -1426,9 +1426,16 @@ __global__ __launch_bounds__(1024) void k_init_eig(InitEigArgs a) {
         for (int hh = 0; hh < 2; ++hh) {
           const int i = l + 64 * hh;
           if (i < m) {
+            // one load per entry from a selected (valid) index, no branch:
+            // row k1 + i's offset is fixed for the lane, row k1 + j's is
+            // wave-uniform
+            const int ti = tri(k1 + i) + k1;
             double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
             for (int j = wv; j < m; j += 8) {
-              const double2 bij = i >= j ? A[tri(k1 + i) + k1 + j] : dconj(A[tri(k1 + j) + k1 + i]);
+              const int up = i < j;
+              const double2 raw = A[up ? tri(k1 + j) + k1 + i : ti + j];
+              const double2 bij = make_double2(raw.x, up ? -raw.y : raw.y);
               acc = dadd(acc, dmul(bij, s_v[j]));
             }
             s_p[wv][i] = acc;
